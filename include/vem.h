@@ -1,0 +1,191 @@
+/*
+ * vem.h - C ABI of the MI355X (gfx950) mixed virtual element solver.
+ *
+ * The library solves the saddle-point system that the mixed virtual element
+ * method produces for the Darcy / mixed Poisson problem on a 3D polyhedral
+ * mesh (Dassi & Scacchi, "Parallel solvers for virtual element
+ * discretizations of elliptic equations in mixed form"):
+ *
+ *     nu u + grad p = 0,   div u = f   in Omega,   p = p_D on dOmega,
+ *
+ * discretised as in Sections 4.1-4.3 of the paper (face normal-flux moments,
+ * L2 projector built through integration by parts, stabilised local forms)
+ * and assembled in the symmetric form (Section 5, matrix with blocks A, B^T,
+ * B, -C, here with C = 0 and A = M):
+ *
+ *     [ M  B^T ] [u]   [  g ]       B = -B_div,
+ *     [ B   0  ] [p] = [ -F ],      g_i = -int_{dOmega} p_D phi_i . n.
+ *
+ * The system is solved by right-preconditioned restarted flexible GMRES with
+ * one of the paper's two block-diagonal preconditioners (Section 5, eqs.
+ * block_schur and block_diag):
+ *   VEM_PREC_SCHUR: diag(M)^{-1} on the flux block, an inner Jacobi-CG solve
+ *                   of S = B diag(M)^{-1} B^T on the pressure block;
+ *   VEM_PREC_REG:   an inner Jacobi-CG solve of M + B^T B / gamma on the flux
+ *                   block, gamma^{-1} I on the pressure block, gamma = h^2 with
+ *                   h the mean cell diameter (eq. meshSize).
+ *
+ * Conventions for every entry point:
+ *   - Every function returns a vem_status: 0 = success, > 0 = warning with
+ *     valid outputs, < 0 = error with the outputs left untouched.  No C++
+ *     exception crosses the ABI.  vem_last_error() gives the message of the
+ *     last failure on a handle.
+ *   - The caller owns every pointer it passes; the library owns only the
+ *     device memory it allocates internally, released by vem_destroy().
+ *   - "device" pointers are HIP device allocations on the handle's device;
+ *     "host" pointers are ordinary host memory.  Device buffers must not be
+ *     aliased unless stated.
+ *   - All device work is enqueued on the stream given to vem_create();
+ *     functions that return host-visible results synchronise that stream.
+ *   - One handle must not be used by two host threads at once.
+ *   - Index arrays are int32; sizes are limited to 2^31 - 1 entries.
+ */
+#ifndef VEM_H
+#define VEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vem_ctx* vem_handle;
+typedef int vem_status;
+
+enum {
+  VEM_OK = 0,
+  VEM_NOT_CONVERGED = 1, /* tolerance not reached within maxit: best iterate written */
+  VEM_EINVAL = -1,       /* invalid argument or call order */
+  VEM_EBADMESH = -2,     /* inconsistent mesh (bad index, open cell, zero area/volume, ...) */
+  VEM_ENOMEM = -3,       /* device allocation failed or size limit exceeded */
+  VEM_EHIP = -4,         /* HIP runtime error */
+  VEM_EBREAKDOWN = -5,   /* Krylov breakdown that could not be recovered */
+  VEM_ENAN = -6          /* NaN or Inf met in the solve */
+};
+
+enum { VEM_MEM_HOST = 0, VEM_MEM_DEVICE = 1 };
+
+/* Element families.  VEM_LO: the lowest-order member of the paper's face
+ * space (Section 4.1) - one normal-flux moment per face, divergence and
+ * pressure constant per cell.  VEM_PAPER: the paper's order-k element (face
+ * space P_k, divergence and pressure P_{k-1}); reserved, not yet built. */
+enum { VEM_LO = 0, VEM_PAPER = 1 };
+
+enum { VEM_PREC_SCHUR = 0, VEM_PREC_REG = 1, VEM_PREC_NONE = 2 };
+
+/* matrices for vem_export_csr */
+enum { VEM_MAT_K = 0, VEM_MAT_SCHUR = 1, VEM_MAT_REG = 2 };
+
+typedef struct {
+  int64_t n_vertices, n_faces, n_cells;
+  int64_t n_u;       /* flux unknowns (face moments, then interior moments) */
+  int64_t n_p;       /* pressure unknowns (moments, cell by cell) */
+  int64_t n;         /* n_u + n_p */
+  int64_t nnz_K;     /* saddle matrix [M B^T; B 0] */
+  int64_t nnz_schur; /* S = B diag(M)^{-1} B^T */
+  int64_t nnz_reg;   /* M + B^T B / gamma */
+  int64_t n_qp_cell; /* volume quadrature points (load f) */
+  int64_t n_qp_face; /* boundary-face quadrature points (p_D) */
+  int32_t load_points; /* quadrature points per direction of the load rule */
+  int32_t max_cell_faces;
+  double h;          /* mean cell diameter (eq. meshSize) */
+  double gamma;      /* default Block-Reg parameter h^2 */
+} vem_sizes;
+
+typedef struct {
+  int32_t precond;     /* VEM_PREC_* */
+  int32_t restart;     /* FGMRES restart length m, 1..32 */
+  int32_t maxit;       /* maximum outer iterations */
+  int32_t use_x0;      /* nonzero: u, p hold the initial guess */
+  double tol;          /* stop when ||b - K x||_2 <= tol ||b||_2 */
+  double inner_tol;    /* relative tolerance of the inner Jacobi-CG (preconditioned residual) */
+  int32_t inner_maxit; /* iteration cap of one inner solve */
+  int32_t inner_check; /* inner iterations enqueued between convergence checks */
+  double gamma;        /* Block-Reg gamma; <= 0 selects h^2 */
+} vem_solve_opts;
+
+typedef struct {
+  int32_t iterations;       /* outer FGMRES iterations */
+  int32_t restarts;         /* completed restart cycles */
+  int64_t inner_iterations; /* total inner CG iterations */
+  double relres;            /* true ||b - K x|| / ||b|| of the returned iterate */
+  double solve_ms;          /* wall time of vem_solve */
+  int32_t status;
+} vem_solve_info;
+
+/* Fill opts with defaults: Block-Schur, m = 30, maxit = 5000, tol = 1e-8,
+ * inner_tol = 1e-6, inner_maxit = 5000, inner_check = 32, gamma = h^2. */
+void vem_solve_opts_default(vem_solve_opts* opts);
+
+/* Create a handle bound to the current HIP device and to `stream`
+ * (a hipStream_t; NULL = the default stream). */
+vem_status vem_create(vem_handle* h, void* stream);
+vem_status vem_destroy(vem_handle h);
+
+/* Set the polyhedral mesh (copied in; the caller may free its arrays on
+ * return).  xyz[nv*3]: vertex coordinates.  face_ptr[nf+1], face_vtx: the
+ * vertex loop of each planar convex face, counter-clockwise about the face's
+ * global normal n_f.  cell_ptr[nc+1], cell_face, cell_face_sign: the faces of
+ * each cell and sigma = +1 if n_f points out of the cell, -1 otherwise.  Every
+ * face must bound one cell (boundary) or two cells of opposite sign.  All
+ * arrays are host or device memory according to mem_kind.  Errors:
+ * VEM_EINVAL (sizes), VEM_EBADMESH (indices out of range, a face used twice
+ * with one sign, a face of no cell, zero area, non-positive volume). */
+vem_status vem_set_mesh(vem_handle h, int64_t nv, const double* xyz, int64_t nf, const int32_t* face_ptr,
+                        const int32_t* face_vtx, int64_t nc, const int32_t* cell_ptr, const int32_t* cell_face,
+                        const int8_t* cell_face_sign, int mem_kind);
+
+/* Build geometry, local matrices (nu = 1) and the sparse patterns.
+ * family: VEM_LO (k ignored).  load_points: points per direction of the
+ * conical-product rule used for f and p_D (1..6; degree 2n-1).  The
+ * coefficient is set to nu = 1 and the right-hand side to zero. */
+vem_status vem_discretize(vem_handle h, int family, int k, int load_points);
+
+vem_status vem_get_sizes(vem_handle h, vem_sizes* out);
+
+/* Write the quadrature points at which the caller evaluates f and p_D
+ * (device buffers): qp_cell[n_qp_cell*3] and qp_face[n_qp_face*3] (either
+ * may be NULL to skip).  Points are ordered cell by cell, then by the
+ * tetrahedra (x_ref, v0, v_a, v_{a+1}) of each face, then by the reference
+ * points; boundary-face points follow the boundary faces in face order. */
+vem_status vem_get_quadrature(vem_handle h, double* qp_cell, double* qp_face);
+
+/* nu = 1/K per cell (device, n_cells doubles, all > 0).  Rescales the flux
+ * block M (M_P is proportional to nu_P, Section 4.3) and rebuilds both
+ * preconditioners; the local projectors are not recomputed. */
+vem_status vem_set_coefficient(vem_handle h, const double* nu);
+
+/* Right-hand side from point values (device): f_qp[n_qp_cell] at the points
+ * of vem_get_quadrature, pD_qp[n_qp_face] (NULL means p_D = 0). */
+vem_status vem_set_rhs(vem_handle h, const double* f_qp, const double* pD_qp);
+
+/* Solve.  u[n_u], p[n_p]: caller-owned device buffers receiving the flux and
+ * pressure unknowns (read as the initial guess when opts->use_x0).  Blocks
+ * until the result is known.  Returns VEM_OK, VEM_NOT_CONVERGED (best
+ * iterate written), or an error.  info may be NULL. */
+vem_status vem_solve(vem_handle h, const vem_solve_opts* opts, double* u, double* p, vem_solve_info* info);
+
+/* y = K x for device vectors of length n (test hook for the saddle SpMV). */
+vem_status vem_apply(vem_handle h, const double* x, double* y);
+
+/* Copy a matrix out in CSR form to device buffers rowptr[rows+1], col[nnz],
+ * val[nnz]; rows = n (VEM_MAT_K), n_p (VEM_MAT_SCHUR), n_u (VEM_MAT_REG). */
+vem_status vem_export_csr(vem_handle h, int which, int32_t* rowptr, int32_t* col, double* val);
+
+/* Copy the assembled right-hand side b = [g; -F] (device, n doubles). */
+vem_status vem_get_rhs(vem_handle h, double* b);
+
+/* Geometry export (device buffers, any may be NULL): face area[nf],
+ * normal[nf*3], centroid[nf*3]; cell volume[nc], centroid[nc*3],
+ * diameter[nc]. */
+vem_status vem_get_geometry(vem_handle h, double* face_area, double* face_normal, double* face_centroid,
+                            double* cell_volume, double* cell_centroid, double* cell_diam);
+
+const char* vem_status_string(vem_status st);
+const char* vem_last_error(vem_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VEM_H */

@@ -1,0 +1,992 @@
+// C ABI entry points, set-up orchestration and the flexible GMRES driver.
+//
+// Everything numerical runs in the kernels of mesh.hip, element_lo.hip,
+// assemble.hip and krylov.hip; this file owns device memory, enqueues those
+// kernels on the handle's stream and runs the host side of FGMRES (Givens
+// rotations on the (m+1) x m Hessenberg matrix, one 8-byte-class read-back per
+// Arnoldi step).
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <new>
+
+#include "vem_internal.h"
+
+using namespace vem;
+
+struct vem_ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string last_error;
+
+  // mesh (device copies) and host copies of the offsets
+  bool has_mesh = false;
+  int nv = 0, nf = 0, nc = 0;
+  int64_t nfv = 0, ncf = 0;
+  std::vector<int> h_fptr, h_cptr;
+  int max_cell_faces = 0;
+  DBuf<double> xyz;
+  DBuf<int> fptr, fvtx, cptr, cface, inc_cell;
+  DBuf<int8_t> csign;
+  DBuf<int> face_cnt, face_cell, face_lidx, is_bnd;
+
+  // geometry
+  DBuf<double> f_area, f_normal, f_cen, f_diam, f_e1, f_e2;
+  DBuf<double> c_vol, c_cen, c_diam, c_xref;
+  double h = 0.0, gamma_default = 0.0;
+
+  // quadrature
+  int load_n = 3;
+  int64_t ntet = 0, nbf = 0, nbtri = 0;
+  DBuf<int> cell_tet_ptr, tet_inc, tet_a, bface, btri_ptr;
+  DBuf<double> qref_cell, qw_cell, qref_face, qw_face;
+  int npts_cell = 0, npts_face = 0;
+
+  // discretisation
+  bool has_disc = false;
+  int family = VEM_LO, korder = 0;
+  DofLayout L{};
+  DBuf<int> ldof_ptr, sorted_gid, sorted_l;
+  DBuf<int64_t> lmat_ptr, lb_ptr;
+  DBuf<double> M1, Bdiv1;
+  DBuf<double> nu, rhs;
+
+  // matrices
+  Csr K, A, S;
+  DBuf<int> Kdiag, Adiag, Sdiag;
+  DBuf<double> dM, dMinv, dAinv, dSinv;
+  double gamma_A = 0.0;
+  int lanesK = 4, lanesA = 4, lanesS = 4;
+
+  // solver workspace
+  int64_t ws_N = 0;
+  int ws_m = 0;
+  DBuf<double> Vb, Zb, xw;
+  DBuf<double> pr, pz, pp, pq;
+  DBuf<double> partials, scal;
+  DBuf<unsigned> counter;
+  DBuf<PcgState> pcg;
+  HBuf<double> hbuf;
+  HBuf<PcgState> hpcg;
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------------------
+// host utilities: Gauss-Jacobi rules (bracketing + bisection on the three-term recurrence)
+void jacobi_eval(int n, double a, double b, double x, double& p) {
+  if (n == 0) {
+    p = 1.0;
+    return;
+  }
+  double p0 = 1.0, p1 = 0.5 * (a - b + (a + b + 2.0) * x);
+  for (int k = 2; k <= n; ++k) {
+    double c = 2.0 * k + a + b;
+    double a1 = 2.0 * k * (k + a + b) * (c - 2.0);
+    double a2 = (c - 1.0) * (a * a - b * b);
+    double a3 = (c - 2.0) * (c - 1.0) * c;
+    double a4 = 2.0 * (k + a - 1.0) * (k + b - 1.0) * c;
+    double p2 = ((a2 + a3 * x) * p1 - a4 * p0) / a1;
+    p0 = p1;
+    p1 = p2;
+  }
+  p = p1;
+}
+
+}  // namespace
+
+namespace vem {
+
+// Nodes and weights of int_0^1 (1 - t)^alpha g(t) dt, exact for degree 2n - 1.
+void gauss_jacobi01(int n, int alpha, double* t, double* w) {
+  const double a = alpha, b = 0.0;
+  std::vector<double> roots;
+  const int grid = 20000;
+  double xl = -1.0, pl;
+  jacobi_eval(n, a, b, xl, pl);
+  for (int i = 1; i <= grid && (int)roots.size() < n; ++i) {
+    double xr = -1.0 + 2.0 * i / grid, pr;
+    jacobi_eval(n, a, b, xr, pr);
+    if (pl == 0.0) {
+      roots.push_back(xl);
+    } else if ((pl < 0) != (pr < 0) && pr != 0.0) {
+      double lo = xl, hi = xr, plo = pl;
+      for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi), pm;
+        if (mid == lo || mid == hi) break;
+        jacobi_eval(n, a, b, mid, pm);
+        if ((pm < 0) == (plo < 0)) {
+          lo = mid;
+          plo = pm;
+        } else {
+          hi = mid;
+        }
+      }
+      roots.push_back(0.5 * (lo + hi));
+    }
+    xl = xr;
+    pl = pr;
+  }
+  VEM_REQUIRE((int)roots.size() == n, VEM_EINVAL, "Gauss-Jacobi root search failed");
+  // w_i = 2^{a+b+1} G(n+a+1) G(n+b+1) / (G(n+a+b+1) n!) / ((1-x^2) P_n'(x)^2),
+  // P_n^{(a,b)}' = (n+a+b+1)/2 P_{n-1}^{(a+1,b+1)}
+  double lc = (a + b + 1.0) * std::log(2.0) + std::lgamma(n + a + 1.0) + std::lgamma(n + b + 1.0) -
+              std::lgamma(n + a + b + 1.0) - std::lgamma(n + 1.0);
+  for (int i = 0; i < n; ++i) {
+    double x = roots[i], q;
+    jacobi_eval(n - 1, a + 1.0, b + 1.0, x, q);
+    double dp = 0.5 * (n + a + b + 1.0) * q;
+    double wi = std::exp(lc) / ((1.0 - x * x) * dp * dp);
+    t[i] = 0.5 * (1.0 + x);
+    w[i] = wi / std::pow(2.0, a + 1.0);
+  }
+}
+
+void tet_reference_rule(int n, std::vector<double>& pts, std::vector<double>& w) {
+  std::vector<double> a(n), wa(n), b(n), wb(n), c(n), wc(n);
+  gauss_jacobi01(n, 2, a.data(), wa.data());
+  gauss_jacobi01(n, 1, b.data(), wb.data());
+  gauss_jacobi01(n, 0, c.data(), wc.data());
+  pts.clear();
+  w.clear();
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      for (int k = 0; k < n; ++k) {
+        pts.push_back(a[i]);
+        pts.push_back(b[j] * (1.0 - a[i]));
+        pts.push_back(c[k] * (1.0 - a[i]) * (1.0 - b[j]));
+        w.push_back(wa[i] * wb[j] * wc[k]);
+      }
+}
+
+void tri_reference_rule(int n, std::vector<double>& pts, std::vector<double>& w) {
+  std::vector<double> a(n), wa(n), b(n), wb(n);
+  gauss_jacobi01(n, 1, a.data(), wa.data());
+  gauss_jacobi01(n, 0, b.data(), wb.data());
+  pts.clear();
+  w.clear();
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      pts.push_back(a[i]);
+      pts.push_back(b[j] * (1.0 - a[i]));
+      w.push_back(wa[i] * wb[j]);
+    }
+}
+
+}  // namespace vem
+
+// ---------------------------------------------------------------------------------------
+// scans and small helper kernels
+namespace {
+
+struct ToI64 {
+  __host__ __device__ int64_t operator()(int v) const { return (int64_t)v; }
+};
+
+__global__ void k_narrow(int64_t n, const int64_t* __restrict__ in, int* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (int)in[i];
+}
+
+__global__ void k_set_last_zero_i32(int* p) { *p = 0; }
+__global__ void k_set_last_zero_i64(int64_t* p) { *p = 0; }
+
+__global__ void k_compact(int64_t n, const int* __restrict__ flag, const int* __restrict__ pos, int* out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && flag[i]) out[pos[i]] = (int)i;
+}
+
+__global__ void k_fill_i32(int64_t n, int v, int* p) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+inline int grid_of(int64_t n) { return (int)((n + 255) / 256); }
+
+void fill_i32(hipStream_t s, int64_t n, int v, int* p) {
+  if (n > 0) k_fill_i32<<<grid_of(n), 256, 0, s>>>(n, v, p);
+}
+
+}  // namespace
+
+namespace vem {
+
+int64_t scan_i64(hipStream_t s, const int64_t* len, int64_t n, int64_t* ptr) {
+  // ptr has n+1 entries; scanning n+1 inputs needs len[n] = 0: scan n and add the last
+  size_t bytes = 0;
+  VEM_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, len, ptr, (int)n, s));
+  DBuf<unsigned char> tmp;
+  tmp.alloc(bytes > 0 ? bytes : 1);
+  VEM_HIP(hipcub::DeviceScan::ExclusiveSum(tmp.p, bytes, len, ptr, (int)n, s));
+  int64_t last_ptr = 0, last_len = 0;
+  if (n > 0) {
+    VEM_HIP(hipMemcpyAsync(&last_ptr, ptr + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    VEM_HIP(hipMemcpyAsync(&last_len, len + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  }
+  VEM_HIP(hipStreamSynchronize(s));
+  int64_t total = last_ptr + last_len;
+  VEM_HIP(hipMemcpyAsync(ptr + n, &total, sizeof(int64_t), hipMemcpyHostToDevice, s));
+  VEM_HIP(hipStreamSynchronize(s));
+  return total;
+}
+
+int64_t scan_i32(hipStream_t s, const int* len, int64_t n, int* ptr) {
+  DBuf<int64_t> p64;
+  p64.alloc(n + 1);
+  hipcub::TransformInputIterator<int64_t, ToI64, const int*> it(len, ToI64());
+  size_t bytes = 0;
+  VEM_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, it, p64.p, (int)n, s));
+  DBuf<unsigned char> tmp;
+  tmp.alloc(bytes > 0 ? bytes : 1);
+  VEM_HIP(hipcub::DeviceScan::ExclusiveSum(tmp.p, bytes, it, p64.p, (int)n, s));
+  int64_t last_ptr = 0;
+  int last_len = 0;
+  if (n > 0) {
+    VEM_HIP(hipMemcpyAsync(&last_ptr, p64.p + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    VEM_HIP(hipMemcpyAsync(&last_len, len + n - 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  }
+  VEM_HIP(hipStreamSynchronize(s));
+  int64_t total = last_ptr + last_len;
+  VEM_REQUIRE(total <= INT_MAX, VEM_ENOMEM, "more than 2^31-1 entries in a sparse pattern");
+  if (n > 0) k_narrow<<<grid_of(n), 256, 0, s>>>(n, p64.p, ptr);
+  int t32 = (int)total;
+  VEM_HIP(hipMemcpyAsync(ptr + n, &t32, sizeof(int), hipMemcpyHostToDevice, s));
+  VEM_HIP(hipStreamSynchronize(s));
+  return total;
+}
+
+void launch_compact_flags(hipStream_t s, int64_t n, const int* flag, const int* pos, int* out) {
+  if (n > 0) k_compact<<<grid_of(n), 256, 0, s>>>(n, flag, pos, out);
+}
+
+}  // namespace vem
+
+// ---------------------------------------------------------------------------------------
+namespace {
+
+template <class F>
+vem_status guarded(vem_handle h, F&& body) {
+  try {
+    body();
+    return VEM_OK;
+  } catch (const Error& e) {
+    if (h) h->last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (h) h->last_error = "host allocation failed";
+    return VEM_ENOMEM;
+  } catch (const std::exception& e) {
+    if (h) h->last_error = e.what();
+    return VEM_EINVAL;
+  }
+}
+
+void sync(vem_handle h) { VEM_HIP(hipStreamSynchronize(h->stream)); }
+
+void check_launch() { VEM_HIP(hipGetLastError()); }
+
+int read_err(vem_handle h, const int* derr) {
+  int e = 0;
+  VEM_HIP(hipMemcpyAsync(&e, derr, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  sync(h);
+  return e;
+}
+
+std::string mesh_err_text(int e) {
+  std::string t;
+  if (e & 1) t += " cell with fewer than 4 or more than 64 faces;";
+  if (e & 2) t += " face index out of range;";
+  if (e & 4) t += " sign not +-1;";
+  if (e & 8) t += " face with fewer than 3 vertices;";
+  if (e & 16) t += " vertex index out of range;";
+  if (e & 32) t += " face not shared by one cell or by two cells of opposite sign;";
+  if (e & 64) t += " face of zero or non-finite area;";
+  if (e & 128) t += " cell of non-positive or non-finite volume;";
+  return "bad mesh:" + t;
+}
+
+void ensure_scratch(vem_handle h) {
+  if (!h->partials.p) {
+    h->partials.alloc((size_t)kRedBlocks * kMaxDots);
+    h->counter.alloc(4);
+    VEM_HIP(hipMemsetAsync(h->counter.p, 0, 4 * sizeof(unsigned), h->stream));
+    h->scal.alloc(4 * kMaxDots + 16);
+    h->pcg.alloc(1);
+    h->hbuf.alloc(4 * kMaxDots + 16);
+    h->hpcg.alloc(1);
+    sync(h);
+  }
+}
+
+// total of a device double array (synchronises)
+double device_sum(vem_handle h, const double* x, int64_t n) {
+  ensure_scratch(h);
+  launch_sum(h->stream, n, x, h->partials, h->counter, h->scal);
+  check_launch();
+  double v = 0.0;
+  VEM_HIP(hipMemcpyAsync(&v, h->scal.p, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  sync(h);
+  return v;
+}
+
+// ----- rebuild every coefficient-dependent value: K, A_gamma, diagonals, S -----
+void rebuild_values(vem_handle h, double gamma) {
+  hipStream_t s = h->stream;
+  DofLayout L = h->L;
+  launch_values(s, L, h->cptr, h->cface, h->csign, h->ldof_ptr, h->sorted_gid, h->sorted_l, h->face_cell,
+                h->face_lidx, h->lmat_ptr, h->M1, h->lb_ptr, h->Bdiv1, h->nu, 1.0 / gamma, h->K.rowptr,
+                h->K.val, h->A.rowptr, h->A.val);
+  check_launch();
+  launch_diag_inv(s, L.Nu, h->Kdiag, h->K.val, h->dM, h->dMinv);
+  launch_diag_inv(s, L.Nu, h->Adiag, h->A.val, nullptr, h->dAinv);
+  launch_schur_values(s, L, h->cptr, h->cface, h->csign, h->ldof_ptr, h->face_cell, h->face_lidx, h->lb_ptr,
+                      h->Bdiv1, h->dM, h->S.rowptr, h->S.col, h->S.val);
+  launch_diag_inv(s, L.Np, h->Sdiag, h->S.val, nullptr, h->dSinv);
+  check_launch();
+  h->gamma_A = gamma;
+}
+
+void ensure_workspace(vem_handle h, int m) {
+  int64_t N = h->L.Nu + h->L.Np;
+  if (h->ws_N == N && h->ws_m >= m) return;
+  h->Vb.alloc((size_t)(m + 1) * N);
+  h->Zb.alloc((size_t)m * N);
+  h->xw.alloc(N);
+  int64_t nm = std::max<int64_t>(h->L.Nu, h->L.Np);
+  h->pr.alloc(nm);
+  h->pz.alloc(nm);
+  h->pp.alloc(nm);
+  h->pq.alloc(nm);
+  h->ws_N = N;
+  h->ws_m = m;
+}
+
+// Inner Jacobi-CG: x ~ A^{-1} b.  Returns the iterations used.
+int inner_pcg(vem_handle h, const Csr& A, int lanes, const double* dinv, const double* b, double* x,
+              const vem_solve_opts& o) {
+  hipStream_t s = h->stream;
+  int64_t n = A.rows;
+  launch_pcg_init(s, n, b, dinv, x, h->pr, h->pz, h->pp, h->pcg, o.inner_tol, o.inner_maxit, h->partials,
+                  h->counter);
+  check_launch();
+  int chunk = std::max(1, o.inner_check);
+  for (;;) {
+    for (int c = 0; c < chunk; ++c)
+      launch_pcg_iter(s, lanes, n, A.rowptr, A.col, A.val, dinv, x, h->pr, h->pz, h->pp, h->pq, h->pcg,
+                      h->partials, h->counter);
+    check_launch();
+    VEM_HIP(hipMemcpyAsync(h->hpcg.p, h->pcg.p, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+    sync(h);
+    if (h->hpcg.p->done) break;
+  }
+  return h->hpcg.p->it;
+}
+
+// z = P^{-1} v for the chosen block preconditioner
+int64_t apply_prec(vem_handle h, const vem_solve_opts& o, const double* v, double* z) {
+  hipStream_t s = h->stream;
+  const int64_t Nu = h->L.Nu, Np = h->L.Np;
+  switch (o.precond) {
+    case VEM_PREC_SCHUR:
+      launch_scale_by(s, Nu, v, h->dMinv, 1.0, z);
+      return inner_pcg(h, h->S, h->lanesS, h->dSinv, v + Nu, z + Nu, o);
+    case VEM_PREC_REG: {
+      int it = inner_pcg(h, h->A, h->lanesA, h->dAinv, v, z, o);
+      launch_scale_by(s, Np, v + Nu, nullptr, 1.0 / h->gamma_A, z + Nu);
+      return it;
+    }
+    default:
+      launch_copy(s, Nu + Np, v, z);
+      return 0;
+  }
+}
+
+void require_disc(vem_handle h) {
+  VEM_REQUIRE(h && h->has_disc, VEM_EINVAL, "call vem_set_mesh and vem_discretize first");
+}
+
+}  // namespace
+
+// =======================================================================================
+extern "C" {
+
+void vem_solve_opts_default(vem_solve_opts* o) {
+  if (!o) return;
+  o->precond = VEM_PREC_SCHUR;
+  o->restart = 30;
+  o->maxit = 5000;
+  o->use_x0 = 0;
+  o->tol = 1e-8;
+  o->inner_tol = 1e-6;
+  o->inner_maxit = 5000;
+  o->inner_check = 32;
+  o->gamma = 0.0;
+}
+
+vem_status vem_create(vem_handle* out, void* stream) {
+  if (!out) return VEM_EINVAL;
+  vem_ctx* h = nullptr;
+  try {
+    h = new vem_ctx();
+  } catch (...) {
+    return VEM_ENOMEM;
+  }
+  vem_status st = guarded(h, [&] {
+    VEM_HIP(hipGetDevice(&h->device));
+    h->stream = (hipStream_t)stream;
+    ensure_scratch(h);
+  });
+  if (st != VEM_OK) {
+    delete h;
+    *out = nullptr;
+    return st;
+  }
+  *out = h;
+  return VEM_OK;
+}
+
+vem_status vem_destroy(vem_handle h) {
+  if (!h) return VEM_OK;
+  (void)hipStreamSynchronize(h->stream);
+  delete h;
+  return VEM_OK;
+}
+
+const char* vem_status_string(vem_status st) {
+  switch (st) {
+    case VEM_OK: return "ok";
+    case VEM_NOT_CONVERGED: return "not converged within maxit";
+    case VEM_EINVAL: return "invalid argument";
+    case VEM_EBADMESH: return "bad mesh";
+    case VEM_ENOMEM: return "out of memory or size limit";
+    case VEM_EHIP: return "HIP runtime error";
+    case VEM_EBREAKDOWN: return "Krylov breakdown";
+    case VEM_ENAN: return "NaN or Inf in the solve";
+    default: return "unknown status";
+  }
+}
+
+const char* vem_last_error(vem_handle h) { return h ? h->last_error.c_str() : "null handle"; }
+
+vem_status vem_set_mesh(vem_handle h, int64_t nv, const double* xyz, int64_t nf, const int32_t* face_ptr,
+                        const int32_t* face_vtx, int64_t nc, const int32_t* cell_ptr, const int32_t* cell_face,
+                        const int8_t* cell_face_sign, int mem_kind) {
+  if (!h) return VEM_EINVAL;
+  return guarded(h, [&] {
+    VEM_REQUIRE(nv > 0 && nf > 0 && nc > 0 && nv < INT_MAX && nf < INT_MAX && nc < INT_MAX, VEM_EINVAL,
+                "mesh sizes must be positive and below 2^31");
+    VEM_REQUIRE(xyz && face_ptr && face_vtx && cell_ptr && cell_face && cell_face_sign, VEM_EINVAL,
+                "null mesh array");
+    VEM_REQUIRE(mem_kind == VEM_MEM_HOST || mem_kind == VEM_MEM_DEVICE, VEM_EINVAL, "bad mem_kind");
+    hipStream_t s = h->stream;
+    h->has_mesh = false;
+    h->has_disc = false;
+    // offsets to the host for validation
+    h->h_fptr.resize(nf + 1);
+    h->h_cptr.resize(nc + 1);
+    if (mem_kind == VEM_MEM_HOST) {
+      std::memcpy(h->h_fptr.data(), face_ptr, (nf + 1) * sizeof(int));
+      std::memcpy(h->h_cptr.data(), cell_ptr, (nc + 1) * sizeof(int));
+    } else {
+      VEM_HIP(hipMemcpyAsync(h->h_fptr.data(), face_ptr, (nf + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
+      VEM_HIP(hipMemcpyAsync(h->h_cptr.data(), cell_ptr, (nc + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
+      sync(h);
+    }
+    VEM_REQUIRE(h->h_fptr[0] == 0 && h->h_cptr[0] == 0, VEM_EBADMESH, "offset arrays must start at 0");
+    for (int64_t i = 0; i < nf; ++i)
+      VEM_REQUIRE(h->h_fptr[i + 1] >= h->h_fptr[i], VEM_EBADMESH, "face_ptr not monotone");
+    int maxcf = 0;
+    for (int64_t i = 0; i < nc; ++i) {
+      VEM_REQUIRE(h->h_cptr[i + 1] >= h->h_cptr[i], VEM_EBADMESH, "cell_ptr not monotone");
+      maxcf = std::max(maxcf, h->h_cptr[i + 1] - h->h_cptr[i]);
+    }
+    h->nv = (int)nv;
+    h->nf = (int)nf;
+    h->nc = (int)nc;
+    h->nfv = h->h_fptr[nf];
+    h->ncf = h->h_cptr[nc];
+    h->max_cell_faces = maxcf;
+    h->xyz.alloc(3 * nv);
+    h->fptr.alloc(nf + 1);
+    h->fvtx.alloc(h->nfv);
+    h->cptr.alloc(nc + 1);
+    h->cface.alloc(h->ncf);
+    h->csign.alloc(h->ncf);
+    h->inc_cell.alloc(h->ncf);
+    VEM_HIP(hipMemcpyAsync(h->xyz.p, xyz, 3 * nv * sizeof(double), hipMemcpyDefault, s));
+    VEM_HIP(hipMemcpyAsync(h->fptr.p, h->h_fptr.data(), (nf + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+    VEM_HIP(hipMemcpyAsync(h->fvtx.p, face_vtx, h->nfv * sizeof(int), hipMemcpyDefault, s));
+    VEM_HIP(hipMemcpyAsync(h->cptr.p, h->h_cptr.data(), (nc + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+    VEM_HIP(hipMemcpyAsync(h->cface.p, cell_face, h->ncf * sizeof(int), hipMemcpyDefault, s));
+    VEM_HIP(hipMemcpyAsync(h->csign.p, cell_face_sign, h->ncf * sizeof(int8_t), hipMemcpyDefault, s));
+    // face -> (cell, local index) for both orientations, with validation
+    h->face_cnt.alloc(2 * (size_t)nf);
+    h->face_cell.alloc(2 * (size_t)nf);
+    h->face_lidx.alloc(2 * (size_t)nf);
+    h->is_bnd.alloc(nf + 1);
+    fill_i32(s, 2 * nf, 0, h->face_cnt);
+    fill_i32(s, 2 * nf, -1, h->face_cell);
+    fill_i32(s, 2 * nf, -1, h->face_lidx);
+    DBuf<int> derr;
+    derr.alloc(1);
+    fill_i32(s, 1, 0, derr);
+    launch_check_mesh(s, h->nv, h->nf, h->nc, h->fptr, h->fvtx, h->cptr, h->cface, h->csign, h->face_cnt,
+                      h->face_cell, h->face_lidx, h->inc_cell, derr);
+    check_launch();
+    int e = read_err(h, derr);
+    VEM_REQUIRE(e == 0, VEM_EBADMESH, mesh_err_text(e));
+    h->has_mesh = true;
+  });
+}
+
+vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
+  if (!h) return VEM_EINVAL;
+  return guarded(h, [&] {
+    VEM_REQUIRE(h->has_mesh, VEM_EINVAL, "call vem_set_mesh first");
+    VEM_REQUIRE(family == VEM_LO, VEM_EINVAL, "only the lowest-order family (VEM_LO) is available");
+    VEM_REQUIRE(load_points >= 1 && load_points <= 6, VEM_EINVAL, "load_points must be in 1..6");
+    (void)k;
+    hipStream_t s = h->stream;
+    h->has_disc = false;
+    const int nf = h->nf, nc = h->nc;
+    // ---- a1: geometry
+    h->f_area.alloc(nf);
+    h->f_normal.alloc(3 * (size_t)nf);
+    h->f_cen.alloc(3 * (size_t)nf);
+    h->f_diam.alloc(nf);
+    h->f_e1.alloc(3 * (size_t)nf);
+    h->f_e2.alloc(3 * (size_t)nf);
+    h->c_vol.alloc(nc);
+    h->c_cen.alloc(3 * (size_t)nc);
+    h->c_diam.alloc(nc);
+    h->c_xref.alloc(3 * (size_t)nc);
+    launch_face_geometry(s, nf, h->xyz, h->fptr, h->fvtx, h->f_area, h->f_normal, h->f_cen, h->f_diam, h->f_e1,
+                         h->f_e2);
+    launch_cell_geometry(s, nc, h->xyz, h->fptr, h->fvtx, h->cptr, h->cface, h->csign, h->c_vol, h->c_cen,
+                         h->c_diam, h->c_xref);
+    check_launch();
+    DBuf<int> derr;
+    derr.alloc(1);
+    fill_i32(s, 1, 0, derr);
+    fill_i32(s, 1, 0, h->is_bnd.p + nf);
+    launch_check_faces(s, nf, h->face_cnt, h->f_area, h->is_bnd, derr);
+    launch_check_cells(s, nc, h->c_vol, derr);
+    check_launch();
+    int e = read_err(h, derr);
+    VEM_REQUIRE(e == 0, VEM_EBADMESH, mesh_err_text(e));
+    h->h = device_sum(h, h->c_diam, nc) / nc;
+    h->gamma_default = h->h * h->h;
+
+    // ---- quadrature support: tetrahedra of the cells, triangles of the boundary faces
+    h->load_n = load_points;
+    {
+      std::vector<double> p, w;
+      tet_reference_rule(load_points, p, w);
+      h->npts_cell = (int)w.size();
+      h->qref_cell.alloc(p.size());
+      h->qw_cell.alloc(w.size());
+      VEM_HIP(hipMemcpyAsync(h->qref_cell.p, p.data(), p.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      VEM_HIP(hipMemcpyAsync(h->qw_cell.p, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      sync(h);
+      tri_reference_rule(load_points, p, w);
+      h->npts_face = (int)w.size();
+      h->qref_face.alloc(p.size());
+      h->qw_face.alloc(w.size());
+      VEM_HIP(hipMemcpyAsync(h->qref_face.p, p.data(), p.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      VEM_HIP(hipMemcpyAsync(h->qw_face.p, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      sync(h);
+    }
+    {
+      DBuf<int> cnt;
+      cnt.alloc(nc + 1);
+      launch_tet_counts(s, nc, h->fptr, h->cptr, h->cface, cnt);
+      check_launch();
+      h->cell_tet_ptr.alloc(nc + 1);
+      h->ntet = scan_i32(s, cnt, nc, h->cell_tet_ptr);
+      h->tet_inc.alloc(h->ntet);
+      h->tet_a.alloc(h->ntet);
+      launch_tets(s, nc, h->fptr, h->cptr, h->cface, h->cell_tet_ptr, h->tet_inc, h->tet_a);
+      check_launch();
+      DBuf<int> pos;
+      pos.alloc(nf + 1);
+      h->nbf = scan_i32(s, h->is_bnd, nf, pos);
+      h->bface.alloc(h->nbf > 0 ? h->nbf : 1);
+      launch_compact_flags(s, nf, h->is_bnd, pos, h->bface);
+      DBuf<int> tc;
+      tc.alloc(h->nbf + 1);
+      launch_bnd_tri_counts(s, (int)h->nbf, h->bface, h->fptr, tc);
+      check_launch();
+      h->btri_ptr.alloc(h->nbf + 1);
+      h->nbtri = h->nbf > 0 ? scan_i32(s, tc, h->nbf, h->btri_ptr) : 0;
+      if (h->nbf == 0) fill_i32(s, 1, 0, h->btri_ptr);
+    }
+
+    // ---- a2-a4: local matrices (coefficient-free)
+    DofLayout L{};
+    L.nf = nf;
+    L.nc = nc;
+    L.nfd = 1;
+    L.nint = 0;
+    L.npd = 1;
+    L.Nu = (int64_t)nf * L.nfd + (int64_t)nc * L.nint;
+    L.Np = (int64_t)nc * L.npd;
+    h->L = L;
+    h->family = family;
+    h->korder = 0;
+    {
+      DBuf<int64_t> nd, nm, nb;
+      nd.alloc(nc + 1);
+      nm.alloc(nc + 1);
+      nb.alloc(nc + 1);
+      launch_cell_sizes(s, L, h->cptr, nd, nm, nb);
+      check_launch();
+      DBuf<int64_t> p64;
+      p64.alloc(nc + 1);
+      int64_t tot = scan_i64(s, nd, nc, p64);
+      VEM_REQUIRE(tot <= INT_MAX, VEM_ENOMEM, "too many local DOFs");
+      h->ldof_ptr.alloc(nc + 1);
+      k_narrow<<<grid_of(nc + 1), 256, 0, s>>>(nc + 1, p64.p, h->ldof_ptr.p);
+      h->lmat_ptr.alloc(nc + 1);
+      int64_t nmat = scan_i64(s, nm, nc, h->lmat_ptr);
+      h->lb_ptr.alloc(nc + 1);
+      int64_t nbd = scan_i64(s, nb, nc, h->lb_ptr);
+      h->M1.alloc(nmat);
+      h->Bdiv1.alloc(nbd);
+      h->sorted_gid.alloc(tot);
+      h->sorted_l.alloc(tot);
+    }
+    launch_lo_local(s, h->ncf, h->inc_cell, h->cptr, h->cface, h->csign, h->f_area, h->f_normal, h->f_cen, h->c_vol,
+                    h->c_cen, h->lmat_ptr, h->M1, h->lb_ptr, h->Bdiv1);
+    launch_ldof_sort(s, L, h->cptr, h->cface, h->ldof_ptr, h->sorted_gid, h->sorted_l);
+    check_launch();
+
+    // ---- a5/a6: patterns of K, A_gamma and S
+    const int64_t N = L.Nu + L.Np;
+    {
+      DBuf<int> lenK, lenA, lenS;
+      lenK.alloc(N + 1);
+      lenA.alloc(L.Nu + 1);
+      lenS.alloc(L.Np + 1);
+      launch_rowlen(s, L, h->cptr, h->ldof_ptr, h->sorted_gid, h->face_cell, h->face_lidx, h->cface, lenK, lenA,
+                    lenS);
+      check_launch();
+      h->K.rows = N;
+      h->A.rows = L.Nu;
+      h->S.rows = L.Np;
+      h->K.rowptr.alloc(N + 1);
+      h->A.rowptr.alloc(L.Nu + 1);
+      h->S.rowptr.alloc(L.Np + 1);
+      h->K.nnz = scan_i32(s, lenK, N, h->K.rowptr);
+      h->A.nnz = scan_i32(s, lenA, L.Nu, h->A.rowptr);
+      h->S.nnz = scan_i32(s, lenS, L.Np, h->S.rowptr);
+    }
+    h->K.col.alloc(h->K.nnz);
+    h->K.val.alloc(h->K.nnz);
+    h->A.col.alloc(h->A.nnz);
+    h->A.val.alloc(h->A.nnz);
+    h->S.col.alloc(h->S.nnz);
+    h->S.val.alloc(h->S.nnz);
+    h->Kdiag.alloc(L.Nu);
+    h->Adiag.alloc(L.Nu);
+    h->Sdiag.alloc(L.Np);
+    launch_fill_patterns(s, L, h->cptr, h->ldof_ptr, h->sorted_gid, h->face_cell, h->face_lidx, h->cface,
+                         h->K.rowptr, h->K.col, h->Kdiag, h->A.rowptr, h->A.col, h->Adiag, h->S.rowptr, h->S.col,
+                         h->Sdiag);
+    check_launch();
+    h->lanesK = spmv_lanes((double)h->K.nnz / N);
+    h->lanesA = spmv_lanes((double)h->A.nnz / L.Nu);
+    h->lanesS = spmv_lanes((double)h->S.nnz / L.Np);
+    h->dM.alloc(L.Nu);
+    h->dMinv.alloc(L.Nu);
+    h->dAinv.alloc(L.Nu);
+    h->dSinv.alloc(L.Np);
+    h->nu.alloc(nc);
+    launch_fill(s, nc, 1.0, h->nu);
+    h->rhs.alloc(N);
+    launch_fill(s, N, 0.0, h->rhs);
+    rebuild_values(h, h->gamma_default);
+    sync(h);
+    h->has_disc = true;
+  });
+}
+
+vem_status vem_get_sizes(vem_handle h, vem_sizes* o) {
+  if (!h || !o) return VEM_EINVAL;
+  return guarded(h, [&] {
+    require_disc(h);
+    std::memset(o, 0, sizeof(*o));
+    o->n_vertices = h->nv;
+    o->n_faces = h->nf;
+    o->n_cells = h->nc;
+    o->n_u = h->L.Nu;
+    o->n_p = h->L.Np;
+    o->n = h->L.Nu + h->L.Np;
+    o->nnz_K = h->K.nnz;
+    o->nnz_schur = h->S.nnz;
+    o->nnz_reg = h->A.nnz;
+    o->n_qp_cell = h->ntet * h->npts_cell;
+    o->n_qp_face = h->nbtri * h->npts_face;
+    o->load_points = h->load_n;
+    o->max_cell_faces = h->max_cell_faces;
+    o->h = h->h;
+    o->gamma = h->gamma_default;
+  });
+}
+
+vem_status vem_get_quadrature(vem_handle h, double* qp_cell, double* qp_face) {
+  if (!h) return VEM_EINVAL;
+  return guarded(h, [&] {
+    require_disc(h);
+    hipStream_t s = h->stream;
+    if (qp_cell)
+      launch_qp_cell(s, h->ntet, h->npts_cell, h->qref_cell, h->tet_inc, h->tet_a, h->inc_cell, h->xyz, h->fptr,
+                     h->fvtx, h->cface, h->c_xref, qp_cell);
+    if (qp_face)
+      launch_qp_face(s, (int)h->nbf, h->npts_face, h->qref_face, h->bface, h->btri_ptr, h->xyz, h->fptr, h->fvtx,
+                     qp_face);
+    check_launch();
+  });
+}
+
+vem_status vem_set_coefficient(vem_handle h, const double* nu) {
+  if (!h || !nu) return VEM_EINVAL;
+  return guarded(h, [&] {
+    require_disc(h);
+    VEM_HIP(hipMemcpyAsync(h->nu.p, nu, h->nc * sizeof(double), hipMemcpyDefault, h->stream));
+    rebuild_values(h, h->gamma_A > 0 ? h->gamma_A : h->gamma_default);
+    sync(h);
+  });
+}
+
+vem_status vem_set_rhs(vem_handle h, const double* f_qp, const double* pD_qp) {
+  if (!h || !f_qp) return VEM_EINVAL;
+  return guarded(h, [&] {
+    require_disc(h);
+    hipStream_t s = h->stream;
+    launch_fill(s, h->L.Nu, 0.0, h->rhs);
+    DBuf<double> tsum;
+    tsum.alloc(h->ntet);
+    launch_load_tets(s, h->ntet, h->npts_cell, h->qw_cell, h->tet_inc, h->tet_a, h->inc_cell, h->xyz, h->fptr,
+                     h->fvtx, h->cface, h->csign, h->c_xref, f_qp, tsum);
+    launch_load_cells(s, h->nc, h->cell_tet_ptr, tsum, h->rhs.p + h->L.Nu);
+    if (pD_qp)
+      launch_bnd_rhs(s, (int)h->nbf, h->npts_face, h->qw_face, h->bface, h->btri_ptr, h->xyz, h->fptr, h->fvtx,
+                     h->face_cell, pD_qp, h->rhs);
+    check_launch();
+    sync(h);
+  });
+}
+
+vem_status vem_apply(vem_handle h, const double* x, double* y) {
+  if (!h || !x || !y) return VEM_EINVAL;
+  return guarded(h, [&] {
+    require_disc(h);
+    launch_spmv(h->stream, h->lanesK, h->K.rows, h->K.rowptr, h->K.col, h->K.val, x, y);
+    check_launch();
+  });
+}
+
+vem_status vem_export_csr(vem_handle h, int which, int32_t* rowptr, int32_t* col, double* val) {
+  if (!h) return VEM_EINVAL;
+  return guarded(h, [&] {
+    require_disc(h);
+    const Csr* M = which == VEM_MAT_K ? &h->K : which == VEM_MAT_SCHUR ? &h->S : which == VEM_MAT_REG ? &h->A : nullptr;
+    VEM_REQUIRE(M, VEM_EINVAL, "unknown matrix");
+    hipStream_t s = h->stream;
+    if (rowptr)
+      VEM_HIP(hipMemcpyAsync(rowptr, M->rowptr.p, (M->rows + 1) * sizeof(int), hipMemcpyDefault, s));
+    if (col) VEM_HIP(hipMemcpyAsync(col, M->col.p, M->nnz * sizeof(int), hipMemcpyDefault, s));
+    if (val) VEM_HIP(hipMemcpyAsync(val, M->val.p, M->nnz * sizeof(double), hipMemcpyDefault, s));
+    sync(h);
+  });
+}
+
+vem_status vem_get_rhs(vem_handle h, double* b) {
+  if (!h || !b) return VEM_EINVAL;
+  return guarded(h, [&] {
+    require_disc(h);
+    VEM_HIP(hipMemcpyAsync(b, h->rhs.p, (h->L.Nu + h->L.Np) * sizeof(double), hipMemcpyDefault, h->stream));
+    sync(h);
+  });
+}
+
+vem_status vem_get_geometry(vem_handle h, double* fa, double* fn, double* fc, double* cv, double* cc, double* cd) {
+  if (!h) return VEM_EINVAL;
+  return guarded(h, [&] {
+    require_disc(h);
+    hipStream_t s = h->stream;
+    auto cp = [&](double* dst, const double* src, size_t n) {
+      if (dst) VEM_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDefault, s));
+    };
+    cp(fa, h->f_area, h->nf);
+    cp(fn, h->f_normal, 3 * (size_t)h->nf);
+    cp(fc, h->f_cen, 3 * (size_t)h->nf);
+    cp(cv, h->c_vol, h->nc);
+    cp(cc, h->c_cen, 3 * (size_t)h->nc);
+    cp(cd, h->c_diam, h->nc);
+    sync(h);
+  });
+}
+
+vem_status vem_solve(vem_handle h, const vem_solve_opts* opts, double* u, double* p, vem_solve_info* info) {
+  if (!h || !u || !p) return VEM_EINVAL;
+  vem_status result = VEM_OK;
+  vem_status st = guarded(h, [&] {
+    require_disc(h);
+    vem_solve_opts o;
+    if (opts)
+      o = *opts;
+    else
+      vem_solve_opts_default(&o);
+    VEM_REQUIRE(o.restart >= 1 && o.restart <= kMaxRestart, VEM_EINVAL, "restart must be in 1..32");
+    VEM_REQUIRE(o.tol > 0 && o.maxit >= 1, VEM_EINVAL, "tol must be > 0 and maxit >= 1");
+    VEM_REQUIRE(o.precond >= VEM_PREC_SCHUR && o.precond <= VEM_PREC_NONE, VEM_EINVAL, "unknown preconditioner");
+    VEM_REQUIRE(o.inner_tol > 0 && o.inner_maxit >= 1, VEM_EINVAL, "inner_tol must be > 0 and inner_maxit >= 1");
+    auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = h->stream;
+    const int m = o.restart;
+    const int64_t Nu = h->L.Nu, Np = h->L.Np, N = Nu + Np;
+    if (o.precond == VEM_PREC_REG) {
+      double g = o.gamma > 0 ? o.gamma : h->gamma_default;
+      if (g != h->gamma_A) rebuild_values(h, g);
+    }
+    ensure_workspace(h, m);
+    double* V = h->Vb;
+    double* Z = h->Zb;
+    double* x = h->xw;
+    double* dh = h->scal.p;                 // h = V^T w          (<= kMaxDots)
+    double* dh2 = h->scal.p + kMaxDots;     // reorthogonalisation + ||w'||^2
+    double* dn = h->scal.p + 2 * kMaxDots;  // ||w''||^2, ||r||^2
+    double* dy = h->scal.p + 3 * kMaxDots;  // combination coefficients
+    double* hb = h->hbuf.p;
+
+    // ||b||
+    launch_dots(s, N, 1, h->rhs, N, h->rhs, h->partials, h->counter, dn);
+    check_launch();
+    VEM_HIP(hipMemcpyAsync(hb, dn, sizeof(double), hipMemcpyDeviceToHost, s));
+    sync(h);
+    const double bnorm = std::sqrt(hb[0]);
+    VEM_REQUIRE(std::isfinite(bnorm), VEM_ENAN, "right-hand side is not finite");
+
+    if (o.use_x0) {
+      VEM_HIP(hipMemcpyAsync(x, u, Nu * sizeof(double), hipMemcpyDeviceToDevice, s));
+      VEM_HIP(hipMemcpyAsync(x + Nu, p, Np * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else {
+      launch_fill(s, N, 0.0, x);
+    }
+    vem_solve_info inf{};
+    if (bnorm == 0.0) {
+      launch_fill(s, N, 0.0, x);
+    }
+    // r0 = b - K x0
+    launch_residual(s, h->lanesK, N, h->K.rowptr, h->K.col, h->K.val, x, h->rhs, V, h->partials, h->counter, dn);
+    check_launch();
+    VEM_HIP(hipMemcpyAsync(hb, dn, sizeof(double), hipMemcpyDeviceToHost, s));
+    sync(h);
+    double beta = std::sqrt(hb[0]);
+    const double bref = bnorm > 0 ? bnorm : 1.0;
+    int its = 0, restarts = 0;
+    int64_t inner = 0;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), yv(m);
+    auto Hc = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
+    bool nan_seen = false;
+    while (beta / bref > o.tol && its < o.maxit && bnorm > 0) {
+      // V0 = r / beta
+      launch_scale_to(s, N, V, dn, V);
+      std::fill(H.begin(), H.end(), 0.0);
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta;
+      int jend = 0;
+      for (int j = 0; j < m; ++j) {
+        double* vj = V + (size_t)j * N;
+        double* zj = Z + (size_t)j * N;
+        double* w = V + (size_t)(j + 1) * N;
+        inner += apply_prec(h, o, vj, zj);
+        launch_spmv(s, h->lanesK, N, h->K.rowptr, h->K.col, h->K.val, zj, w);
+        // classical Gram-Schmidt, twice
+        launch_dots(s, N, j + 1, V, N, w, h->partials, h->counter, dh);
+        launch_update_dots(s, N, j + 1, V, N, dh, w, h->partials, h->counter, dh2);
+        launch_update_norm(s, N, j + 1, V, N, dh2, w, h->partials, h->counter, dn);
+        launch_scale_to(s, N, w, dn, w);
+        check_launch();
+        VEM_HIP(hipMemcpyAsync(hb, dh, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        VEM_HIP(hipMemcpyAsync(hb + kMaxDots, dh2, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        VEM_HIP(hipMemcpyAsync(hb + 2 * kMaxDots, dn, sizeof(double), hipMemcpyDeviceToHost, s));
+        sync(h);
+        for (int i = 0; i <= j; ++i) Hc(i, j) = hb[i] + hb[kMaxDots + i];
+        double hn = std::sqrt(hb[2 * kMaxDots]);
+        Hc(j + 1, j) = hn;
+        for (int i = 0; i <= j + 1; ++i)
+          if (!std::isfinite(Hc(i, j))) nan_seen = true;
+        if (nan_seen) break;
+        for (int i = 0; i < j; ++i) {
+          double t = cs[i] * Hc(i, j) + sn[i] * Hc(i + 1, j);
+          Hc(i + 1, j) = -sn[i] * Hc(i, j) + cs[i] * Hc(i + 1, j);
+          Hc(i, j) = t;
+        }
+        double den = std::hypot(Hc(j, j), Hc(j + 1, j));
+        if (den == 0.0) {
+          jend = j;
+          break;
+        }
+        cs[j] = Hc(j, j) / den;
+        sn[j] = Hc(j + 1, j) / den;
+        Hc(j, j) = den;
+        Hc(j + 1, j) = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        ++its;
+        jend = j + 1;
+        if (std::fabs(g[j + 1]) / bref <= o.tol || its >= o.maxit || hn == 0.0) break;
+      }
+      if (nan_seen) break;
+      if (jend > 0) {
+        for (int i = jend - 1; i >= 0; --i) {
+          double t = g[i];
+          for (int k = i + 1; k < jend; ++k) t -= Hc(i, k) * yv[k];
+          yv[i] = t / Hc(i, i);
+        }
+        std::memcpy(hb + 3 * kMaxDots, yv.data(), jend * sizeof(double));
+        VEM_HIP(hipMemcpyAsync(dy, hb + 3 * kMaxDots, jend * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_combine(s, N, jend, Z, N, dy, x);
+      }
+      ++restarts;
+      launch_residual(s, h->lanesK, N, h->K.rowptr, h->K.col, h->K.val, x, h->rhs, V, h->partials, h->counter,
+                      dn);
+      check_launch();
+      VEM_HIP(hipMemcpyAsync(hb, dn, sizeof(double), hipMemcpyDeviceToHost, s));
+      sync(h);
+      double nb = std::sqrt(hb[0]);
+      if (!std::isfinite(nb)) {
+        nan_seen = true;
+        break;
+      }
+      if (jend == 0 && nb >= beta) {
+        beta = nb;
+        break;  // no progress possible (breakdown at the first step)
+      }
+      beta = nb;
+    }
+    VEM_REQUIRE(!nan_seen, VEM_ENAN, "NaN or Inf met in the Krylov iteration");
+    VEM_HIP(hipMemcpyAsync(u, x, Nu * sizeof(double), hipMemcpyDeviceToDevice, s));
+    VEM_HIP(hipMemcpyAsync(p, x + Nu, Np * sizeof(double), hipMemcpyDeviceToDevice, s));
+    sync(h);
+    auto t1 = std::chrono::steady_clock::now();
+    inf.iterations = its;
+    inf.restarts = restarts;
+    inf.inner_iterations = inner;
+    inf.relres = bnorm > 0 ? beta / bnorm : 0.0;
+    inf.solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    result = (bnorm == 0.0 || inf.relres <= o.tol) ? VEM_OK : VEM_NOT_CONVERGED;
+    inf.status = result;
+    if (info) *info = inf;
+  });
+  return st != VEM_OK ? st : result;
+}
+
+}  // extern "C"

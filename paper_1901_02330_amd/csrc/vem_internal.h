@@ -1,0 +1,197 @@
+// Internal declarations of the mixed-VEM HIP library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "vem.h"
+
+namespace vem {
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define VEM_HIP(call)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      throw ::vem::Error{VEM_EHIP, std::string(#call) + " failed: " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define VEM_REQUIRE(cond, code, text)                   \
+  do {                                                  \
+    if (!(cond)) throw ::vem::Error{(code), (text)};    \
+  } while (0)
+
+// Owned device buffer.
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    if (count == n && p) return;
+    release();
+    if (count) {
+      hipError_t e = hipMalloc(&p, count * sizeof(T));
+      if (e != hipSuccess) {
+        p = nullptr;
+        throw Error{VEM_ENOMEM, "device allocation of " + std::to_string(count * sizeof(T)) + " bytes failed"};
+      }
+    }
+    n = count;
+  }
+  operator T*() const { return p; }
+};
+
+// Pinned host buffer.
+template <class T>
+struct HBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  HBuf() = default;
+  HBuf(const HBuf&) = delete;
+  HBuf& operator=(const HBuf&) = delete;
+  ~HBuf() {
+    if (p) (void)hipHostFree(p);
+  }
+  void alloc(size_t count) {
+    if (count <= n && p) return;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    VEM_HIP(hipHostMalloc((void**)&p, count * sizeof(T), hipHostMallocDefault));
+    n = count;
+  }
+  T& operator[](size_t i) { return p[i]; }
+};
+
+// Block-reduction scratch: per-block partials and arrival counters.
+constexpr int kRedBlocks = 1024;   // grid of the reduction kernels
+constexpr int kRedThreads = 256;
+constexpr int kMaxDots = 34;       // largest number of simultaneous dot products
+constexpr int kMaxRestart = 32;
+constexpr int kMaxCellFaces = 64;
+
+// Device-resident state of one inner Jacobi-CG solve.
+struct PcgState {
+  double rho, rho0, alpha, beta, tol2;
+  int it, maxit, done, pad;
+};
+
+// Compressed sparse row matrix on the device.
+struct Csr {
+  int64_t rows = 0, nnz = 0;
+  DBuf<int> rowptr, col;
+  DBuf<double> val;
+};
+
+// ---- launchers (one translation unit each; all take the handle's stream) ----
+
+// mesh / geometry
+void launch_face_geometry(hipStream_t s, int nf, const double* xyz, const int* fptr, const int* fvtx, double* area,
+                          double* normal, double* cen, double* diam, double* e1, double* e2);
+void launch_cell_geometry(hipStream_t s, int nc, const double* xyz, const int* fptr, const int* fvtx,
+                          const int* cptr, const int* cface, const int8_t* csign, double* vol, double* cen,
+                          double* diam, double* xref);
+void launch_check_mesh(hipStream_t s, int nv, int nf, int nc, const int* fptr, const int* fvtx, const int* cptr,
+                       const int* cface, const int8_t* csign, int* face_cnt, int* face_cell, int* face_lidx,
+                       int* inc_cell, int* err);
+void launch_check_faces(hipStream_t s, int nf, const int* face_cnt, const double* area, int* is_bnd, int* err);
+void launch_check_cells(hipStream_t s, int nc, const double* vol, int* err);
+void launch_tets(hipStream_t s, int nc, const int* fptr, const int* cptr, const int* cface, const int* cell_tet_ptr,
+                 int* tet_inc, int* tet_a);
+void launch_tet_counts(hipStream_t s, int nc, const int* fptr, const int* cptr, const int* cface, int* cnt);
+void launch_bnd_tri_counts(hipStream_t s, int nb, const int* bface, const int* fptr, int* cnt);
+void launch_qp_cell(hipStream_t s, int64_t ntet, int npts, const double* ref, const int* tet_inc, const int* tet_a,
+                    const int* inc_cell, const double* xyz, const int* fptr, const int* fvtx, const int* cface,
+                    const double* xref, double* qp);
+void launch_qp_face(hipStream_t s, int nb, int npts, const double* ref, const int* bface, const int* btri_ptr,
+                    const double* xyz, const int* fptr, const int* fvtx, double* qp);
+void launch_load_tets(hipStream_t s, int64_t ntet, int npts, const double* refw, const int* tet_inc,
+                      const int* tet_a, const int* inc_cell, const double* xyz, const int* fptr, const int* fvtx,
+                      const int* cface, const int8_t* csign, const double* xref, const double* fq,
+                      double* tet_sum);
+void launch_load_cells(hipStream_t s, int nc, const int* cell_tet_ptr, const double* tet_sum, double* rhs_p);
+void launch_bnd_rhs(hipStream_t s, int nb, int npts, const double* refw, const int* bface, const int* btri_ptr,
+                    const double* xyz, const int* fptr, const int* fvtx, const int* face_cell, const double* pq,
+                    double* rhs_u);
+
+// lowest-order local matrices
+void launch_lo_local(hipStream_t s, int64_t ninc, const int* inc_cell, const int* cptr, const int* cface,
+                     const int8_t* csign, const double* farea, const double* fnormal, const double* fcen,
+                     const double* cvol, const double* ccen, const int64_t* lmat_ptr, double* M1,
+                     const int64_t* lb_ptr, double* Bdiv1);
+
+// generic assembly (element described by nfd face DOFs per face, nint interior and npd pressure DOFs per cell)
+struct DofLayout {
+  int nf, nc, nfd, nint, npd;
+  int64_t Nu, Np;
+};
+void launch_ldof_sort(hipStream_t s, DofLayout L, const int* cptr, const int* cface, const int* ldof_ptr,
+                      int* sorted_gid, int* sorted_l);
+void launch_rowlen(hipStream_t s, DofLayout L, const int* cptr, const int* ldof_ptr, const int* sorted_gid,
+                   const int* face_cell, const int* face_lidx, const int* cface, int* lenK, int* lenA, int* lenS);
+void launch_fill_patterns(hipStream_t s, DofLayout L, const int* cptr, const int* ldof_ptr, const int* sorted_gid,
+                          const int* face_cell, const int* face_lidx, const int* cface, const int* Kptr, int* Kcol,
+                          int* Kdiag, const int* Aptr, int* Acol, int* Adiag, const int* Sptr, int* Scol,
+                          int* Sdiag);
+void launch_cell_sizes(hipStream_t s, DofLayout L, const int* cptr, int64_t* ndof, int64_t* nmat, int64_t* nb);
+void launch_values(hipStream_t s, DofLayout L, const int* cptr, const int* cface, const int8_t* csign,
+                   const int* ldof_ptr, const int* sorted_gid, const int* sorted_l, const int* face_cell,
+                   const int* face_lidx, const int64_t* lmat_ptr, const double* M1, const int64_t* lb_ptr,
+                   const double* Bdiv1, const double* nu, double inv_gamma, const int* Kptr, double* Kval,
+                   const int* Aptr, double* Aval);
+void launch_diag_inv(hipStream_t s, int64_t n, const int* diagpos, const double* val, double* d, double* dinv);
+void launch_schur_values(hipStream_t s, DofLayout L, const int* cptr, const int* cface, const int8_t* csign,
+                         const int* ldof_ptr, const int* face_cell, const int* face_lidx, const int64_t* lb_ptr,
+                         const double* Bdiv1, const double* dM, const int* Sptr, const int* Scol, double* Sval);
+void launch_rhs_from_moments(hipStream_t s, int64_t Nu, int64_t Np, double* rhs);
+
+// sparse/Krylov
+int spmv_lanes(double avg_row);
+void launch_spmv(hipStream_t s, int lanes, int64_t rows, const int* rowptr, const int* col, const double* val,
+                 const double* x, double* y);
+void launch_residual(hipStream_t s, int lanes, int64_t rows, const int* rowptr, const int* col, const double* val,
+                     const double* x, const double* b, double* r, double* partials, unsigned* counter,
+                     double* out);
+void launch_dots(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* w, double* partials,
+                 unsigned* counter, double* out);
+void launch_update_dots(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* h, double* w,
+                        double* partials, unsigned* counter, double* out);
+void launch_update_norm(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* h, double* w,
+                        double* partials, unsigned* counter, double* out);
+void launch_scale_to(hipStream_t s, int64_t n, const double* w, const double* norm2, double* dst);
+void launch_scale_by(hipStream_t s, int64_t n, const double* x, const double* d, double c, double* y);
+void launch_combine(hipStream_t s, int64_t n, int k, const double* Z, int64_t ldz, const double* y, double* x);
+void launch_copy(hipStream_t s, int64_t n, const double* x, double* y);
+void launch_fill(hipStream_t s, int64_t n, double v, double* y);
+void launch_pcg_init(hipStream_t s, int64_t n, const double* b, const double* dinv, double* x, double* r, double* z,
+                     double* p, PcgState* st, double tol, int maxit, double* partials, unsigned* counter);
+void launch_pcg_iter(hipStream_t s, int lanes, int64_t n, const int* rowptr, const int* col, const double* val,
+                     const double* dinv, double* x, double* r, double* z, double* p, double* q, PcgState* st,
+                     double* partials, unsigned* counter);
+void launch_sum(hipStream_t s, int64_t n, const double* x, double* partials, unsigned* counter, double* out);
+
+// host utilities
+void gauss_jacobi01(int n, int alpha, double* t, double* w);  // int_0^1 (1-t)^alpha g(t) dt
+void tet_reference_rule(int n, std::vector<double>& pts, std::vector<double>& w);
+void tri_reference_rule(int n, std::vector<double>& pts, std::vector<double>& w);
+// ptr[0..n] = exclusive prefix sums of len[0..n-1]; returns the total (synchronises)
+int64_t scan_i32(hipStream_t s, const int* len, int64_t n, int* ptr);
+int64_t scan_i64(hipStream_t s, const int64_t* len, int64_t n, int64_t* ptr);
+void launch_compact_flags(hipStream_t s, int64_t n, const int* flag, const int* pos, int* out);
+
+}  // namespace vem

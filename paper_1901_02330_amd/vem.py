@@ -1,0 +1,262 @@
+"""Python binding of the C ABI in include/vem.h (argument marshalling only).
+
+Device memory and streams come from PyTorch: every device argument is a
+torch CUDA (HIP) tensor and work is enqueued on torch's current stream.  All
+numerical work runs in the HIP library; if the library is not built, loading
+fails with an error (there is no fallback).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_char_p, c_double, c_int, c_int64, c_void_p
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvem_mi355x.so")
+
+VEM_LO, VEM_PAPER = 0, 1
+PREC = {"schur": 0, "reg": 1, "none": 2}
+MATS = {"K": 0, "schur": 1, "reg": 2}
+STATUS = {0: "VEM_OK", 1: "VEM_NOT_CONVERGED", -1: "VEM_EINVAL", -2: "VEM_EBADMESH", -3: "VEM_ENOMEM",
+          -4: "VEM_EHIP", -5: "VEM_EBREAKDOWN", -6: "VEM_ENAN"}
+
+
+class VemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Sizes(ctypes.Structure):
+    _fields_ = [
+        ("n_vertices", c_int64), ("n_faces", c_int64), ("n_cells", c_int64),
+        ("n_u", c_int64), ("n_p", c_int64), ("n", c_int64),
+        ("nnz_K", c_int64), ("nnz_schur", c_int64), ("nnz_reg", c_int64),
+        ("n_qp_cell", c_int64), ("n_qp_face", c_int64),
+        ("load_points", ctypes.c_int32), ("max_cell_faces", ctypes.c_int32),
+        ("h", c_double), ("gamma", c_double),
+    ]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [
+        ("precond", ctypes.c_int32), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32),
+        ("use_x0", ctypes.c_int32), ("tol", c_double), ("inner_tol", c_double),
+        ("inner_maxit", ctypes.c_int32), ("inner_check", ctypes.c_int32), ("gamma", c_double),
+    ]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int32), ("restarts", ctypes.c_int32), ("inner_iterations", c_int64),
+        ("relres", c_double), ("solve_ms", c_double), ("status", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load():
+    """Load the HIP library (after torch, so that both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library {LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    H = c_void_p
+    P = c_void_p
+    sigs = {
+        "vem_create": ([POINTER(c_void_p), c_void_p], c_int),
+        "vem_destroy": ([H], c_int),
+        "vem_set_mesh": ([H, c_int64, P, c_int64, P, P, c_int64, P, P, P, c_int], c_int),
+        "vem_discretize": ([H, c_int, c_int, c_int], c_int),
+        "vem_get_sizes": ([H, POINTER(Sizes)], c_int),
+        "vem_get_quadrature": ([H, P, P], c_int),
+        "vem_set_coefficient": ([H, P], c_int),
+        "vem_set_rhs": ([H, P, P], c_int),
+        "vem_solve": ([H, POINTER(SolveOpts), P, P, POINTER(SolveInfo)], c_int),
+        "vem_apply": ([H, P, P], c_int),
+        "vem_export_csr": ([H, c_int, P, P, P], c_int),
+        "vem_get_rhs": ([H, P], c_int),
+        "vem_get_geometry": ([H, P, P, P, P, P, P], c_int),
+        "vem_status_string": ([c_int], c_char_p),
+        "vem_last_error": ([H], c_char_p),
+        "vem_solve_opts_default": ([POINTER(SolveOpts)], None),
+    }
+    for name, (args, res) in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return None if t is None else c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One mesh + discretisation + solver state on the current device and stream."""
+
+    def __init__(self, stream=None):
+        import torch
+
+        self.torch = torch
+        self.lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device visible")
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = s
+        self.h = c_void_p()
+        self._check(self.lib.vem_create(byref(self.h), c_void_p(s.cuda_stream)))
+        self._sizes = None
+
+    # -- helpers
+    def _check(self, code):
+        if code < 0:
+            msg = self.lib.vem_last_error(self.h).decode() if self.h else ""
+            raise VemError(code, msg)
+        return code
+
+    def close(self):
+        if self.h:
+            self.lib.vem_destroy(self.h)
+            self.h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, a, dtype):
+        t = self.torch
+        if isinstance(a, t.Tensor):
+            return a.to(device=self.device, dtype=dtype).contiguous()
+        return t.as_tensor(a, dtype=dtype, device=self.device).contiguous()
+
+    # -- C ABI wrappers
+    def set_mesh(self, mesh):
+        t = self.torch
+        xyz = self._dev(mesh["xyz"], t.float64)
+        fp = self._dev(mesh["face_ptr"], t.int32)
+        fv = self._dev(mesh["face_vtx"], t.int32)
+        cp = self._dev(mesh["cell_ptr"], t.int32)
+        cf = self._dev(mesh["cell_face"], t.int32)
+        cs = self._dev(mesh["cell_face_sign"], t.int8)
+        self._check(self.lib.vem_set_mesh(self.h, xyz.shape[0], _ptr(xyz), fp.numel() - 1, _ptr(fp), _ptr(fv),
+                                          cp.numel() - 1, _ptr(cp), _ptr(cf), _ptr(cs), 1))
+        self._sizes = None
+
+    def discretize(self, family="lo", k=0, load_points=3):
+        fam = {"lo": VEM_LO, "paper": VEM_PAPER}[family]
+        self._check(self.lib.vem_discretize(self.h, fam, int(k), int(load_points)))
+        self._sizes = None
+
+    def sizes(self):
+        if self._sizes is None:
+            s = Sizes()
+            self._check(self.lib.vem_get_sizes(self.h, byref(s)))
+            self._sizes = {f: getattr(s, f) for f, _ in Sizes._fields_}
+        return self._sizes
+
+    def quadrature(self):
+        t = self.torch
+        sz = self.sizes()
+        qc = t.empty((sz["n_qp_cell"], 3), dtype=t.float64, device=self.device)
+        qf = t.empty((sz["n_qp_face"], 3), dtype=t.float64, device=self.device)
+        self._check(self.lib.vem_get_quadrature(self.h, _ptr(qc) if qc.numel() else None,
+                                                _ptr(qf) if qf.numel() else None))
+        return qc, qf
+
+    def set_coefficient(self, nu):
+        nu = self._dev(nu, self.torch.float64)
+        self._check(self.lib.vem_set_coefficient(self.h, _ptr(nu)))
+
+    def set_rhs(self, f_qp, pD_qp=None):
+        f_qp = self._dev(f_qp, self.torch.float64)
+        pD = None if pD_qp is None else self._dev(pD_qp, self.torch.float64)
+        self._check(self.lib.vem_set_rhs(self.h, _ptr(f_qp), _ptr(pD) if pD is not None and pD.numel() else None))
+
+    def set_rhs_functions(self, f, pD=None):
+        """Evaluate f (and p_D) with torch at the library's quadrature points, then load them."""
+        qc, qf = self.quadrature()
+        fv = f(qc)
+        pv = None if pD is None else pD(qf)
+        del qc, qf
+        self.set_rhs(fv, pv)
+
+    def solve(self, precond="schur", tol=1e-8, restart=30, maxit=5000, inner_tol=1e-6, inner_maxit=5000,
+              inner_check=32, gamma=0.0, x0=None):
+        t = self.torch
+        sz = self.sizes()
+        o = SolveOpts()
+        self.lib.vem_solve_opts_default(byref(o))
+        o.precond = PREC[precond]
+        o.restart, o.maxit, o.tol = int(restart), int(maxit), float(tol)
+        o.inner_tol, o.inner_maxit, o.inner_check = float(inner_tol), int(inner_maxit), int(inner_check)
+        o.gamma = float(gamma)
+        if x0 is not None:
+            u = self._dev(x0[0], t.float64).clone()
+            p = self._dev(x0[1], t.float64).clone()
+            o.use_x0 = 1
+        else:
+            u = t.empty(sz["n_u"], dtype=t.float64, device=self.device)
+            p = t.empty(sz["n_p"], dtype=t.float64, device=self.device)
+        info = SolveInfo()
+        code = self._check(self.lib.vem_solve(self.h, byref(o), _ptr(u), _ptr(p), byref(info)))
+        out = {f: getattr(info, f) for f, _ in SolveInfo._fields_}
+        out["converged"] = code == 0
+        return u, p, out
+
+    def apply(self, x):
+        t = self.torch
+        x = self._dev(x, t.float64)
+        y = t.empty_like(x)
+        self._check(self.lib.vem_apply(self.h, _ptr(x), _ptr(y)))
+        return y
+
+    def export_csr(self, which="K"):
+        t = self.torch
+        sz = self.sizes()
+        rows = {"K": sz["n"], "schur": sz["n_p"], "reg": sz["n_u"]}[which]
+        nnz = {"K": sz["nnz_K"], "schur": sz["nnz_schur"], "reg": sz["nnz_reg"]}[which]
+        rp = t.empty(rows + 1, dtype=t.int32, device=self.device)
+        col = t.empty(nnz, dtype=t.int32, device=self.device)
+        val = t.empty(nnz, dtype=t.float64, device=self.device)
+        self._check(self.lib.vem_export_csr(self.h, MATS[which], _ptr(rp), _ptr(col), _ptr(val)))
+        return rp, col, val
+
+    def rhs(self):
+        t = self.torch
+        b = t.empty(self.sizes()["n"], dtype=t.float64, device=self.device)
+        self._check(self.lib.vem_get_rhs(self.h, _ptr(b)))
+        return b
+
+    def geometry(self):
+        t = self.torch
+        sz = self.sizes()
+        nf, nc = sz["n_faces"], sz["n_cells"]
+        out = {
+            "area": t.empty(nf, dtype=t.float64, device=self.device),
+            "normal": t.empty((nf, 3), dtype=t.float64, device=self.device),
+            "fcentroid": t.empty((nf, 3), dtype=t.float64, device=self.device),
+            "volume": t.empty(nc, dtype=t.float64, device=self.device),
+            "centroid": t.empty((nc, 3), dtype=t.float64, device=self.device),
+            "diam": t.empty(nc, dtype=t.float64, device=self.device),
+        }
+        self._check(self.lib.vem_get_geometry(self.h, _ptr(out["area"]), _ptr(out["normal"]),
+                                              _ptr(out["fcentroid"]), _ptr(out["volume"]), _ptr(out["centroid"]),
+                                              _ptr(out["diam"])))
+        return out
+
+
+EXPORTED = [
+    "vem_solve_opts_default", "vem_create", "vem_destroy", "vem_set_mesh", "vem_discretize", "vem_get_sizes",
+    "vem_get_quadrature", "vem_set_coefficient", "vem_set_rhs", "vem_solve", "vem_apply", "vem_export_csr",
+    "vem_get_rhs", "vem_get_geometry", "vem_status_string", "vem_last_error",
+]

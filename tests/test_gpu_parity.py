@@ -1,0 +1,160 @@
+"""GPU parity: every step of the HIP path against the FP64 oracle on the same seeded inputs."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.assemble import discretize, interpolate_lo
+from oracle.solvers import block_reg, block_schur, direct_solve
+from paper_1901_02330_amd.inputs import (LinearSolution, SineSolution, cube_mesh, lognormal_field,
+                                         voronoi_mesh)
+from tests.gpu_helpers import assert_same_csr, gpu_solver, rel, to_scipy
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+MESHES = {
+    "cube8": lambda: cube_mesh(8),
+    "cube534": lambda: cube_mesh(5, 3, 4),
+    "voronoi80": lambda: voronoi_mesh(80, seed=4),
+}
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_geometry(name):
+    _say("geometry", name)
+    m = MESHES[name]()
+    s = gpu_solver(m)
+    g = {k: v.cpu().numpy() for k, v in s.geometry().items()}
+    d = discretize(m)
+    fg, cg = d["fgeo"], d["cgeo"]
+    assert np.allclose(g["area"], fg["area"], rtol=1e-13, atol=0)
+    assert np.allclose(g["normal"], fg["normal"], rtol=0, atol=1e-14)
+    assert np.allclose(g["fcentroid"], fg["centroid"], rtol=0, atol=1e-14)
+    assert np.allclose(g["volume"], cg["volume"], rtol=1e-13, atol=0)
+    assert np.allclose(g["centroid"], cg["centroid"], rtol=0, atol=1e-14)
+    assert np.allclose(g["diam"], cg["diam"], rtol=1e-14, atol=0)
+    sz = s.sizes()
+    assert sz["h"] == pytest.approx(cg["h"], rel=1e-14)
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_matrices_and_rhs(name):
+    _say("matrices", name)
+    m = MESHES[name]()
+    nc = len(m["cell_ptr"]) - 1
+    nu = 1.0 / lognormal_field(nc, 2.0, 0)
+    sol = LinearSolution(0.25, (0.5, -1.0, 2.0))
+    s = gpu_solver(m, nu=nu, rhs=sol)
+    d = discretize(m, nu=nu, rhs=sol)
+    N = d["Nu"] + d["Np"]
+    G = to_scipy(*s.export_csr("K"), (N, N))
+    assert_same_csr(G, d["K"])
+    Sg = to_scipy(*s.export_csr("schur"), (d["Np"], d["Np"]))
+    assert_same_csr(Sg, block_schur(d["M"], d["B"]).S)
+    gam = s.sizes()["gamma"]
+    Ag = to_scipy(*s.export_csr("reg"), (d["Nu"], d["Nu"]))
+    assert_same_csr(Ag, block_reg(d["M"], d["B"], gam, inner="pcg").A)
+    b = s.rhs().cpu().numpy()
+    assert np.abs(b - d["b"]).max() <= 1e-13 * np.abs(d["b"]).max()
+    # sine load (non-polynomial f): same rule on both sides
+    s.set_rhs_functions(SineSolution.f, SineSolution.pD)
+    d2 = discretize(m, nu=nu, rhs=SineSolution(), local=d["local"], geo=(d["fgeo"], d["cgeo"]))
+    b = s.rhs().cpu().numpy()
+    assert np.abs(b - d2["b"]).max() <= 1e-13 * np.abs(d2["b"]).max()
+
+
+def test_spmv():
+    import torch
+
+    _say("spmv")
+    m = voronoi_mesh(120, seed=9)
+    nc = len(m["cell_ptr"]) - 1
+    nu = 1.0 / lognormal_field(nc, 1.0, 3)
+    s = gpu_solver(m, nu=nu)
+    d = discretize(m, nu=nu)
+    x = np.random.default_rng(0).standard_normal(d["Nu"] + d["Np"])
+    y = s.apply(torch.as_tensor(x)).cpu().numpy()
+    yo = d["K"] @ x
+    assert np.abs(y - yo).max() <= 1e-13 * np.abs(yo).max()
+
+
+@pytest.mark.parametrize("precond", ["schur", "reg"])
+@pytest.mark.parametrize("case", ["cube8_K1", "cube675_lognormal", "voronoi150_lognormal"])
+def test_solve_matches_oracle(case, precond):
+    _say("solve", case, precond)
+    if case == "cube8_K1":
+        m, nu = cube_mesh(8), None
+    elif case == "cube675_lognormal":
+        m = cube_mesh(6, 7, 5)
+        nu = 1.0 / lognormal_field(210, 2.0, 0)
+    else:
+        m = voronoi_mesh(150, seed=11)
+        nu = 1.0 / lognormal_field(150, 1.0, 5)
+    s = gpu_solver(m, nu=nu, rhs=SineSolution())
+    u, p, info = s.solve(precond=precond, tol=1e-13, maxit=3000, inner_tol=1e-10)
+    assert info["converged"], info
+    d = discretize(m, nu=nu, rhs=SineSolution())
+    x = direct_solve(d["K"], d["b"])
+    uo, po = x[: d["Nu"]], x[d["Nu"]:]
+    u, p = u.cpu().numpy(), p.cpu().numpy()
+    _say(info, rel(u, uo), rel(p, po))
+    assert rel(u, uo) <= 1e-10
+    assert rel(p, po) <= 1e-10
+    # mass conservation B_div u = F per cell
+    r = d["Bdiv"] @ u - d["F"]
+    assert np.abs(r).max() <= 1e-10 * np.abs(d["F"]).max()
+
+
+def test_patch_test_exact_on_gpu():
+    _say("patch")
+    m = voronoi_mesh(60, seed=8)
+    sol = LinearSolution(0.1, (2.0, 1.0, -1.0))
+    s = gpu_solver(m, rhs=sol)
+    u, p, info = s.solve(precond="schur", tol=1e-14, maxit=500, inner_tol=1e-12)
+    d = discretize(m)
+    ue, pe = interpolate_lo(m, d["fgeo"], d["cgeo"], sol)
+    assert np.abs(u.cpu().numpy() - ue).max() < 1e-11
+    assert np.abs(p.cpu().numpy() - pe).max() < 1e-11
+
+
+def test_deterministic_bits():
+    import torch
+
+    _say("determinism")
+    m = cube_mesh(7)
+    nu = 1.0 / lognormal_field(343, 2.0, 1)
+    s = gpu_solver(m, nu=nu, rhs=SineSolution())
+    u1, p1, _ = s.solve(precond="schur", tol=1e-10)
+    u2, p2, _ = s.solve(precond="schur", tol=1e-10)
+    assert torch.equal(u1, u2) and torch.equal(p1, p2)
+
+
+def test_error_paths():
+    import torch
+
+    from paper_1901_02330_amd.vem import Solver, VemError
+
+    _say("errors")
+    m = cube_mesh(3)
+    bad = dict(m)
+    bad["cell_face"] = m["cell_face"].copy()
+    bad["cell_face"][5] = 10**6  # out of range face id: caught by the validation kernel
+    s = Solver()
+    with pytest.raises(VemError) as e:
+        s.set_mesh(bad)
+    assert e.value.code == -2
+    s = gpu_solver(m, rhs=SineSolution())
+    u, p, info = s.solve(tol=1e-14, maxit=1)
+    assert not info["converged"] and info["iterations"] == 1
+    qc, qf = s.quadrature()
+    f = torch.full((qc.shape[0],), float("nan"), dtype=torch.float64, device=qc.device)
+    s.set_rhs(f)
+    with pytest.raises(VemError) as e:
+        s.solve()
+    assert e.value.code == -6
