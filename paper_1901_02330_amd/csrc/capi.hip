@@ -58,18 +58,17 @@ struct vem_ctx {
 
   // matrices
   Csr K, A, S;
+  Sell Ks, As, Ss;
   DBuf<int> Kdiag, Adiag, Sdiag;
   DBuf<double> dM, dMinv, dAinv, dSinv;
   double gamma_A = 0.0;
-  int lanesK = 4, lanesA = 4, lanesS = 4;
 
   // solver workspace
   int64_t ws_N = 0;
   int ws_m = 0;
   DBuf<double> Vb, Zb, xw;
-  DBuf<double> pr, pz, pp, pq;
-  DBuf<double> partials, scal;
-  DBuf<unsigned> counter;
+  DBuf<double> pr, pz, ps, pp, pw0, pw1;
+  DBuf<double> partials, pcgpart, scal;
   DBuf<PcgState> pcg;
   HBuf<double> hbuf;
   HBuf<PcgState> hpcg;
@@ -313,8 +312,7 @@ std::string mesh_err_text(int e) {
 void ensure_scratch(vem_handle h) {
   if (!h->partials.p) {
     h->partials.alloc((size_t)kRedBlocks * kMaxDots);
-    h->counter.alloc(4);
-    VEM_HIP(hipMemsetAsync(h->counter.p, 0, 4 * sizeof(unsigned), h->stream));
+    h->pcgpart.alloc(4 * (size_t)kPcgBlocks);
     h->scal.alloc(4 * kMaxDots + 16);
     h->pcg.alloc(1);
     h->hbuf.alloc(4 * kMaxDots + 16);
@@ -326,7 +324,7 @@ void ensure_scratch(vem_handle h) {
 // total of a device double array (synchronises)
 double device_sum(vem_handle h, const double* x, int64_t n) {
   ensure_scratch(h);
-  launch_sum(h->stream, n, x, h->partials, h->counter, h->scal);
+  launch_sum(h->stream, n, x, h->partials, h->scal);
   check_launch();
   double v = 0.0;
   VEM_HIP(hipMemcpyAsync(&v, h->scal.p, sizeof(double), hipMemcpyDeviceToHost, h->stream));
@@ -347,6 +345,11 @@ void rebuild_values(vem_handle h, double gamma) {
   launch_schur_values(s, L, h->cptr, h->cface, h->csign, h->ldof_ptr, h->face_cell, h->face_lidx, h->lb_ptr,
                       h->Bdiv1, h->dM, h->S.rowptr, h->S.col, h->S.val);
   launch_diag_inv(s, L.Np, h->Sdiag, h->S.val, nullptr, h->dSinv);
+  refresh_sell(s, h->K, h->Ks);
+  refresh_sell(s, h->A, h->As);
+  refresh_sell(s, h->S, h->Ss);
+  launch_col_scale(s, h->As, h->dAinv);
+  launch_col_scale(s, h->Ss, h->dSinv);
   check_launch();
   h->gamma_A = gamma;
 }
@@ -360,31 +363,31 @@ void ensure_workspace(vem_handle h, int m) {
   int64_t nm = std::max<int64_t>(h->L.Nu, h->L.Np);
   h->pr.alloc(nm);
   h->pz.alloc(nm);
+  h->ps.alloc(nm);
   h->pp.alloc(nm);
-  h->pq.alloc(nm);
+  h->pw0.alloc(nm);
+  h->pw1.alloc(nm);
   h->ws_N = N;
   h->ws_m = m;
 }
 
 // Inner Jacobi-CG: x ~ A^{-1} b.  Returns the iterations used.
-int inner_pcg(vem_handle h, const Csr& A, int lanes, const double* dinv, const double* b, double* x,
+int inner_pcg(vem_handle h, const Sell& A, const double* dinv, const double* b, double* x,
               const vem_solve_opts& o) {
   hipStream_t s = h->stream;
-  int64_t n = A.rows;
-  launch_pcg_init(s, n, b, dinv, x, h->pr, h->pz, h->pp, h->pcg, o.inner_tol, o.inner_maxit, h->partials,
-                  h->counter);
+  PcgWork w{x, h->pr, h->pz, h->ps, h->pp, h->pw0, h->pw1, dinv};
+  launch_pcg_init(s, A, w, b, h->pcg, o.inner_tol, o.inner_maxit, h->pcgpart);
   check_launch();
   int chunk = std::max(1, o.inner_check);
+  int i = 0;
   for (;;) {
-    for (int c = 0; c < chunk; ++c)
-      launch_pcg_iter(s, lanes, n, A.rowptr, A.col, A.val, dinv, x, h->pr, h->pz, h->pp, h->pq, h->pcg,
-                      h->partials, h->counter);
+    for (int c = 0; c < chunk && i < o.inner_maxit; ++c, ++i) launch_pcg_iter(s, i, A, w, h->pcg, h->pcgpart);
     check_launch();
     VEM_HIP(hipMemcpyAsync(h->hpcg.p, h->pcg.p, sizeof(PcgState), hipMemcpyDeviceToHost, s));
     sync(h);
-    if (h->hpcg.p->done) break;
+    if (h->hpcg.p->done || i >= o.inner_maxit) break;
   }
-  return h->hpcg.p->it;
+  return h->hpcg.p->count;
 }
 
 // z = P^{-1} v for the chosen block preconditioner
@@ -394,9 +397,9 @@ int64_t apply_prec(vem_handle h, const vem_solve_opts& o, const double* v, doubl
   switch (o.precond) {
     case VEM_PREC_SCHUR:
       launch_scale_by(s, Nu, v, h->dMinv, 1.0, z);
-      return inner_pcg(h, h->S, h->lanesS, h->dSinv, v + Nu, z + Nu, o);
+      return inner_pcg(h, h->Ss, h->dSinv, v + Nu, z + Nu, o);
     case VEM_PREC_REG: {
-      int it = inner_pcg(h, h->A, h->lanesA, h->dAinv, v, z, o);
+      int it = inner_pcg(h, h->As, h->dAinv, v, z, o);
       launch_scale_by(s, Np, v + Nu, nullptr, 1.0 / h->gamma_A, z + Nu);
       return it;
     }
@@ -698,9 +701,9 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
                          h->K.rowptr, h->K.col, h->Kdiag, h->A.rowptr, h->A.col, h->Adiag, h->S.rowptr, h->S.col,
                          h->Sdiag);
     check_launch();
-    h->lanesK = spmv_lanes((double)h->K.nnz / N);
-    h->lanesA = spmv_lanes((double)h->A.nnz / L.Nu);
-    h->lanesS = spmv_lanes((double)h->S.nnz / L.Np);
+    build_sell(s, h->K, h->Ks);
+    build_sell(s, h->A, h->As);
+    build_sell(s, h->S, h->Ss);
     h->dM.alloc(L.Nu);
     h->dMinv.alloc(L.Nu);
     h->dAinv.alloc(L.Nu);
@@ -786,7 +789,7 @@ vem_status vem_apply(vem_handle h, const double* x, double* y) {
   if (!h || !x || !y) return VEM_EINVAL;
   return guarded(h, [&] {
     require_disc(h);
-    launch_spmv(h->stream, h->lanesK, h->K.rows, h->K.rowptr, h->K.col, h->K.val, x, y);
+    launch_spmv(h->stream, h->Ks, x, y);
     check_launch();
   });
 }
@@ -866,7 +869,7 @@ vem_status vem_solve(vem_handle h, const vem_solve_opts* opts, double* u, double
     double* hb = h->hbuf.p;
 
     // ||b||
-    launch_dots(s, N, 1, h->rhs, N, h->rhs, h->partials, h->counter, dn);
+    launch_dots(s, N, 1, h->rhs, N, h->rhs, h->partials, dn);
     check_launch();
     VEM_HIP(hipMemcpyAsync(hb, dn, sizeof(double), hipMemcpyDeviceToHost, s));
     sync(h);
@@ -884,7 +887,7 @@ vem_status vem_solve(vem_handle h, const vem_solve_opts* opts, double* u, double
       launch_fill(s, N, 0.0, x);
     }
     // r0 = b - K x0
-    launch_residual(s, h->lanesK, N, h->K.rowptr, h->K.col, h->K.val, x, h->rhs, V, h->partials, h->counter, dn);
+    launch_residual(s, h->Ks, x, h->rhs, V, h->partials, dn);
     check_launch();
     VEM_HIP(hipMemcpyAsync(hb, dn, sizeof(double), hipMemcpyDeviceToHost, s));
     sync(h);
@@ -907,11 +910,11 @@ vem_status vem_solve(vem_handle h, const vem_solve_opts* opts, double* u, double
         double* zj = Z + (size_t)j * N;
         double* w = V + (size_t)(j + 1) * N;
         inner += apply_prec(h, o, vj, zj);
-        launch_spmv(s, h->lanesK, N, h->K.rowptr, h->K.col, h->K.val, zj, w);
+        launch_spmv(s, h->Ks, zj, w);
         // classical Gram-Schmidt, twice
-        launch_dots(s, N, j + 1, V, N, w, h->partials, h->counter, dh);
-        launch_update_dots(s, N, j + 1, V, N, dh, w, h->partials, h->counter, dh2);
-        launch_update_norm(s, N, j + 1, V, N, dh2, w, h->partials, h->counter, dn);
+        launch_dots(s, N, j + 1, V, N, w, h->partials, dh);
+        launch_update_dots(s, N, j + 1, V, N, dh, w, h->partials, dh2);
+        launch_update_norm(s, N, j + 1, V, N, dh2, w, h->partials, dn);
         launch_scale_to(s, N, w, dn, w);
         check_launch();
         VEM_HIP(hipMemcpyAsync(hb, dh, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -956,8 +959,7 @@ vem_status vem_solve(vem_handle h, const vem_solve_opts* opts, double* u, double
         launch_combine(s, N, jend, Z, N, dy, x);
       }
       ++restarts;
-      launch_residual(s, h->lanesK, N, h->K.rowptr, h->K.col, h->K.val, x, h->rhs, V, h->partials, h->counter,
-                      dn);
+      launch_residual(s, h->Ks, x, h->rhs, V, h->partials, dn);
       check_launch();
       VEM_HIP(hipMemcpyAsync(hb, dn, sizeof(double), hipMemcpyDeviceToHost, s));
       sync(h);

@@ -1,17 +1,17 @@
 // Sparse matrix-vector products and the vector kernels of flexible GMRES and
 // of the inner Jacobi-preconditioned conjugate gradients.
 //
-// Reductions are deterministic: every block writes its partial sums, the last
-// block to arrive (atomic ticket) adds the partials in block order and, where
-// the solver needs it, updates the device-resident scalar state.  The flux
-// and pressure vectors are HBM-streamed; every kernel here is bandwidth bound.
+// Reductions are deterministic and use neither atomics nor fences: every block
+// writes its partial sums, and a later kernel on the same stream adds them in
+// block order (a one-block finalize kernel, or every block of the consumer
+// kernel itself for the inner CG).  Every kernel here is bandwidth bound.
 #include "vem_internal.h"
 
 namespace vem {
 namespace {
 
 constexpr int kThreads = kRedThreads;
-constexpr int kWaves = kThreads / 64;
+constexpr int kMaxWaves = 16;
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -19,14 +19,14 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// Block-reduce K accumulators, publish per-block partials, and let the last
-// block sum them in block order into res[] (shared).  Returns true in the
-// last block (all its threads), where res[] holds the grid totals.
+// Block-reduce K accumulators and store this block's partial sums at
+// partials[blockIdx.x * K + k].  No atomics and no fences: the consumer is a
+// later kernel on the same stream, and the kernel boundary makes the partials
+// visible to every XCD.
 template <int K>
-__device__ inline bool grid_reduce(const double (&acc)[K], double* partials, unsigned* counter, double* res) {
-  __shared__ double sh[kWaves][K];
-  __shared__ int last;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+__device__ inline void block_partials(const double (&acc)[K], double* partials) {
+  __shared__ double sh[kMaxWaves][K];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
   for (int i = 0; i < K; ++i) {
     double v = wave_sum(acc[i]);
@@ -35,31 +35,39 @@ __device__ inline bool grid_reduce(const double (&acc)[K], double* partials, uns
   __syncthreads();
   if (threadIdx.x < K) {
     double s = 0.0;
-#pragma unroll
-    for (int w = 0; w < kWaves; ++w) s += sh[w][threadIdx.x];
+    for (int w = 0; w < nw; ++w) s += sh[w][threadIdx.x];
     partials[(size_t)blockIdx.x * K + threadIdx.x] = s;
   }
-  __threadfence();
+}
+
+// Sum of nparts partials (stride K, component k) by the whole block, in a fixed
+// order: every block that calls it obtains the same bits.
+__device__ inline double block_sum_partials(const double* __restrict__ partials, int nparts, int K, int k) {
+  __shared__ double sh[kMaxWaves];
+  __shared__ double total;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x) s += partials[(size_t)b * K + k];
+  s = wave_sum(s);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) sh[wid] = s;
   __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(counter, 1u) == gridDim.x - 1) ? 1 : 0;
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
-  for (int i = 0; i < K; ++i) {
-    double s = 0.0;
-    for (unsigned b = threadIdx.x; b < gridDim.x; b += blockDim.x) s += partials[(size_t)b * K + i];
-    s = wave_sum(s);
-    if (lane == 0) sh[wid][0] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int w = 0; w < kWaves; ++w) t += sh[w][0];
-      res[i] = t;
-    }
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += sh[w];
+    total = t;
   }
-  if (threadIdx.x == 0) *counter = 0u;
-  return true;
+  __syncthreads();
+  double r = total;
+  __syncthreads();
+  return r;
+}
+
+// out[k] = sum over nparts partials; block k handles component k
+__global__ void __launch_bounds__(kThreads) k_finalize(int nparts, int K, const double* __restrict__ partials,
+                                                       double* __restrict__ out) {
+  const int k = blockIdx.x;
+  double v = block_sum_partials(partials, nparts, K, k);
+  if (threadIdx.x == 0) out[k] = v;
 }
 
 inline int red_grid(int64_t n) {
@@ -67,58 +75,53 @@ inline int red_grid(int64_t n) {
   return (int)(b < kRedBlocks ? (b < 1 ? 1 : b) : kRedBlocks);
 }
 
-// ---- SpMV: L lanes per row, rows in consecutive groups -------------------------------------
-template <int L>
-__device__ inline double row_dot(int64_t row, int lane, const int* __restrict__ rowptr, const int* __restrict__ col,
-                                 const double* __restrict__ val, const double* __restrict__ x) {
-  double s = 0.0;
-  int e = rowptr[row + 1];
-  for (int j = rowptr[row] + lane; j < e; j += L) s += val[j] * x[col[j]];
-#pragma unroll
-  for (int o = L / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, L);
-  return s;
+// ---- SELL-64 SpMV: one thread per row -------------------------------------------------------
+struct SellView {
+  int64_t rows;
+  const int* __restrict__ slice_ptr;
+  const int* __restrict__ slice_len;
+  const int* __restrict__ col;
+  const double* __restrict__ val;
+};
+
+inline SellView view(const Sell& A) { return {A.rows, A.slice_ptr, A.slice_len, A.col, A.val}; }
+
+// Whole waves share a slice because every block size here is a multiple of 64.
+__device__ inline double sell_dot(const SellView& A, int64_t row, const double* __restrict__ x) {
+  const int64_t s = row >> 6;
+  const int64_t base = A.slice_ptr[s] + (row & 63);
+  const int len = A.slice_len[s];
+  double acc = 0.0;
+#pragma unroll 4
+  for (int k = 0; k < len; ++k) acc += A.val[base + 64 * k] * x[A.col[base + 64 * k]];
+  return acc;
 }
 
-template <int L>
-__global__ void __launch_bounds__(kThreads) k_spmv(int64_t rows, const int* __restrict__ rowptr,
-                                                   const int* __restrict__ col, const double* __restrict__ val,
-                                                   const double* __restrict__ x, double* __restrict__ y) {
-  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t row = g / L;
-  int lane = (int)(g & (L - 1));
-  if (row >= rows) return;
-  double s = row_dot<L>(row, lane, rowptr, col, val, x);
-  if (lane == 0) y[row] = s;
+__global__ void __launch_bounds__(kThreads) k_spmv(SellView A, const double* __restrict__ x, double* __restrict__ y) {
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < A.rows;
+       row += (int64_t)gridDim.x * blockDim.x)
+    y[row] = sell_dot(A, row, x);
 }
 
-// r = b - A x and ||r||^2 (grid-stride over row groups)
-template <int L>
-__global__ void __launch_bounds__(kThreads) k_residual(int64_t rows, const int* __restrict__ rowptr,
-                                                       const int* __restrict__ col, const double* __restrict__ val,
-                                                       const double* __restrict__ x, const double* __restrict__ b,
-                                                       double* __restrict__ r, double* partials, unsigned* counter,
-                                                       double* out) {
-  const int lane = threadIdx.x & (L - 1);
-  const int64_t groups_per_grid = (int64_t)gridDim.x * blockDim.x / L;
+// r = b - A x and per-block partials of ||r||^2
+__global__ void __launch_bounds__(kThreads) k_residual(SellView A, const double* __restrict__ x,
+                                                       const double* __restrict__ b, double* __restrict__ r,
+                                                       double* partials) {
   double acc[1] = {0.0};
-  for (int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / L; row < rows; row += groups_per_grid) {
-    double s = row_dot<L>(row, lane, rowptr, col, val, x);
-    if (lane == 0) {
-      double ri = b[row] - s;
-      r[row] = ri;
-      acc[0] += ri * ri;
-    }
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < A.rows;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    double ri = b[row] - sell_dot(A, row, x);
+    r[row] = ri;
+    acc[0] += ri * ri;
   }
-  __shared__ double res[1];
-  if (grid_reduce<1>(acc, partials, counter, res) && threadIdx.x == 0) out[0] = res[0];
+  block_partials<1>(acc, partials);
 }
 
 // ---- Gram-Schmidt kernels ------------------------------------------------------------------
-// out[k] = V_k . w
+// partials of V_k . w
 template <int K>
 __global__ void __launch_bounds__(kThreads) k_dots(int64_t n, const double* __restrict__ V, int64_t ldv,
-                                                   const double* __restrict__ w, double* partials,
-                                                   unsigned* counter, double* out) {
+                                                   const double* __restrict__ w, double* partials) {
   double acc[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = 0.0;
@@ -127,16 +130,14 @@ __global__ void __launch_bounds__(kThreads) k_dots(int64_t n, const double* __re
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] += V[k * ldv + i] * wi;
   }
-  __shared__ double res[K];
-  if (grid_reduce<K>(acc, partials, counter, res) && threadIdx.x == 0)
-    for (int k = 0; k < K; ++k) out[k] = res[k];
+  block_partials<K>(acc, partials);
 }
 
-// w -= V h; out[k] = V_k . w (k < K), out[K] = ||w||^2
+// w -= V h; partials of V_k . w (k < K) and of ||w||^2 (component K)
 template <int K>
 __global__ void __launch_bounds__(kThreads) k_update_dots(int64_t n, const double* __restrict__ V, int64_t ldv,
                                                           const double* __restrict__ h, double* __restrict__ w,
-                                                          double* partials, unsigned* counter, double* out) {
+                                                          double* partials) {
   double hk[K], acc[K + 1];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
@@ -157,16 +158,14 @@ __global__ void __launch_bounds__(kThreads) k_update_dots(int64_t n, const doubl
     for (int k = 0; k < K; ++k) acc[k] += v[k] * wi;
     acc[K] += wi * wi;
   }
-  __shared__ double res[K + 1];
-  if (grid_reduce<K + 1>(acc, partials, counter, res) && threadIdx.x == 0)
-    for (int k = 0; k <= K; ++k) out[k] = res[k];
+  block_partials<K + 1>(acc, partials);
 }
 
-// w -= V h; out[0] = ||w||^2
+// w -= V h; partials of ||w||^2
 template <int K>
 __global__ void __launch_bounds__(kThreads) k_update_norm(int64_t n, const double* __restrict__ V, int64_t ldv,
                                                           const double* __restrict__ h, double* __restrict__ w,
-                                                          double* partials, unsigned* counter, double* out) {
+                                                          double* partials) {
   double hk[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) hk[k] = h[k];
@@ -178,8 +177,7 @@ __global__ void __launch_bounds__(kThreads) k_update_norm(int64_t n, const doubl
     w[i] = wi;
     acc[0] += wi * wi;
   }
-  __shared__ double res[1];
-  if (grid_reduce<1>(acc, partials, counter, res) && threadIdx.x == 0) out[0] = res[0];
+  block_partials<1>(acc, partials);
 }
 
 // x += sum_k Z_k y_k
@@ -215,106 +213,132 @@ __global__ void k_fill(int64_t n, double v, double* __restrict__ y) {
     y[i] = v;
 }
 
-__global__ void k_sum(int64_t n, const double* __restrict__ x, double* partials, unsigned* counter, double* out) {
+__global__ void k_sum(int64_t n, const double* __restrict__ x, double* partials) {
   double acc[1] = {0.0};
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     acc[0] += x[i];
-  __shared__ double res[1];
-  if (grid_reduce<1>(acc, partials, counter, res) && threadIdx.x == 0) out[0] = res[0];
+  block_partials<1>(acc, partials);
 }
 
-// ---- inner Jacobi-preconditioned CG, state kept on the device -----------------------------
-// x = 0, r = b, z = D^{-1} b, p = z, rho0 = r.z
-__global__ void __launch_bounds__(kThreads) k_pcg_init(int64_t n, const double* __restrict__ b,
-                                                       const double* __restrict__ dinv, double* __restrict__ x,
-                                                       double* __restrict__ r, double* __restrict__ z,
-                                                       double* __restrict__ p, PcgState* st, double tol2, int maxit,
-                                                       double* partials, unsigned* counter) {
-  double acc[1] = {0.0};
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    double bi = b[i], zi = dinv[i] * bi;
-    x[i] = 0.0;
-    r[i] = bi;
-    z[i] = zi;
-    p[i] = zi;
-    acc[0] += bi * zi;
+// ---- inner Jacobi-preconditioned CG, pipelined: one kernel per iteration ------------------
+// Pipelined CG (Ghysels & Vanroose) overlaps the two dot products of an
+// iteration with its matrix-vector product, so one kernel per iteration
+// suffices: it sums the dot-product partials that the previous kernel left
+// (every block in the same order, hence the same scalars everywhere), forms
+// alpha and beta, performs the product and every vector update, and writes
+// the partials of the next iteration's dots.  With the Jacobi preconditioner
+// D^{-1} the preconditioned vectors are diagonal scalings (u = D^{-1} r,
+// q = D^{-1} s, m = D^{-1} w), and the product A D^{-1} w uses the
+// column-scaled copy A D^{-1}, so only r, w, s, z, p, x are stored; w
+// alternates between two buffers because neighbours read it while its owner
+// updates it.  Iteration i, with gamma = r.D^{-1}r, delta = w.D^{-1}r:
+//   beta = gamma_i / gamma_{i-1},  alpha = gamma_i / (delta - beta gamma_i / alpha_{i-1})
+//   n = (A D^{-1}) w,  z = n + beta z,  s = w + beta s,  p = D^{-1} r + beta p,
+//   x += alpha p,  r -= alpha s,  w -= alpha z.
+// The stopping test is gamma_i <= tol^2 gamma_0, as for the plain algorithm.
+struct PcgView {
+  double* __restrict__ x;
+  double* __restrict__ r;
+  double* __restrict__ z;
+  double* __restrict__ s;
+  double* __restrict__ p;
+  double* __restrict__ w0;
+  double* __restrict__ w1;
+  const double* __restrict__ dinv;
+};
+
+// w = (A D^{-1}) b, x = 0, r = b; partials of gamma_0, delta_0 (slot 0)
+__global__ void __launch_bounds__(kPcgThreads) k_ppcg_init(SellView Ac, PcgView v, const double* __restrict__ b,
+                                                           PcgState* st, double tol2, int maxit,
+                                                           double* __restrict__ part) {
+  double acc[2] = {0.0, 0.0};
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < Ac.rows;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    const double bi = b[row], di = v.dinv[row];
+    const double wi = sell_dot(Ac, row, b);
+    v.x[row] = 0.0;
+    v.r[row] = bi;
+    v.w0[row] = wi;
+    acc[0] += bi * bi * di;
+    acc[1] += wi * bi * di;
   }
-  __shared__ double res[1];
-  if (grid_reduce<1>(acc, partials, counter, res) && threadIdx.x == 0) {
-    st->rho = res[0];
-    st->rho0 = res[0];
-    st->alpha = 0.0;
-    st->beta = 0.0;
+  block_partials<2>(acc, part);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->gamma[0] = st->gamma[1] = 0.0;
+    st->alpha[0] = st->alpha[1] = 0.0;
+    st->gamma0 = 0.0;
     st->tol2 = tol2;
-    st->it = 0;
+    st->count = 0;
     st->maxit = maxit;
-    st->done = (!(res[0] > 0.0) || maxit <= 0) ? 1 : 0;
+    st->done = maxit <= 0 ? 1 : 0;
   }
 }
 
-// q = A p, alpha = rho / (p.q)
-template <int L>
-__global__ void __launch_bounds__(kThreads) k_pcg_spmv(int64_t rows, const int* __restrict__ rowptr,
-                                                       const int* __restrict__ col, const double* __restrict__ val,
-                                                       const double* __restrict__ p, double* __restrict__ q,
-                                                       PcgState* st, double* partials, unsigned* counter) {
+template <bool kFirst>
+__global__ void __launch_bounds__(kPcgThreads) k_ppcg_iter(int parity, SellView Ac, PcgView v, PcgState* st,
+                                                           double* __restrict__ part) {
   if (st->done) return;
-  const int lane = threadIdx.x & (L - 1);
-  const int64_t groups_per_grid = (int64_t)gridDim.x * blockDim.x / L;
-  double acc[1] = {0.0};
-  for (int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / L; row < rows; row += groups_per_grid) {
-    double s = row_dot<L>(row, lane, rowptr, col, val, p);
-    if (lane == 0) {
-      q[row] = s;
-      acc[0] += s * p[row];
-    }
+  const int P = gridDim.x;
+  const int cur = parity;
+  const double* pin = part + (size_t)cur * 2 * P;
+  const double gamma = block_sum_partials(pin, P, 2, 0);
+  const double delta = block_sum_partials(pin, P, 2, 1);
+  double gamma0, beta, alpha;
+  if (kFirst) {
+    gamma0 = gamma;
+    beta = 0.0;
+    alpha = gamma / delta;
+  } else {
+    gamma0 = st->gamma0;
+    beta = gamma / st->gamma[1 - cur];
+    alpha = gamma / (delta - beta * gamma / st->alpha[1 - cur]);
   }
-  __shared__ double res[1];
-  if (grid_reduce<1>(acc, partials, counter, res) && threadIdx.x == 0) {
-    double pq = res[0];
-    if (pq > 0.0) {
-      st->alpha = st->rho / pq;
+  int done = 0;
+  if (!(gamma > st->tol2 * gamma0)) done = 1;
+  else if (!(alpha > 0.0) || !isfinite(alpha)) done = 2;  // loss of positivity: keep the iterate
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (kFirst) st->gamma0 = gamma0;
+    st->gamma[cur] = gamma;
+    st->alpha[cur] = alpha;
+    if (done) st->done = done;
+  }
+  if (done) return;
+  const double* __restrict__ win = cur ? v.w1 : v.w0;
+  double* __restrict__ wout = cur ? v.w0 : v.w1;
+  double acc[2] = {0.0, 0.0};
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < Ac.rows;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    const double n = sell_dot(Ac, row, win);
+    const double wi = win[row], di = v.dinv[row], ri = v.r[row];
+    double zz, ss, pp;
+    if (kFirst) {
+      zz = n;
+      ss = wi;
+      pp = di * ri;
     } else {
-      st->alpha = 0.0;
-      st->done = 2;  // loss of positivity: stop with the current iterate
+      zz = n + beta * v.z[row];
+      ss = wi + beta * v.s[row];
+      pp = di * ri + beta * v.p[row];
     }
+    v.z[row] = zz;
+    v.s[row] = ss;
+    v.p[row] = pp;
+    v.x[row] += alpha * pp;
+    const double rn = ri - alpha * ss;
+    const double wn = wi - alpha * zz;
+    v.r[row] = rn;
+    wout[row] = wn;
+    acc[0] += rn * rn * di;
+    acc[1] += wn * rn * di;
   }
+  block_partials<2>(acc, part + (size_t)(1 - cur) * 2 * P);
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->count += 1;
 }
 
-// x += alpha p, r -= alpha q, z = D^{-1} r, rho' = r.z, beta = rho'/rho
-__global__ void __launch_bounds__(kThreads) k_pcg_update(int64_t n, double* __restrict__ x, double* __restrict__ r,
-                                                         double* __restrict__ z, const double* __restrict__ q,
-                                                         const double* __restrict__ p,
-                                                         const double* __restrict__ dinv, PcgState* st,
-                                                         double* partials, unsigned* counter) {
-  if (st->done) return;
-  const double alpha = st->alpha;
-  double acc[1] = {0.0};
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    x[i] += alpha * p[i];
-    double ri = r[i] - alpha * q[i];
-    r[i] = ri;
-    double zi = dinv[i] * ri;
-    z[i] = zi;
-    acc[0] += ri * zi;
-  }
-  __shared__ double res[1];
-  if (grid_reduce<1>(acc, partials, counter, res) && threadIdx.x == 0) {
-    double rn = res[0];
-    st->beta = rn / st->rho;
-    st->rho = rn;
-    st->it += 1;
-    if (rn <= st->tol2 * st->rho0 || st->it >= st->maxit || !(rn == rn)) st->done = 1;
-  }
-}
-
-// p = z + beta p
-__global__ void __launch_bounds__(kThreads) k_pcg_dir(int64_t n, const double* __restrict__ z,
-                                                      double* __restrict__ p, const PcgState* st) {
-  if (st->done) return;
-  const double beta = st->beta;
+__global__ void k_col_scale(int64_t n, const int* __restrict__ col, const double* __restrict__ val,
+                            const double* __restrict__ dinv, double* __restrict__ out) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = z[i] + beta * p[i];
+    out[i] = val[i] * dinv[col[i]];
 }
 
 inline int stream_grid(int64_t n) {
@@ -323,80 +347,71 @@ inline int stream_grid(int64_t n) {
   return (int)(b < cap ? (b < 1 ? 1 : b) : cap);
 }
 
+inline int pcg_grid(int64_t n) {
+  int64_t b = (n + kPcgThreads - 1) / kPcgThreads;
+  return (int)(b < kPcgBlocks ? (b < 1 ? 1 : b) : kPcgBlocks);
+}
+
 #define VEM_K_CASES(X) \
   X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20) \
   X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
 
+void finalize(hipStream_t s, int nparts, int K, const double* partials, double* out) {
+  k_finalize<<<K, kThreads, 0, s>>>(nparts, K, partials, out);
+}
+
 }  // namespace
 
-int spmv_lanes(double avg_row) {
-  int L = 1;
-  while (L < 64 && 2 * L <= avg_row) L *= 2;
-  if (L < 2) L = 2;
-  return L;
+void launch_spmv(hipStream_t s, const Sell& A, const double* x, double* y) {
+  if (A.rows <= 0) return;
+  int64_t blocks = (A.rows + kThreads - 1) / kThreads;
+  k_spmv<<<(int)(blocks < 65536 ? blocks : 65536), kThreads, 0, s>>>(view(A), x, y);
 }
 
-void launch_spmv(hipStream_t s, int lanes, int64_t rows, const int* rowptr, const int* col, const double* val,
-                 const double* x, double* y) {
-  if (rows <= 0) return;
-  int64_t threads = rows * lanes;
-  int grid = (int)((threads + kThreads - 1) / kThreads);
-  switch (lanes) {
-#define X(L) \
-  case L: k_spmv<L><<<grid, kThreads, 0, s>>>(rows, rowptr, col, val, x, y); break;
-    X(2) X(4) X(8) X(16) X(32) X(64)
-#undef X
-    default: throw Error{VEM_EINVAL, "bad lanes per row"};
-  }
-}
-
-void launch_residual(hipStream_t s, int lanes, int64_t rows, const int* rowptr, const int* col, const double* val,
-                     const double* x, const double* b, double* r, double* partials, unsigned* counter,
+void launch_residual(hipStream_t s, const Sell& A, const double* x, const double* b, double* r, double* partials,
                      double* out) {
-  int grid = red_grid(rows * lanes);
-  switch (lanes) {
-#define X(L) \
-  case L: k_residual<L><<<grid, kThreads, 0, s>>>(rows, rowptr, col, val, x, b, r, partials, counter, out); break;
-    X(2) X(4) X(8) X(16) X(32) X(64)
-#undef X
-    default: throw Error{VEM_EINVAL, "bad lanes per row"};
-  }
+  int grid = red_grid(A.rows);
+  k_residual<<<grid, kThreads, 0, s>>>(view(A), x, b, r, partials);
+  finalize(s, grid, 1, partials, out);
 }
 
 void launch_dots(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* w, double* partials,
-                 unsigned* counter, double* out) {
+                 double* out) {
   int grid = red_grid(n);
   switch (k) {
 #define X(K) \
-  case K: k_dots<K><<<grid, kThreads, 0, s>>>(n, V, ldv, w, partials, counter, out); break;
+  case K: k_dots<K><<<grid, kThreads, 0, s>>>(n, V, ldv, w, partials); break;
     VEM_K_CASES(X)
 #undef X
     default: throw Error{VEM_EINVAL, "too many basis vectors"};
   }
+  finalize(s, grid, k, partials, out);
 }
 
 void launch_update_dots(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* h, double* w,
-                        double* partials, unsigned* counter, double* out) {
+                        double* partials, double* out) {
   int grid = red_grid(n);
   switch (k) {
 #define X(K) \
-  case K: k_update_dots<K><<<grid, kThreads, 0, s>>>(n, V, ldv, h, w, partials, counter, out); break;
+  case K: k_update_dots<K><<<grid, kThreads, 0, s>>>(n, V, ldv, h, w, partials); break;
     VEM_K_CASES(X)
 #undef X
     default: throw Error{VEM_EINVAL, "too many basis vectors"};
   }
+  finalize(s, grid, k + 1, partials, out);
 }
 
 void launch_update_norm(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* h, double* w,
-                        double* partials, unsigned* counter, double* out) {
+                        double* partials, double* out) {
   int grid = red_grid(n);
   switch (k) {
 #define X(K) \
-  case K: k_update_norm<K><<<grid, kThreads, 0, s>>>(n, V, ldv, h, w, partials, counter, out); break;
+  case K: k_update_norm<K><<<grid, kThreads, 0, s>>>(n, V, ldv, h, w, partials); break;
     VEM_K_CASES(X)
 #undef X
     default: throw Error{VEM_EINVAL, "too many basis vectors"};
   }
+  finalize(s, grid, 1, partials, out);
 }
 
 void launch_combine(hipStream_t s, int64_t n, int k, const double* Z, int64_t ldz, const double* y, double* x) {
@@ -422,30 +437,34 @@ void launch_copy(hipStream_t s, int64_t n, const double* x, double* y) {
 void launch_fill(hipStream_t s, int64_t n, double v, double* y) {
   if (n > 0) k_fill<<<stream_grid(n), kThreads, 0, s>>>(n, v, y);
 }
-void launch_sum(hipStream_t s, int64_t n, const double* x, double* partials, unsigned* counter, double* out) {
-  k_sum<<<red_grid(n), kThreads, 0, s>>>(n, x, partials, counter, out);
+void launch_sum(hipStream_t s, int64_t n, const double* x, double* partials, double* out) {
+  int grid = red_grid(n);
+  k_sum<<<grid, kThreads, 0, s>>>(n, x, partials);
+  finalize(s, grid, 1, partials, out);
 }
 
-void launch_pcg_init(hipStream_t s, int64_t n, const double* b, const double* dinv, double* x, double* r, double* z,
-                     double* p, PcgState* st, double tol, int maxit, double* partials, unsigned* counter) {
-  k_pcg_init<<<red_grid(n), kThreads, 0, s>>>(n, b, dinv, x, r, z, p, st, tol * tol, maxit, partials, counter);
+void launch_col_scale(hipStream_t s, Sell& A, const double* dinv) {
+  if (A.nnz <= 0) return;
+  A.val_cs.alloc(A.nnz);
+  VEM_REQUIRE(A.val_cs.p && A.val.p && A.col.p, VEM_EINVAL, "column scaling of an unbuilt matrix");
+  k_col_scale<<<stream_grid(A.nnz), kThreads, 0, s>>>(A.nnz, A.col, A.val, dinv, A.val_cs);
 }
 
-void launch_pcg_iter(hipStream_t s, int lanes, int64_t n, const int* rowptr, const int* col, const double* val,
-                     const double* dinv, double* x, double* r, double* z, double* p, double* q, PcgState* st,
-                     double* partials, unsigned* counter) {
-  int grid_spmv = red_grid(n * lanes);
-  switch (lanes) {
-#define X(L)                                                                                                     \
-  case L:                                                                                                        \
-    k_pcg_spmv<L><<<grid_spmv, kThreads, 0, s>>>(n, rowptr, col, val, p, q, st, partials, counter);              \
-    break;
-    X(2) X(4) X(8) X(16) X(32) X(64)
-#undef X
-    default: throw Error{VEM_EINVAL, "bad lanes per row"};
-  }
-  k_pcg_update<<<red_grid(n), kThreads, 0, s>>>(n, x, r, z, q, p, dinv, st, partials, counter);
-  k_pcg_dir<<<stream_grid(n), kThreads, 0, s>>>(n, z, p, st);
+static PcgView pview(const PcgWork& w) { return {w.x, w.r, w.z, w.s, w.p, w.w0, w.w1, w.dinv}; }
+
+static SellView view_cs(const Sell& A) { return {A.rows, A.slice_ptr, A.slice_len, A.col, A.val_cs}; }
+
+void launch_pcg_init(hipStream_t s, const Sell& A, const PcgWork& w, const double* b, PcgState* st, double tol,
+                     int maxit, double* part) {
+  k_ppcg_init<<<pcg_grid(A.rows), kPcgThreads, 0, s>>>(view_cs(A), pview(w), b, st, tol * tol, maxit, part);
+}
+
+void launch_pcg_iter(hipStream_t s, int i, const Sell& A, const PcgWork& w, PcgState* st, double* part) {
+  const int P = pcg_grid(A.rows);
+  if (i == 0)
+    k_ppcg_iter<true><<<P, kPcgThreads, 0, s>>>(0, view_cs(A), pview(w), st, part);
+  else
+    k_ppcg_iter<false><<<P, kPcgThreads, 0, s>>>(i & 1, view_cs(A), pview(w), st, part);
 }
 
 }  // namespace vem

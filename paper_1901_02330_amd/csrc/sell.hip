@@ -1,0 +1,103 @@
+// SELL-64 (sliced ELLPACK) copies of the assembled CSR matrices.
+//
+// A slice is 64 consecutive rows, one wavefront: the slice is padded to its
+// longest row and stored column-major, so entry k of the 64 rows is one
+// contiguous 512-byte load of values and a 256-byte load of column indices.
+// A thread owns a row; its loads do not depend on a row pointer and are
+// independent of each other, which keeps many loads in flight per wave.
+// Padding entries carry value 0 and the row's own column.  The CSR matrix
+// stays the assembly target: src[] maps every SELL slot to its CSR entry
+// (-1 for padding) so that new values (a new coefficient) are copied over
+// without rebuilding the layout.  Entries of a row keep their CSR order, so
+// a row's sum is formed in the same order as a sequential CSR product.
+#include "vem_internal.h"
+
+namespace vem {
+namespace {
+
+__global__ void k_sell_len(int64_t rows, int64_t nslices, const int* __restrict__ rowptr, int* slice_len,
+                           int64_t* slice_sz) {
+  int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nslices) return;
+  int64_t r0 = s * 64, r1 = r0 + 64 < rows ? r0 + 64 : rows;
+  int m = 0;
+  for (int64_t r = r0; r < r1; ++r) {
+    int l = rowptr[r + 1] - rowptr[r];
+    m = l > m ? l : m;
+  }
+  slice_len[s] = m;
+  slice_sz[s] = (int64_t)m * 64;
+}
+
+__global__ void k_sell_fill(int64_t rows, const int* __restrict__ rowptr, const int* __restrict__ col,
+                            const int64_t* __restrict__ slice_ptr, const int* __restrict__ slice_len, int* scol,
+                            int* src) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t nrow_pad = ((rows + 63) / 64) * 64;
+  if (r >= nrow_pad) return;
+  int64_t s = r >> 6;
+  int lane = (int)(r & 63);
+  int64_t base = slice_ptr[s] + lane;
+  int len = slice_len[s];
+  int b = 0, e = 0;
+  if (r < rows) {
+    b = rowptr[r];
+    e = rowptr[r + 1];
+  }
+  for (int k = 0; k < len; ++k) {
+    int64_t o = base + (int64_t)k * 64;
+    if (b + k < e) {
+      scol[o] = col[b + k];
+      src[o] = b + k;
+    } else {
+      scol[o] = r < rows ? (int)r : 0;
+      src[o] = -1;
+    }
+  }
+}
+
+__global__ void k_sell_vals(int64_t n, const int* __restrict__ src, const double* __restrict__ val,
+                            double* __restrict__ sval) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int j = src[i];
+  sval[i] = j >= 0 ? val[j] : 0.0;
+}
+
+__global__ void k_narrow64(int64_t n, const int64_t* __restrict__ in, int* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (int)in[i];
+}
+
+inline int grid256(int64_t n) { return (int)((n + 255) / 256); }
+
+}  // namespace
+
+void build_sell(hipStream_t s, const Csr& A, Sell& S) {
+  S.rows = A.rows;
+  S.nslices = (A.rows + 63) / 64;
+  S.slice_len.alloc(S.nslices);
+  DBuf<int64_t> sz, ptr;
+  sz.alloc(S.nslices + 1);
+  ptr.alloc(S.nslices + 1);
+  k_sell_len<<<grid256(S.nslices), 256, 0, s>>>(A.rows, S.nslices, A.rowptr, S.slice_len, sz);
+  VEM_HIP(hipGetLastError());
+  int64_t total = scan_i64(s, sz, S.nslices, ptr);
+  VEM_REQUIRE(total < INT32_MAX, VEM_ENOMEM, "padded matrix exceeds 2^31-1 entries");
+  S.nnz = total;
+  S.slice_ptr.alloc(S.nslices + 1);
+  k_narrow64<<<grid256(S.nslices + 1), 256, 0, s>>>(S.nslices + 1, ptr, S.slice_ptr);
+  S.col.alloc(total);
+  S.src.alloc(total);
+  S.val.alloc(total);
+  int64_t nrow_pad = S.nslices * 64;
+  k_sell_fill<<<grid256(nrow_pad), 256, 0, s>>>(A.rows, A.rowptr, A.col, ptr, S.slice_len, S.col, S.src);
+  VEM_HIP(hipGetLastError());
+  VEM_HIP(hipStreamSynchronize(s));
+}
+
+void refresh_sell(hipStream_t s, const Csr& A, Sell& S) {
+  if (S.nnz > 0) k_sell_vals<<<grid256(S.nnz), 256, 0, s>>>(S.nnz, S.src, A.val, S.val);
+}
+
+}  // namespace vem

@@ -78,17 +78,25 @@ struct HBuf {
   T& operator[](size_t i) { return p[i]; }
 };
 
-// Block-reduction scratch: per-block partials and arrival counters.
+// Reduction scratch: per-block partial sums.
 constexpr int kRedBlocks = 1024;   // grid of the reduction kernels
 constexpr int kRedThreads = 256;
 constexpr int kMaxDots = 34;       // largest number of simultaneous dot products
 constexpr int kMaxRestart = 32;
 constexpr int kMaxCellFaces = 64;
+constexpr int kPcgBlocks = 1024;   // largest grid of the inner-CG kernels
+constexpr int kPcgThreads = 1024;  // block size of the inner-CG kernels
 
-// Device-resident state of one inner Jacobi-CG solve.
+// Device-resident state of one inner (pipelined) Jacobi-CG solve.
 struct PcgState {
-  double rho, rho0, alpha, beta, tol2;
-  int it, maxit, done, pad;
+  double gamma[2], alpha[2], gamma0, tol2;
+  int count, maxit, done, pad;
+};
+
+// Vectors of one inner CG solve (x is the solution).
+struct PcgWork {
+  double *x, *r, *z, *s, *p, *w0, *w1;
+  const double* dinv;
 };
 
 // Compressed sparse row matrix on the device.
@@ -97,6 +105,16 @@ struct Csr {
   DBuf<int> rowptr, col;
   DBuf<double> val;
 };
+
+// SELL-64 copy of a CSR matrix (64-row slices, column-major inside a slice).
+struct Sell {
+  int64_t rows = 0, nslices = 0, nnz = 0;
+  DBuf<int> slice_ptr, slice_len, col, src;
+  DBuf<double> val;
+  DBuf<double> val_cs;  // column-scaled copy A D^{-1} (inner CG matrices only)
+};
+void build_sell(hipStream_t s, const Csr& A, Sell& S);
+void refresh_sell(hipStream_t s, const Csr& A, Sell& S);
 
 // ---- launchers (one translation unit each; all take the handle's stream) ----
 
@@ -161,29 +179,26 @@ void launch_schur_values(hipStream_t s, DofLayout L, const int* cptr, const int*
 void launch_rhs_from_moments(hipStream_t s, int64_t Nu, int64_t Np, double* rhs);
 
 // sparse/Krylov
-int spmv_lanes(double avg_row);
-void launch_spmv(hipStream_t s, int lanes, int64_t rows, const int* rowptr, const int* col, const double* val,
-                 const double* x, double* y);
-void launch_residual(hipStream_t s, int lanes, int64_t rows, const int* rowptr, const int* col, const double* val,
-                     const double* x, const double* b, double* r, double* partials, unsigned* counter,
+void launch_spmv(hipStream_t s, const Sell& A, const double* x, double* y);
+void launch_residual(hipStream_t s, const Sell& A, const double* x, const double* b, double* r, double* partials,
                      double* out);
 void launch_dots(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* w, double* partials,
-                 unsigned* counter, double* out);
+                 double* out);
 void launch_update_dots(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* h, double* w,
-                        double* partials, unsigned* counter, double* out);
+                        double* partials, double* out);
 void launch_update_norm(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* h, double* w,
-                        double* partials, unsigned* counter, double* out);
+                        double* partials, double* out);
 void launch_scale_to(hipStream_t s, int64_t n, const double* w, const double* norm2, double* dst);
 void launch_scale_by(hipStream_t s, int64_t n, const double* x, const double* d, double c, double* y);
 void launch_combine(hipStream_t s, int64_t n, int k, const double* Z, int64_t ldz, const double* y, double* x);
 void launch_copy(hipStream_t s, int64_t n, const double* x, double* y);
 void launch_fill(hipStream_t s, int64_t n, double v, double* y);
-void launch_pcg_init(hipStream_t s, int64_t n, const double* b, const double* dinv, double* x, double* r, double* z,
-                     double* p, PcgState* st, double tol, int maxit, double* partials, unsigned* counter);
-void launch_pcg_iter(hipStream_t s, int lanes, int64_t n, const int* rowptr, const int* col, const double* val,
-                     const double* dinv, double* x, double* r, double* z, double* p, double* q, PcgState* st,
-                     double* partials, unsigned* counter);
-void launch_sum(hipStream_t s, int64_t n, const double* x, double* partials, unsigned* counter, double* out);
+void launch_sum(hipStream_t s, int64_t n, const double* x, double* partials, double* out);
+// inner CG: part needs 4 * kPcgBlocks doubles; launch_col_scale fills A.val_cs = A D^{-1}
+void launch_col_scale(hipStream_t s, Sell& A, const double* dinv);
+void launch_pcg_init(hipStream_t s, const Sell& A, const PcgWork& w, const double* b, PcgState* st, double tol,
+                     int maxit, double* part);
+void launch_pcg_iter(hipStream_t s, int i, const Sell& A, const PcgWork& w, PcgState* st, double* part);
 
 // host utilities
 void gauss_jacobi01(int n, int alpha, double* t, double* w);  // int_0^1 (1-t)^alpha g(t) dt
