@@ -181,6 +181,20 @@ vem_status vem_get_rhs(vem_handle h, double* b);
 vem_status vem_get_geometry(vem_handle h, double* face_area, double* face_normal, double* face_centroid,
                             double* cell_volume, double* cell_centroid, double* cell_diam);
 
+/* Hot kernels that vem_time_kernel can time. */
+enum { VEM_KERNEL_SPMV = 0, VEM_KERNEL_CG_SCHUR = 1, VEM_KERNEL_CG_REG = 2 };
+
+/* Measurement hook for benchmarks: time `reps` back-to-back launches of one
+ * hot kernel with HIP events recorded on the handle's stream.
+ *   VEM_KERNEL_SPMV:     the saddle product y = K x;
+ *   VEM_KERNEL_CG_SCHUR: one pipelined inner-CG iteration on S (Block-Schur);
+ *   VEM_KERNEL_CG_REG:   one pipelined inner-CG iteration on M + B^T B / gamma.
+ * avg_ms receives the mean duration of one launch; bytes (may be NULL) the
+ * algorithmic bytes one launch moves (every matrix entry and every vector
+ * element read or written once).  Uses the solver workspace; the results of
+ * a previous vem_solve are not affected. */
+vem_status vem_time_kernel(vem_handle h, int which, int reps, double* avg_ms, double* bytes);
+
 const char* vem_status_string(vem_status st);
 const char* vem_last_error(vem_handle h);
 

@@ -62,6 +62,7 @@ struct vem_ctx {
   DBuf<int> Kdiag, Adiag, Sdiag;
   DBuf<double> dM, dMinv, dAinv, dSinv;
   double gamma_A = 0.0;
+  int expect_S = 0, expect_A = 0;  // last inner-CG iteration counts (chunk sizing)
 
   // solver workspace
   int64_t ws_N = 0;
@@ -372,13 +373,18 @@ void ensure_workspace(vem_handle h, int m) {
 }
 
 // Inner Jacobi-CG: x ~ A^{-1} b.  Returns the iterations used.
+// Inner pipelined Jacobi-CG: x ~ A^{-1} b to inner_tol.  Iterations are
+// enqueued in chunks between convergence checks; the first chunk is sized
+// from the previous solve on the same matrix so that few launches find the
+// solve already converged.  Returns the iterations performed.
 int inner_pcg(vem_handle h, const Sell& A, const double* dinv, const double* b, double* x,
-              const vem_solve_opts& o) {
+              const vem_solve_opts& o, int& expect) {
   hipStream_t s = h->stream;
   PcgWork w{x, h->pr, h->pz, h->ps, h->pp, h->pw0, h->pw1, dinv};
   launch_pcg_init(s, A, w, b, h->pcg, o.inner_tol, o.inner_maxit, h->pcgpart);
   check_launch();
-  int chunk = std::max(1, o.inner_check);
+  const int step = std::max(1, o.inner_check);
+  int chunk = expect > 4 ? (expect * 7) / 8 : step;
   int i = 0;
   for (;;) {
     for (int c = 0; c < chunk && i < o.inner_maxit; ++c, ++i) launch_pcg_iter(s, i, A, w, h->pcg, h->pcgpart);
@@ -386,7 +392,9 @@ int inner_pcg(vem_handle h, const Sell& A, const double* dinv, const double* b, 
     VEM_HIP(hipMemcpyAsync(h->hpcg.p, h->pcg.p, sizeof(PcgState), hipMemcpyDeviceToHost, s));
     sync(h);
     if (h->hpcg.p->done || i >= o.inner_maxit) break;
+    chunk = expect > 4 ? std::max(2, std::min(step, expect / 8)) : step;
   }
+  expect = h->hpcg.p->count;
   return h->hpcg.p->count;
 }
 
@@ -397,9 +405,9 @@ int64_t apply_prec(vem_handle h, const vem_solve_opts& o, const double* v, doubl
   switch (o.precond) {
     case VEM_PREC_SCHUR:
       launch_scale_by(s, Nu, v, h->dMinv, 1.0, z);
-      return inner_pcg(h, h->Ss, h->dSinv, v + Nu, z + Nu, o);
+      return inner_pcg(h, h->Ss, h->dSinv, v + Nu, z + Nu, o, h->expect_S);
     case VEM_PREC_REG: {
-      int it = inner_pcg(h, h->As, h->dAinv, v, z, o);
+      int it = inner_pcg(h, h->As, h->dAinv, v, z, o, h->expect_A);
       launch_scale_by(s, Np, v + Nu, nullptr, 1.0 / h->gamma_A, z + Nu);
       return it;
     }
@@ -833,6 +841,63 @@ vem_status vem_get_geometry(vem_handle h, double* fa, double* fn, double* fc, do
     cp(cc, h->c_cen, 3 * (size_t)h->nc);
     cp(cd, h->c_diam, h->nc);
     sync(h);
+  });
+}
+
+vem_status vem_time_kernel(vem_handle h, int which, int reps, double* avg_ms, double* bytes) {
+  if (!h || !avg_ms || reps < 1) return VEM_EINVAL;
+  return guarded(h, [&] {
+    require_disc(h);
+    VEM_REQUIRE(which >= VEM_KERNEL_SPMV && which <= VEM_KERNEL_CG_REG, VEM_EINVAL, "unknown kernel");
+    hipStream_t s = h->stream;
+    ensure_workspace(h, std::max(1, h->ws_m));
+    const int64_t Nu = h->L.Nu, Np = h->L.Np, N = Nu + Np;
+    hipEvent_t e0, e1;
+    VEM_HIP(hipEventCreate(&e0));
+    VEM_HIP(hipEventCreate(&e1));
+    double b = 0.0;
+    try {
+      if (which == VEM_KERNEL_SPMV) {
+        launch_spmv(s, h->Ks, h->rhs, h->Vb);  // warm-up
+        VEM_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) launch_spmv(s, h->Ks, h->rhs, h->Vb);
+        VEM_HIP(hipEventRecord(e1, s));
+        b = 12.0 * h->K.nnz + 8.0 * N + 8.0 * N;  // matrix, x once, y once
+      } else {
+        Sell& A = which == VEM_KERNEL_CG_SCHUR ? h->Ss : h->As;
+        const Csr& C = which == VEM_KERNEL_CG_SCHUR ? h->S : h->A;
+        const double* dinv = which == VEM_KERNEL_CG_SCHUR ? h->dSinv.p : h->dAinv.p;
+        // a constant right-hand side: never zero, whatever the loads are
+        launch_fill(s, A.rows, 1.0, h->Vb);
+        const double* rhs = h->Vb;
+        PcgWork w{h->xw.p, h->pr, h->pz, h->ps, h->pp, h->pw0, h->pw1, dinv};
+        // tol = 0: the solve never stops, every timed launch does a full iteration
+        launch_pcg_init(s, A, w, rhs, h->pcg, 0.0, INT_MAX, h->pcgpart);
+        launch_pcg_iter(s, 0, A, w, h->pcg, h->pcgpart);
+        launch_pcg_iter(s, 1, A, w, h->pcg, h->pcgpart);
+        VEM_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) launch_pcg_iter(s, 2 + r, A, w, h->pcg, h->pcgpart);
+        VEM_HIP(hipEventRecord(e1, s));
+        // matrix once; w gathered; dinv, r, z, s, p, x read; z, s, p, x, r, w written
+        b = 12.0 * C.nnz + 8.0 * C.rows * 13.0;
+      }
+      check_launch();
+      VEM_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      VEM_HIP(hipEventElapsedTime(&ms, e0, e1));
+      VEM_HIP(hipMemcpyAsync(h->hpcg.p, h->pcg.p, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+      sync(h);
+      VEM_REQUIRE(which == VEM_KERNEL_SPMV || h->hpcg.p->done == 0, VEM_EBREAKDOWN,
+                  "inner CG stopped during the timing loop");
+      *avg_ms = (double)ms / reps;
+      if (bytes) *bytes = b;
+    } catch (...) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
   });
 }
 

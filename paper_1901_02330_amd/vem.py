@@ -85,6 +85,7 @@ def load():
         "vem_status_string": ([c_int], c_char_p),
         "vem_last_error": ([H], c_char_p),
         "vem_solve_opts_default": ([POINTER(SolveOpts)], None),
+        "vem_time_kernel": ([H, c_int, c_int, POINTER(c_double), POINTER(c_double)], c_int),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -237,6 +238,13 @@ class Solver:
         self._check(self.lib.vem_get_rhs(self.h, _ptr(b)))
         return b
 
+    def time_kernel(self, which="cg_schur", reps=50):
+        """Mean duration (ms) of one launch of a hot kernel, timed with HIP events, and its algorithmic bytes."""
+        code = {"spmv": 0, "cg_schur": 1, "cg_reg": 2}[which]
+        ms, nb = c_double(), c_double()
+        self._check(self.lib.vem_time_kernel(self.h, code, int(reps), byref(ms), byref(nb)))
+        return ms.value, nb.value
+
     def geometry(self):
         t = self.torch
         sz = self.sizes()
@@ -258,5 +266,5 @@ class Solver:
 EXPORTED = [
     "vem_solve_opts_default", "vem_create", "vem_destroy", "vem_set_mesh", "vem_discretize", "vem_get_sizes",
     "vem_get_quadrature", "vem_set_coefficient", "vem_set_rhs", "vem_solve", "vem_apply", "vem_export_csr",
-    "vem_get_rhs", "vem_get_geometry", "vem_status_string", "vem_last_error",
+    "vem_get_rhs", "vem_get_geometry", "vem_status_string", "vem_last_error", "vem_time_kernel",
 ]
