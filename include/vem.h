@@ -67,8 +67,10 @@ enum { VEM_MEM_HOST = 0, VEM_MEM_DEVICE = 1 };
 
 /* Element families.  VEM_LO: the lowest-order member of the paper's face
  * space (Section 4.1) - one normal-flux moment per face, divergence and
- * pressure constant per cell.  VEM_PAPER: the paper's order-k element (face
- * space P_k, divergence and pressure P_{k-1}); reserved, not yet built. */
+ * pressure constant per cell.  VEM_PAPER: the paper's order-k element
+ * (Sections 4.1-4.3: face space P_k with (k+1)(k+2)/2 moments per face,
+ * gradient and cross interior moments, divergence and pressure P_{k-1}),
+ * k = 1, 2, 3. */
 enum { VEM_LO = 0, VEM_PAPER = 1 };
 
 enum { VEM_PREC_SCHUR = 0, VEM_PREC_REG = 1, VEM_PREC_NONE = 2 };
@@ -136,7 +138,12 @@ vem_status vem_set_mesh(vem_handle h, int64_t nv, const double* xyz, int64_t nf,
                         const int8_t* cell_face_sign, int mem_kind);
 
 /* Build geometry, local matrices (nu = 1) and the sparse patterns.
- * family: VEM_LO (k ignored).  load_points: points per direction of the
+ * family: VEM_LO (k ignored) or VEM_PAPER (k = 1, 2, 3).  Flux unknowns are
+ * ordered face by face (the face moments, w.r.t. the global normal and the
+ * face frame: origin at the face centroid, e1 along the longest loop edge,
+ * e2 = n_f x e1), then cell by cell (gradient moments, then cross moments:
+ * x part, y part, z part; multi-indices graded, x power then y power
+ * descending); pressure unknowns cell by cell.  load_points: points per direction of the
  * conical-product rule used for f and p_D (1..6; degree 2n-1).  The
  * coefficient is set to nu = 1 and the right-hand side to zero. */
 vem_status vem_discretize(vem_handle h, int family, int k, int load_points);

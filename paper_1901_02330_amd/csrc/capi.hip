@@ -55,6 +55,8 @@ struct vem_ctx {
   DBuf<int64_t> lmat_ptr, lb_ptr;
   DBuf<double> M1, Bdiv1;
   DBuf<double> nu, rhs;
+  // paper's element: face transfer matrices T_f = |f| H_f^{-1}, cell moments of the scaled monomials
+  DBuf<double> pk_Tf, pk_cmom;
 
   // matrices
   Csr K, A, S;
@@ -559,9 +561,9 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
   if (!h) return VEM_EINVAL;
   return guarded(h, [&] {
     VEM_REQUIRE(h->has_mesh, VEM_EINVAL, "call vem_set_mesh first");
-    VEM_REQUIRE(family == VEM_LO, VEM_EINVAL, "only the lowest-order family (VEM_LO) is available");
+    VEM_REQUIRE(family == VEM_LO || (family == VEM_PAPER && k >= 1 && k <= 3), VEM_EINVAL,
+                "family must be VEM_LO, or VEM_PAPER with k in 1..3");
     VEM_REQUIRE(load_points >= 1 && load_points <= 6, VEM_EINVAL, "load_points must be in 1..6");
-    (void)k;
     hipStream_t s = h->stream;
     h->has_disc = false;
     const int nf = h->nf, nc = h->nc;
@@ -644,11 +646,18 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
     L.nfd = 1;
     L.nint = 0;
     L.npd = 1;
+    if (family == VEM_PAPER) {
+      PaperSizes z = paper_sizes(k);
+      L.nfd = z.nfd;
+      L.nint = z.nint;
+      L.npd = z.npd;
+    }
     L.Nu = (int64_t)nf * L.nfd + (int64_t)nc * L.nint;
     L.Np = (int64_t)nc * L.npd;
     h->L = L;
     h->family = family;
-    h->korder = 0;
+    h->korder = family == VEM_PAPER ? k : 0;
+    int64_t tot_ldof = 0;
     {
       DBuf<int64_t> nd, nm, nb;
       nd.alloc(nc + 1);
@@ -660,6 +669,7 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
       p64.alloc(nc + 1);
       int64_t tot = scan_i64(s, nd, nc, p64);
       VEM_REQUIRE(tot <= INT_MAX, VEM_ENOMEM, "too many local DOFs");
+      tot_ldof = tot;
       h->ldof_ptr.alloc(nc + 1);
       k_narrow<<<grid_of(nc + 1), 256, 0, s>>>(nc + 1, p64.p, h->ldof_ptr.p);
       h->lmat_ptr.alloc(nc + 1);
@@ -671,8 +681,68 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
       h->sorted_gid.alloc(tot);
       h->sorted_l.alloc(tot);
     }
-    launch_lo_local(s, h->ncf, h->inc_cell, h->cptr, h->cface, h->csign, h->f_area, h->f_normal, h->f_cen, h->c_vol,
-                    h->c_cen, h->lmat_ptr, h->M1, h->lb_ptr, h->Bdiv1);
+    if (family == VEM_LO) {
+      launch_lo_local(s, h->ncf, h->inc_cell, h->cptr, h->cface, h->csign, h->f_area, h->f_normal, h->f_cen,
+                      h->c_vol, h->c_cen, h->lmat_ptr, h->M1, h->lb_ptr, h->Bdiv1);
+    } else {
+      PaperSizes z = paper_sizes(k);
+      std::vector<double> p2, w2, trip;
+      tri_reference_rule(z.nq, p2, w2);
+      for (size_t r = 0; r < w2.size(); ++r) {
+        trip.push_back(p2[2 * r]);
+        trip.push_back(p2[2 * r + 1]);
+        trip.push_back(w2[r]);
+      }
+      DBuf<double> tri, FP, FM, Dg, Pg, Xg, Cg;
+      tri.alloc(trip.size());
+      VEM_HIP(hipMemcpyAsync(tri.p, trip.data(), trip.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      FP.alloc((size_t)h->ncf * z.nsm);
+      FM.alloc((size_t)h->ncf * z.nfm);
+      h->pk_Tf.alloc((size_t)nf * z.nfd * z.nfd);
+      h->pk_cmom.alloc((size_t)nc * z.nsm);
+      Dg.alloc((size_t)tot_ldof * z.n3);
+      Pg.alloc((size_t)tot_ldof * z.n3);
+      Xg.alloc((size_t)tot_ldof * z.n3);
+      Cg.alloc((size_t)tot_ldof * z.npd);
+      PaperLocalArgs a{};
+      a.s = s;
+      a.nf = nf;
+      a.nc = nc;
+      a.ninc = h->ncf;
+      a.inc_cell = h->inc_cell;
+      a.cptr = h->cptr;
+      a.cface = h->cface;
+      a.fptr = h->fptr;
+      a.fvtx = h->fvtx;
+      a.ldof_ptr = h->ldof_ptr;
+      a.csign = h->csign;
+      a.xyz = h->xyz;
+      a.farea = h->f_area;
+      a.fnormal = h->f_normal;
+      a.fcen = h->f_cen;
+      a.fdiam = h->f_diam;
+      a.fe1 = h->f_e1;
+      a.fe2 = h->f_e2;
+      a.cvol = h->c_vol;
+      a.ccen = h->c_cen;
+      a.cdiam = h->c_diam;
+      a.tri_ref = tri;
+      a.FP = FP;
+      a.FM = FM;
+      a.Tf = h->pk_Tf;
+      a.cmom = h->pk_cmom;
+      a.Dg = Dg;
+      a.Pg = Pg;
+      a.Xg = Xg;
+      a.Cg = Cg;
+      a.lmat_ptr = h->lmat_ptr;
+      a.lb_ptr = h->lb_ptr;
+      a.M1 = h->M1;
+      a.Bdiv1 = h->Bdiv1;
+      launch_paper_local(k, a);
+      check_launch();
+      sync(h);  // the scratch buffers are released at the end of this scope
+    }
     launch_ldof_sort(s, L, h->cptr, h->cface, h->ldof_ptr, h->sorted_gid, h->sorted_l);
     check_launch();
 
@@ -781,13 +851,56 @@ vem_status vem_set_rhs(vem_handle h, const double* f_qp, const double* pD_qp) {
     hipStream_t s = h->stream;
     launch_fill(s, h->L.Nu, 0.0, h->rhs);
     DBuf<double> tsum;
-    tsum.alloc(h->ntet);
-    launch_load_tets(s, h->ntet, h->npts_cell, h->qw_cell, h->tet_inc, h->tet_a, h->inc_cell, h->xyz, h->fptr,
-                     h->fvtx, h->cface, h->csign, h->c_xref, f_qp, tsum);
-    launch_load_cells(s, h->nc, h->cell_tet_ptr, tsum, h->rhs.p + h->L.Nu);
-    if (pD_qp)
-      launch_bnd_rhs(s, (int)h->nbf, h->npts_face, h->qw_face, h->bface, h->btri_ptr, h->xyz, h->fptr, h->fvtx,
-                     h->face_cell, pD_qp, h->rhs);
+    if (h->family == VEM_LO) {
+      tsum.alloc(h->ntet);
+      launch_load_tets(s, h->ntet, h->npts_cell, h->qw_cell, h->tet_inc, h->tet_a, h->inc_cell, h->xyz, h->fptr,
+                       h->fvtx, h->cface, h->csign, h->c_xref, f_qp, tsum);
+      launch_load_cells(s, h->nc, h->cell_tet_ptr, tsum, h->rhs.p + h->L.Nu);
+      if (pD_qp)
+        launch_bnd_rhs(s, (int)h->nbf, h->npts_face, h->qw_face, h->bface, h->btri_ptr, h->xyz, h->fptr, h->fvtx,
+                       h->face_cell, pD_qp, h->rhs);
+    } else {
+      tsum.alloc((size_t)h->ntet * h->L.npd);
+      PaperLoadArgs a{};
+      a.s = s;
+      a.nc = h->nc;
+      a.nb = (int)h->nbf;
+      a.npts_cell = h->npts_cell;
+      a.npts_face = h->npts_face;
+      a.ntet = h->ntet;
+      a.ref_cell = h->qref_cell;
+      a.w_cell = h->qw_cell;
+      a.ref_face = h->qref_face;
+      a.w_face = h->qw_face;
+      a.tet_inc = h->tet_inc;
+      a.tet_a = h->tet_a;
+      a.inc_cell = h->inc_cell;
+      a.fptr = h->fptr;
+      a.fvtx = h->fvtx;
+      a.cface = h->cface;
+      a.cell_tet_ptr = h->cell_tet_ptr;
+      a.bface = h->bface;
+      a.btri_ptr = h->btri_ptr;
+      a.face_cell = h->face_cell;
+      a.csign = h->csign;
+      a.xyz = h->xyz;
+      a.xref = h->c_xref;
+      a.ccen = h->c_cen;
+      a.cdiam = h->c_diam;
+      a.cvol = h->c_vol;
+      a.cmom = h->pk_cmom;
+      a.fcen = h->f_cen;
+      a.fdiam = h->f_diam;
+      a.fe1 = h->f_e1;
+      a.fe2 = h->f_e2;
+      a.Tf = h->pk_Tf;
+      a.fq = f_qp;
+      a.pq = pD_qp;
+      a.tet_sum = tsum;
+      a.rhs_p = h->rhs.p + h->L.Nu;
+      a.rhs_u = h->rhs;
+      launch_paper_loads(h->korder, a);
+    }
     check_launch();
     sync(h);
   });

@@ -153,6 +153,39 @@ void launch_lo_local(hipStream_t s, int64_t ninc, const int* inc_cell, const int
                      const double* cvol, const double* ccen, const int64_t* lmat_ptr, double* M1,
                      const int64_t* lb_ptr, double* Bdiv1);
 
+// the paper's order-k element (k = 1, 2, 3)
+struct PaperSizes {
+  int nfd, npd, nint, n3, nsm, nfm, nq;  // face DOFs, pressure DOFs, interior DOFs, 3 dim P_k,
+                                         // cell moments, face integrals per incidence, face rule points
+};
+PaperSizes paper_sizes(int k);
+struct PaperLocalArgs {
+  hipStream_t s;
+  int nf, nc;
+  int64_t ninc;
+  const int *inc_cell, *cptr, *cface, *fptr, *fvtx, *ldof_ptr;
+  const int8_t* csign;
+  const double *xyz, *farea, *fnormal, *fcen, *fdiam, *fe1, *fe2, *cvol, *ccen, *cdiam;
+  const double* tri_ref;  // (xi, eta, w) per point of the face rule with k+1 points per direction
+  double *FP, *FM, *Tf, *cmom;
+  double *Dg, *Pg, *Xg, *Cg;  // per-cell scratch (sum of ndof) x {3 dim P_k, 3 dim P_k, 3 dim P_k, npd}
+  const int64_t *lmat_ptr, *lb_ptr;
+  double *M1, *Bdiv1;
+};
+void launch_paper_local(int k, const PaperLocalArgs& a);
+struct PaperLoadArgs {
+  hipStream_t s;
+  int nc, nb, npts_cell, npts_face;
+  int64_t ntet;
+  const double *ref_cell, *w_cell, *ref_face, *w_face;
+  const int *tet_inc, *tet_a, *inc_cell, *fptr, *fvtx, *cface, *cell_tet_ptr, *bface, *btri_ptr, *face_cell;
+  const int8_t* csign;
+  const double *xyz, *xref, *ccen, *cdiam, *cvol, *cmom, *fcen, *fdiam, *fe1, *fe2, *Tf;
+  const double *fq, *pq;
+  double *tet_sum, *rhs_p, *rhs_u;
+};
+void launch_paper_loads(int k, const PaperLoadArgs& a);
+
 // generic assembly (element described by nfd face DOFs per face, nint interior and npd pressure DOFs per cell)
 struct DofLayout {
   int nf, nc, nfd, nint, npd;

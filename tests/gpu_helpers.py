@@ -36,9 +36,11 @@ def assert_same_csr(G, O, rtol=1e-13):
     Gp.data[:] = 1.0
     Op = O.copy()
     Op.data[:] = 1.0
-    extra = (Gp - Gp.multiply(Op))
+    extra = (Gp - Gp.multiply(Op)).tocsr()
+    extra.eliminate_zeros()
     if extra.nnz:
-        assert np.abs(G.multiply(extra).data).max() <= rtol * scale
+        vals = G.multiply(extra).data
+        assert vals.size == 0 or np.abs(vals).max() <= rtol * scale
 
 
 def rel(a, b):
