@@ -75,6 +75,14 @@ enum { VEM_LO = 0, VEM_PAPER = 1 };
 
 enum { VEM_PREC_SCHUR = 0, VEM_PREC_REG = 1, VEM_PREC_NONE = 2 };
 
+/* Arithmetic of the inner preconditioner solves.  VEM_FP64: everything in
+ * FP64.  VEM_MIXED: the inner Jacobi-CG of either block preconditioner runs
+ * with FP32 vectors and FP32 matrix values (dot products accumulated in
+ * FP64); the outer FGMRES, its residuals, Gram-Schmidt and all assembly stay
+ * FP64, so the outer tolerance is met in FP64 (flexible GMRES absorbs the
+ * FP32 preconditioner as it absorbs any inexact inner solve). */
+enum { VEM_FP64 = 0, VEM_MIXED = 1 };
+
 /* matrices for vem_export_csr */
 enum { VEM_MAT_K = 0, VEM_MAT_SCHUR = 1, VEM_MAT_REG = 2 };
 
@@ -104,6 +112,7 @@ typedef struct {
   int32_t inner_maxit; /* iteration cap of one inner solve */
   int32_t inner_check; /* inner iterations enqueued between convergence checks */
   double gamma;        /* Block-Reg gamma; <= 0 selects h^2 */
+  int32_t precision;   /* VEM_FP64 or VEM_MIXED */
 } vem_solve_opts;
 
 typedef struct {
@@ -116,7 +125,7 @@ typedef struct {
 } vem_solve_info;
 
 /* Fill opts with defaults: Block-Schur, m = 30, maxit = 5000, tol = 1e-8,
- * inner_tol = 1e-6, inner_maxit = 5000, inner_check = 32, gamma = h^2. */
+ * inner_tol = 1e-6, inner_maxit = 5000, inner_check = 32, gamma = h^2, FP64. */
 void vem_solve_opts_default(vem_solve_opts* opts);
 
 /* Create a handle bound to the current HIP device and to `stream`
@@ -189,13 +198,15 @@ vem_status vem_get_geometry(vem_handle h, double* face_area, double* face_normal
                             double* cell_volume, double* cell_centroid, double* cell_diam);
 
 /* Hot kernels that vem_time_kernel can time. */
-enum { VEM_KERNEL_SPMV = 0, VEM_KERNEL_CG_SCHUR = 1, VEM_KERNEL_CG_REG = 2 };
+enum { VEM_KERNEL_SPMV = 0, VEM_KERNEL_CG_SCHUR = 1, VEM_KERNEL_CG_REG = 2, VEM_KERNEL_CG_SCHUR32 = 3,
+       VEM_KERNEL_CG_REG32 = 4 };
 
 /* Measurement hook for benchmarks: time `reps` back-to-back launches of one
  * hot kernel with HIP events recorded on the handle's stream.
  *   VEM_KERNEL_SPMV:     the saddle product y = K x;
  *   VEM_KERNEL_CG_SCHUR: one pipelined inner-CG iteration on S (Block-Schur);
- *   VEM_KERNEL_CG_REG:   one pipelined inner-CG iteration on M + B^T B / gamma.
+ *   VEM_KERNEL_CG_REG:   one pipelined inner-CG iteration on M + B^T B / gamma;
+ *   VEM_KERNEL_CG_SCHUR32, VEM_KERNEL_CG_REG32: the same in FP32 (VEM_MIXED).
  * avg_ms receives the mean duration of one launch; bytes (may be NULL) the
  * algorithmic bytes one launch moves (every matrix entry and every vector
  * element read or written once).  Uses the solver workspace; the results of

@@ -63,6 +63,7 @@ struct vem_ctx {
   Sell Ks, As, Ss;
   DBuf<int> Kdiag, Adiag, Sdiag;
   DBuf<double> dM, dMinv, dAinv, dSinv;
+  DBuf<float> dAinv32, dSinv32;
   double gamma_A = 0.0;
   int expect_S = 0, expect_A = 0;  // last inner-CG iteration counts (chunk sizing)
 
@@ -71,6 +72,7 @@ struct vem_ctx {
   int ws_m = 0;
   DBuf<double> Vb, Zb, xw;
   DBuf<double> pr, pz, ps, pp, pw0, pw1;
+  DBuf<float> px32;
   DBuf<double> partials, pcgpart, scal;
   DBuf<PcgState> pcg;
   HBuf<double> hbuf;
@@ -353,6 +355,8 @@ void rebuild_values(vem_handle h, double gamma) {
   refresh_sell(s, h->S, h->Ss);
   launch_col_scale(s, h->As, h->dAinv);
   launch_col_scale(s, h->Ss, h->dSinv);
+  launch_col_scale32(s, h->As, h->dAinv, h->dAinv32);
+  launch_col_scale32(s, h->Ss, h->dSinv, h->dSinv32);
   check_launch();
   h->gamma_A = gamma;
 }
@@ -370,6 +374,7 @@ void ensure_workspace(vem_handle h, int m) {
   h->pp.alloc(nm);
   h->pw0.alloc(nm);
   h->pw1.alloc(nm);
+  h->px32.alloc(nm);
   h->ws_N = N;
   h->ws_m = m;
 }
@@ -379,23 +384,36 @@ void ensure_workspace(vem_handle h, int m) {
 // enqueued in chunks between convergence checks; the first chunk is sized
 // from the previous solve on the same matrix so that few launches find the
 // solve already converged.  Returns the iterations performed.
-int inner_pcg(vem_handle h, const Sell& A, const double* dinv, const double* b, double* x,
+int inner_pcg(vem_handle h, const Sell& A, const double* dinv, const float* dinv32, const double* b, double* x,
               const vem_solve_opts& o, int& expect) {
   hipStream_t s = h->stream;
+  const bool mixed = o.precision == VEM_MIXED;
   PcgWork w{x, h->pr, h->pz, h->ps, h->pp, h->pw0, h->pw1, dinv};
-  launch_pcg_init(s, A, w, b, h->pcg, o.inner_tol, o.inner_maxit, h->pcgpart);
+  // FP32 vectors live in the first half of the FP64 work buffers
+  PcgWork32 w32{h->px32, (float*)h->pr.p, (float*)h->pz.p, (float*)h->ps.p, (float*)h->pp.p, (float*)h->pw0.p,
+                (float*)h->pw1.p, dinv32};
+  if (mixed)
+    launch_pcg_init32(s, A, w32, b, h->pcg, o.inner_tol, o.inner_maxit, h->pcgpart);
+  else
+    launch_pcg_init(s, A, w, b, h->pcg, o.inner_tol, o.inner_maxit, h->pcgpart);
   check_launch();
   const int step = std::max(1, o.inner_check);
   int chunk = expect > 4 ? (expect * 7) / 8 : step;
   int i = 0;
   for (;;) {
-    for (int c = 0; c < chunk && i < o.inner_maxit; ++c, ++i) launch_pcg_iter(s, i, A, w, h->pcg, h->pcgpart);
+    for (int c = 0; c < chunk && i < o.inner_maxit; ++c, ++i) {
+      if (mixed)
+        launch_pcg_iter32(s, i, A, w32, h->pcg, h->pcgpart);
+      else
+        launch_pcg_iter(s, i, A, w, h->pcg, h->pcgpart);
+    }
     check_launch();
     VEM_HIP(hipMemcpyAsync(h->hpcg.p, h->pcg.p, sizeof(PcgState), hipMemcpyDeviceToHost, s));
     sync(h);
     if (h->hpcg.p->done || i >= o.inner_maxit) break;
     chunk = expect > 4 ? std::max(2, std::min(step, expect / 8)) : step;
   }
+  if (mixed) launch_to_f64(s, A.rows, h->px32, x);
   expect = h->hpcg.p->count;
   return h->hpcg.p->count;
 }
@@ -407,9 +425,9 @@ int64_t apply_prec(vem_handle h, const vem_solve_opts& o, const double* v, doubl
   switch (o.precond) {
     case VEM_PREC_SCHUR:
       launch_scale_by(s, Nu, v, h->dMinv, 1.0, z);
-      return inner_pcg(h, h->Ss, h->dSinv, v + Nu, z + Nu, o, h->expect_S);
+      return inner_pcg(h, h->Ss, h->dSinv, h->dSinv32, v + Nu, z + Nu, o, h->expect_S);
     case VEM_PREC_REG: {
-      int it = inner_pcg(h, h->As, h->dAinv, v, z, o, h->expect_A);
+      int it = inner_pcg(h, h->As, h->dAinv, h->dAinv32, v, z, o, h->expect_A);
       launch_scale_by(s, Np, v + Nu, nullptr, 1.0 / h->gamma_A, z + Nu);
       return it;
     }
@@ -439,6 +457,7 @@ void vem_solve_opts_default(vem_solve_opts* o) {
   o->inner_maxit = 5000;
   o->inner_check = 32;
   o->gamma = 0.0;
+  o->precision = VEM_FP64;
 }
 
 vem_status vem_create(vem_handle* out, void* stream) {
@@ -786,6 +805,8 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
     h->dMinv.alloc(L.Nu);
     h->dAinv.alloc(L.Nu);
     h->dSinv.alloc(L.Np);
+    h->dAinv32.alloc(L.Nu);
+    h->dSinv32.alloc(L.Np);
     h->nu.alloc(nc);
     launch_fill(s, nc, 1.0, h->nu);
     h->rhs.alloc(N);
@@ -961,7 +982,7 @@ vem_status vem_time_kernel(vem_handle h, int which, int reps, double* avg_ms, do
   if (!h || !avg_ms || reps < 1) return VEM_EINVAL;
   return guarded(h, [&] {
     require_disc(h);
-    VEM_REQUIRE(which >= VEM_KERNEL_SPMV && which <= VEM_KERNEL_CG_REG, VEM_EINVAL, "unknown kernel");
+    VEM_REQUIRE(which >= VEM_KERNEL_SPMV && which <= VEM_KERNEL_CG_REG32, VEM_EINVAL, "unknown kernel");
     hipStream_t s = h->stream;
     ensure_workspace(h, std::max(1, h->ws_m));
     const int64_t Nu = h->L.Nu, Np = h->L.Np, N = Nu + Np;
@@ -977,22 +998,39 @@ vem_status vem_time_kernel(vem_handle h, int which, int reps, double* avg_ms, do
         VEM_HIP(hipEventRecord(e1, s));
         b = 12.0 * h->K.nnz + 8.0 * N + 8.0 * N;  // matrix, x once, y once
       } else {
-        Sell& A = which == VEM_KERNEL_CG_SCHUR ? h->Ss : h->As;
-        const Csr& C = which == VEM_KERNEL_CG_SCHUR ? h->S : h->A;
-        const double* dinv = which == VEM_KERNEL_CG_SCHUR ? h->dSinv.p : h->dAinv.p;
+        const bool schur = which == VEM_KERNEL_CG_SCHUR || which == VEM_KERNEL_CG_SCHUR32;
+        const bool f32 = which == VEM_KERNEL_CG_SCHUR32 || which == VEM_KERNEL_CG_REG32;
+        Sell& A = schur ? h->Ss : h->As;
+        const Csr& C = schur ? h->S : h->A;
+        const double* dinv = schur ? h->dSinv.p : h->dAinv.p;
+        const float* dinv32 = schur ? h->dSinv32.p : h->dAinv32.p;
         // a constant right-hand side: never zero, whatever the loads are
         launch_fill(s, A.rows, 1.0, h->Vb);
         const double* rhs = h->Vb;
         PcgWork w{h->xw.p, h->pr, h->pz, h->ps, h->pp, h->pw0, h->pw1, dinv};
+        PcgWork32 w32{h->px32, (float*)h->pr.p, (float*)h->pz.p, (float*)h->ps.p, (float*)h->pp.p,
+                      (float*)h->pw0.p, (float*)h->pw1.p, dinv32};
         // tol = 0: the solve never stops, every timed launch does a full iteration
-        launch_pcg_init(s, A, w, rhs, h->pcg, 0.0, INT_MAX, h->pcgpart);
-        launch_pcg_iter(s, 0, A, w, h->pcg, h->pcgpart);
-        launch_pcg_iter(s, 1, A, w, h->pcg, h->pcgpart);
-        VEM_HIP(hipEventRecord(e0, s));
-        for (int r = 0; r < reps; ++r) launch_pcg_iter(s, 2 + r, A, w, h->pcg, h->pcgpart);
-        VEM_HIP(hipEventRecord(e1, s));
-        // matrix once; w gathered; dinv, r, z, s, p, x read; z, s, p, x, r, w written
-        b = 12.0 * C.nnz + 8.0 * C.rows * 13.0;
+        if (f32) {
+          launch_pcg_init32(s, A, w32, rhs, h->pcg, 0.0, INT_MAX, h->pcgpart);
+          launch_pcg_iter32(s, 0, A, w32, h->pcg, h->pcgpart);
+          launch_pcg_iter32(s, 1, A, w32, h->pcg, h->pcgpart);
+          VEM_HIP(hipEventRecord(e0, s));
+          for (int r = 0; r < reps; ++r) launch_pcg_iter32(s, 2 + r, A, w32, h->pcg, h->pcgpart);
+          VEM_HIP(hipEventRecord(e1, s));
+          // one classical CG iteration (two launches): FP32 values + int32 columns once; z and p
+          // gathered, p and Ap written; x, r, Ap, p, D^{-1} read and x, r, z written (12 FP32 accesses per row)
+          b = 8.0 * C.nnz + 4.0 * C.rows * 12.0;
+        } else {
+          launch_pcg_init(s, A, w, rhs, h->pcg, 0.0, INT_MAX, h->pcgpart);
+          launch_pcg_iter(s, 0, A, w, h->pcg, h->pcgpart);
+          launch_pcg_iter(s, 1, A, w, h->pcg, h->pcgpart);
+          VEM_HIP(hipEventRecord(e0, s));
+          for (int r = 0; r < reps; ++r) launch_pcg_iter(s, 2 + r, A, w, h->pcg, h->pcgpart);
+          VEM_HIP(hipEventRecord(e1, s));
+          // matrix once; w gathered; dinv, r, z, s, p, x read; z, s, p, x, r, w written
+          b = 12.0 * C.nnz + 8.0 * C.rows * 13.0;
+        }
       }
       check_launch();
       VEM_HIP(hipEventSynchronize(e1));
@@ -1028,6 +1066,7 @@ vem_status vem_solve(vem_handle h, const vem_solve_opts* opts, double* u, double
     VEM_REQUIRE(o.tol > 0 && o.maxit >= 1, VEM_EINVAL, "tol must be > 0 and maxit >= 1");
     VEM_REQUIRE(o.precond >= VEM_PREC_SCHUR && o.precond <= VEM_PREC_NONE, VEM_EINVAL, "unknown preconditioner");
     VEM_REQUIRE(o.inner_tol > 0 && o.inner_maxit >= 1, VEM_EINVAL, "inner_tol must be > 0 and inner_maxit >= 1");
+    VEM_REQUIRE(o.precision == VEM_FP64 || o.precision == VEM_MIXED, VEM_EINVAL, "unknown precision mode");
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = h->stream;
     const int m = o.restart;

@@ -76,24 +76,28 @@ inline int red_grid(int64_t n) {
 }
 
 // ---- SELL-64 SpMV: one thread per row -------------------------------------------------------
-struct SellView {
+template <typename T>
+struct SellViewT {
   int64_t rows;
   const int* __restrict__ slice_ptr;
   const int* __restrict__ slice_len;
   const int* __restrict__ col;
-  const double* __restrict__ val;
+  const T* __restrict__ val;
 };
+using SellView = SellViewT<double>;
 
 inline SellView view(const Sell& A) { return {A.rows, A.slice_ptr, A.slice_len, A.col, A.val}; }
 
 // Whole waves share a slice because every block size here is a multiple of 64.
-__device__ inline double sell_dot(const SellView& A, int64_t row, const double* __restrict__ x) {
+// The product is formed in the matrix's precision T from x of type X.
+template <typename T, typename X>
+__device__ inline T sell_dot(const SellViewT<T>& A, int64_t row, const X* __restrict__ x) {
   const int64_t s = row >> 6;
   const int64_t base = A.slice_ptr[s] + (row & 63);
   const int len = A.slice_len[s];
-  double acc = 0.0;
+  T acc = T(0);
 #pragma unroll 4
-  for (int k = 0; k < len; ++k) acc += A.val[base + 64 * k] * x[A.col[base + 64 * k]];
+  for (int k = 0; k < len; ++k) acc += A.val[base + 64 * k] * (T)x[A.col[base + 64 * k]];
   return acc;
 }
 
@@ -236,31 +240,34 @@ __global__ void k_sum(int64_t n, const double* __restrict__ x, double* partials)
 //   n = (A D^{-1}) w,  z = n + beta z,  s = w + beta s,  p = D^{-1} r + beta p,
 //   x += alpha p,  r -= alpha s,  w -= alpha z.
 // The stopping test is gamma_i <= tol^2 gamma_0, as for the plain algorithm.
-struct PcgView {
-  double* __restrict__ x;
-  double* __restrict__ r;
-  double* __restrict__ z;
-  double* __restrict__ s;
-  double* __restrict__ p;
-  double* __restrict__ w0;
-  double* __restrict__ w1;
-  const double* __restrict__ dinv;
+template <typename T>
+struct PcgViewT {
+  T* __restrict__ x;
+  T* __restrict__ r;
+  T* __restrict__ z;
+  T* __restrict__ s;
+  T* __restrict__ p;
+  T* __restrict__ w0;
+  T* __restrict__ w1;
+  const T* __restrict__ dinv;
 };
 
-// w = (A D^{-1}) b, x = 0, r = b; partials of gamma_0, delta_0 (slot 0)
-__global__ void __launch_bounds__(kPcgThreads) k_ppcg_init(SellView Ac, PcgView v, const double* __restrict__ b,
-                                                           PcgState* st, double tol2, int maxit,
-                                                           double* __restrict__ part) {
+// w = (A D^{-1}) b, x = 0, r = b; partials of gamma_0, delta_0 (slot 0).  b is FP64 and is
+// rounded to T element by element (also where it is gathered).
+template <typename T>
+__global__ void __launch_bounds__(kPcgThreads) k_ppcg_init(SellViewT<T> Ac, PcgViewT<T> v,
+                                                           const double* __restrict__ b, PcgState* st, double tol2,
+                                                           int maxit, double* __restrict__ part) {
   double acc[2] = {0.0, 0.0};
   for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < Ac.rows;
        row += (int64_t)gridDim.x * blockDim.x) {
-    const double bi = b[row], di = v.dinv[row];
-    const double wi = sell_dot(Ac, row, b);
-    v.x[row] = 0.0;
+    const T bi = (T)b[row], di = v.dinv[row];
+    const T wi = sell_dot(Ac, row, b);
+    v.x[row] = T(0);
     v.r[row] = bi;
     v.w0[row] = wi;
-    acc[0] += bi * bi * di;
-    acc[1] += wi * bi * di;
+    acc[0] += (double)bi * (double)bi * (double)di;
+    acc[1] += (double)wi * (double)bi * (double)di;
   }
   block_partials<2>(acc, part);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -274,8 +281,9 @@ __global__ void __launch_bounds__(kPcgThreads) k_ppcg_init(SellView Ac, PcgView 
   }
 }
 
-template <bool kFirst>
-__global__ void __launch_bounds__(kPcgThreads) k_ppcg_iter(int parity, SellView Ac, PcgView v, PcgState* st,
+// One pipelined CG iteration.  Vectors and matrix values in T; scalars and dot products in FP64.
+template <typename T, bool kFirst>
+__global__ void __launch_bounds__(kPcgThreads) k_ppcg_iter(int parity, SellViewT<T> Ac, PcgViewT<T> v, PcgState* st,
                                                            double* __restrict__ part) {
   if (st->done) return;
   const int P = gridDim.x;
@@ -303,36 +311,153 @@ __global__ void __launch_bounds__(kPcgThreads) k_ppcg_iter(int parity, SellView 
     if (done) st->done = done;
   }
   if (done) return;
-  const double* __restrict__ win = cur ? v.w1 : v.w0;
-  double* __restrict__ wout = cur ? v.w0 : v.w1;
+  const T a = (T)alpha, bt = (T)beta;
+  const T* __restrict__ win = cur ? v.w1 : v.w0;
+  T* __restrict__ wout = cur ? v.w0 : v.w1;
   double acc[2] = {0.0, 0.0};
   for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < Ac.rows;
        row += (int64_t)gridDim.x * blockDim.x) {
-    const double n = sell_dot(Ac, row, win);
-    const double wi = win[row], di = v.dinv[row], ri = v.r[row];
-    double zz, ss, pp;
+    const T n = sell_dot(Ac, row, win);
+    const T wi = win[row], di = v.dinv[row], ri = v.r[row];
+    T zz, ss, pp;
     if (kFirst) {
       zz = n;
       ss = wi;
       pp = di * ri;
     } else {
-      zz = n + beta * v.z[row];
-      ss = wi + beta * v.s[row];
-      pp = di * ri + beta * v.p[row];
+      zz = n + bt * v.z[row];
+      ss = wi + bt * v.s[row];
+      pp = di * ri + bt * v.p[row];
     }
     v.z[row] = zz;
     v.s[row] = ss;
     v.p[row] = pp;
-    v.x[row] += alpha * pp;
-    const double rn = ri - alpha * ss;
-    const double wn = wi - alpha * zz;
+    v.x[row] += a * pp;
+    const T rn = ri - a * ss;
+    const T wn = wi - a * zz;
     v.r[row] = rn;
     wout[row] = wn;
-    acc[0] += rn * rn * di;
-    acc[1] += wn * rn * di;
+    acc[0] += (double)rn * (double)rn * (double)di;
+    acc[1] += (double)wn * (double)rn * (double)di;
   }
   block_partials<2>(acc, part + (size_t)(1 - cur) * 2 * P);
   if (blockIdx.x == 0 && threadIdx.x == 0) st->count += 1;
+}
+
+// ---- classical Jacobi-PCG in FP32 (mixed-precision inner solves) --------------------------
+// alpha = rho / p.Ap stays positive for an SPD matrix, which the pipelined
+// recurrences do not guarantee once FP32 rounding meets an ill-conditioned
+// operator.  Two kernels per iteration; the direction update p = z + beta p
+// is fused into the product through two p buffers, and every kernel sums the
+// partials the previous one left.  Vectors and matrix values in T (FP32),
+// dot products and scalars in FP64.
+//   [spmv]   rho_k, beta = rho_k / rho_{k-1}; stop test; p_k = z + beta p_{k-1}; q = A p_k; partials p_k.q
+//   [update] alpha = rho_k / p_k.q; x += alpha p_k; r -= alpha q; z = D^{-1} r; partials rho_{k+1}
+template <typename T>
+__global__ void __launch_bounds__(kPcgThreads) k_cg_init(int64_t n, const double* __restrict__ b,
+                                                         const T* __restrict__ dinv, T* __restrict__ x,
+                                                         T* __restrict__ r, T* __restrict__ z, PcgState* st,
+                                                         double tol2, double* __restrict__ prho0) {
+  double acc[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const T bi = (T)b[i], zi = dinv[i] * bi;
+    x[i] = T(0);
+    r[i] = bi;
+    z[i] = zi;
+    acc[0] += (double)bi * (double)zi;
+  }
+  block_partials<1>(acc, prho0);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->gamma[0] = st->gamma[1] = 0.0;
+    st->gamma0 = 0.0;
+    st->tol2 = tol2;
+    st->count = 0;
+    st->done = 0;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kPcgThreads) k_cg_spmv(int k, SellViewT<T> A, const T* __restrict__ z,
+                                                         const T* __restrict__ pold, T* __restrict__ pnew,
+                                                         T* __restrict__ q, PcgState* st,
+                                                         const double* __restrict__ prho, double* __restrict__ ppq) {
+  if (st->done) return;
+  const int P = gridDim.x;
+  const int cur = k & 1;
+  const double rho = block_sum_partials(prho + (size_t)cur * P, P, 1, 0);
+  const double rho0 = k == 0 ? rho : st->gamma0;
+  const double beta = k == 0 ? 0.0 : rho / st->gamma[1 - cur];
+  const bool done = !(rho > st->tol2 * rho0);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (k == 0) st->gamma0 = rho0;
+    st->gamma[cur] = rho;
+    if (done) st->done = 1;
+  }
+  if (done) return;
+  const T bt = (T)beta;
+  double acc[1] = {0.0};
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < A.rows;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t sl = row >> 6;
+    const int64_t base = A.slice_ptr[sl] + (row & 63);
+    const int len = A.slice_len[sl];
+    T s = T(0), pn;
+    if (k == 0) {
+#pragma unroll 4
+      for (int j = 0; j < len; ++j) s += A.val[base + 64 * j] * z[A.col[base + 64 * j]];
+      pn = z[row];
+    } else {
+#pragma unroll 4
+      for (int j = 0; j < len; ++j) {
+        const int c = A.col[base + 64 * j];
+        s += A.val[base + 64 * j] * (z[c] + bt * pold[c]);
+      }
+      pn = z[row] + bt * pold[row];
+    }
+    pnew[row] = pn;
+    q[row] = s;
+    acc[0] += (double)pn * (double)s;
+  }
+  block_partials<1>(acc, ppq);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kPcgThreads) k_cg_update(int k, int64_t n, T* __restrict__ x, T* __restrict__ r,
+                                                           T* __restrict__ z, const T* __restrict__ q,
+                                                           const T* __restrict__ p, const T* __restrict__ dinv,
+                                                           PcgState* st, double* __restrict__ prho,
+                                                           const double* __restrict__ ppq) {
+  if (st->done) return;
+  const int P = gridDim.x;
+  const int cur = k & 1;
+  const double rho = block_sum_partials(prho + (size_t)cur * P, P, 1, 0);
+  const double pq = block_sum_partials(ppq, P, 1, 0);
+  if (!(pq > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->done = 2;
+    return;
+  }
+  const T a = (T)(rho / pq);
+  double acc[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] += a * p[i];
+    const T ri = r[i] - a * q[i];
+    r[i] = ri;
+    const T zi = dinv[i] * ri;
+    z[i] = zi;
+    acc[0] += (double)ri * (double)zi;
+  }
+  block_partials<1>(acc, prho + (size_t)(1 - cur) * P);
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->count += 1;
+}
+
+__global__ void k_to_f32(int64_t n, const double* __restrict__ x, float* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+
+__global__ void k_to_f64(int64_t n, const float* __restrict__ x, double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (double)x[i];
 }
 
 __global__ void k_col_scale(int64_t n, const int* __restrict__ col, const double* __restrict__ val,
@@ -450,21 +575,53 @@ void launch_col_scale(hipStream_t s, Sell& A, const double* dinv) {
   k_col_scale<<<stream_grid(A.nnz), kThreads, 0, s>>>(A.nnz, A.col, A.val, dinv, A.val_cs);
 }
 
-static PcgView pview(const PcgWork& w) { return {w.x, w.r, w.z, w.s, w.p, w.w0, w.w1, w.dinv}; }
+template <typename T>
+static PcgViewT<T> pview(const PcgWorkT<T>& w) {
+  return {w.x, w.r, w.z, w.s, w.p, w.w0, w.w1, w.dinv};
+}
 
 static SellView view_cs(const Sell& A) { return {A.rows, A.slice_ptr, A.slice_len, A.col, A.val_cs}; }
+static SellViewT<float> view32(const Sell& A) { return {A.rows, A.slice_ptr, A.slice_len, A.col, A.val32}; }
+
+void launch_col_scale32(hipStream_t s, Sell& A, const double* dinv, float* dinv32) {
+  if (A.nnz <= 0) return;
+  A.val32.alloc(A.nnz);
+  k_to_f32<<<stream_grid(A.nnz), kThreads, 0, s>>>(A.nnz, A.val, A.val32);
+  k_to_f32<<<stream_grid(A.rows), kThreads, 0, s>>>(A.rows, dinv, dinv32);
+}
+
+void launch_to_f64(hipStream_t s, int64_t n, const float* x, double* y) {
+  if (n > 0) k_to_f64<<<stream_grid(n), kThreads, 0, s>>>(n, x, y);
+}
 
 void launch_pcg_init(hipStream_t s, const Sell& A, const PcgWork& w, const double* b, PcgState* st, double tol,
                      int maxit, double* part) {
-  k_ppcg_init<<<pcg_grid(A.rows), kPcgThreads, 0, s>>>(view_cs(A), pview(w), b, st, tol * tol, maxit, part);
+  k_ppcg_init<double><<<pcg_grid(A.rows), kPcgThreads, 0, s>>>(view_cs(A), pview(w), b, st, tol * tol, maxit, part);
 }
 
 void launch_pcg_iter(hipStream_t s, int i, const Sell& A, const PcgWork& w, PcgState* st, double* part) {
   const int P = pcg_grid(A.rows);
   if (i == 0)
-    k_ppcg_iter<true><<<P, kPcgThreads, 0, s>>>(0, view_cs(A), pview(w), st, part);
+    k_ppcg_iter<double, true><<<P, kPcgThreads, 0, s>>>(0, view_cs(A), pview(w), st, part);
   else
-    k_ppcg_iter<false><<<P, kPcgThreads, 0, s>>>(i & 1, view_cs(A), pview(w), st, part);
+    k_ppcg_iter<double, false><<<P, kPcgThreads, 0, s>>>(i & 1, view_cs(A), pview(w), st, part);
+}
+
+void launch_pcg_init32(hipStream_t s, const Sell& A, const PcgWork32& w, const double* b, PcgState* st, double tol,
+                       int maxit, double* part) {
+  (void)maxit;
+  k_cg_init<float><<<pcg_grid(A.rows), kPcgThreads, 0, s>>>(A.rows, b, w.dinv, w.x, w.r, w.z, st, tol * tol, part);
+}
+
+// FP32 work layout: r, z as named; s and p hold the two direction buffers, w0 holds A p
+void launch_pcg_iter32(hipStream_t s, int i, const Sell& A, const PcgWork32& w, PcgState* st, double* part) {
+  const int P = pcg_grid(A.rows);
+  double* prho = part;  // 2 x P slots
+  double* ppq = part + 2 * (size_t)P;
+  float* pold = (i & 1) ? w.p : w.s;
+  float* pnew = (i & 1) ? w.s : w.p;
+  k_cg_spmv<float><<<P, kPcgThreads, 0, s>>>(i, view32(A), w.z, pold, pnew, w.w0, st, prho, ppq);
+  k_cg_update<float><<<P, kPcgThreads, 0, s>>>(i, A.rows, w.x, w.r, w.z, w.w0, pnew, w.dinv, st, prho, ppq);
 }
 
 }  // namespace vem

@@ -93,11 +93,14 @@ struct PcgState {
   int count, maxit, done, pad;
 };
 
-// Vectors of one inner CG solve (x is the solution).
-struct PcgWork {
-  double *x, *r, *z, *s, *p, *w0, *w1;
-  const double* dinv;
+// Vectors of one inner CG solve (x is the solution), FP64 or FP32.
+template <typename T>
+struct PcgWorkT {
+  T *x, *r, *z, *s, *p, *w0, *w1;
+  const T* dinv;
 };
+using PcgWork = PcgWorkT<double>;
+using PcgWork32 = PcgWorkT<float>;
 
 // Compressed sparse row matrix on the device.
 struct Csr {
@@ -111,7 +114,8 @@ struct Sell {
   int64_t rows = 0, nslices = 0, nnz = 0;
   DBuf<int> slice_ptr, slice_len, col, src;
   DBuf<double> val;
-  DBuf<double> val_cs;  // column-scaled copy A D^{-1} (inner CG matrices only)
+  DBuf<double> val_cs;   // column-scaled copy A D^{-1} (inner CG matrices only)
+  DBuf<float> val32;     // FP32 rounding of val (mixed-precision inner solves)
 };
 void build_sell(hipStream_t s, const Csr& A, Sell& S);
 void refresh_sell(hipStream_t s, const Csr& A, Sell& S);
@@ -232,6 +236,13 @@ void launch_col_scale(hipStream_t s, Sell& A, const double* dinv);
 void launch_pcg_init(hipStream_t s, const Sell& A, const PcgWork& w, const double* b, PcgState* st, double tol,
                      int maxit, double* part);
 void launch_pcg_iter(hipStream_t s, int i, const Sell& A, const PcgWork& w, PcgState* st, double* part);
+// FP32 inner CG: classical Jacobi-PCG on FP32 copies of the matrix values and of D^{-1}, FP32 vectors,
+// dot products accumulated in FP64 (launch_col_scale32 makes the FP32 copies)
+void launch_col_scale32(hipStream_t s, Sell& A, const double* dinv, float* dinv32);
+void launch_pcg_init32(hipStream_t s, const Sell& A, const PcgWork32& w, const double* b, PcgState* st, double tol,
+                       int maxit, double* part);
+void launch_pcg_iter32(hipStream_t s, int i, const Sell& A, const PcgWork32& w, PcgState* st, double* part);
+void launch_to_f64(hipStream_t s, int64_t n, const float* x, double* y);
 
 // host utilities
 void gauss_jacobi01(int n, int alpha, double* t, double* w);  // int_0^1 (1-t)^alpha g(t) dt

@@ -43,6 +43,7 @@ class SolveOpts(ctypes.Structure):
         ("precond", ctypes.c_int32), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32),
         ("use_x0", ctypes.c_int32), ("tol", c_double), ("inner_tol", c_double),
         ("inner_maxit", ctypes.c_int32), ("inner_check", ctypes.c_int32), ("gamma", c_double),
+        ("precision", ctypes.c_int32),
     ]
 
 
@@ -192,7 +193,7 @@ class Solver:
         self.set_rhs(fv, pv)
 
     def solve(self, precond="schur", tol=1e-8, restart=30, maxit=5000, inner_tol=1e-6, inner_maxit=5000,
-              inner_check=32, gamma=0.0, x0=None):
+              inner_check=32, gamma=0.0, x0=None, precision="fp64"):
         t = self.torch
         sz = self.sizes()
         o = SolveOpts()
@@ -201,6 +202,7 @@ class Solver:
         o.restart, o.maxit, o.tol = int(restart), int(maxit), float(tol)
         o.inner_tol, o.inner_maxit, o.inner_check = float(inner_tol), int(inner_maxit), int(inner_check)
         o.gamma = float(gamma)
+        o.precision = {"fp64": 0, "mixed": 1}[precision]
         if x0 is not None:
             u = self._dev(x0[0], t.float64).clone()
             p = self._dev(x0[1], t.float64).clone()
@@ -240,7 +242,7 @@ class Solver:
 
     def time_kernel(self, which="cg_schur", reps=50):
         """Mean duration (ms) of one launch of a hot kernel, timed with HIP events, and its algorithmic bytes."""
-        code = {"spmv": 0, "cg_schur": 1, "cg_reg": 2}[which]
+        code = {"spmv": 0, "cg_schur": 1, "cg_reg": 2, "cg_schur32": 3, "cg_reg32": 4}[which]
         ms, nb = c_double(), c_double()
         self._check(self.lib.vem_time_kernel(self.h, code, int(reps), byref(ms), byref(nb)))
         return ms.value, nb.value

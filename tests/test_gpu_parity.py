@@ -158,3 +158,24 @@ def test_error_paths():
     with pytest.raises(VemError) as e:
         s.solve()
     assert e.value.code == -6
+
+
+@pytest.mark.parametrize("precond", ["schur", "reg"])
+def test_mixed_precision_inner_solves(precond):
+    """FP32 inner CG under FP64 FGMRES: the FP64 outer residual test still reaches the tolerance,
+    and the solution agrees with the oracle's FP64 direct solve to the tolerance times the
+    conditioning of this small system."""
+    _say("mixed", precond)
+    m = cube_mesh(6, 7, 5)
+    nu = 1.0 / lognormal_field(210, 2.0, 0)
+    s = gpu_solver(m, nu=nu, rhs=SineSolution())
+    u, p, info = s.solve(precond=precond, tol=1e-10, maxit=3000, inner_tol=1e-3, precision="mixed")
+    assert info["converged"], info
+    d = discretize(m, nu=nu, rhs=SineSolution())
+    xg = np.concatenate([u.cpu().numpy(), p.cpu().numpy()])
+    berr = np.linalg.norm(d["b"] - d["K"] @ xg) / np.linalg.norm(d["b"])
+    assert berr <= 1.01e-10
+    x = direct_solve(d["K"], d["b"])
+    _say(info, berr, rel(xg[: d["Nu"]], x[: d["Nu"]]), rel(xg[d["Nu"]:], x[d["Nu"]:]))
+    assert rel(xg[: d["Nu"]], x[: d["Nu"]]) <= 1e-7
+    assert rel(xg[d["Nu"]:], x[d["Nu"]:]) <= 1e-7
