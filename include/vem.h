@@ -181,6 +181,20 @@ vem_status vem_set_rhs(vem_handle h, const double* f_qp, const double* pD_qp);
  * iterate written), or an error.  info may be NULL. */
 vem_status vem_solve(vem_handle h, const vem_solve_opts* opts, double* u, double* p, vem_solve_info* info);
 
+/* Solve K x = rhs for a caller-supplied right-hand side (device, n
+ * doubles) instead of the assembled [g; -F]; otherwise as vem_solve.  K is
+ * symmetric, so this is also the adjoint solve K^T lambda = dJ/dx of a
+ * functional J of the solution (same operator, same preconditioners). */
+vem_status vem_solve_rhs(vem_handle h, const vem_solve_opts* opts, const double* rhs, double* u, double* p,
+                         vem_solve_info* info);
+
+/* Per-cell derivative for the adjoint method (Section 4.3: M_P = nu_P M1_P
+ * with nu piecewise constant): g[P] = nu_P lambda_P^T M1_P u_P, with u_P and
+ * lambda_P the cell's oriented local flux DOFs of the device vectors u and
+ * lam (n_u doubles each).  For nu = exp(-log K) and K x = b, a functional J
+ * of x with K lambda = dJ/dx has dJ/d(log K_P) = g[P].  g: device, n_cells. */
+vem_status vem_coefficient_gradient(vem_handle h, const double* u, const double* lam, double* g);
+
 /* y = K x for device vectors of length n (test hook for the saddle SpMV). */
 vem_status vem_apply(vem_handle h, const double* x, double* y);
 

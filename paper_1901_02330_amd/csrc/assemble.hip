@@ -339,6 +339,35 @@ __global__ void k_schur_values(DofLayout L, const int* __restrict__ cptr, const 
   }
 }
 
+// g[P] = nu_P lambda_P^T M1_P u_P over the cell's oriented local flux DOFs (one wavefront per cell)
+__global__ void __launch_bounds__(64) k_coef_grad(DofLayout L, const int* __restrict__ cptr,
+                                                  const int* __restrict__ cface, const int8_t* __restrict__ csign,
+                                                  const int64_t* __restrict__ lmat_ptr,
+                                                  const double* __restrict__ M1, const double* __restrict__ nu,
+                                                  const double* __restrict__ u, const double* __restrict__ lam,
+                                                  double* __restrict__ g) {
+  const int P = blockIdx.x;
+  if (P >= L.nc) return;
+  const int nd = ndof_of(L, cptr, P);
+  const double* M = M1 + lmat_ptr[P];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nd; i += 64) {
+    int gi;
+    double si;
+    ldof_gid_sign(L, cptr, cface, csign, P, i, gi, si);
+    double t = 0.0;
+    for (int j = 0; j < nd; ++j) {
+      int gj;
+      double sj;
+      ldof_gid_sign(L, cptr, cface, csign, P, j, gj, sj);
+      t += M[(int64_t)i * nd + j] * sj * u[gj];
+    }
+    acc += si * lam[gi] * t;
+  }
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if (threadIdx.x == 0) g[P] = nu[P] * acc;
+}
+
 __global__ void k_cell_sizes(DofLayout L, const int* __restrict__ cptr, int64_t* ndof, int64_t* nmat,
                              int64_t* nb) {
   int P = blockIdx.x * blockDim.x + threadIdx.x;
@@ -350,6 +379,12 @@ __global__ void k_cell_sizes(DofLayout L, const int* __restrict__ cptr, int64_t*
 }
 
 }  // namespace
+
+void launch_coef_grad(hipStream_t s, DofLayout L, const int* cptr, const int* cface, const int8_t* csign,
+                      const int64_t* lmat_ptr, const double* M1, const double* nu, const double* u,
+                      const double* lam, double* g) {
+  if (L.nc > 0) k_coef_grad<<<L.nc, 64, 0, s>>>(L, cptr, cface, csign, lmat_ptr, M1, nu, u, lam, g);
+}
 
 void launch_cell_sizes(hipStream_t s, DofLayout L, const int* cptr, int64_t* ndof, int64_t* nmat, int64_t* nb) {
   k_cell_sizes<<<nblocks(L.nc), kThreads, 0, s>>>(L, cptr, ndof, nmat, nb);

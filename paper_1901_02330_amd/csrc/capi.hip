@@ -1052,11 +1052,15 @@ vem_status vem_time_kernel(vem_handle h, int which, int reps, double* avg_ms, do
   });
 }
 
-vem_status vem_solve(vem_handle h, const vem_solve_opts* opts, double* u, double* p, vem_solve_info* info) {
+}  // extern "C"
+
+static vem_status solve_impl(vem_handle h, const vem_solve_opts* opts, const double* user_rhs, double* u, double* p,
+                             vem_solve_info* info) {
   if (!h || !u || !p) return VEM_EINVAL;
   vem_status result = VEM_OK;
   vem_status st = guarded(h, [&] {
     require_disc(h);
+    const double* rhs = user_rhs ? user_rhs : h->rhs.p;
     vem_solve_opts o;
     if (opts)
       o = *opts;
@@ -1086,7 +1090,7 @@ vem_status vem_solve(vem_handle h, const vem_solve_opts* opts, double* u, double
     double* hb = h->hbuf.p;
 
     // ||b||
-    launch_dots(s, N, 1, h->rhs, N, h->rhs, h->partials, dn);
+    launch_dots(s, N, 1, rhs, N, rhs, h->partials, dn);
     check_launch();
     VEM_HIP(hipMemcpyAsync(hb, dn, sizeof(double), hipMemcpyDeviceToHost, s));
     sync(h);
@@ -1104,7 +1108,7 @@ vem_status vem_solve(vem_handle h, const vem_solve_opts* opts, double* u, double
       launch_fill(s, N, 0.0, x);
     }
     // r0 = b - K x0
-    launch_residual(s, h->Ks, x, h->rhs, V, h->partials, dn);
+    launch_residual(s, h->Ks, x, rhs, V, h->partials, dn);
     check_launch();
     VEM_HIP(hipMemcpyAsync(hb, dn, sizeof(double), hipMemcpyDeviceToHost, s));
     sync(h);
@@ -1176,7 +1180,7 @@ vem_status vem_solve(vem_handle h, const vem_solve_opts* opts, double* u, double
         launch_combine(s, N, jend, Z, N, dy, x);
       }
       ++restarts;
-      launch_residual(s, h->Ks, x, h->rhs, V, h->partials, dn);
+      launch_residual(s, h->Ks, x, rhs, V, h->partials, dn);
       check_launch();
       VEM_HIP(hipMemcpyAsync(hb, dn, sizeof(double), hipMemcpyDeviceToHost, s));
       sync(h);
@@ -1206,6 +1210,27 @@ vem_status vem_solve(vem_handle h, const vem_solve_opts* opts, double* u, double
     if (info) *info = inf;
   });
   return st != VEM_OK ? st : result;
+}
+
+extern "C" {
+
+vem_status vem_solve(vem_handle h, const vem_solve_opts* opts, double* u, double* p, vem_solve_info* info) {
+  return solve_impl(h, opts, nullptr, u, p, info);
+}
+
+vem_status vem_solve_rhs(vem_handle h, const vem_solve_opts* opts, const double* rhs, double* u, double* p,
+                         vem_solve_info* info) {
+  if (!rhs) return VEM_EINVAL;
+  return solve_impl(h, opts, rhs, u, p, info);
+}
+
+vem_status vem_coefficient_gradient(vem_handle h, const double* u, const double* lam, double* g) {
+  if (!h || !u || !lam || !g) return VEM_EINVAL;
+  return guarded(h, [&] {
+    require_disc(h);
+    launch_coef_grad(h->stream, h->L, h->cptr, h->cface, h->csign, h->lmat_ptr, h->M1, h->nu, u, lam, g);
+    check_launch();
+  });
 }
 
 }  // extern "C"

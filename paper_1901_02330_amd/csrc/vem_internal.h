@@ -204,6 +204,9 @@ void launch_fill_patterns(hipStream_t s, DofLayout L, const int* cptr, const int
                           int* Kdiag, const int* Aptr, int* Acol, int* Adiag, const int* Sptr, int* Scol,
                           int* Sdiag);
 void launch_cell_sizes(hipStream_t s, DofLayout L, const int* cptr, int64_t* ndof, int64_t* nmat, int64_t* nb);
+void launch_coef_grad(hipStream_t s, DofLayout L, const int* cptr, const int* cface, const int8_t* csign,
+                      const int64_t* lmat_ptr, const double* M1, const double* nu, const double* u,
+                      const double* lam, double* g);
 void launch_values(hipStream_t s, DofLayout L, const int* cptr, const int* cface, const int8_t* csign,
                    const int* ldof_ptr, const int* sorted_gid, const int* sorted_l, const int* face_cell,
                    const int* face_lidx, const int64_t* lmat_ptr, const double* M1, const int64_t* lb_ptr,

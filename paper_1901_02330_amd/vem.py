@@ -87,6 +87,8 @@ def load():
         "vem_last_error": ([H], c_char_p),
         "vem_solve_opts_default": ([POINTER(SolveOpts)], None),
         "vem_time_kernel": ([H, c_int, c_int, POINTER(c_double), POINTER(c_double)], c_int),
+        "vem_solve_rhs": ([H, POINTER(SolveOpts), P, P, P, POINTER(SolveInfo)], c_int),
+        "vem_coefficient_gradient": ([H, P, P, P], c_int),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -193,7 +195,7 @@ class Solver:
         self.set_rhs(fv, pv)
 
     def solve(self, precond="schur", tol=1e-8, restart=30, maxit=5000, inner_tol=1e-6, inner_maxit=5000,
-              inner_check=32, gamma=0.0, x0=None, precision="fp64"):
+              inner_check=32, gamma=0.0, x0=None, precision="fp64", rhs=None):
         t = self.torch
         sz = self.sizes()
         o = SolveOpts()
@@ -211,10 +213,24 @@ class Solver:
             u = t.empty(sz["n_u"], dtype=t.float64, device=self.device)
             p = t.empty(sz["n_p"], dtype=t.float64, device=self.device)
         info = SolveInfo()
-        code = self._check(self.lib.vem_solve(self.h, byref(o), _ptr(u), _ptr(p), byref(info)))
+        if rhs is None:
+            code = self._check(self.lib.vem_solve(self.h, byref(o), _ptr(u), _ptr(p), byref(info)))
+        else:
+            rhs = self._dev(rhs, t.float64)
+            assert rhs.numel() == sz["n"]
+            code = self._check(self.lib.vem_solve_rhs(self.h, byref(o), _ptr(rhs), _ptr(u), _ptr(p), byref(info)))
         out = {f: getattr(info, f) for f, _ in SolveInfo._fields_}
         out["converged"] = code == 0
         return u, p, out
+
+    def coefficient_gradient(self, u, lam):
+        """g[P] = nu_P lambda_P^T M1_P u_P (flux parts u, lam of length n_u)."""
+        t = self.torch
+        u = self._dev(u, t.float64)
+        lam = self._dev(lam, t.float64)
+        g = t.empty(self.sizes()["n_cells"], dtype=t.float64, device=self.device)
+        self._check(self.lib.vem_coefficient_gradient(self.h, _ptr(u), _ptr(lam), _ptr(g)))
+        return g
 
     def apply(self, x):
         t = self.torch
@@ -269,4 +285,5 @@ EXPORTED = [
     "vem_solve_opts_default", "vem_create", "vem_destroy", "vem_set_mesh", "vem_discretize", "vem_get_sizes",
     "vem_get_quadrature", "vem_set_coefficient", "vem_set_rhs", "vem_solve", "vem_apply", "vem_export_csr",
     "vem_get_rhs", "vem_get_geometry", "vem_status_string", "vem_last_error", "vem_time_kernel",
+    "vem_solve_rhs", "vem_coefficient_gradient",
 ]
