@@ -113,6 +113,8 @@ typedef struct {
   int32_t inner_check; /* inner iterations enqueued between convergence checks */
   double gamma;        /* Block-Reg gamma; <= 0 selects h^2 */
   int32_t precision;   /* VEM_FP64 or VEM_MIXED */
+  int32_t use_graphs;  /* nonzero: replay the inner-CG iterations as a captured HIP graph (same
+                          kernels and arguments, identical results; inner_maxit rounded up to 8) */
 } vem_solve_opts;
 
 typedef struct {
@@ -125,7 +127,8 @@ typedef struct {
 } vem_solve_info;
 
 /* Fill opts with defaults: Block-Schur, m = 30, maxit = 5000, tol = 1e-8,
- * inner_tol = 1e-6, inner_maxit = 5000, inner_check = 32, gamma = h^2, FP64. */
+ * inner_tol = 1e-6, inner_maxit = 5000, inner_check = 32, gamma = h^2, FP64,
+ * graphs on. */
 void vem_solve_opts_default(vem_solve_opts* opts);
 
 /* Create a handle bound to the current HIP device and to `stream`

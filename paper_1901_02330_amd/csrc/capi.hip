@@ -19,7 +19,29 @@
 
 using namespace vem;
 
+// A captured run of kGraphIters inner-CG iterations (parities fixed by position), replayed on the
+// handle's stream; `key` records the buffers it references so that it is re-captured when they move.
+constexpr int kGraphIters = 8;
+struct InnerGraph {
+  hipGraphExec_t exec = nullptr;
+  const void* key[8] = {};
+  InnerGraph() = default;
+  InnerGraph(const InnerGraph&) = delete;
+  InnerGraph& operator=(const InnerGraph&) = delete;
+  ~InnerGraph() { reset(); }
+  void reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    exec = nullptr;
+  }
+};
+
 struct vem_ctx {
+  ~vem_ctx() {
+    for (InnerGraph* g : {&gS, &gA, &gS32, &gA32}) g->reset();
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+  InnerGraph gS, gA, gS32, gA32;
+  hipStream_t cap = nullptr;  // private stream used only to capture graphs
   hipStream_t stream = nullptr;
   int device = 0;
   std::string last_error;
@@ -71,7 +93,7 @@ struct vem_ctx {
   int64_t ws_N = 0;
   int ws_m = 0;
   DBuf<double> Vb, Zb, xw;
-  DBuf<double> pr, pz, ps, pp, pw0, pw1;
+  DBuf<double> pr, pz, ps, pp, pw0, pw1, pxw;
   DBuf<float> px32;
   DBuf<double> partials, pcgpart, scal;
   DBuf<PcgState> pcg;
@@ -375,37 +397,88 @@ void ensure_workspace(vem_handle h, int m) {
   h->pw0.alloc(nm);
   h->pw1.alloc(nm);
   h->px32.alloc(nm);
+  h->pxw.alloc(nm);
   h->ws_N = N;
   h->ws_m = m;
 }
 
-// Inner Jacobi-CG: x ~ A^{-1} b.  Returns the iterations used.
-// Inner pipelined Jacobi-CG: x ~ A^{-1} b to inner_tol.  Iterations are
-// enqueued in chunks between convergence checks; the first chunk is sized
-// from the previous solve on the same matrix so that few launches find the
-// solve already converged.  Returns the iterations performed.
+// The graph of kGraphIters iterations (2 .. 2+kGraphIters-1) for this matrix and precision,
+// captured on the private stream on first use or when a referenced buffer moved.
+hipGraphExec_t inner_graph(vem_handle h, const Sell& A, const PcgWork& w, const PcgWork32& w32, bool mixed,
+                           InnerGraph& g) {
+  const void* key[8] = {mixed ? (const void*)A.val32.p : (const void*)A.val_cs.p, A.col.p, h->pr.p, h->pcg.p,
+                        mixed ? (const void*)h->px32.p : (const void*)w.x, mixed ? (const void*)w32.dinv : w.dinv,
+                        (const void*)(intptr_t)A.rows, (const void*)(intptr_t)A.nnz};
+  if (g.exec && std::equal(key, key + 8, g.key)) return g.exec;
+  g.reset();
+  if (!h->cap) VEM_HIP(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+  VEM_HIP(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+  hipGraph_t graph = nullptr;
+  try {
+    for (int t = 0; t < kGraphIters; ++t) {
+      if (mixed)
+        launch_pcg_iter32(h->cap, 2 + t, A, w32, h->pcg, h->pcgpart);
+      else
+        launch_pcg_iter(h->cap, 2 + t, A, w, h->pcg, h->pcgpart);
+    }
+  } catch (...) {
+    (void)hipStreamEndCapture(h->cap, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    throw;
+  }
+  VEM_HIP(hipStreamEndCapture(h->cap, &graph));
+  hipError_t e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    g.exec = nullptr;
+    throw Error{VEM_EHIP, std::string("hipGraphInstantiate failed: ") + hipGetErrorString(e)};
+  }
+  std::copy(key, key + 8, g.key);
+  return g.exec;
+}
+
+// Inner Jacobi-CG: x ~ A^{-1} b to inner_tol (pipelined in FP64, classical in FP32).
+// Iterations are enqueued in chunks between convergence checks; the first
+// chunk is sized from the previous solve on the same matrix so that few
+// launches find the solve already converged.  With graphs, iterations 0 and
+// 1 are launched directly and the rest by replaying a captured run of
+// kGraphIters iterations (inner_maxit is then rounded up to that length);
+// the iterate is formed in a fixed workspace and copied to x.  Returns the
+// iterations performed.
 int inner_pcg(vem_handle h, const Sell& A, const double* dinv, const float* dinv32, const double* b, double* x,
-              const vem_solve_opts& o, int& expect) {
+              const vem_solve_opts& o, int& expect, InnerGraph& g64, InnerGraph& g32) {
   hipStream_t s = h->stream;
   const bool mixed = o.precision == VEM_MIXED;
-  PcgWork w{x, h->pr, h->pz, h->ps, h->pp, h->pw0, h->pw1, dinv};
+  const bool graphs = o.use_graphs != 0;
+  PcgWork w{graphs ? h->pxw.p : x, h->pr, h->pz, h->ps, h->pp, h->pw0, h->pw1, dinv};
   // FP32 vectors live in the first half of the FP64 work buffers
   PcgWork32 w32{h->px32, (float*)h->pr.p, (float*)h->pz.p, (float*)h->ps.p, (float*)h->pp.p, (float*)h->pw0.p,
                 (float*)h->pw1.p, dinv32};
+  hipGraphExec_t exec = graphs ? inner_graph(h, A, w, w32, mixed, mixed ? g32 : g64) : nullptr;
   if (mixed)
     launch_pcg_init32(s, A, w32, b, h->pcg, o.inner_tol, o.inner_maxit, h->pcgpart);
   else
     launch_pcg_init(s, A, w, b, h->pcg, o.inner_tol, o.inner_maxit, h->pcgpart);
   check_launch();
+  auto one = [&](int i) {
+    if (mixed)
+      launch_pcg_iter32(s, i, A, w32, h->pcg, h->pcgpart);
+    else
+      launch_pcg_iter(s, i, A, w, h->pcg, h->pcgpart);
+  };
   const int step = std::max(1, o.inner_check);
   int chunk = expect > 4 ? (expect * 7) / 8 : step;
   int i = 0;
   for (;;) {
-    for (int c = 0; c < chunk && i < o.inner_maxit; ++c, ++i) {
-      if (mixed)
-        launch_pcg_iter32(s, i, A, w32, h->pcg, h->pcgpart);
-      else
-        launch_pcg_iter(s, i, A, w, h->pcg, h->pcgpart);
+    const int stop = std::min(o.inner_maxit, i + chunk);
+    while (i < stop) {
+      if (exec && i >= 2) {
+        VEM_HIP(hipGraphLaunch(exec, s));
+        i += kGraphIters;
+      } else {
+        one(i);
+        ++i;
+      }
     }
     check_launch();
     VEM_HIP(hipMemcpyAsync(h->hpcg.p, h->pcg.p, sizeof(PcgState), hipMemcpyDeviceToHost, s));
@@ -413,7 +486,10 @@ int inner_pcg(vem_handle h, const Sell& A, const double* dinv, const float* dinv
     if (h->hpcg.p->done || i >= o.inner_maxit) break;
     chunk = expect > 4 ? std::max(2, std::min(step, expect / 8)) : step;
   }
-  if (mixed) launch_to_f64(s, A.rows, h->px32, x);
+  if (mixed)
+    launch_to_f64(s, A.rows, h->px32, x);
+  else if (graphs)
+    launch_copy(s, A.rows, h->pxw, x);
   expect = h->hpcg.p->count;
   return h->hpcg.p->count;
 }
@@ -425,9 +501,9 @@ int64_t apply_prec(vem_handle h, const vem_solve_opts& o, const double* v, doubl
   switch (o.precond) {
     case VEM_PREC_SCHUR:
       launch_scale_by(s, Nu, v, h->dMinv, 1.0, z);
-      return inner_pcg(h, h->Ss, h->dSinv, h->dSinv32, v + Nu, z + Nu, o, h->expect_S);
+      return inner_pcg(h, h->Ss, h->dSinv, h->dSinv32, v + Nu, z + Nu, o, h->expect_S, h->gS, h->gS32);
     case VEM_PREC_REG: {
-      int it = inner_pcg(h, h->As, h->dAinv, h->dAinv32, v, z, o, h->expect_A);
+      int it = inner_pcg(h, h->As, h->dAinv, h->dAinv32, v, z, o, h->expect_A, h->gA, h->gA32);
       launch_scale_by(s, Np, v + Nu, nullptr, 1.0 / h->gamma_A, z + Nu);
       return it;
     }
@@ -458,6 +534,7 @@ void vem_solve_opts_default(vem_solve_opts* o) {
   o->inner_check = 32;
   o->gamma = 0.0;
   o->precision = VEM_FP64;
+  o->use_graphs = 1;
 }
 
 vem_status vem_create(vem_handle* out, void* stream) {

@@ -43,7 +43,7 @@ class SolveOpts(ctypes.Structure):
         ("precond", ctypes.c_int32), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32),
         ("use_x0", ctypes.c_int32), ("tol", c_double), ("inner_tol", c_double),
         ("inner_maxit", ctypes.c_int32), ("inner_check", ctypes.c_int32), ("gamma", c_double),
-        ("precision", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("use_graphs", ctypes.c_int32),
     ]
 
 
@@ -195,7 +195,7 @@ class Solver:
         self.set_rhs(fv, pv)
 
     def solve(self, precond="schur", tol=1e-8, restart=30, maxit=5000, inner_tol=1e-6, inner_maxit=5000,
-              inner_check=32, gamma=0.0, x0=None, precision="fp64", rhs=None):
+              inner_check=32, gamma=0.0, x0=None, precision="fp64", rhs=None, graphs=True):
         t = self.torch
         sz = self.sizes()
         o = SolveOpts()
@@ -205,6 +205,7 @@ class Solver:
         o.inner_tol, o.inner_maxit, o.inner_check = float(inner_tol), int(inner_maxit), int(inner_check)
         o.gamma = float(gamma)
         o.precision = {"fp64": 0, "mixed": 1}[precision]
+        o.use_graphs = 1 if graphs else 0
         if x0 is not None:
             u = self._dev(x0[0], t.float64).clone()
             p = self._dev(x0[1], t.float64).clone()

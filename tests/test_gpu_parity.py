@@ -179,3 +179,24 @@ def test_mixed_precision_inner_solves(precond):
     _say(info, berr, rel(xg[: d["Nu"]], x[: d["Nu"]]), rel(xg[d["Nu"]:], x[d["Nu"]:]))
     assert rel(xg[: d["Nu"]], x[: d["Nu"]]) <= 1e-7
     assert rel(xg[d["Nu"]:], x[d["Nu"]:]) <= 1e-7
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replays_match_eager(precision):
+    """Inner-CG iterations replayed from a captured HIP graph give the same bits as direct launches,
+    over several solves with eager work and synchronisations in between."""
+    import torch
+
+    _say("graphs", precision)
+    m = cube_mesh(9, 8, 7)
+    nu = 1.0 / lognormal_field(9 * 8 * 7, 2.0, 3)
+    s = gpu_solver(m, nu=nu, rhs=SineSolution())
+    for precond in ("schur", "reg"):
+        ue, pe, ie = s.solve(precond=precond, tol=1e-10, inner_tol=1e-4, precision=precision, graphs=False)
+        for rep in range(3):
+            y = s.apply(torch.cat([ue, pe]))  # eager work between replays
+            torch.cuda.synchronize()
+            ug, pg, ig = s.solve(precond=precond, tol=1e-10, inner_tol=1e-4, precision=precision, graphs=True)
+            assert ig["iterations"] == ie["iterations"]
+            assert torch.equal(ug, ue) and torch.equal(pg, pe), (precond, rep)
+            assert torch.isfinite(y).all()
