@@ -44,8 +44,13 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=64, help="cells per direction of the Cube mesh")
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--schur-inner-tol", type=float, default=1e-2)
+    ap.add_argument("--schur-inner-tol", type=float, default=1e-12)
+    ap.add_argument("--schur-inner-maxit", type=int, default=32)
     ap.add_argument("--reg-inner-tol", type=float, default=1e-1)
+    ap.add_argument("--no-extras", action="store_true", help="skip the adjoint / mixed / batch / 128^3 measurements")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="short run for rocprofv3 --pmc: discretize, 20 launches of each hot kernel, and a plain "
+                         "256 MiB device copy that calibrates FETCH_SIZE / WRITE_SIZE")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=32, help="Cube size of the CPU oracle sample")
     ap.add_argument("--summarize", metavar="PREFIX", default=None,
@@ -86,6 +91,24 @@ def summarize(prefix: str):
     print("\n".join(out))
 
 
+def traffic_from_profiles():
+    """HBM bytes per launch of the dominant kernel from the committed counter summary, if it was
+    taken on the current kernel source (its hash is recorded there); else None."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic_k_ppcg_iter_cube64_lo.md")
+    src = os.path.join(ROOT, "paper_1901_02330_amd", "csrc", "krylov.hip")
+    if not os.path.exists(path):
+        return None
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    for line in open(path):
+        if line.startswith("{") and '"traffic"' in line:
+            rec = json.loads(line)
+            if rec.get("krylov_hip_sha256_16") == digest:
+                return rec["traffic"]
+    return None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -124,6 +147,132 @@ def cpu_baseline(n_gpu: int, n_cpu: int):
     }
 
 
+def pmc_probe(mesh, n):
+    """Counter run: a plain copy of known size, then 20 launches of each hot kernel (one
+    dispatch each), so that per-dispatch FETCH_SIZE / WRITE_SIZE can be scaled by the copy's."""
+    import torch
+
+    from paper_1901_02330_amd.inputs import SineSolution, lognormal_field
+    from paper_1901_02330_amd.vem import Solver
+
+    src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")  # 256 MiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    s = Solver()
+    s.set_mesh(mesh)
+    s.discretize("lo", load_points=3)
+    s.set_coefficient(torch.as_tensor(1.0 / lognormal_field(n**3, 2.0, 0), device="cuda"))
+    s.set_rhs_functions(SineSolution.f, SineSolution.pD)
+    for which in ("cg_reg", "cg_schur", "spmv"):
+        ms, nb = s.time_kernel(which, reps=20)
+        log(f"{which}: {ms * 1e3:.1f} us, algorithmic {nb / 1e6:.1f} MB")
+    print(json.dumps({"probe": "done", "copy_bytes": 2 * src.numel() * 8}), flush=True)
+
+
+def extras(args, torch, dev):
+    """Measurements outside the timed region (each states its own workload)."""
+    import numpy as np
+
+    from paper_1901_02330_amd.adjoint import solve_logk
+    from paper_1901_02330_amd.batch import BatchSolver, percentiles
+    from paper_1901_02330_amd.inputs import SineSolution, cube_mesh, lognormal_field
+    from paper_1901_02330_amd.vem import Solver
+
+    out = {}
+    # adjoint: Cube 48^3, log K ~ N(0,1) seed 0, p_obs from the seed-1 field, J = 1/2 ||p - p_obs||^2
+    m48 = cube_mesh(48)
+    s = Solver()
+    s.set_mesh(m48)
+    s.discretize("lo")
+    s.set_rhs_functions(SineSolution.f, SineSolution.pD)
+    kw = dict(precond="schur", tol=1e-10, inner_tol=1e-12, inner_maxit=32)
+    s.set_coefficient(torch.as_tensor(1.0 / lognormal_field(48**3, 1.0, 1), device=dev))
+    _, p_obs, _ = s.solve(**kw)
+    logk = torch.tensor(np.log(lognormal_field(48**3, 1.0, 0)), dtype=torch.float64, device=dev,
+                        requires_grad=True)
+    ts = []
+    for _ in range(3):
+        logk.grad = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, p = solve_logk(s, logk, **kw)
+        J = 0.5 * torch.sum((p - p_obs) ** 2)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        J.backward()
+        torch.cuda.synchronize()
+        ts.append((t1 - t0, time.perf_counter() - t1))
+    fw, bw = min(t[0] for t in ts), min(t[1] for t in ts)
+    out["adjoint_cube48"] = {"forward_s": fw, "backward_s": bw, "backward_over_forward": bw / fw,
+                             "note": "forward = set coefficient + Block-Schur solve to 1e-10; backward = adjoint "
+                                     "solve + per-cell gradient kernel"}
+    s.close()
+    # mixed precision on the headline workload, error against the FP64 GPU solution
+    n = args.n
+    s = Solver()
+    s.set_mesh(cube_mesh(n))
+    s.discretize("lo")
+    s.set_coefficient(torch.as_tensor(1.0 / lognormal_field(n**3, 2.0, 0), device=dev))
+    s.set_rhs_functions(SineSolution.f, SineSolution.pD)
+    mixed = {}
+    for prec, kwp in (("schur", dict(inner_tol=1e-12, inner_maxit=32)), ("reg", dict(inner_tol=1e-1))):
+        u64, p64, i64 = s.solve(prec, tol=1e-10, **kwp)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u32, p32, i32 = s.solve(prec, tol=1e-10, precision="mixed", **kwp)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        u64b, p64b, _ = s.solve(prec, tol=1e-10, **kwp)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        mixed[prec] = {"mixed_s": t1 - t0, "fp64_s": t2 - t1, "mixed_iterations": i32["iterations"],
+                       "fp64_iterations": i64["iterations"], "mixed_relres": i32["relres"],
+                       "rel_err_u_vs_fp64": float(torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64)),
+                       "rel_err_p_vs_fp64": float(torch.linalg.norm(p32 - p64) / torch.linalg.norm(p64))}
+    out["mixed_precision_cube64_tol1e-10"] = mixed
+    s.close()
+    # batched: 16 log-normal fields (sigma 1.5, seeds 0..15) on the 64^3 mesh, Block-Schur
+    nus = [torch.as_tensor(1.0 / lognormal_field(n**3, 1.5, sd), device=dev) for sd in range(16)]
+    torch.cuda.synchronize()
+    bat = {}
+    for lanes in (1, 8):
+        bs = BatchSolver(cube_mesh(n), lanes=lanes, rhs=SineSolution())
+        bs.solve(nus[:lanes], precond="schur", tol=1e-8, inner_tol=1e-12, inner_maxit=32)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, infos = bs.solve(nus, precond="schur", tol=1e-8, inner_tol=1e-12, inner_maxit=32)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        bat[f"lanes{lanes}"] = {"solves_per_s": len(nus) / wall, "wall_s": wall, **percentiles(infos)}
+        bs.close()
+    out["batch_cube64_16fields"] = bat
+    # one 128^3 solve (8.4M unknowns), log-normal sigma 1.5 seed 0
+    s = Solver()
+    m128 = cube_mesh(128)
+    mdev = {k: torch.as_tensor(m128[k]).to(dev) for k in
+            ("xyz", "face_ptr", "face_vtx", "cell_ptr", "cell_face", "cell_face_sign")}
+    nu128 = torch.as_tensor(1.0 / lognormal_field(128**3, 1.5, 0), device=dev)
+    big = {}
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.set_mesh(mdev)
+        s.discretize("lo")
+        s.set_coefficient(nu128)
+        s.set_rhs_functions(SineSolution.f, SineSolution.pD)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        u, p, info = s.solve("schur", tol=1e-8, inner_tol=1e-12, inner_maxit=32)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        big = {"n_unknowns": s.sizes()["n"], "assembly_s": t1 - t0, "solve_schur_s": t2 - t1,
+               "iterations": info["iterations"], "relres": info["relres"]}
+    out["cube128_lo"] = big
+    s.close()
+    return out
+
+
 def main():
     args = parse()
     if args.summarize:
@@ -142,6 +291,9 @@ def main():
     torch.cuda.set_device(dev)
     n = args.n
     mesh = cube_mesh(n)
+    if args.pmc_probe:
+        pmc_probe(mesh, n)
+        return
     # inputs resident in HBM before the timed region
     mdev = {k: torch.as_tensor(mesh[k]).to(dev) for k in
             ("xyz", "face_ptr", "face_vtx", "cell_ptr", "cell_face", "cell_face_sign")}
@@ -157,7 +309,8 @@ def main():
         solver.set_rhs_functions(SineSolution.f, SineSolution.pD)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        u, p, i_s = solver.solve("schur", tol=args.tol, inner_tol=args.schur_inner_tol)
+        u, p, i_s = solver.solve("schur", tol=args.tol, inner_tol=args.schur_inner_tol,
+                                 inner_maxit=args.schur_inner_maxit)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         u2, p2, i_r = solver.solve("reg", tol=args.tol, inner_tol=args.reg_inner_tol, maxit=5000)
@@ -231,6 +384,13 @@ def main():
         },
         "kernels": kern,
     }
+    if not args.no_extras:
+        log("extras ...")
+        line["extras"] = extras(args, torch, dev)
+    tr = traffic_from_profiles()
+    if tr is not None:
+        line["roofline"]["traffic"] = tr["bytes_per_launch"]
+        line["roofline"]["traffic_note"] = tr["note"]
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         line["cpu_baseline"] = cpu_baseline(n, args.cpu_n)
