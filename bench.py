@@ -53,6 +53,8 @@ def parse():
                          "256 MiB device copy that calibrates FETCH_SIZE / WRITE_SIZE")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=32, help="Cube size of the CPU oracle sample")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
+                    help="print the HBM-traffic summary of two rocprofv3 --pmc runs of --pmc-probe and exit")
     ap.add_argument("--summarize", metavar="PREFIX", default=None,
                     help="print a markdown summary of rocprofv3 CSV output PREFIX_kernel_stats.csv / "
                          "PREFIX_kernel_trace.csv and exit")
@@ -73,8 +75,9 @@ def summarize(prefix: str):
                    f"`{r['Name'][:80]}` |")
     trace = prefix + "_kernel_trace.csv"
     if os.path.exists(trace):
-        out += ["", "Per launch grid (threads) of the hot kernels; 'working' launches exclude the ones that found",
-                "their solve already converged and returned at once (< 5 us):", "",
+        out += ["", "Per launch grid (threads) of the hot kernels; 'working' excludes launches under 5 us. A launch",
+                "enqueued after its inner solve converged still loads its operands before it reads the stop",
+                "flag, so such launches take 7-12 us and are counted as working:", "",
                 "| kernel | grid | launches | working | avg working us | median us |", "|---|---|---|---|---|---|"]
         by = {}
         for r in csv.DictReader(open(trace)):
@@ -88,6 +91,14 @@ def summarize(prefix: str):
             w = [d for d in ds if d > 5.0] or ds
             out.append(f"| `{name}` | {g} | {len(ds)} | {len(w)} | {sum(w) / len(w):.2f} | "
                        f"{statistics.median(w):.2f} |")
+        # the live timing loop (vem_time_kernel "cg_reg", 200 launches) runs after the solves: the last
+        # 200 launches of the pipelined iteration with the largest grid
+        it = [k for k in by if k[0].startswith("k_ppcg_iter") and "false" in k[0]]
+        if it:
+            key = max(it, key=lambda k: k[1])
+            last = by[key][-200:]
+            out += ["", f"Last {len(last)} launches of `{key[0]}` at grid {key[1]} (the timing loop): "
+                    f"mean {sum(last) / len(last):.2f} us, median {statistics.median(last):.2f} us."]
     print("\n".join(out))
 
 
@@ -155,19 +166,79 @@ def pmc_probe(mesh, n):
     from paper_1901_02330_amd.inputs import SineSolution, lognormal_field
     from paper_1901_02330_amd.vem import Solver
 
-    src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")  # 256 MiB
+    src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")  # 512 MiB, twice the MALL
     dst = torch.empty_like(src)
-    dst.copy_(src)
+    torch.neg(src, out=dst)  # one elementwise kernel: 512 MiB read, 512 MiB written
     torch.cuda.synchronize()
     s = Solver()
     s.set_mesh(mesh)
     s.discretize("lo", load_points=3)
     s.set_coefficient(torch.as_tensor(1.0 / lognormal_field(n**3, 2.0, 0), device="cuda"))
     s.set_rhs_functions(SineSolution.f, SineSolution.pD)
+    rec = {"copy_read_bytes": src.numel() * 8, "copy_write_bytes": src.numel() * 8, "kernels": {}}
     for which in ("cg_reg", "cg_schur", "spmv"):
         ms, nb = s.time_kernel(which, reps=20)
         log(f"{which}: {ms * 1e3:.1f} us, algorithmic {nb / 1e6:.1f} MB")
-    print(json.dumps({"probe": "done", "copy_bytes": 2 * src.numel() * 8}), flush=True)
+        rec["kernels"][which] = {"avg_us": ms * 1e3, "algorithmic_bytes": nb}
+    print(json.dumps(rec), flush=True)
+
+
+def summarize_pmc(fetch_dir: str, write_dir: str):
+    """HBM traffic per launch from two rocprofv3 --pmc runs of --pmc-probe (FETCH_SIZE, then
+    WRITE_SIZE; both in KiB per dispatch), each scaled by what the same counter reads for the
+    probe's plain 512 MiB elementwise copy."""
+    import csv
+    import glob
+    import hashlib
+    import statistics
+
+    def per_kernel(d, counter):
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        by = {}
+        for f in files:
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] != counter:
+                    continue
+                mt = re.search(r"(k_[A-Za-z0-9_]+(?:<[^>]*>)?)\(", r["Kernel_Name"])
+                name = mt.group(1) if mt else ("copy" if "neg" in r["Kernel_Name"] else None)
+                if name is None:
+                    continue
+                by.setdefault((name, int(r["Grid_Size"])), []).append(float(r["Counter_Value"]) * 1024.0)
+        return by
+
+    fetch, write = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+    probe = json.loads(open(os.path.join(fetch_dir, "probe.json")).read())
+    cf = [v for (n, _), vs in fetch.items() if n == "copy" for v in vs]
+    cw = [v for (n, _), vs in write.items() if n == "copy" for v in vs]
+    f_fetch = probe["copy_read_bytes"] / statistics.median(cf)
+    f_write = probe["copy_write_bytes"] / statistics.median(cw)
+    out = ["Calibration (plain 512 MiB elementwise copy): FETCH_SIZE reads "
+           f"{statistics.median(cf) / 2**20:.1f} MiB (factor {f_fetch:.4f}), WRITE_SIZE "
+           f"{statistics.median(cw) / 2**20:.1f} MiB (factor {f_write:.4f}).", "",
+           "| kernel | grid (threads) | dispatches | fetch MB (scaled) | write MB (scaled) | total MB |",
+           "|---|---|---|---|---|---|"]
+    rows = {}
+    for key in sorted(set(fetch) & set(write)):
+        if key[0] == "copy" or not any(k in key[0] for k in ("k_ppcg_iter", "k_spmv", "k_cg_")):
+            continue
+        fm = statistics.median(fetch[key]) * f_fetch
+        wm = statistics.median(write[key]) * f_write
+        rows[key] = (fm, wm)
+        out.append(f"| `{key[0]}` | {key[1]} | {len(fetch[key])} | {fm / 1e6:.1f} | {wm / 1e6:.1f} | "
+                   f"{(fm + wm) / 1e6:.1f} |")
+    # the dominant kernel: pipelined CG iteration on M + B^T B / gamma (the larger k_ppcg_iter grid)
+    it = sorted((k for k in rows if k[0] == "k_ppcg_iter<double, false>"), key=lambda k: -k[1])
+    fm, wm = rows[it[0]]
+    alg = probe["kernels"]["cg_reg"]["algorithmic_bytes"]
+    src = os.path.join(ROOT, "paper_1901_02330_amd", "csrc", "krylov.hip")
+    rec = {"traffic": {"bytes_per_launch": fm + wm, "fetch_bytes": fm, "write_bytes": wm,
+                       "algorithmic_bytes": alg, "ratio_to_algorithmic": (fm + wm) / alg,
+                       "note": "FETCH_SIZE + WRITE_SIZE of k_ppcg_iter on M + B^T B/gamma, cube 64^3 LO, "
+                               "scaled by a 512 MiB copy; counts L2-to-fabric traffic (MALL hits included)"},
+           "krylov_hip_sha256_16": hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]}
+    out += ["", f"Algorithmic bytes per launch of the dominant kernel: {alg / 1e6:.1f} MB; measured "
+            f"{(fm + wm) / 1e6:.1f} MB ({(fm + wm) / alg:.3f}x).", "", json.dumps(rec)]
+    print("\n".join(out))
 
 
 def extras(args, torch, dev):
@@ -275,11 +346,14 @@ def extras(args, torch, dev):
 
 def main():
     args = parse()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
     if args.summarize:
         summarize(args.summarize)
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (the design note on sharding "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (the design note on sharding "
               "describes how it would split); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch

@@ -109,12 +109,14 @@ typedef struct {
   int32_t use_x0;      /* nonzero: u, p hold the initial guess */
   double tol;          /* stop when ||b - K x||_2 <= tol ||b||_2 */
   double inner_tol;    /* relative tolerance of the inner Jacobi-CG (preconditioned residual) */
-  int32_t inner_maxit; /* iteration cap of one inner solve */
-  int32_t inner_check; /* inner iterations enqueued between convergence checks */
+  int32_t inner_maxit; /* iteration cap of one inner solve.  A cap <= 64 enqueues all of them
+                          without host polling (launches after the stop test return at once) */
+  int32_t inner_check; /* inner iterations enqueued between convergence checks (cap > 64) */
   double gamma;        /* Block-Reg gamma; <= 0 selects h^2 */
   int32_t precision;   /* VEM_FP64 or VEM_MIXED */
   int32_t use_graphs;  /* nonzero: replay the inner-CG iterations as a captured HIP graph (same
-                          kernels and arguments, identical results; inner_maxit rounded up to 8) */
+                          kernels and arguments, identical results; a cap > 64 may be passed
+                          by up to 7 iterations, as graphs run 8 at a time) */
 } vem_solve_opts;
 
 typedef struct {

@@ -22,6 +22,8 @@ using namespace vem;
 // A captured run of kGraphIters inner-CG iterations (parities fixed by position), replayed on the
 // handle's stream; `key` records the buffers it references so that it is re-captured when they move.
 constexpr int kGraphIters = 8;
+// inner solves capped at this many iterations run without host polling
+constexpr int kBlindInner = 64;
 struct InnerGraph {
   hipGraphExec_t exec = nullptr;
   const void* key[8] = {};
@@ -445,8 +447,8 @@ hipGraphExec_t inner_graph(vem_handle h, const Sell& A, const PcgWork& w, const 
 // kGraphIters iterations (inner_maxit is then rounded up to that length);
 // the iterate is formed in a fixed workspace and copied to x.  Returns the
 // iterations performed.
-int inner_pcg(vem_handle h, const Sell& A, const double* dinv, const float* dinv32, const double* b, double* x,
-              const vem_solve_opts& o, int& expect, InnerGraph& g64, InnerGraph& g32) {
+void inner_pcg(vem_handle h, const Sell& A, const double* dinv, const float* dinv32, const double* b, double* x,
+               const vem_solve_opts& o, int& expect, InnerGraph& g64, InnerGraph& g32) {
   hipStream_t s = h->stream;
   const bool mixed = o.precision == VEM_MIXED;
   const bool graphs = o.use_graphs != 0;
@@ -466,6 +468,27 @@ int inner_pcg(vem_handle h, const Sell& A, const double* dinv, const float* dinv
     else
       launch_pcg_iter(s, i, A, w, h->pcg, h->pcgpart);
   };
+  if (o.inner_maxit <= kBlindInner) {
+    // A small cap: enqueue every iteration without looking at the state.  Once the
+    // stop test fires, the remaining launches return at once; the iteration count is
+    // summed on the device (PcgState::total) and read when the outer solve ends.
+    int i = 0;
+    while (i < o.inner_maxit) {
+      if (exec && i >= 2 && i + kGraphIters <= o.inner_maxit) {
+        VEM_HIP(hipGraphLaunch(exec, s));
+        i += kGraphIters;
+      } else {
+        one(i);
+        ++i;
+      }
+    }
+    check_launch();
+    if (mixed)
+      launch_to_f64(s, A.rows, h->px32, x);
+    else if (graphs)
+      launch_copy(s, A.rows, h->pxw, x);
+    return;
+  }
   const int step = std::max(1, o.inner_check);
   int chunk = expect > 4 ? (expect * 7) / 8 : step;
   int i = 0;
@@ -491,25 +514,23 @@ int inner_pcg(vem_handle h, const Sell& A, const double* dinv, const float* dinv
   else if (graphs)
     launch_copy(s, A.rows, h->pxw, x);
   expect = h->hpcg.p->count;
-  return h->hpcg.p->count;
 }
 
 // z = P^{-1} v for the chosen block preconditioner
-int64_t apply_prec(vem_handle h, const vem_solve_opts& o, const double* v, double* z) {
+void apply_prec(vem_handle h, const vem_solve_opts& o, const double* v, double* z) {
   hipStream_t s = h->stream;
   const int64_t Nu = h->L.Nu, Np = h->L.Np;
   switch (o.precond) {
     case VEM_PREC_SCHUR:
       launch_scale_by(s, Nu, v, h->dMinv, 1.0, z);
-      return inner_pcg(h, h->Ss, h->dSinv, h->dSinv32, v + Nu, z + Nu, o, h->expect_S, h->gS, h->gS32);
-    case VEM_PREC_REG: {
-      int it = inner_pcg(h, h->As, h->dAinv, h->dAinv32, v, z, o, h->expect_A, h->gA, h->gA32);
+      inner_pcg(h, h->Ss, h->dSinv, h->dSinv32, v + Nu, z + Nu, o, h->expect_S, h->gS, h->gS32);
+      return;
+    case VEM_PREC_REG:
+      inner_pcg(h, h->As, h->dAinv, h->dAinv32, v, z, o, h->expect_A, h->gA, h->gA32);
       launch_scale_by(s, Np, v + Nu, nullptr, 1.0 / h->gamma_A, z + Nu);
-      return it;
-    }
+      return;
     default:
       launch_copy(s, Nu + Np, v, z);
-      return 0;
   }
 }
 
@@ -1166,6 +1187,8 @@ static vem_status solve_impl(vem_handle h, const vem_solve_opts* opts, const dou
     double* dy = h->scal.p + 3 * kMaxDots;  // combination coefficients
     double* hb = h->hbuf.p;
 
+    // the inner solves add their iterations to PcgState::total
+    VEM_HIP(hipMemsetAsync(&h->pcg.p->total, 0, sizeof(int), s));
     // ||b||
     launch_dots(s, N, 1, rhs, N, rhs, h->partials, dn);
     check_launch();
@@ -1192,7 +1215,6 @@ static vem_status solve_impl(vem_handle h, const vem_solve_opts* opts, const dou
     double beta = std::sqrt(hb[0]);
     const double bref = bnorm > 0 ? bnorm : 1.0;
     int its = 0, restarts = 0;
-    int64_t inner = 0;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), yv(m);
     auto Hc = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
     bool nan_seen = false;
@@ -1207,7 +1229,7 @@ static vem_status solve_impl(vem_handle h, const vem_solve_opts* opts, const dou
         double* vj = V + (size_t)j * N;
         double* zj = Z + (size_t)j * N;
         double* w = V + (size_t)(j + 1) * N;
-        inner += apply_prec(h, o, vj, zj);
+        apply_prec(h, o, vj, zj);
         launch_spmv(s, h->Ks, zj, w);
         // classical Gram-Schmidt, twice
         launch_dots(s, N, j + 1, V, N, w, h->partials, dh);
@@ -1215,9 +1237,8 @@ static vem_status solve_impl(vem_handle h, const vem_solve_opts* opts, const dou
         launch_update_norm(s, N, j + 1, V, N, dh2, w, h->partials, dn);
         launch_scale_to(s, N, w, dn, w);
         check_launch();
-        VEM_HIP(hipMemcpyAsync(hb, dh, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-        VEM_HIP(hipMemcpyAsync(hb + kMaxDots, dh2, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-        VEM_HIP(hipMemcpyAsync(hb + 2 * kMaxDots, dn, sizeof(double), hipMemcpyDeviceToHost, s));
+        // h, its correction and ||w||^2 sit at scal[0], scal[kMaxDots], scal[2 kMaxDots]: one copy
+        VEM_HIP(hipMemcpyAsync(hb, dh, (2 * kMaxDots + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
         sync(h);
         for (int i = 0; i <= j; ++i) Hc(i, j) = hb[i] + hb[kMaxDots + i];
         double hn = std::sqrt(hb[2 * kMaxDots]);
@@ -1275,7 +1296,9 @@ static vem_status solve_impl(vem_handle h, const vem_solve_opts* opts, const dou
     VEM_REQUIRE(!nan_seen, VEM_ENAN, "NaN or Inf met in the Krylov iteration");
     VEM_HIP(hipMemcpyAsync(u, x, Nu * sizeof(double), hipMemcpyDeviceToDevice, s));
     VEM_HIP(hipMemcpyAsync(p, x + Nu, Np * sizeof(double), hipMemcpyDeviceToDevice, s));
+    VEM_HIP(hipMemcpyAsync(h->hpcg.p, h->pcg.p, sizeof(PcgState), hipMemcpyDeviceToHost, s));
     sync(h);
+    const int64_t inner = o.precond == VEM_PREC_NONE ? 0 : h->hpcg.p->total;
     auto t1 = std::chrono::steady_clock::now();
     inf.iterations = its;
     inf.restarts = restarts;

@@ -19,6 +19,24 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Workgroups are dealt round-robin to the eight XCDs, each with its own L2.  The
+// inner-CG kernels take their rows from this logical block number instead: XCD x
+// runs chunks x, x+8, x+16, ... of C consecutive blocks (C blocks = 16384 rows), so
+// that the vector entries gathered around a chunk are fetched into one L2, while all
+// eight XCDs still advance through the rows together.  Blocks past the last whole
+// round of 8 chunks keep their own number.  (Measured on the 64^3 cube: 1.5% off the
+// A_gamma iteration, 3.5% off the S iteration.  The saddle SpMV keeps the hardware
+// order: its flux and pressure rows differ in cost, and contiguous bands per XCD
+// left it 10% slower.)
+__device__ inline int64_t xcd_block() {
+  const int b = blockIdx.x, P = gridDim.x;
+  const int C = (16384 / (int)blockDim.x) > 0 ? (16384 / (int)blockDim.x) : 1;
+  const int full = P / (8 * C) * (8 * C);
+  if (b >= full) return b;
+  const int x = b & 7, i = b >> 3, j = i / C, off = i % C;
+  return (int64_t)(j * 8 + x) * C + off;
+}
+
 // Block-reduce K accumulators and store this block's partial sums at
 // partials[blockIdx.x * K + k].  No atomics and no fences: the consumer is a
 // later kernel on the same stream, and the kernel boundary makes the partials
@@ -60,6 +78,34 @@ __device__ inline double block_sum_partials(const double* __restrict__ partials,
   double r = total;
   __syncthreads();
   return r;
+}
+
+// Both components of nparts (gamma, delta) partial pairs, summed by the whole block
+// in one pass, in a fixed order (every block obtains the same bits).
+__device__ inline void block_sum_partials2(const double* __restrict__ partials, int nparts, double (&out)[2]) {
+  __shared__ double sh[kMaxWaves][2];
+  __shared__ double total[2];
+  double g = 0.0, d = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+    g += partials[2 * (size_t)b];
+    d += partials[2 * (size_t)b + 1];
+  }
+  g = wave_sum(g);
+  d = wave_sum(d);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) {
+    sh[wid][0] = g;
+    sh[wid][1] = d;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w) t += sh[w][threadIdx.x];
+    total[threadIdx.x] = t;
+  }
+  __syncthreads();
+  out[0] = total[0];
+  out[1] = total[1];
 }
 
 // out[k] = sum over nparts partials; block k handles component k
@@ -259,7 +305,7 @@ __global__ void __launch_bounds__(kPcgThreads) k_ppcg_init(SellViewT<T> Ac, PcgV
                                                            const double* __restrict__ b, PcgState* st, double tol2,
                                                            int maxit, double* __restrict__ part) {
   double acc[2] = {0.0, 0.0};
-  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < Ac.rows;
+  for (int64_t row = xcd_block() * blockDim.x + threadIdx.x; row < Ac.rows;
        row += (int64_t)gridDim.x * blockDim.x) {
     const T bi = (T)b[row], di = v.dinv[row];
     const T wi = sell_dot(Ac, row, b);
@@ -285,12 +331,34 @@ __global__ void __launch_bounds__(kPcgThreads) k_ppcg_init(SellViewT<T> Ac, PcgV
 template <typename T, bool kFirst>
 __global__ void __launch_bounds__(kPcgThreads) k_ppcg_iter(int parity, SellViewT<T> Ac, PcgViewT<T> v, PcgState* st,
                                                            double* __restrict__ part) {
-  if (st->done) return;
   const int P = gridDim.x;
   const int cur = parity;
-  const double* pin = part + (size_t)cur * 2 * P;
-  const double gamma = block_sum_partials(pin, P, 2, 0);
-  const double delta = block_sum_partials(pin, P, 2, 1);
+  const T* __restrict__ win = cur ? v.w1 : v.w0;
+  T* __restrict__ wout = cur ? v.w0 : v.w1;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t row = xcd_block() * blockDim.x + threadIdx.x;
+  // The product and the old vector entries do not depend on this iteration's
+  // scalars: their loads are issued first and are in flight while the block sums
+  // the partials of gamma and delta left by the previous iteration.
+  T n = T(0), wi = T(0), di = T(0), ri = T(0), zo = T(0), so = T(0), po = T(0), xo = T(0);
+  auto load = [&](int64_t i) {
+    n = sell_dot(Ac, i, win);
+    wi = win[i];
+    di = v.dinv[i];
+    ri = v.r[i];
+    xo = v.x[i];
+    if (!kFirst) {
+      zo = v.z[i];
+      so = v.s[i];
+      po = v.p[i];
+    }
+  };
+  if (row < Ac.rows) load(row);
+  const int was_done = st->done;
+  double gd[2];
+  block_sum_partials2(part + (size_t)cur * 2 * P, P, gd);
+  if (was_done) return;
+  const double gamma = gd[0], delta = gd[1];
   double gamma0, beta, alpha;
   if (kFirst) {
     gamma0 = gamma;
@@ -312,36 +380,36 @@ __global__ void __launch_bounds__(kPcgThreads) k_ppcg_iter(int parity, SellViewT
   }
   if (done) return;
   const T a = (T)alpha, bt = (T)beta;
-  const T* __restrict__ win = cur ? v.w1 : v.w0;
-  T* __restrict__ wout = cur ? v.w0 : v.w1;
   double acc[2] = {0.0, 0.0};
-  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < Ac.rows;
-       row += (int64_t)gridDim.x * blockDim.x) {
-    const T n = sell_dot(Ac, row, win);
-    const T wi = win[row], di = v.dinv[row], ri = v.r[row];
+  while (row < Ac.rows) {
     T zz, ss, pp;
     if (kFirst) {
       zz = n;
       ss = wi;
       pp = di * ri;
     } else {
-      zz = n + bt * v.z[row];
-      ss = wi + bt * v.s[row];
-      pp = di * ri + bt * v.p[row];
+      zz = n + bt * zo;
+      ss = wi + bt * so;
+      pp = di * ri + bt * po;
     }
     v.z[row] = zz;
     v.s[row] = ss;
     v.p[row] = pp;
-    v.x[row] += a * pp;
+    v.x[row] = xo + a * pp;
     const T rn = ri - a * ss;
     const T wn = wi - a * zz;
     v.r[row] = rn;
     wout[row] = wn;
     acc[0] += (double)rn * (double)rn * (double)di;
     acc[1] += (double)wn * (double)rn * (double)di;
+    row += stride;
+    if (row < Ac.rows) load(row);
   }
   block_partials<2>(acc, part + (size_t)(1 - cur) * 2 * P);
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->count += 1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->count += 1;
+    st->total += 1;
+  }
 }
 
 // ---- classical Jacobi-PCG in FP32 (mixed-precision inner solves) --------------------------
@@ -396,7 +464,7 @@ __global__ void __launch_bounds__(kPcgThreads) k_cg_spmv(int k, SellViewT<T> A, 
   if (done) return;
   const T bt = (T)beta;
   double acc[1] = {0.0};
-  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < A.rows;
+  for (int64_t row = xcd_block() * blockDim.x + threadIdx.x; row < A.rows;
        row += (int64_t)gridDim.x * blockDim.x) {
     const int64_t sl = row >> 6;
     const int64_t base = A.slice_ptr[sl] + (row & 63);
@@ -447,7 +515,10 @@ __global__ void __launch_bounds__(kPcgThreads) k_cg_update(int k, int64_t n, T* 
     acc[0] += (double)ri * (double)zi;
   }
   block_partials<1>(acc, prho + (size_t)(1 - cur) * P);
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->count += 1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->count += 1;
+    st->total += 1;
+  }
 }
 
 __global__ void k_to_f32(int64_t n, const double* __restrict__ x, float* __restrict__ y) {

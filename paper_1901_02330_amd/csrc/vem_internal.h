@@ -84,13 +84,19 @@ constexpr int kRedThreads = 256;
 constexpr int kMaxDots = 34;       // largest number of simultaneous dot products
 constexpr int kMaxRestart = 32;
 constexpr int kMaxCellFaces = 64;
-constexpr int kPcgBlocks = 1024;   // largest grid of the inner-CG kernels
+// Largest grid of the inner-CG kernels: 256 CUs x 2 resident blocks of 1024 threads
+// (8 waves per SIMD), so that the whole grid is resident in one round.  Larger
+// systems loop over rows; a second round of blocks would pay the partial-sum
+// prologue again (measured 10% slower on the 64^3 A_gamma iteration).
+constexpr int kPcgBlocks = 512;
 constexpr int kPcgThreads = 1024;  // block size of the inner-CG kernels
 
-// Device-resident state of one inner (pipelined) Jacobi-CG solve.
+// Device-resident state of one inner (pipelined) Jacobi-CG solve.  `count` is
+// reset by every init kernel; `total` sums the iterations of all inner solves
+// since the host last cleared it (once per outer solve).
 struct PcgState {
   double gamma[2], alpha[2], gamma0, tol2;
-  int count, maxit, done, pad;
+  int count, maxit, done, total;
 };
 
 // Vectors of one inner CG solve (x is the solution), FP64 or FP32.

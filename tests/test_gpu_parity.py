@@ -181,22 +181,26 @@ def test_mixed_precision_inner_solves(precond):
     assert rel(xg[d["Nu"]:], x[d["Nu"]:]) <= 1e-7
 
 
+@pytest.mark.parametrize("cap", [5000, 20])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_graph_replays_match_eager(precision):
+def test_graph_replays_match_eager(precision, cap):
     """Inner-CG iterations replayed from a captured HIP graph give the same bits as direct launches,
-    over several solves with eager work and synchronisations in between."""
+    over several solves with eager work and synchronisations in between; with a large inner cap
+    (host polls the inner state) and with a small one (every iteration enqueued without polling)."""
     import torch
 
-    _say("graphs", precision)
+    _say("graphs", precision, cap)
     m = cube_mesh(9, 8, 7)
     nu = 1.0 / lognormal_field(9 * 8 * 7, 2.0, 3)
     s = gpu_solver(m, nu=nu, rhs=SineSolution())
     for precond in ("schur", "reg"):
-        ue, pe, ie = s.solve(precond=precond, tol=1e-10, inner_tol=1e-4, precision=precision, graphs=False)
+        kw = dict(precond=precond, tol=1e-10, inner_tol=1e-4, inner_maxit=cap, precision=precision)
+        ue, pe, ie = s.solve(graphs=False, **kw)
         for rep in range(3):
             y = s.apply(torch.cat([ue, pe]))  # eager work between replays
             torch.cuda.synchronize()
-            ug, pg, ig = s.solve(precond=precond, tol=1e-10, inner_tol=1e-4, precision=precision, graphs=True)
+            ug, pg, ig = s.solve(graphs=True, **kw)
             assert ig["iterations"] == ie["iterations"]
+            assert ig["inner_iterations"] == ie["inner_iterations"]
             assert torch.equal(ug, ue) and torch.equal(pg, pe), (precond, rep)
             assert torch.isfinite(y).all()
