@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--n", type=int, default=64, help="cells per direction of the Cube mesh")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--schur-inner-tol", type=float, default=1e-12)
-    ap.add_argument("--schur-inner-maxit", type=int, default=32)
+    ap.add_argument("--schur-inner-maxit", type=int, default=24)
     ap.add_argument("--reg-inner-tol", type=float, default=1e-1)
     ap.add_argument("--no-extras", action="store_true", help="skip the adjoint / mixed / batch / 128^3 measurements")
     ap.add_argument("--pmc-probe", action="store_true",

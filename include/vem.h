@@ -165,10 +165,11 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points);
 vem_status vem_get_sizes(vem_handle h, vem_sizes* out);
 
 /* Write the quadrature points at which the caller evaluates f and p_D
- * (device buffers): qp_cell[n_qp_cell*3] and qp_face[n_qp_face*3] (either
- * may be NULL to skip).  Points are ordered cell by cell, then by the
- * tetrahedra (x_ref, v0, v_a, v_{a+1}) of each face, then by the reference
- * points; boundary-face points follow the boundary faces in face order. */
+ * (device buffers): qp_cell[3*n_qp_cell] and qp_face[3*n_qp_face] (either
+ * may be NULL to skip), as structures of arrays: all x coordinates, then all
+ * y, then all z.  Points are ordered cell by cell, then by the tetrahedra
+ * (x_ref, v0, v_a, v_{a+1}) of each face, then by the reference points;
+ * boundary-face points follow the boundary faces in face order. */
 vem_status vem_get_quadrature(vem_handle h, double* qp_cell, double* qp_face);
 
 /* nu = 1/K per cell (device, n_cells doubles, all > 0).  Rescales the flux

@@ -24,6 +24,8 @@ using namespace vem;
 constexpr int kGraphIters = 8;
 // inner solves capped at this many iterations run without host polling
 constexpr int kBlindInner = 64;
+// doubles per Arnoldi step read back by the host: h, its correction and ||w||^2
+constexpr int kColSlot = 2 * kMaxDots + 1;
 struct InnerGraph {
   hipGraphExec_t exec = nullptr;
   const void* key[8] = {};
@@ -41,6 +43,8 @@ struct vem_ctx {
   ~vem_ctx() {
     for (InnerGraph* g : {&gS, &gA, &gS32, &gA32}) g->reset();
     if (cap) (void)hipStreamDestroy(cap);
+    for (hipEvent_t& e : step_done)
+      if (e) (void)hipEventDestroy(e);
   }
   InnerGraph gS, gA, gS32, gA32;
   hipStream_t cap = nullptr;  // private stream used only to capture graphs
@@ -100,6 +104,11 @@ struct vem_ctx {
   DBuf<double> partials, pcgpart, scal;
   DBuf<PcgState> pcg;
   HBuf<double> hbuf;
+  // Arnoldi scalars of every step of a restart cycle, one slot per step (pinned), and
+  // the events that mark each step's copy (steps alternate between the two)
+  HBuf<double> hcol;
+  Scratch tmp;  // temporaries of the set-up calls
+  hipEvent_t step_done[2] = {nullptr, nullptr};
   HBuf<PcgState> hpcg;
 };
 
@@ -221,6 +230,12 @@ __global__ void k_narrow(int64_t n, const int64_t* __restrict__ in, int* __restr
   if (i < n) out[i] = (int)in[i];
 }
 
+// ptr[n] = ptr[n-1] + len[n-1] (0 when n = 0): the total after an exclusive scan of n entries
+template <typename It>
+__global__ void k_scan_tail(int64_t n, It len, int64_t* __restrict__ ptr) {
+  ptr[n] = n > 0 ? ptr[n - 1] + (int64_t)len[n - 1] : 0;
+}
+
 __global__ void k_set_last_zero_i32(int* p) { *p = 0; }
 __global__ void k_set_last_zero_i64(int64_t* p) { *p = 0; }
 
@@ -244,47 +259,35 @@ void fill_i32(hipStream_t s, int64_t n, int v, int* p) {
 
 namespace vem {
 
-int64_t scan_i64(hipStream_t s, const int64_t* len, int64_t n, int64_t* ptr) {
-  // ptr has n+1 entries; scanning n+1 inputs needs len[n] = 0: scan n and add the last
+int64_t scan_i64(hipStream_t s, Scratch& tmp, const int64_t* len, int64_t n, int64_t* ptr) {
   size_t bytes = 0;
   VEM_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, len, ptr, (int)n, s));
-  DBuf<unsigned char> tmp;
-  tmp.alloc(bytes > 0 ? bytes : 1);
-  VEM_HIP(hipcub::DeviceScan::ExclusiveSum(tmp.p, bytes, len, ptr, (int)n, s));
-  int64_t last_ptr = 0, last_len = 0;
-  if (n > 0) {
-    VEM_HIP(hipMemcpyAsync(&last_ptr, ptr + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    VEM_HIP(hipMemcpyAsync(&last_len, len + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  }
-  VEM_HIP(hipStreamSynchronize(s));
-  int64_t total = last_ptr + last_len;
-  VEM_HIP(hipMemcpyAsync(ptr + n, &total, sizeof(int64_t), hipMemcpyHostToDevice, s));
+  tmp.cub.reserve(bytes > 0 ? bytes : 1);
+  VEM_HIP(hipcub::DeviceScan::ExclusiveSum(tmp.cub.p, bytes, len, ptr, (int)n, s));
+  k_scan_tail<<<1, 1, 0, s>>>(n, len, ptr);  // ptr[n] = ptr[n-1] + len[n-1]
+  VEM_HIP(hipGetLastError());
+  int64_t total = 0;
+  VEM_HIP(hipMemcpyAsync(&total, ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   VEM_HIP(hipStreamSynchronize(s));
   return total;
 }
 
-int64_t scan_i32(hipStream_t s, const int* len, int64_t n, int* ptr) {
-  DBuf<int64_t> p64;
-  p64.alloc(n + 1);
+int64_t scan_i32(hipStream_t s, Scratch& tmp, const int* len, int64_t n, int* ptr) {
+  DBuf<int64_t>& p64 = tmp.i64[3];
+  p64.reserve(n + 1);
   hipcub::TransformInputIterator<int64_t, ToI64, const int*> it(len, ToI64());
   size_t bytes = 0;
   VEM_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, it, p64.p, (int)n, s));
-  DBuf<unsigned char> tmp;
-  tmp.alloc(bytes > 0 ? bytes : 1);
-  VEM_HIP(hipcub::DeviceScan::ExclusiveSum(tmp.p, bytes, it, p64.p, (int)n, s));
-  int64_t last_ptr = 0;
-  int last_len = 0;
-  if (n > 0) {
-    VEM_HIP(hipMemcpyAsync(&last_ptr, p64.p + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    VEM_HIP(hipMemcpyAsync(&last_len, len + n - 1, sizeof(int), hipMemcpyDeviceToHost, s));
-  }
+  tmp.cub.reserve(bytes > 0 ? bytes : 1);
+  VEM_HIP(hipcub::DeviceScan::ExclusiveSum(tmp.cub.p, bytes, it, p64.p, (int)n, s));
+  k_scan_tail<<<1, 1, 0, s>>>(n, it, p64.p);
+  VEM_HIP(hipGetLastError());
+  int64_t total = 0;
+  VEM_HIP(hipMemcpyAsync(&total, p64.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   VEM_HIP(hipStreamSynchronize(s));
-  int64_t total = last_ptr + last_len;
   VEM_REQUIRE(total <= INT_MAX, VEM_ENOMEM, "more than 2^31-1 entries in a sparse pattern");
-  if (n > 0) k_narrow<<<grid_of(n), 256, 0, s>>>(n, p64.p, ptr);
-  int t32 = (int)total;
-  VEM_HIP(hipMemcpyAsync(ptr + n, &t32, sizeof(int), hipMemcpyHostToDevice, s));
-  VEM_HIP(hipStreamSynchronize(s));
+  k_narrow<<<grid_of(n + 1), 256, 0, s>>>(n + 1, p64.p, ptr);
+  VEM_HIP(hipGetLastError());
   return total;
 }
 
@@ -345,7 +348,9 @@ void ensure_scratch(vem_handle h) {
     h->scal.alloc(4 * kMaxDots + 16);
     h->pcg.alloc(1);
     h->hbuf.alloc(4 * kMaxDots + 16);
+    h->hcol.alloc((size_t)(kMaxRestart + 1) * kColSlot);
     h->hpcg.alloc(1);
+    for (hipEvent_t& e : h->step_done) VEM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     sync(h);
   }
 }
@@ -662,8 +667,8 @@ vem_status vem_set_mesh(vem_handle h, int64_t nv, const double* xyz, int64_t nf,
     fill_i32(s, 2 * nf, 0, h->face_cnt);
     fill_i32(s, 2 * nf, -1, h->face_cell);
     fill_i32(s, 2 * nf, -1, h->face_lidx);
-    DBuf<int> derr;
-    derr.alloc(1);
+    DBuf<int>& derr = h->tmp.i32[0];
+    derr.reserve(1);
     fill_i32(s, 1, 0, derr);
     launch_check_mesh(s, h->nv, h->nf, h->nc, h->fptr, h->fvtx, h->cptr, h->cface, h->csign, h->face_cnt,
                       h->face_cell, h->face_lidx, h->inc_cell, derr);
@@ -700,8 +705,8 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
     launch_cell_geometry(s, nc, h->xyz, h->fptr, h->fvtx, h->cptr, h->cface, h->csign, h->c_vol, h->c_cen,
                          h->c_diam, h->c_xref);
     check_launch();
-    DBuf<int> derr;
-    derr.alloc(1);
+    DBuf<int>& derr = h->tmp.i32[0];
+    derr.reserve(1);
     fill_i32(s, 1, 0, derr);
     fill_i32(s, 1, 0, h->is_bnd.p + nf);
     launch_check_faces(s, nf, h->face_cnt, h->f_area, h->is_bnd, derr);
@@ -732,27 +737,27 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
       sync(h);
     }
     {
-      DBuf<int> cnt;
-      cnt.alloc(nc + 1);
+      DBuf<int>& cnt = h->tmp.i32[1];
+      cnt.reserve(nc + 1);
       launch_tet_counts(s, nc, h->fptr, h->cptr, h->cface, cnt);
       check_launch();
       h->cell_tet_ptr.alloc(nc + 1);
-      h->ntet = scan_i32(s, cnt, nc, h->cell_tet_ptr);
+      h->ntet = scan_i32(s, h->tmp, cnt, nc, h->cell_tet_ptr);
       h->tet_inc.alloc(h->ntet);
       h->tet_a.alloc(h->ntet);
       launch_tets(s, nc, h->fptr, h->cptr, h->cface, h->cell_tet_ptr, h->tet_inc, h->tet_a);
       check_launch();
-      DBuf<int> pos;
-      pos.alloc(nf + 1);
-      h->nbf = scan_i32(s, h->is_bnd, nf, pos);
+      DBuf<int>& pos = h->tmp.i32[2];
+      pos.reserve(nf + 1);
+      h->nbf = scan_i32(s, h->tmp, h->is_bnd, nf, pos);
       h->bface.alloc(h->nbf > 0 ? h->nbf : 1);
       launch_compact_flags(s, nf, h->is_bnd, pos, h->bface);
-      DBuf<int> tc;
-      tc.alloc(h->nbf + 1);
+      DBuf<int>& tc = h->tmp.i32[3];
+      tc.reserve(h->nbf + 1);
       launch_bnd_tri_counts(s, (int)h->nbf, h->bface, h->fptr, tc);
       check_launch();
       h->btri_ptr.alloc(h->nbf + 1);
-      h->nbtri = h->nbf > 0 ? scan_i32(s, tc, h->nbf, h->btri_ptr) : 0;
+      h->nbtri = h->nbf > 0 ? scan_i32(s, h->tmp, tc, h->nbf, h->btri_ptr) : 0;
       if (h->nbf == 0) fill_i32(s, 1, 0, h->btri_ptr);
     }
 
@@ -776,23 +781,25 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
     h->korder = family == VEM_PAPER ? k : 0;
     int64_t tot_ldof = 0;
     {
-      DBuf<int64_t> nd, nm, nb;
-      nd.alloc(nc + 1);
-      nm.alloc(nc + 1);
-      nb.alloc(nc + 1);
+      DBuf<int64_t>& nd = h->tmp.i64[0];
+      DBuf<int64_t>& nm = h->tmp.i64[1];
+      DBuf<int64_t>& nb = h->tmp.i64[2];
+      nd.reserve(nc + 1);
+      nm.reserve(nc + 1);
+      nb.reserve(nc + 1);
       launch_cell_sizes(s, L, h->cptr, nd, nm, nb);
       check_launch();
-      DBuf<int64_t> p64;
-      p64.alloc(nc + 1);
-      int64_t tot = scan_i64(s, nd, nc, p64);
+      DBuf<int64_t>& p64 = h->tmp.i64[3];
+      p64.reserve(nc + 1);
+      int64_t tot = scan_i64(s, h->tmp, nd, nc, p64);
       VEM_REQUIRE(tot <= INT_MAX, VEM_ENOMEM, "too many local DOFs");
       tot_ldof = tot;
       h->ldof_ptr.alloc(nc + 1);
       k_narrow<<<grid_of(nc + 1), 256, 0, s>>>(nc + 1, p64.p, h->ldof_ptr.p);
       h->lmat_ptr.alloc(nc + 1);
-      int64_t nmat = scan_i64(s, nm, nc, h->lmat_ptr);
+      int64_t nmat = scan_i64(s, h->tmp, nm, nc, h->lmat_ptr);
       h->lb_ptr.alloc(nc + 1);
-      int64_t nbd = scan_i64(s, nb, nc, h->lb_ptr);
+      int64_t nbd = scan_i64(s, h->tmp, nb, nc, h->lb_ptr);
       h->M1.alloc(nmat);
       h->Bdiv1.alloc(nbd);
       h->sorted_gid.alloc(tot);
@@ -810,17 +817,23 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
         trip.push_back(p2[2 * r + 1]);
         trip.push_back(w2[r]);
       }
-      DBuf<double> tri, FP, FM, Dg, Pg, Xg, Cg;
-      tri.alloc(trip.size());
+      DBuf<double>& tri = h->tmp.f64[0];
+      DBuf<double>& FP = h->tmp.f64[1];
+      DBuf<double>& FM = h->tmp.f64[2];
+      DBuf<double>& Dg = h->tmp.f64[3];
+      DBuf<double>& Pg = h->tmp.f64[4];
+      DBuf<double>& Xg = h->tmp.f64[5];
+      DBuf<double>& Cg = h->tmp.f64[6];
+      tri.reserve(trip.size());
       VEM_HIP(hipMemcpyAsync(tri.p, trip.data(), trip.size() * sizeof(double), hipMemcpyHostToDevice, s));
-      FP.alloc((size_t)h->ncf * z.nsm);
-      FM.alloc((size_t)h->ncf * z.nfm);
+      FP.reserve((size_t)h->ncf * z.nsm);
+      FM.reserve((size_t)h->ncf * z.nfm);
       h->pk_Tf.alloc((size_t)nf * z.nfd * z.nfd);
       h->pk_cmom.alloc((size_t)nc * z.nsm);
-      Dg.alloc((size_t)tot_ldof * z.n3);
-      Pg.alloc((size_t)tot_ldof * z.n3);
-      Xg.alloc((size_t)tot_ldof * z.n3);
-      Cg.alloc((size_t)tot_ldof * z.npd);
+      Dg.reserve((size_t)tot_ldof * z.n3);
+      Pg.reserve((size_t)tot_ldof * z.n3);
+      Xg.reserve((size_t)tot_ldof * z.n3);
+      Cg.reserve((size_t)tot_ldof * z.npd);
       PaperLocalArgs a{};
       a.s = s;
       a.nf = nf;
@@ -858,7 +871,7 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
       a.Bdiv1 = h->Bdiv1;
       launch_paper_local(k, a);
       check_launch();
-      sync(h);  // the scratch buffers are released at the end of this scope
+      sync(h);  // the host-side table `trip` is released at the end of this scope
     }
     launch_ldof_sort(s, L, h->cptr, h->cface, h->ldof_ptr, h->sorted_gid, h->sorted_l);
     check_launch();
@@ -866,10 +879,12 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
     // ---- a5/a6: patterns of K, A_gamma and S
     const int64_t N = L.Nu + L.Np;
     {
-      DBuf<int> lenK, lenA, lenS;
-      lenK.alloc(N + 1);
-      lenA.alloc(L.Nu + 1);
-      lenS.alloc(L.Np + 1);
+      DBuf<int>& lenK = h->tmp.i32[1];
+      DBuf<int>& lenA = h->tmp.i32[2];
+      DBuf<int>& lenS = h->tmp.i32[3];
+      lenK.reserve(N + 1);
+      lenA.reserve(L.Nu + 1);
+      lenS.reserve(L.Np + 1);
       launch_rowlen(s, L, h->cptr, h->ldof_ptr, h->sorted_gid, h->face_cell, h->face_lidx, h->cface, lenK, lenA,
                     lenS);
       check_launch();
@@ -879,9 +894,9 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
       h->K.rowptr.alloc(N + 1);
       h->A.rowptr.alloc(L.Nu + 1);
       h->S.rowptr.alloc(L.Np + 1);
-      h->K.nnz = scan_i32(s, lenK, N, h->K.rowptr);
-      h->A.nnz = scan_i32(s, lenA, L.Nu, h->A.rowptr);
-      h->S.nnz = scan_i32(s, lenS, L.Np, h->S.rowptr);
+      h->K.nnz = scan_i32(s, h->tmp, lenK, N, h->K.rowptr);
+      h->A.nnz = scan_i32(s, h->tmp, lenA, L.Nu, h->A.rowptr);
+      h->S.nnz = scan_i32(s, h->tmp, lenS, L.Np, h->S.rowptr);
     }
     h->K.col.alloc(h->K.nnz);
     h->K.val.alloc(h->K.nnz);
@@ -896,9 +911,9 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
                          h->K.rowptr, h->K.col, h->Kdiag, h->A.rowptr, h->A.col, h->Adiag, h->S.rowptr, h->S.col,
                          h->Sdiag);
     check_launch();
-    build_sell(s, h->K, h->Ks);
-    build_sell(s, h->A, h->As);
-    build_sell(s, h->S, h->Ss);
+    build_sell(s, h->tmp, h->K, h->Ks);
+    build_sell(s, h->tmp, h->A, h->As);
+    build_sell(s, h->tmp, h->S, h->Ss);
     h->dM.alloc(L.Nu);
     h->dMinv.alloc(L.Nu);
     h->dAinv.alloc(L.Nu);
@@ -947,8 +962,8 @@ vem_status vem_get_quadrature(vem_handle h, double* qp_cell, double* qp_face) {
       launch_qp_cell(s, h->ntet, h->npts_cell, h->qref_cell, h->tet_inc, h->tet_a, h->inc_cell, h->xyz, h->fptr,
                      h->fvtx, h->cface, h->c_xref, qp_cell);
     if (qp_face)
-      launch_qp_face(s, (int)h->nbf, h->npts_face, h->qref_face, h->bface, h->btri_ptr, h->xyz, h->fptr, h->fvtx,
-                     qp_face);
+      launch_qp_face(s, (int)h->nbf, h->npts_face, (int64_t)h->nbtri * h->npts_face, h->qref_face, h->bface,
+                     h->btri_ptr, h->xyz, h->fptr, h->fvtx, qp_face);
     check_launch();
   });
 }
@@ -969,9 +984,9 @@ vem_status vem_set_rhs(vem_handle h, const double* f_qp, const double* pD_qp) {
     require_disc(h);
     hipStream_t s = h->stream;
     launch_fill(s, h->L.Nu, 0.0, h->rhs);
-    DBuf<double> tsum;
+    DBuf<double>& tsum = h->tmp.f64[0];
     if (h->family == VEM_LO) {
-      tsum.alloc(h->ntet);
+      tsum.reserve(h->ntet);
       launch_load_tets(s, h->ntet, h->npts_cell, h->qw_cell, h->tet_inc, h->tet_a, h->inc_cell, h->xyz, h->fptr,
                        h->fvtx, h->cface, h->csign, h->c_xref, f_qp, tsum);
       launch_load_cells(s, h->nc, h->cell_tet_ptr, tsum, h->rhs.p + h->L.Nu);
@@ -979,7 +994,7 @@ vem_status vem_set_rhs(vem_handle h, const double* f_qp, const double* pD_qp) {
         launch_bnd_rhs(s, (int)h->nbf, h->npts_face, h->qw_face, h->bface, h->btri_ptr, h->xyz, h->fptr, h->fvtx,
                        h->face_cell, pD_qp, h->rhs);
     } else {
-      tsum.alloc((size_t)h->ntet * h->L.npd);
+      tsum.reserve((size_t)h->ntet * h->L.npd);
       PaperLoadArgs a{};
       a.s = s;
       a.nc = h->nc;
@@ -1225,7 +1240,11 @@ static vem_status solve_impl(vem_handle h, const vem_solve_opts* opts, const dou
       std::fill(g.begin(), g.end(), 0.0);
       g[0] = beta;
       int jend = 0;
-      for (int j = 0; j < m; ++j) {
+      // One Arnoldi step, enqueued without waiting: the next basis vector is normalised on
+      // the device, so step j+1 is enqueued before the host reads step j's scalars and the
+      // device never idles on the host's Givens rotations.  A step enqueued past the
+      // convergence point is discarded (its outputs are never read).
+      auto enqueue_step = [&](int j) {
         double* vj = V + (size_t)j * N;
         double* zj = Z + (size_t)j * N;
         double* w = V + (size_t)(j + 1) * N;
@@ -1237,11 +1256,18 @@ static vem_status solve_impl(vem_handle h, const vem_solve_opts* opts, const dou
         launch_update_norm(s, N, j + 1, V, N, dh2, w, h->partials, dn);
         launch_scale_to(s, N, w, dn, w);
         check_launch();
-        // h, its correction and ||w||^2 sit at scal[0], scal[kMaxDots], scal[2 kMaxDots]: one copy
-        VEM_HIP(hipMemcpyAsync(hb, dh, (2 * kMaxDots + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
-        sync(h);
-        for (int i = 0; i <= j; ++i) Hc(i, j) = hb[i] + hb[kMaxDots + i];
-        double hn = std::sqrt(hb[2 * kMaxDots]);
+        // h, its correction and ||w||^2 sit at scal[0], scal[kMaxDots], scal[2 kMaxDots]
+        VEM_HIP(hipMemcpyAsync(h->hcol.p + (size_t)j * kColSlot, dh, kColSlot * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+        VEM_HIP(hipEventRecord(h->step_done[j & 1], s));
+      };
+      enqueue_step(0);
+      for (int j = 0; j < m; ++j) {
+        if (j + 1 < m && its + 1 < o.maxit) enqueue_step(j + 1);
+        VEM_HIP(hipEventSynchronize(h->step_done[j & 1]));
+        const double* col = h->hcol.p + (size_t)j * kColSlot;
+        for (int i = 0; i <= j; ++i) Hc(i, j) = col[i] + col[kMaxDots + i];
+        double hn = std::sqrt(col[2 * kMaxDots]);
         Hc(j + 1, j) = hn;
         for (int i = 0; i <= j + 1; ++i)
           if (!std::isfinite(Hc(i, j))) nan_seen = true;

@@ -21,6 +21,12 @@ __device__ inline void st3(double* p, int64_t i, V3 v) {
   p[3 * i + 1] = v.y;
   p[3 * i + 2] = v.z;
 }
+// structure of arrays: x[0..n), y[n..2n), z[2n..3n)
+__device__ inline void st3_soa(double* p, int64_t n, int64_t i, V3 v) {
+  p[i] = v.x;
+  p[n + i] = v.y;
+  p[2 * n + i] = v.z;
+}
 __device__ inline V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
 __device__ inline V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
 __device__ inline V3 operator*(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
@@ -233,13 +239,13 @@ __global__ void k_qp_cell(int64_t total, int npts, const double* __restrict__ re
   V3 O = ld3(xref, inc_cell[j]);
   V3 A = ld3(xyz, fvtx[fs]), B = ld3(xyz, fvtx[fs + a]), C = ld3(xyz, fvtx[fs + a + 1]);
   double xi = ref[3 * r], eta = ref[3 * r + 1], zeta = ref[3 * r + 2];
-  st3(qp, g, O + xi * (A - O) + eta * (B - O) + zeta * (C - O));
+  st3_soa(qp, total, g, O + xi * (A - O) + eta * (B - O) + zeta * (C - O));
 }
 
 // Boundary-face points: triangles (v0, v_a, v_{a+1}), x = v0 + xi (v_a - v0) + eta (v_{a+1} - v0).
-__global__ void k_qp_face(int nb, int npts, const double* __restrict__ ref, const int* __restrict__ bface,
-                          const int* __restrict__ btp, const double* __restrict__ xyz, const int* __restrict__ fptr,
-                          const int* __restrict__ fvtx, double* qp) {
+__global__ void k_qp_face(int nb, int npts, int64_t total, const double* __restrict__ ref,
+                          const int* __restrict__ bface, const int* __restrict__ btp, const double* __restrict__ xyz,
+                          const int* __restrict__ fptr, const int* __restrict__ fvtx, double* qp) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nb) return;
   int f = bface[i];
@@ -248,7 +254,7 @@ __global__ void k_qp_face(int nb, int npts, const double* __restrict__ ref, cons
   V3 A = ld3(xyz, fvtx[fs]);
   for (int a = 1; a + 1 < n; ++a) {
     V3 B = ld3(xyz, fvtx[fs + a]), C = ld3(xyz, fvtx[fs + a + 1]);
-    for (int r = 0; r < npts; ++r, ++q) st3(qp, q, A + ref[2 * r] * (B - A) + ref[2 * r + 1] * (C - A));
+    for (int r = 0; r < npts; ++r, ++q) st3_soa(qp, total, q, A + ref[2 * r] * (B - A) + ref[2 * r + 1] * (C - A));
   }
 }
 
@@ -347,9 +353,10 @@ void launch_qp_cell(hipStream_t s, int64_t ntet, int npts, const double* ref, co
     k_qp_cell<<<nblocks(total), kThreads, 0, s>>>(total, npts, ref, tet_inc, tet_a, inc_cell, xyz, fptr, fvtx,
                                                   cface, xref, qp);
 }
-void launch_qp_face(hipStream_t s, int nb, int npts, const double* ref, const int* bface, const int* btri_ptr,
-                    const double* xyz, const int* fptr, const int* fvtx, double* qp) {
-  if (nb > 0) k_qp_face<<<nblocks(nb), kThreads, 0, s>>>(nb, npts, ref, bface, btri_ptr, xyz, fptr, fvtx, qp);
+void launch_qp_face(hipStream_t s, int nb, int npts, int64_t total, const double* ref, const int* bface,
+                    const int* btri_ptr, const double* xyz, const int* fptr, const int* fvtx, double* qp) {
+  if (nb > 0)
+    k_qp_face<<<nblocks(nb), kThreads, 0, s>>>(nb, npts, total, ref, bface, btri_ptr, xyz, fptr, fvtx, qp);
 }
 void launch_load_tets(hipStream_t s, int64_t ntet, int npts, const double* refw, const int* tet_inc,
                       const int* tet_a, const int* inc_cell, const double* xyz, const int* fptr, const int* fvtx,

@@ -73,16 +73,17 @@ inline int grid256(int64_t n) { return (int)((n + 255) / 256); }
 
 }  // namespace
 
-void build_sell(hipStream_t s, const Csr& A, Sell& S) {
+void build_sell(hipStream_t s, Scratch& tmp, const Csr& A, Sell& S) {
   S.rows = A.rows;
   S.nslices = (A.rows + 63) / 64;
   S.slice_len.alloc(S.nslices);
-  DBuf<int64_t> sz, ptr;
-  sz.alloc(S.nslices + 1);
-  ptr.alloc(S.nslices + 1);
+  DBuf<int64_t>& sz = tmp.i64[0];
+  DBuf<int64_t>& ptr = tmp.i64[1];
+  sz.reserve(S.nslices + 1);
+  ptr.reserve(S.nslices + 1);
   k_sell_len<<<grid256(S.nslices), 256, 0, s>>>(A.rows, S.nslices, A.rowptr, S.slice_len, sz);
   VEM_HIP(hipGetLastError());
-  int64_t total = scan_i64(s, sz, S.nslices, ptr);
+  int64_t total = scan_i64(s, tmp, sz, S.nslices, ptr);
   VEM_REQUIRE(total < INT32_MAX, VEM_ENOMEM, "padded matrix exceeds 2^31-1 entries");
   S.nnz = total;
   S.slice_ptr.alloc(S.nslices + 1);

@@ -54,7 +54,22 @@ struct DBuf {
     }
     n = count;
   }
+  // grow-only: keeps the allocation when it is already large enough
+  void reserve(size_t count) {
+    if (count <= n && p) return;
+    alloc(count);
+  }
   operator T*() const { return p; }
+};
+
+// Grow-only device scratch owned by a handle, for the temporaries of the set-up calls:
+// a hipMalloc/hipFree pair per call synchronises the device and costs 0.1-0.5 ms.
+// Slots are handed out by the caller; no two live temporaries share a slot.
+struct Scratch {
+  DBuf<unsigned char> cub;  // hipcub temporary storage
+  DBuf<int64_t> i64[4];
+  DBuf<int> i32[4];
+  DBuf<double> f64[8];
 };
 
 // Pinned host buffer.
@@ -123,7 +138,7 @@ struct Sell {
   DBuf<double> val_cs;   // column-scaled copy A D^{-1} (inner CG matrices only)
   DBuf<float> val32;     // FP32 rounding of val (mixed-precision inner solves)
 };
-void build_sell(hipStream_t s, const Csr& A, Sell& S);
+void build_sell(hipStream_t s, Scratch& tmp, const Csr& A, Sell& S);
 void refresh_sell(hipStream_t s, const Csr& A, Sell& S);
 
 // ---- launchers (one translation unit each; all take the handle's stream) ----
@@ -146,8 +161,8 @@ void launch_bnd_tri_counts(hipStream_t s, int nb, const int* bface, const int* f
 void launch_qp_cell(hipStream_t s, int64_t ntet, int npts, const double* ref, const int* tet_inc, const int* tet_a,
                     const int* inc_cell, const double* xyz, const int* fptr, const int* fvtx, const int* cface,
                     const double* xref, double* qp);
-void launch_qp_face(hipStream_t s, int nb, int npts, const double* ref, const int* bface, const int* btri_ptr,
-                    const double* xyz, const int* fptr, const int* fvtx, double* qp);
+void launch_qp_face(hipStream_t s, int nb, int npts, int64_t total, const double* ref, const int* bface,
+                    const int* btri_ptr, const double* xyz, const int* fptr, const int* fvtx, double* qp);
 void launch_load_tets(hipStream_t s, int64_t ntet, int npts, const double* refw, const int* tet_inc,
                       const int* tet_a, const int* inc_cell, const double* xyz, const int* fptr, const int* fvtx,
                       const int* cface, const int8_t* csign, const double* xref, const double* fq,
@@ -258,8 +273,10 @@ void gauss_jacobi01(int n, int alpha, double* t, double* w);  // int_0^1 (1-t)^a
 void tet_reference_rule(int n, std::vector<double>& pts, std::vector<double>& w);
 void tri_reference_rule(int n, std::vector<double>& pts, std::vector<double>& w);
 // ptr[0..n] = exclusive prefix sums of len[0..n-1]; returns the total (synchronises)
-int64_t scan_i32(hipStream_t s, const int* len, int64_t n, int* ptr);
-int64_t scan_i64(hipStream_t s, const int64_t* len, int64_t n, int64_t* ptr);
+// Exclusive prefix sums with the total appended (ptr has n+1 entries); return the total
+// (synchronises).  The temporaries come from `tmp` (scan_i32 uses tmp.i64[3]).
+int64_t scan_i32(hipStream_t s, Scratch& tmp, const int* len, int64_t n, int* ptr);
+int64_t scan_i64(hipStream_t s, Scratch& tmp, const int64_t* len, int64_t n, int64_t* ptr);
 void launch_compact_flags(hipStream_t s, int64_t n, const int* flag, const int* pos, int* out);
 
 }  // namespace vem

@@ -171,11 +171,12 @@ class Solver:
     def quadrature(self):
         t = self.torch
         sz = self.sizes()
-        qc = t.empty((sz["n_qp_cell"], 3), dtype=t.float64, device=self.device)
-        qf = t.empty((sz["n_qp_face"], 3), dtype=t.float64, device=self.device)
+        # the library writes x, y, z as separate arrays; the (n, 3) views keep each column contiguous
+        qc = t.empty((3, sz["n_qp_cell"]), dtype=t.float64, device=self.device)
+        qf = t.empty((3, sz["n_qp_face"]), dtype=t.float64, device=self.device)
         self._check(self.lib.vem_get_quadrature(self.h, _ptr(qc) if qc.numel() else None,
                                                 _ptr(qf) if qf.numel() else None))
-        return qc, qf
+        return qc.t(), qf.t()
 
     def set_coefficient(self, nu):
         nu = self._dev(nu, self.torch.float64)
