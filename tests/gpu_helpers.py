@@ -45,3 +45,137 @@ def assert_same_csr(G, O, rtol=1e-13):
 
 def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+def submesh(mesh, cells):
+    """The mesh restricted to `cells` (global ids) and their faces, renumbered (vertices kept).
+
+    Returns (sub, faces) with faces[local face] = global face id; sub cell i is cells[i].  Face loops,
+    orientations and signs are copied, so every face and cell quantity the oracle derives from them is
+    the same as on the full mesh."""
+    cp, cf, cs = mesh["cell_ptr"], mesh["cell_face"], mesh["cell_face_sign"]
+    fp, fv = mesh["face_ptr"], mesh["face_vtx"]
+    cells = np.asarray(cells, dtype=np.int64)
+    idx = np.concatenate([np.arange(cp[c], cp[c + 1]) for c in cells])
+    gface = cf[idx].astype(np.int64)
+    faces = np.unique(gface)
+    nl = (fp[faces + 1] - fp[faces]).astype(np.int64)
+    sub = {
+        "xyz": mesh["xyz"],
+        "face_ptr": np.concatenate([[0], np.cumsum(nl)]).astype(fp.dtype),
+        "face_vtx": np.concatenate([fv[fp[f]:fp[f + 1]] for f in faces]).astype(fv.dtype),
+        "cell_ptr": np.concatenate([[0], np.cumsum(cp[cells + 1] - cp[cells])]).astype(cp.dtype),
+        "cell_face": np.searchsorted(faces, gface).astype(cf.dtype),
+        "cell_face_sign": cs[idx],
+    }
+    return sub, faces
+
+
+def oracle_sampled_rows(mesh, nu, faces, cells, rhs, family="lo", k=0, nq_load=3):
+    """Rows of the oracle's K and entries of b for the flux DOFs of the sampled faces and for the
+    interior and pressure DOFs of the sampled cells, on the full mesh, without discretising it whole.
+
+    The oracle discretises the sub-mesh of every cell that touches a sampled face or is a sampled cell;
+    a row of a sampled face (both of its cells present) or of a sampled cell is then complete.  Returns
+    {global row: (global cols, vals)} and {global row: b}.  The boundary data of the sub-mesh differ
+    from the full mesh's at the cut, so b is returned for cell rows only (and for face rows when p_D is
+    not used), {global row: largest condition number of the local Gram systems behind the row} (1 for
+    the lowest order) and {global row: largest entry of the local matrices behind the row}."""
+    from oracle.assemble import discretize
+
+    cp, cf = mesh["cell_ptr"], mesh["cell_face"]
+    nf = len(mesh["face_ptr"]) - 1
+    nc = len(cp) - 1
+    owner = np.repeat(np.arange(nc), np.diff(cp))
+    near = owner[np.isin(cf, faces)]
+    sel = np.unique(np.concatenate([near, np.asarray(cells, dtype=np.int64)]))
+    sub, gfaces = submesh(mesh, sel)
+    d = discretize(sub, nu=np.asarray(nu)[sel], rhs=rhs, family=family, k=k, nq_load=nq_load)
+    if family == "lo":
+        nfd, nint, npd = 1, 0, 1
+    else:
+        nfd, nint, npd = d["nfd"], d["nint"], d["npd"]
+    Nu = nf * nfd + nc * nint
+    nfs = len(gfaces)
+    # sub DOF -> global DOF
+    umap = np.concatenate([(gfaces[:, None] * nfd + np.arange(nfd)[None, :]).ravel(),
+                           (nf * nfd + sel[:, None] * nint + np.arange(nint)[None, :]).ravel()])
+    pmap = Nu + (sel[:, None] * npd + np.arange(npd)[None, :]).ravel()
+    gmap = np.concatenate([umap, pmap])
+    K = d["K"].tocsr()
+    want = {}
+    fpos = np.searchsorted(gfaces, faces)
+    for fl in fpos:
+        for b_ in range(nfd):
+            want[fl * nfd + b_] = True
+    cpos = np.searchsorted(sel, cells)
+    for cl in cpos:
+        for j in range(nint):
+            want[nfs * nfd + cl * nint + j] = False
+        for a in range(npd):
+            want[d["Nu"] + cl * npd + a] = False
+    # condition number of the local Gram systems each row depends on (H_k, H_{k-1}, the face Grams
+    # H_f of the cells that touch it): both sides solve them, by different algorithms
+    ccond = np.ones(len(sel))
+    # size of each cell's local matrices nu_P M1_P and B_div,P: the errors of dense local computations
+    # are bounded relative to these (normwise), not relative to each entry
+    cscale = np.zeros(len(sel))
+    nus = np.asarray(nu)[sel]
+    if family != "lo":
+        for P, loc in enumerate(d["local"]):
+            ccond[P] = max([np.linalg.cond(loc["G"]), np.linalg.cond(loc["Hk1"])] +
+                           [np.linalg.cond(T) for T in loc["T"]])
+            cscale[P] = max(nus[P] * np.abs(loc["M1"]).max(), np.abs(loc["Bdiv"]).max())
+    else:
+        for grp in d["local"].values():
+            cscale[grp["cells"]] = np.maximum(nus[grp["cells"]] * np.abs(grp["M1"]).max(axis=(1, 2)),
+                                              np.abs(grp["Bdiv"]).max(axis=1))
+    sub_owner = np.repeat(np.arange(len(sel)), np.diff(sub["cell_ptr"]))
+    rows, bvals, conds, scales = {}, {}, {}, {}
+    for r, is_face in want.items():
+        lo_, hi_ = K.indptr[r], K.indptr[r + 1]
+        g = int(gmap[r])
+        rows[g] = (gmap[K.indices[lo_:hi_]], K.data[lo_:hi_].copy())
+        if is_face:
+            near_cells = sub_owner[sub["cell_face"] == r // nfd]
+        else:
+            near_cells = [(r - nfs * nfd) // nint if r < d["Nu"] else (r - d["Nu"]) // npd]
+            bvals[g] = float(d["b"][r])
+        conds[g] = float(ccond[near_cells].max())
+        scales[g] = float(cscale[near_cells].max())
+    return rows, bvals, conds, scales
+
+
+def gpu_rows(rp, col, val, rows):
+    """{row: (cols, vals)} for the given rows of a device CSR (rp, col, val), copied to the host."""
+    import torch
+
+    rows = sorted(int(r) for r in rows)
+    rph = rp.cpu().numpy().astype(np.int64)
+    idx = np.concatenate([np.arange(rph[r], rph[r + 1]) for r in rows])
+    it = torch.as_tensor(idx, device=col.device)
+    c = col[it].cpu().numpy()
+    v = val[it].cpu().numpy()
+    out, k = {}, 0
+    for r in rows:
+        n = rph[r + 1] - rph[r]
+        out[r] = (c[k:k + n], v[k:k + n])
+        k += n
+    return out
+
+
+def compare_rows(g_rows, o_rows, rtol, scales=None):
+    """Each oracle row against the GPU's row: same entries within rtol (a number, or {row: bound})
+    times the row's scale ({row: scale}, default the row's own max |entry|); a GPU entry outside the
+    oracle's pattern must be zero to the same bound.  Returns the worst ratio of difference to bound."""
+    worst = 0.0
+    for r, (oc, ov) in o_rows.items():
+        tol = rtol[r] if isinstance(rtol, dict) else rtol
+        gc, gv = g_rows[r]
+        o = dict(zip(oc.tolist(), ov.tolist()))
+        g = dict(zip(gc.tolist(), gv.tolist()))
+        scale = scales[r] if scales is not None else max(abs(x) for x in o.values())
+        diff = max(abs(o.get(c, 0.0) - g.get(c, 0.0)) for c in set(o) | set(g))
+        worst = max(worst, diff / (tol * scale))
+        assert diff <= tol * scale, (r, diff, scale, tol)
+    return worst

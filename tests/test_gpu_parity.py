@@ -9,6 +9,7 @@ from oracle.solvers import block_reg, block_schur, direct_solve
 from paper_1901_02330_amd.inputs import (LinearSolution, SineSolution, cube_mesh, lognormal_field,
                                          voronoi_mesh)
 from tests.gpu_helpers import assert_same_csr, gpu_solver, rel, to_scipy
+from tests.meshes import single_prism, single_tet
 
 pytestmark = pytest.mark.gpu
 
@@ -18,10 +19,15 @@ def _say(*a):
     sys.stdout.flush()
 
 
+TET = [[0.1, 0.0, 0.0], [1.0, 0.2, 0.0], [0.0, 1.0, 0.1], [0.2, 0.1, 0.9]]
+
 MESHES = {
     "cube8": lambda: cube_mesh(8),
     "cube534": lambda: cube_mesh(5, 3, 4),
     "voronoi80": lambda: voronoi_mesh(80, seed=4),
+    # degenerate sizes: one cell, every face on the boundary
+    "tet1": lambda: single_tet(TET),
+    "prism1": lambda: single_prism(0.7),
 }
 
 
@@ -85,11 +91,13 @@ def test_spmv():
 
 
 @pytest.mark.parametrize("precond", ["schur", "reg"])
-@pytest.mark.parametrize("case", ["cube8_K1", "cube675_lognormal", "voronoi150_lognormal"])
+@pytest.mark.parametrize("case", ["cube8_K1", "cube675_lognormal", "voronoi150_lognormal", "tet1"])
 def test_solve_matches_oracle(case, precond):
     _say("solve", case, precond)
     if case == "cube8_K1":
         m, nu = cube_mesh(8), None
+    elif case == "tet1":
+        m, nu = single_tet(TET), None
     elif case == "cube675_lognormal":
         m = cube_mesh(6, 7, 5)
         nu = 1.0 / lognormal_field(210, 2.0, 0)
