@@ -172,9 +172,11 @@ vem_status vem_get_sizes(vem_handle h, vem_sizes* out);
  * boundary-face points follow the boundary faces in face order. */
 vem_status vem_get_quadrature(vem_handle h, double* qp_cell, double* qp_face);
 
-/* nu = 1/K per cell (device, n_cells doubles, all > 0).  Rescales the flux
- * block M (M_P is proportional to nu_P, Section 4.3) and rebuilds both
- * preconditioners; the local projectors are not recomputed. */
+/* nu = 1/K per cell (device or host, n_cells doubles, all > 0; copied in).
+ * The flux block M (M_P is proportional to nu_P, Section 4.3) and both
+ * preconditioners are rebuilt from the stored coefficient-free local
+ * matrices by the next call that uses them (vem_solve, vem_apply,
+ * vem_export_csr, vem_time_kernel); the local projectors are not recomputed. */
 vem_status vem_set_coefficient(vem_handle h, const double* nu);
 
 /* Right-hand side from point values (device): f_qp[n_qp_cell] at the points

@@ -93,6 +93,10 @@ struct vem_ctx {
   DBuf<double> dM, dMinv, dAinv, dSinv;
   DBuf<float> dAinv32, dSinv32;
   double gamma_A = 0.0;
+  // the coefficient-dependent values (K, A_gamma, S, diagonals, SELL copies) are built on first use
+  // after vem_discretize / vem_set_coefficient, so that a coefficient set right after discretising
+  // costs one build
+  bool values_ready = false;
   int expect_S = 0, expect_A = 0;  // last inner-CG iteration counts (chunk sizing)
 
   // solver workspace
@@ -388,6 +392,11 @@ void rebuild_values(vem_handle h, double gamma) {
   launch_col_scale32(s, h->Ss, h->dSinv, h->dSinv32);
   check_launch();
   h->gamma_A = gamma;
+  h->values_ready = true;
+}
+
+void ensure_values(vem_handle h) {
+  if (!h->values_ready) rebuild_values(h, h->gamma_A > 0 ? h->gamma_A : h->gamma_default);
 }
 
 void ensure_workspace(vem_handle h, int m) {
@@ -924,7 +933,8 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
     launch_fill(s, nc, 1.0, h->nu);
     h->rhs.alloc(N);
     launch_fill(s, N, 0.0, h->rhs);
-    rebuild_values(h, h->gamma_default);
+    h->gamma_A = h->gamma_default;
+    h->values_ready = false;
     sync(h);
     h->has_disc = true;
   });
@@ -973,7 +983,7 @@ vem_status vem_set_coefficient(vem_handle h, const double* nu) {
   return guarded(h, [&] {
     require_disc(h);
     VEM_HIP(hipMemcpyAsync(h->nu.p, nu, h->nc * sizeof(double), hipMemcpyDefault, h->stream));
-    rebuild_values(h, h->gamma_A > 0 ? h->gamma_A : h->gamma_default);
+    h->values_ready = false;
     sync(h);
   });
 }
@@ -1044,6 +1054,7 @@ vem_status vem_apply(vem_handle h, const double* x, double* y) {
   if (!h || !x || !y) return VEM_EINVAL;
   return guarded(h, [&] {
     require_disc(h);
+    ensure_values(h);
     launch_spmv(h->stream, h->Ks, x, y);
     check_launch();
   });
@@ -1053,6 +1064,7 @@ vem_status vem_export_csr(vem_handle h, int which, int32_t* rowptr, int32_t* col
   if (!h) return VEM_EINVAL;
   return guarded(h, [&] {
     require_disc(h);
+    ensure_values(h);
     const Csr* M = which == VEM_MAT_K ? &h->K : which == VEM_MAT_SCHUR ? &h->S : which == VEM_MAT_REG ? &h->A : nullptr;
     VEM_REQUIRE(M, VEM_EINVAL, "unknown matrix");
     hipStream_t s = h->stream;
@@ -1095,6 +1107,7 @@ vem_status vem_time_kernel(vem_handle h, int which, int reps, double* avg_ms, do
   if (!h || !avg_ms || reps < 1) return VEM_EINVAL;
   return guarded(h, [&] {
     require_disc(h);
+    ensure_values(h);
     VEM_REQUIRE(which >= VEM_KERNEL_SPMV && which <= VEM_KERNEL_CG_REG32, VEM_EINVAL, "unknown kernel");
     hipStream_t s = h->stream;
     ensure_workspace(h, std::max(1, h->ws_m));
@@ -1190,8 +1203,9 @@ static vem_status solve_impl(vem_handle h, const vem_solve_opts* opts, const dou
     const int64_t Nu = h->L.Nu, Np = h->L.Np, N = Nu + Np;
     if (o.precond == VEM_PREC_REG) {
       double g = o.gamma > 0 ? o.gamma : h->gamma_default;
-      if (g != h->gamma_A) rebuild_values(h, g);
+      if (g != h->gamma_A || !h->values_ready) rebuild_values(h, g);
     }
+    ensure_values(h);
     ensure_workspace(h, m);
     double* V = h->Vb;
     double* Z = h->Zb;

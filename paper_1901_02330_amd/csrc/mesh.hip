@@ -224,21 +224,38 @@ __global__ void k_bnd_tri_counts(int nb, const int* __restrict__ bface, const in
 }
 
 // One thread per quadrature point: x = O + xi (v0 - O) + eta (v_a - O) + zeta (v_{a+1} - O).
-__global__ void k_qp_cell(int64_t total, int npts, const double* __restrict__ ref, const int* __restrict__ tet_inc,
-                          const int* __restrict__ tet_a, const int* __restrict__ inc_cell,
-                          const double* __restrict__ xyz, const int* __restrict__ fptr,
-                          const int* __restrict__ fvtx, const int* __restrict__ cface,
-                          const double* __restrict__ xref, double* qp) {
-  int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// A block maps kThreads consecutive points; the corners of the (at most kThreads + 1)
+// tetrahedra they belong to are fetched once into LDS instead of once per point.
+__global__ void __launch_bounds__(kThreads) k_qp_cell(int64_t total, int npts, const double* __restrict__ ref,
+                                                      const int* __restrict__ tet_inc, const int* __restrict__ tet_a,
+                                                      const int* __restrict__ inc_cell, const double* __restrict__ xyz,
+                                                      const int* __restrict__ fptr, const int* __restrict__ fvtx,
+                                                      const int* __restrict__ cface, const double* __restrict__ xref,
+                                                      double* qp) {
+  __shared__ double corner[kThreads + 1][12];  // O, v0, v_a, v_{a+1}
+  const int64_t g0 = (int64_t)blockIdx.x * kThreads;
+  const int64_t gl = (g0 + kThreads < total ? g0 + kThreads : total) - 1;
+  const int64_t t0 = g0 / npts;
+  const int nt = (int)(gl / npts - t0 + 1);
+  for (int i = threadIdx.x; i < nt; i += kThreads) {
+    const int64_t t = t0 + i;
+    const int j = tet_inc[t], a = tet_a[t];
+    const int fs = fptr[cface[j]];
+    const V3 v[4] = {ld3(xref, inc_cell[j]), ld3(xyz, fvtx[fs]), ld3(xyz, fvtx[fs + a]), ld3(xyz, fvtx[fs + a + 1])};
+    for (int c = 0; c < 4; ++c) {
+      corner[i][3 * c] = v[c].x;
+      corner[i][3 * c + 1] = v[c].y;
+      corner[i][3 * c + 2] = v[c].z;
+    }
+  }
+  __syncthreads();
+  const int64_t g = g0 + threadIdx.x;
   if (g >= total) return;
-  int64_t t = g / npts;
-  int r = (int)(g - t * npts);
-  int j = tet_inc[t], a = tet_a[t];
-  int f = cface[j];
-  int fs = fptr[f];
-  V3 O = ld3(xref, inc_cell[j]);
-  V3 A = ld3(xyz, fvtx[fs]), B = ld3(xyz, fvtx[fs + a]), C = ld3(xyz, fvtx[fs + a + 1]);
-  double xi = ref[3 * r], eta = ref[3 * r + 1], zeta = ref[3 * r + 2];
+  const int64_t t = g / npts;
+  const int r = (int)(g - t * npts);
+  const double* c = corner[t - t0];
+  const V3 O{c[0], c[1], c[2]}, A{c[3], c[4], c[5]}, B{c[6], c[7], c[8]}, C{c[9], c[10], c[11]};
+  const double xi = ref[3 * r], eta = ref[3 * r + 1], zeta = ref[3 * r + 2];
   st3_soa(qp, total, g, O + xi * (A - O) + eta * (B - O) + zeta * (C - O));
 }
 
@@ -258,24 +275,42 @@ __global__ void k_qp_face(int nb, int npts, int64_t total, const double* __restr
   }
 }
 
-// Per tetrahedron: sigma det * sum_r w_r f(x_r).
-__global__ void k_load_tets(int64_t ntet, int npts, const double* __restrict__ refw, const int* __restrict__ tet_inc,
-                            const int* __restrict__ tet_a, const int* __restrict__ inc_cell,
-                            const double* __restrict__ xyz, const int* __restrict__ fptr,
-                            const int* __restrict__ fvtx, const int* __restrict__ cface,
-                            const int8_t* __restrict__ csign, const double* __restrict__ xref,
-                            const double* __restrict__ fq, double* tet_sum) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ntet) return;
+// Per tetrahedron: sigma det * sum_r w_r f(x_r).  A block takes kThreads consecutive
+// tetrahedra; their point values are contiguous and are read in coalesced chunks
+// through LDS, each thread summing its own points in order.
+__global__ void __launch_bounds__(kThreads) k_load_tets(int64_t ntet, int npts, const double* __restrict__ refw,
+                                                        const int* __restrict__ tet_inc, const int* __restrict__ tet_a,
+                                                        const int* __restrict__ inc_cell,
+                                                        const double* __restrict__ xyz, const int* __restrict__ fptr,
+                                                        const int* __restrict__ fvtx, const int* __restrict__ cface,
+                                                        const int8_t* __restrict__ csign,
+                                                        const double* __restrict__ xref, const double* __restrict__ fq,
+                                                        double* tet_sum) {
+  constexpr int kChunk = 2048;
+  __shared__ double chunk[kChunk];
+  const int64_t t0 = (int64_t)blockIdx.x * kThreads;
+  const int64_t tend = t0 + kThreads < ntet ? t0 + kThreads : ntet;
+  const int64_t t = t0 + threadIdx.x;
+  const int64_t q1 = tend * npts;
+  const int64_t my0 = t * npts, my1 = my0 + npts;
+  double acc = 0.0;
+  for (int64_t c0 = t0 * npts; c0 < q1; c0 += kChunk) {
+    const int64_t c1 = c0 + kChunk < q1 ? c0 + kChunk : q1;
+    __syncthreads();  // the previous chunk has been read
+    for (int64_t q = c0 + threadIdx.x; q < c1; q += kThreads) chunk[q - c0] = fq[q];
+    __syncthreads();
+    if (t < tend) {
+      const int64_t a = my0 > c0 ? my0 : c0, b = my1 < c1 ? my1 : c1;
+      for (int64_t q = a; q < b; ++q) acc += refw[q - my0] * chunk[q - c0];
+    }
+  }
+  if (t >= tend) return;
   int j = tet_inc[t], a = tet_a[t];
   int f = cface[j];
   int fs = fptr[f];
   V3 O = ld3(xref, inc_cell[j]);
   V3 A = ld3(xyz, fvtx[fs]), B = ld3(xyz, fvtx[fs + a]), C = ld3(xyz, fvtx[fs + a + 1]);
   double det = dot(A - O, cross(B - O, C - O)) * (double)csign[j];
-  const double* fv = fq + t * npts;
-  double acc = 0.0;
-  for (int r = 0; r < npts; ++r) acc += refw[r] * fv[r];
   tet_sum[t] = det * acc;
 }
 
