@@ -227,7 +227,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str):
         out.append(f"| `{key[0]}` | {key[1]} | {len(fetch[key])} | {fm / 1e6:.1f} | {wm / 1e6:.1f} | "
                    f"{(fm + wm) / 1e6:.1f} |")
     # the dominant kernel: pipelined CG iteration on M + B^T B / gamma (the larger k_ppcg_iter grid)
-    it = sorted((k for k in rows if k[0] == "k_ppcg_iter<double, false>"), key=lambda k: -k[1])
+    it = sorted((k for k in rows if k[0].startswith("k_ppcg_iter<double, false")), key=lambda k: -k[1])
     fm, wm = rows[it[0]]
     alg = probe["kernels"]["cg_reg"]["algorithmic_bytes"]
     src = os.path.join(ROOT, "paper_1901_02330_amd", "csrc", "krylov.hip")

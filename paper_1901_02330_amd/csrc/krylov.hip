@@ -300,8 +300,8 @@ struct PcgViewT {
 
 // w = (A D^{-1}) b, x = 0, r = b; partials of gamma_0, delta_0 (slot 0).  b is FP64 and is
 // rounded to T element by element (also where it is gathered).
-template <typename T>
-__global__ void __launch_bounds__(kPcgThreads) k_ppcg_init(SellViewT<T> Ac, PcgViewT<T> v,
+template <typename T, int kBlock>
+__global__ void __launch_bounds__(kBlock) k_ppcg_init(SellViewT<T> Ac, PcgViewT<T> v,
                                                            const double* __restrict__ b, PcgState* st, double tol2,
                                                            int maxit, double* __restrict__ part) {
   double acc[2] = {0.0, 0.0};
@@ -328,8 +328,8 @@ __global__ void __launch_bounds__(kPcgThreads) k_ppcg_init(SellViewT<T> Ac, PcgV
 }
 
 // One pipelined CG iteration.  Vectors and matrix values in T; scalars and dot products in FP64.
-template <typename T, bool kFirst>
-__global__ void __launch_bounds__(kPcgThreads) k_ppcg_iter(int parity, SellViewT<T> Ac, PcgViewT<T> v, PcgState* st,
+template <typename T, bool kFirst, int kBlock>
+__global__ void __launch_bounds__(kBlock) k_ppcg_iter(int parity, SellViewT<T> Ac, PcgViewT<T> v, PcgState* st,
                                                            double* __restrict__ part) {
   const int P = gridDim.x;
   const int cur = parity;
@@ -543,9 +543,10 @@ inline int stream_grid(int64_t n) {
   return (int)(b < cap ? (b < 1 ? 1 : b) : cap);
 }
 
-inline int pcg_grid(int64_t n) {
-  int64_t b = (n + kPcgThreads - 1) / kPcgThreads;
-  return (int)(b < kPcgBlocks ? (b < 1 ? 1 : b) : kPcgBlocks);
+inline int pcg_grid(int64_t n, int block = kPcgThreads) {
+  const int64_t cap = kPcgMaxThreads / block;
+  int64_t b = (n + block - 1) / block;
+  return (int)(b < cap ? (b < 1 ? 1 : b) : cap);
 }
 
 #define VEM_K_CASES(X) \
@@ -665,17 +666,35 @@ void launch_to_f64(hipStream_t s, int64_t n, const float* x, double* y) {
   if (n > 0) k_to_f64<<<stream_grid(n), kThreads, 0, s>>>(n, x, y);
 }
 
+template <int kBlock>
+void pcg_init_as(hipStream_t s, const Sell& A, const PcgWork& w, const double* b, PcgState* st, double tol, int maxit,
+                 double* part) {
+  k_ppcg_init<double, kBlock><<<pcg_grid(A.rows, kBlock), kBlock, 0, s>>>(view_cs(A), pview(w), b, st, tol * tol,
+                                                                           maxit, part);
+}
+
+template <int kBlock>
+void pcg_iter_as(hipStream_t s, int i, const Sell& A, const PcgWork& w, PcgState* st, double* part) {
+  const int P = pcg_grid(A.rows, kBlock);
+  if (i == 0)
+    k_ppcg_iter<double, true, kBlock><<<P, kBlock, 0, s>>>(0, view_cs(A), pview(w), st, part);
+  else
+    k_ppcg_iter<double, false, kBlock><<<P, kBlock, 0, s>>>(i & 1, view_cs(A), pview(w), st, part);
+}
+
 void launch_pcg_init(hipStream_t s, const Sell& A, const PcgWork& w, const double* b, PcgState* st, double tol,
                      int maxit, double* part) {
-  k_ppcg_init<double><<<pcg_grid(A.rows), kPcgThreads, 0, s>>>(view_cs(A), pview(w), b, st, tol * tol, maxit, part);
+  if (A.rows > kPcgMaxThreads)  // threads loop over rows
+    pcg_init_as<256>(s, A, w, b, st, tol, maxit, part);
+  else
+    pcg_init_as<1024>(s, A, w, b, st, tol, maxit, part);
 }
 
 void launch_pcg_iter(hipStream_t s, int i, const Sell& A, const PcgWork& w, PcgState* st, double* part) {
-  const int P = pcg_grid(A.rows);
-  if (i == 0)
-    k_ppcg_iter<double, true><<<P, kPcgThreads, 0, s>>>(0, view_cs(A), pview(w), st, part);
+  if (A.rows > kPcgMaxThreads)  // threads loop over rows
+    pcg_iter_as<256>(s, i, A, w, st, part);
   else
-    k_ppcg_iter<double, false><<<P, kPcgThreads, 0, s>>>(i & 1, view_cs(A), pview(w), st, part);
+    pcg_iter_as<1024>(s, i, A, w, st, part);
 }
 
 void launch_pcg_init32(hipStream_t s, const Sell& A, const PcgWork32& w, const double* b, PcgState* st, double tol,

@@ -99,12 +99,15 @@ constexpr int kRedThreads = 256;
 constexpr int kMaxDots = 34;       // largest number of simultaneous dot products
 constexpr int kMaxRestart = 32;
 constexpr int kMaxCellFaces = 64;
-// Largest grid of the inner-CG kernels: 256 CUs x 2 resident blocks of 1024 threads
-// (8 waves per SIMD), so that the whole grid is resident in one round.  Larger
-// systems loop over rows; a second round of blocks would pay the partial-sum
-// prologue again (measured 10% slower on the 64^3 A_gamma iteration).
-constexpr int kPcgBlocks = 512;
-constexpr int kPcgThreads = 1024;  // block size of the inner-CG kernels
+// Inner-CG grids: at most 256 CUs x 2048 resident threads, so that the whole grid is
+// resident in one round (larger systems loop over rows; a second round of blocks would
+// pay the partial-sum prologue again: 10% slower on the 64^3 A_gamma iteration).  The
+// FP64 pipelined iteration takes 1024-thread blocks when every row has a thread, and
+// 256-thread blocks when threads loop over rows (measured on 64^3: S 10.8 us with 1024
+// against 11.7 us with 256; A_gamma 31.5 us with 256 against 33.5 us with 1024).
+constexpr int kPcgMaxThreads = 256 * 2048;
+constexpr int kPcgBlocks = kPcgMaxThreads / 256;  // most blocks of any inner-CG grid
+constexpr int kPcgThreads = 1024;  // block size of the FP32 inner-CG kernels
 
 // Device-resident state of one inner (pipelined) Jacobi-CG solve.  `count` is
 // reset by every init kernel; `total` sums the iterations of all inner solves
