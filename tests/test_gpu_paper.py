@@ -129,3 +129,19 @@ def test_paper_mixed_precision_voronoi(precond):
     eu, ep = rel(xg[: d["Nu"]], x[: d["Nu"]]), rel(xg[d["Nu"]:], x[d["Nu"]:])
     _say(info, "backward error", berr, "error vs FP64 oracle: u", eu, "p", ep)
     assert berr <= 1.5 * tol
+
+
+def test_gpu_sizes_match_the_papers_cube_tables():
+    """The library's unknown counts on the paper's Cube meshes equal the DOF counts its tables print,
+    minus the one global unknown of the paper's zero-mean pressure constraint (Tables 1 and 4)."""
+    import json
+    import os
+
+    golden = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_dof_counts.json")))
+    for row in golden["cube"]:
+        n = round(row["cells"] ** (1 / 3))
+        assert n**3 == row["cells"]
+        _say("paper sizes cube", n, "k", row["k"])
+        s = solver_for(cube_mesh(n), row["k"])
+        assert s.sizes()["n"] + 1 == row["dofs"], (row, s.sizes()["n"])
+        s.close()
