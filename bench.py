@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--pmc-probe", action="store_true",
                     help="short run for rocprofv3 --pmc: discretize, 20 launches of each hot kernel, and a plain "
                          "256 MiB device copy that calibrates FETCH_SIZE / WRITE_SIZE")
+    ap.add_argument("--k2-batch", type=int, default=0, metavar="FIELDS",
+                    help="also time FIELDS log-normal fields (sigma 1.5, seeds 0..) on the Cube 32^3 k=2 mesh: "
+                         "Block-Reg with FP32 inner solves, sequential and on FIELDS concurrent lanes (minutes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=32, help="Cube size of the CPU oracle sample")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
@@ -376,6 +379,30 @@ def extras(args, torch, dev):
     return out
 
 
+def k2_batch(fields, torch, dev):
+    """Fields seeds 0..fields-1 (log K = 1.5 N(0,1)) on the Cube 32^3 mesh, the paper's k = 2, Block-Reg
+    with FP32 inner solves to 1e-8: one lane (sequential) and `fields` concurrent lanes."""
+    from paper_1901_02330_amd.batch import BatchSolver, percentiles
+    from paper_1901_02330_amd.inputs import SineSolution, cube_mesh, lognormal_field
+
+    nus = [torch.as_tensor(1.0 / lognormal_field(32**3, 1.5, sd), device=dev) for sd in range(fields)]
+    kw = dict(precond="reg", tol=1e-8, inner_tol=1e-1, precision="mixed", maxit=1000)
+    out = {"fields": fields, "note": "a sample of the 64-field batch; each solve takes seconds"}
+    for lanes in (1, fields):
+        bs = BatchSolver(cube_mesh(32), lanes=lanes, family="paper", k=2, rhs=SineSolution())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, infos = bs.solve(nus, **kw)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[f"lanes{lanes}"] = {"solves_per_s": fields / wall, "wall_s": wall,
+                                "iterations": [i["iterations"] for i in infos],
+                                "converged": all(i["converged"] for i in infos), **percentiles(infos)}
+        log(f"k2 batch lanes {lanes}: {wall:.1f} s")
+        bs.close()
+    return out
+
+
 def main():
     args = parse()
     if args.summarize_pmc:
@@ -493,6 +520,9 @@ def main():
     if not args.no_extras:
         log("extras ...")
         line["extras"] = extras(args, torch, dev)
+    if args.k2_batch > 0:
+        log("k=2 batch ...")
+        line.setdefault("extras", {})["batch_cube32_k2"] = k2_batch(args.k2_batch, torch, dev)
     tr = traffic_from_profiles()
     if tr is not None:
         line["roofline"]["traffic"] = tr["bytes_per_launch"]
