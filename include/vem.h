@@ -74,6 +74,11 @@ enum { VEM_MEM_HOST = 0, VEM_MEM_DEVICE = 1 };
 enum { VEM_LO = 0, VEM_PAPER = 1 };
 
 enum { VEM_PREC_SCHUR = 0, VEM_PREC_REG = 1, VEM_PREC_NONE = 2 };
+/* Boundary data (vem_set_boundary).  VEM_BC_PRESSURE: the pressure p_D is given on the whole
+ * boundary (natural in mixed form, the default).  VEM_BC_FLUX: the normal flux u.n = u_N is given on
+ * the whole boundary and the pressure has zero mean, the paper's model problem (Section 3, eq.
+ * mod_prob_eq; its DOF counts add one multiplier for the mean). */
+enum { VEM_BC_PRESSURE = 0, VEM_BC_FLUX = 1 };
 
 /* Arithmetic of the inner preconditioner solves.  VEM_FP64: everything in
  * FP64.  VEM_MIXED: the inner Jacobi-CG of either block preconditioner runs
@@ -182,6 +187,26 @@ vem_status vem_set_coefficient(vem_handle h, const double* nu);
 /* Right-hand side from point values (device): f_qp[n_qp_cell] at the points
  * of vem_get_quadrature, pD_qp[n_qp_face] (NULL means p_D = 0). */
 vem_status vem_set_rhs(vem_handle h, const double* f_qp, const double* pD_qp);
+
+/* Select the boundary data: VEM_BC_PRESSURE (the default) or VEM_BC_FLUX, before or after
+ * vem_discretize; a change clears the right-hand side.  With VEM_BC_FLUX the DOFs of the
+ * boundary faces are prescribed: they hold identity rows and columns in K and A_gamma, B has no
+ * column for them (so S neither), the right-hand side comes from vem_set_rhs_flux, Block-Schur's
+ * inner solve takes the part of r_p orthogonal to the constant pressure (the kernel of S), and
+ * vem_solve returns, of the pressures that solve the system, the one with zero mean
+ * (sum_P |P| p_{P,0} = 0).  vem_set_rhs then fails with VEM_EINVAL. */
+vem_status vem_set_boundary(vem_handle h, int kind);
+
+/* Right-hand side with flux boundary data (Section 3, eq. mod_prob_eq): f_qp[n_qp_cell] as in
+ * vem_set_rhs, and u_qp[3*n_qp_face] the flux field u at the boundary points of
+ * vem_get_quadrature (structure of arrays: all x components, then y, then z; device).  The
+ * prescribed DOFs are the face moments (1/|f|) int_f (u.n_f) m^f_b (eq. facePoly) with n_f the
+ * face's global normal.  The system's right-hand side (b - K x_B on the free rows, x_B on the
+ * prescribed ones, its pressure part projected off the constant pressure, which removes the
+ * quadrature-level mismatch between int f and the boundary flux) depends on the coefficient and
+ * is formed when it is used; vem_get_rhs returns it.  VEM_EINVAL unless the boundary data kind is
+ * VEM_BC_FLUX. */
+vem_status vem_set_rhs_flux(vem_handle h, const double* f_qp, const double* u_qp);
 
 /* Solve.  u[n_u], p[n_p]: caller-owned device buffers receiving the flux and
  * pressure unknowns (read as the initial guess when opts->use_x0).  Blocks

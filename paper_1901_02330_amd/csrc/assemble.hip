@@ -44,6 +44,12 @@ __device__ inline double ldof_sign(const DofLayout& L, const int* cptr, const in
   return l < F * L.nfd ? (double)csign[s + l / L.nfd] : 1.0;
 }
 
+// With flux boundary data (bnd != nullptr: bnd[f] = 1 on boundary faces) the DOFs of the
+// boundary faces are prescribed.
+__device__ inline bool fixed_dof(const DofLayout& L, const int* bnd, int64_t gid) {
+  return bnd && gid < (int64_t)L.nf * L.nfd && bnd[gid / L.nfd];
+}
+
 // Cells holding flux DOF d (ascending cell id) and the DOF's local index in each.
 __device__ inline int dof_cells(const DofLayout& L, int64_t d, const int* cptr, const int* face_cell,
                                 const int* face_lidx, int P[2], int l[2]) {
@@ -223,9 +229,11 @@ __global__ void k_values(DofLayout L, const int* __restrict__ cptr, const int* _
                          const int* __restrict__ face_cell, const int* __restrict__ face_lidx,
                          const int64_t* __restrict__ lmat_ptr, const double* __restrict__ M1,
                          const int64_t* __restrict__ lb_ptr, const double* __restrict__ Bdiv1,
-                         const double* __restrict__ nu, double inv_gamma, const int* __restrict__ Kptr,
-                         double* Kval, const int* __restrict__ Aptr, double* Aval) {
+                         const double* __restrict__ nu, double inv_gamma, const int* __restrict__ bnd,
+                         const int* __restrict__ Kptr, double* Kval, const int* __restrict__ Aptr, double* Aval) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // prescribed flux DOFs: identity rows and columns in K and A_gamma
+  const bool fixed_row = r < L.Nu && fixed_dof(L, bnd, r);
   if (r < L.Nu) {
     int P[2], l[2];
     int nc = dof_cells(L, r, cptr, face_cell, face_lidx, P, l);
@@ -269,11 +277,15 @@ __global__ void k_values(DofLayout L, const int* __restrict__ cptr, const int* _
         bb += ss * t;
         ++ib;
       }
+      if (fixed_row || fixed_dof(L, bnd, g)) {
+        mv = g == r ? 1.0 : 0.0;
+        bb = 0.0;
+      }
       Kval[k++] = mv;
       Aval[a++] = mv + inv_gamma * bb;
     }
     for (int s = 0; s < nc; ++s)
-      for (int q = 0; q < L.npd; ++q) Kval[k++] = -sr[s] * Bp[s][q * nd[s] + l[s]];
+      for (int q = 0; q < L.npd; ++q) Kval[k++] = fixed_row ? 0.0 : -sr[s] * Bp[s][q * nd[s] + l[s]];
   } else if (r < L.Nu + L.Np) {
     int64_t q = r - L.Nu;
     int P = (int)(q / L.npd), g = (int)(q - (int64_t)P * L.npd);
@@ -282,7 +294,7 @@ __global__ void k_values(DofLayout L, const int* __restrict__ cptr, const int* _
     int k = Kptr[r];
     for (int i = ldof_ptr[P]; i < ldof_ptr[P + 1]; ++i) {
       int lg = sorted_l[i];
-      Kval[k++] = -ldof_sign(L, cptr, csign, P, lg) * Bp[lg];
+      Kval[k++] = fixed_dof(L, bnd, sorted_gid[i]) ? 0.0 : -ldof_sign(L, cptr, csign, P, lg) * Bp[lg];
     }
   }
 }
@@ -301,8 +313,8 @@ __global__ void k_schur_values(DofLayout L, const int* __restrict__ cptr, const 
                                const int8_t* __restrict__ csign, const int* __restrict__ ldof_ptr,
                                const int* __restrict__ face_cell, const int* __restrict__ face_lidx,
                                const int64_t* __restrict__ lb_ptr, const double* __restrict__ Bdiv1,
-                               const double* __restrict__ dM, const int* __restrict__ Sptr,
-                               const int* __restrict__ Scol, double* Sval) {
+                               const double* __restrict__ dM, const int* __restrict__ bnd,
+                               const int* __restrict__ Sptr, const int* __restrict__ Scol, double* Sval) {
   int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= L.Np) return;
   int P = (int)(q / L.npd), g = (int)(q - (int64_t)P * L.npd);
@@ -318,6 +330,7 @@ __global__ void k_schur_values(DofLayout L, const int* __restrict__ cptr, const 
         int gid;
         double sg;
         ldof_gid_sign(L, cptr, cface, csign, P, l, gid, sg);
+        if (fixed_dof(L, bnd, gid)) continue;  // B has no column for a prescribed flux
         v += BP[g * ndP + l] * BP[e * ndP + l] / dM[gid];  // the two signs cancel
       }
     } else {
@@ -337,6 +350,68 @@ __global__ void k_schur_values(DofLayout L, const int* __restrict__ cptr, const 
     }
     Sval[k] = v;
   }
+}
+
+// Right-hand side with flux boundary data: out = b - K xB on the free rows and out = xB on the
+// prescribed ones, with xB the prescribed fluxes (zero elsewhere).  K xB is formed from the
+// coefficient-free local matrices (only prescribed columns contribute), so it does not depend on the
+// identity rows K holds in this mode.  One thread per row, the row's cells in a fixed order.
+__global__ void k_flux_rhs(DofLayout L, const int* __restrict__ cptr, const int* __restrict__ cface,
+                           const int8_t* __restrict__ csign, const int* __restrict__ face_cell,
+                           const int* __restrict__ face_lidx, const int64_t* __restrict__ lmat_ptr,
+                           const double* __restrict__ M1, const int64_t* __restrict__ lb_ptr,
+                           const double* __restrict__ Bdiv1, const double* __restrict__ nu,
+                           const int* __restrict__ bnd, const double* __restrict__ xB,
+                           const double* __restrict__ b, double* __restrict__ out) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= L.Nu + L.Np) return;
+  double acc = 0.0;
+  if (r < L.Nu) {
+    if (fixed_dof(L, bnd, r)) {
+      out[r] = xB[r];
+      return;
+    }
+    int P[2], l[2];
+    int nc = dof_cells(L, r, cptr, face_cell, face_lidx, P, l);
+    for (int c = 0; c < nc; ++c) {
+      const int nd = ndof_of(L, cptr, P[c]);
+      const double sr = ldof_sign(L, cptr, csign, P[c], l[c]);
+      const double* Mrow = M1 + lmat_ptr[P[c]] + (int64_t)l[c] * nd;
+      const int F = cptr[P[c] + 1] - cptr[P[c]];
+      for (int j = 0; j < F * L.nfd; ++j) {
+        int gid;
+        double sg;
+        ldof_gid_sign(L, cptr, cface, csign, P[c], j, gid, sg);
+        if (fixed_dof(L, bnd, gid)) acc += nu[P[c]] * sr * sg * Mrow[j] * xB[gid];
+      }
+    }
+  } else {
+    const int64_t q = r - L.Nu;
+    const int P = (int)(q / L.npd), g = (int)(q - (int64_t)P * L.npd);
+    const int nd = ndof_of(L, cptr, P);
+    const double* Bp = Bdiv1 + lb_ptr[P] + (int64_t)g * nd;
+    const int F = cptr[P + 1] - cptr[P];
+    for (int j = 0; j < F * L.nfd; ++j) {
+      int gid;
+      double sg;
+      ldof_gid_sign(L, cptr, cface, csign, P, j, gid, sg);
+      if (fixed_dof(L, bnd, gid)) acc += -sg * Bp[j] * xB[gid];
+    }
+  }
+  out[r] = b[r] - acc;
+}
+
+// The discrete constant pressure n_p (the moment DOFs of p = 1: (1/|P|) int_P m_a, from the
+// cell monomial moments when given, else 1) and the mean weights w (w . p = int_Omega p_h:
+// |P| on the moment of the constant, 0 on the others).
+__global__ void k_pressure_constants(DofLayout L, int nsm, const double* __restrict__ cmom,
+                                     const double* __restrict__ cvol, double* __restrict__ np,
+                                     double* __restrict__ w) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= L.Np) return;
+  const int P = (int)(q / L.npd), a = (int)(q - (int64_t)P * L.npd);
+  np[q] = cmom ? cmom[(int64_t)P * nsm + a] / cvol[P] : 1.0;
+  w[q] = a == 0 ? cvol[P] : 0.0;
 }
 
 // g[P] = nu_P lambda_P^T M1_P u_P over the cell's oriented local flux DOFs (one wavefront per cell)
@@ -410,20 +485,32 @@ void launch_fill_patterns(hipStream_t s, DofLayout L, const int* cptr, const int
 void launch_values(hipStream_t s, DofLayout L, const int* cptr, const int* cface, const int8_t* csign,
                    const int* ldof_ptr, const int* sorted_gid, const int* sorted_l, const int* face_cell,
                    const int* face_lidx, const int64_t* lmat_ptr, const double* M1, const int64_t* lb_ptr,
-                   const double* Bdiv1, const double* nu, double inv_gamma, const int* Kptr, double* Kval,
-                   const int* Aptr, double* Aval) {
+                   const double* Bdiv1, const double* nu, double inv_gamma, const int* bnd, const int* Kptr,
+                   double* Kval, const int* Aptr, double* Aval) {
   k_values<<<nblocks(L.Nu + L.Np), kThreads, 0, s>>>(L, cptr, cface, csign, ldof_ptr, sorted_gid, sorted_l,
                                                      face_cell, face_lidx, lmat_ptr, M1, lb_ptr, Bdiv1, nu,
-                                                     inv_gamma, Kptr, Kval, Aptr, Aval);
+                                                     inv_gamma, bnd, Kptr, Kval, Aptr, Aval);
+}
+void launch_flux_rhs(hipStream_t s, DofLayout L, const int* cptr, const int* cface, const int8_t* csign,
+                     const int* face_cell, const int* face_lidx, const int64_t* lmat_ptr, const double* M1,
+                     const int64_t* lb_ptr, const double* Bdiv1, const double* nu, const int* bnd, const double* xB,
+                     const double* b, double* out) {
+  k_flux_rhs<<<nblocks(L.Nu + L.Np), kThreads, 0, s>>>(L, cptr, cface, csign, face_cell, face_lidx, lmat_ptr, M1,
+                                                       lb_ptr, Bdiv1, nu, bnd, xB, b, out);
+}
+void launch_pressure_constants(hipStream_t s, DofLayout L, int nsm, const double* cmom, const double* cvol,
+                               double* np, double* w) {
+  if (L.Np > 0) k_pressure_constants<<<nblocks(L.Np), kThreads, 0, s>>>(L, nsm, cmom, cvol, np, w);
 }
 void launch_diag_inv(hipStream_t s, int64_t n, const int* diagpos, const double* val, double* d, double* dinv) {
   if (n > 0) k_diag_inv<<<nblocks(n), kThreads, 0, s>>>(n, diagpos, val, d, dinv);
 }
 void launch_schur_values(hipStream_t s, DofLayout L, const int* cptr, const int* cface, const int8_t* csign,
                          const int* ldof_ptr, const int* face_cell, const int* face_lidx, const int64_t* lb_ptr,
-                         const double* Bdiv1, const double* dM, const int* Sptr, const int* Scol, double* Sval) {
+                         const double* Bdiv1, const double* dM, const int* bnd, const int* Sptr, const int* Scol,
+                         double* Sval) {
   k_schur_values<<<nblocks(L.Np), kThreads, 0, s>>>(L, cptr, cface, csign, ldof_ptr, face_cell, face_lidx, lb_ptr,
-                                                    Bdiv1, dM, Sptr, Scol, Sval);
+                                                    Bdiv1, dM, bnd, Sptr, Scol, Sval);
 }
 
 }  // namespace vem

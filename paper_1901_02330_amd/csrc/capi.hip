@@ -112,6 +112,11 @@ struct vem_ctx {
   // the events that mark each step's copy (steps alternate between the two)
   HBuf<double> hcol;
   Scratch tmp;  // temporaries of the set-up calls
+  // boundary data: VEM_BC_PRESSURE (natural, in g) or VEM_BC_FLUX (prescribed boundary fluxes xB and
+  // a zero-mean pressure; n_p is the discrete constant pressure, pw the mean weights)
+  int bc = VEM_BC_PRESSURE;
+  DBuf<double> xB, rhs_flux, n_p, pw, ptmp;
+  double np_nn = 1.0, np_wn = 1.0;
   hipEvent_t step_done[2] = {nullptr, nullptr};
   HBuf<PcgState> hpcg;
 };
@@ -374,14 +379,15 @@ double device_sum(vem_handle h, const double* x, int64_t n) {
 void rebuild_values(vem_handle h, double gamma) {
   hipStream_t s = h->stream;
   DofLayout L = h->L;
+  const int* bnd = h->bc == VEM_BC_FLUX ? h->is_bnd.p : nullptr;
   launch_values(s, L, h->cptr, h->cface, h->csign, h->ldof_ptr, h->sorted_gid, h->sorted_l, h->face_cell,
-                h->face_lidx, h->lmat_ptr, h->M1, h->lb_ptr, h->Bdiv1, h->nu, 1.0 / gamma, h->K.rowptr,
+                h->face_lidx, h->lmat_ptr, h->M1, h->lb_ptr, h->Bdiv1, h->nu, 1.0 / gamma, bnd, h->K.rowptr,
                 h->K.val, h->A.rowptr, h->A.val);
   check_launch();
   launch_diag_inv(s, L.Nu, h->Kdiag, h->K.val, h->dM, h->dMinv);
   launch_diag_inv(s, L.Nu, h->Adiag, h->A.val, nullptr, h->dAinv);
   launch_schur_values(s, L, h->cptr, h->cface, h->csign, h->ldof_ptr, h->face_cell, h->face_lidx, h->lb_ptr,
-                      h->Bdiv1, h->dM, h->S.rowptr, h->S.col, h->S.val);
+                      h->Bdiv1, h->dM, bnd, h->S.rowptr, h->S.col, h->S.val);
   launch_diag_inv(s, L.Np, h->Sdiag, h->S.val, nullptr, h->dSinv);
   refresh_sell(s, h->K, h->Ks);
   refresh_sell(s, h->A, h->As);
@@ -535,10 +541,20 @@ void apply_prec(vem_handle h, const vem_solve_opts& o, const double* v, double* 
   hipStream_t s = h->stream;
   const int64_t Nu = h->L.Nu, Np = h->L.Np;
   switch (o.precond) {
-    case VEM_PREC_SCHUR:
+    case VEM_PREC_SCHUR: {
       launch_scale_by(s, Nu, v, h->dMinv, 1.0, z);
-      inner_pcg(h, h->Ss, h->dSinv, h->dSinv32, v + Nu, z + Nu, o, h->expect_S, h->gS, h->gS32);
+      const double* rp = v + Nu;
+      if (h->bc == VEM_BC_FLUX) {
+        // S has the constant pressure in its kernel: the inner CG takes the part of r_p
+        // orthogonal to it (its own range)
+        double* d = h->scal.p + 4 * kMaxDots;
+        launch_dots(s, Np, 1, h->n_p, Np, rp, h->partials, d);
+        launch_project(s, Np, rp, h->n_p, d, 1.0 / h->np_nn, h->ptmp);
+        rp = h->ptmp;
+      }
+      inner_pcg(h, h->Ss, h->dSinv, h->dSinv32, rp, z + Nu, o, h->expect_S, h->gS, h->gS32);
       return;
+    }
     case VEM_PREC_REG:
       inner_pcg(h, h->As, h->dAinv, h->dAinv32, v, z, o, h->expect_A, h->gA, h->gA32);
       launch_scale_by(s, Np, v + Nu, nullptr, 1.0 / h->gamma_A, z + Nu);
@@ -546,6 +562,94 @@ void apply_prec(vem_handle h, const vem_solve_opts& o, const double* v, double* 
     default:
       launch_copy(s, Nu + Np, v, z);
   }
+}
+
+// Right-hand side with flux boundary data (needs the values): the known fluxes move to the right, the
+// prescribed rows carry them, and the pressure part is projected off the constant pressure (this
+// removes the quadrature-level mismatch between int f and the boundary flux, so the system is
+// consistent).
+const double* flux_rhs(vem_handle h) {
+  hipStream_t s = h->stream;
+  const DofLayout L = h->L;
+  ensure_values(h);
+  launch_flux_rhs(s, L, h->cptr, h->cface, h->csign, h->face_cell, h->face_lidx, h->lmat_ptr, h->M1, h->lb_ptr,
+                  h->Bdiv1, h->nu, h->is_bnd, h->xB, h->rhs, h->rhs_flux);
+  double* d = h->scal.p + 4 * kMaxDots;
+  double* bp = h->rhs_flux.p + L.Nu;
+  launch_dots(s, L.Np, 1, h->n_p, L.Np, bp, h->partials, d);
+  launch_project(s, L.Np, bp, h->n_p, d, 1.0 / h->np_nn, bp);
+  check_launch();
+  return h->rhs_flux.p;
+}
+
+// Loads F from f at the cell points, and either the pressure term g from p_D at the boundary points
+// or the prescribed boundary fluxes xB from u at the boundary points (structure of arrays).
+void set_loads(vem_handle h, const double* f_qp, const double* pD_qp, const double* u_qp) {
+    hipStream_t s = h->stream;
+    const int64_t nqf = (int64_t)h->nbtri * h->npts_face;
+    if (u_qp) launch_fill(s, h->L.Nu, 0.0, h->xB);
+    launch_fill(s, h->L.Nu, 0.0, h->rhs);
+    DBuf<double>& tsum = h->tmp.f64[0];
+    if (h->family == VEM_LO) {
+      tsum.reserve(h->ntet);
+      launch_load_tets(s, h->ntet, h->npts_cell, h->qw_cell, h->tet_inc, h->tet_a, h->inc_cell, h->xyz, h->fptr,
+                       h->fvtx, h->cface, h->csign, h->c_xref, f_qp, tsum);
+      launch_load_cells(s, h->nc, h->cell_tet_ptr, tsum, h->rhs.p + h->L.Nu);
+      if (pD_qp)
+        launch_bnd_rhs(s, (int)h->nbf, h->npts_face, h->qw_face, h->bface, h->btri_ptr, h->xyz, h->fptr, h->fvtx,
+                       h->face_cell, pD_qp, h->rhs);
+      if (u_qp)
+        launch_bnd_flux(s, (int)h->nbf, h->npts_face, nqf, h->qw_face, h->bface, h->btri_ptr, h->xyz, h->fptr,
+                        h->fvtx, h->f_normal, h->f_area, u_qp, h->xB);
+    } else {
+      tsum.reserve((size_t)h->ntet * h->L.npd);
+      PaperLoadArgs a{};
+      a.s = s;
+      a.nc = h->nc;
+      a.nb = (int)h->nbf;
+      a.npts_cell = h->npts_cell;
+      a.npts_face = h->npts_face;
+      a.ntet = h->ntet;
+      a.ref_cell = h->qref_cell;
+      a.w_cell = h->qw_cell;
+      a.ref_face = h->qref_face;
+      a.w_face = h->qw_face;
+      a.tet_inc = h->tet_inc;
+      a.tet_a = h->tet_a;
+      a.inc_cell = h->inc_cell;
+      a.fptr = h->fptr;
+      a.fvtx = h->fvtx;
+      a.cface = h->cface;
+      a.cell_tet_ptr = h->cell_tet_ptr;
+      a.bface = h->bface;
+      a.btri_ptr = h->btri_ptr;
+      a.face_cell = h->face_cell;
+      a.csign = h->csign;
+      a.xyz = h->xyz;
+      a.xref = h->c_xref;
+      a.ccen = h->c_cen;
+      a.cdiam = h->c_diam;
+      a.cvol = h->c_vol;
+      a.cmom = h->pk_cmom;
+      a.fcen = h->f_cen;
+      a.fdiam = h->f_diam;
+      a.fe1 = h->f_e1;
+      a.fe2 = h->f_e2;
+      a.Tf = h->pk_Tf;
+      a.fq = f_qp;
+      a.pq = pD_qp;
+      a.tet_sum = tsum;
+      a.rhs_p = h->rhs.p + h->L.Nu;
+      a.rhs_u = h->rhs;
+      a.uq = u_qp;
+      a.fnormal = h->f_normal;
+      a.farea = h->f_area;
+      a.nq_face_total = nqf;
+      a.xB = h->xB;
+      launch_paper_loads(h->korder, a);
+    }
+    check_launch();
+    sync(h);
 }
 
 void require_disc(vem_handle h) {
@@ -933,6 +1037,26 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
     launch_fill(s, nc, 1.0, h->nu);
     h->rhs.alloc(N);
     launch_fill(s, N, 0.0, h->rhs);
+    // flux boundary data: prescribed fluxes, the constant pressure and the mean weights
+    h->xB.alloc(L.Nu);
+    launch_fill(s, L.Nu, 0.0, h->xB);
+    h->rhs_flux.alloc(N);
+    h->n_p.alloc(L.Np);
+    h->pw.alloc(L.Np);
+    h->ptmp.alloc(L.Np);
+    launch_pressure_constants(s, L, family == VEM_PAPER ? paper_sizes(k).nsm : 0,
+                              family == VEM_PAPER ? h->pk_cmom.p : nullptr, h->c_vol, h->n_p, h->pw);
+    {
+      double* d = h->scal.p + 4 * kMaxDots;
+      double two[2];
+      launch_dots(s, L.Np, 1, h->n_p, L.Np, h->n_p, h->partials, d);
+      launch_dots(s, L.Np, 1, h->pw, L.Np, h->n_p, h->partials, d + 1);
+      check_launch();
+      VEM_HIP(hipMemcpyAsync(two, d, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+      sync(h);
+      h->np_nn = two[0];
+      h->np_wn = two[1];
+    }
     h->gamma_A = h->gamma_default;
     h->values_ready = false;
     sync(h);
@@ -988,65 +1112,38 @@ vem_status vem_set_coefficient(vem_handle h, const double* nu) {
   });
 }
 
+vem_status vem_set_boundary(vem_handle h, int kind) {
+  if (!h) return VEM_EINVAL;
+  return guarded(h, [&] {
+    VEM_REQUIRE(kind == VEM_BC_PRESSURE || kind == VEM_BC_FLUX, VEM_EINVAL, "unknown boundary data kind");
+    if (kind != h->bc) {
+      h->bc = kind;
+      h->values_ready = false;
+      if (h->has_disc) {
+        launch_fill(h->stream, h->L.Nu + h->L.Np, 0.0, h->rhs);
+        launch_fill(h->stream, h->L.Nu, 0.0, h->xB);
+        check_launch();
+        sync(h);
+      }
+    }
+  });
+}
+
 vem_status vem_set_rhs(vem_handle h, const double* f_qp, const double* pD_qp) {
   if (!h || !f_qp) return VEM_EINVAL;
   return guarded(h, [&] {
     require_disc(h);
-    hipStream_t s = h->stream;
-    launch_fill(s, h->L.Nu, 0.0, h->rhs);
-    DBuf<double>& tsum = h->tmp.f64[0];
-    if (h->family == VEM_LO) {
-      tsum.reserve(h->ntet);
-      launch_load_tets(s, h->ntet, h->npts_cell, h->qw_cell, h->tet_inc, h->tet_a, h->inc_cell, h->xyz, h->fptr,
-                       h->fvtx, h->cface, h->csign, h->c_xref, f_qp, tsum);
-      launch_load_cells(s, h->nc, h->cell_tet_ptr, tsum, h->rhs.p + h->L.Nu);
-      if (pD_qp)
-        launch_bnd_rhs(s, (int)h->nbf, h->npts_face, h->qw_face, h->bface, h->btri_ptr, h->xyz, h->fptr, h->fvtx,
-                       h->face_cell, pD_qp, h->rhs);
-    } else {
-      tsum.reserve((size_t)h->ntet * h->L.npd);
-      PaperLoadArgs a{};
-      a.s = s;
-      a.nc = h->nc;
-      a.nb = (int)h->nbf;
-      a.npts_cell = h->npts_cell;
-      a.npts_face = h->npts_face;
-      a.ntet = h->ntet;
-      a.ref_cell = h->qref_cell;
-      a.w_cell = h->qw_cell;
-      a.ref_face = h->qref_face;
-      a.w_face = h->qw_face;
-      a.tet_inc = h->tet_inc;
-      a.tet_a = h->tet_a;
-      a.inc_cell = h->inc_cell;
-      a.fptr = h->fptr;
-      a.fvtx = h->fvtx;
-      a.cface = h->cface;
-      a.cell_tet_ptr = h->cell_tet_ptr;
-      a.bface = h->bface;
-      a.btri_ptr = h->btri_ptr;
-      a.face_cell = h->face_cell;
-      a.csign = h->csign;
-      a.xyz = h->xyz;
-      a.xref = h->c_xref;
-      a.ccen = h->c_cen;
-      a.cdiam = h->c_diam;
-      a.cvol = h->c_vol;
-      a.cmom = h->pk_cmom;
-      a.fcen = h->f_cen;
-      a.fdiam = h->f_diam;
-      a.fe1 = h->f_e1;
-      a.fe2 = h->f_e2;
-      a.Tf = h->pk_Tf;
-      a.fq = f_qp;
-      a.pq = pD_qp;
-      a.tet_sum = tsum;
-      a.rhs_p = h->rhs.p + h->L.Nu;
-      a.rhs_u = h->rhs;
-      launch_paper_loads(h->korder, a);
-    }
-    check_launch();
-    sync(h);
+    VEM_REQUIRE(h->bc == VEM_BC_PRESSURE, VEM_EINVAL, "flux boundary data: use vem_set_rhs_flux");
+    set_loads(h, f_qp, pD_qp, nullptr);
+  });
+}
+
+vem_status vem_set_rhs_flux(vem_handle h, const double* f_qp, const double* u_qp) {
+  if (!h || !f_qp || !u_qp) return VEM_EINVAL;
+  return guarded(h, [&] {
+    require_disc(h);
+    VEM_REQUIRE(h->bc == VEM_BC_FLUX, VEM_EINVAL, "call vem_set_boundary(h, VEM_BC_FLUX) first");
+    set_loads(h, f_qp, nullptr, u_qp);
   });
 }
 
@@ -1080,7 +1177,8 @@ vem_status vem_get_rhs(vem_handle h, double* b) {
   if (!h || !b) return VEM_EINVAL;
   return guarded(h, [&] {
     require_disc(h);
-    VEM_HIP(hipMemcpyAsync(b, h->rhs.p, (h->L.Nu + h->L.Np) * sizeof(double), hipMemcpyDefault, h->stream));
+    const double* src = h->bc == VEM_BC_FLUX ? flux_rhs(h) : h->rhs.p;
+    VEM_HIP(hipMemcpyAsync(b, src, (h->L.Nu + h->L.Np) * sizeof(double), hipMemcpyDefault, h->stream));
     sync(h);
   });
 }
@@ -1206,6 +1304,7 @@ static vem_status solve_impl(vem_handle h, const vem_solve_opts* opts, const dou
       if (g != h->gamma_A || !h->values_ready) rebuild_values(h, g);
     }
     ensure_values(h);
+    if (!user_rhs && h->bc == VEM_BC_FLUX) rhs = flux_rhs(h);
     ensure_workspace(h, m);
     double* V = h->Vb;
     double* Z = h->Zb;
@@ -1334,6 +1433,13 @@ static vem_status solve_impl(vem_handle h, const vem_solve_opts* opts, const dou
       beta = nb;
     }
     VEM_REQUIRE(!nan_seen, VEM_ENAN, "NaN or Inf met in the Krylov iteration");
+    if (h->bc == VEM_BC_FLUX) {
+      // of the pressures that solve the system (they differ by the constant), the one with zero mean
+      double* d = h->scal.p + 4 * kMaxDots;
+      launch_dots(s, Np, 1, h->pw, Np, x + Nu, h->partials, d);
+      launch_project(s, Np, x + Nu, h->n_p, d, 1.0 / h->np_wn, x + Nu);
+      check_launch();
+    }
     VEM_HIP(hipMemcpyAsync(u, x, Nu * sizeof(double), hipMemcpyDeviceToDevice, s));
     VEM_HIP(hipMemcpyAsync(p, x + Nu, Np * sizeof(double), hipMemcpyDeviceToDevice, s));
     VEM_HIP(hipMemcpyAsync(h->hpcg.p, h->pcg.p, sizeof(PcgState), hipMemcpyDeviceToHost, s));

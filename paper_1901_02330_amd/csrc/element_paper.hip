@@ -638,6 +638,54 @@ void run_local(const PaperLocalArgs& a) {
   (void)sizeof(C);
 }
 
+// Prescribed boundary fluxes (flux boundary data): the face moments (1/|f|) int_f (u.n_f) m^f_b
+// (eq. facePoly) of a boundary face, from u at the face points (structure of arrays).
+template <int K>
+__global__ void k_pk_bnd_flux(int nb, int npts, int64_t total, const double* __restrict__ ref,
+                              const double* __restrict__ refw, const int* __restrict__ bface,
+                              const int* __restrict__ btp, const double* __restrict__ xyz,
+                              const int* __restrict__ fptr, const int* __restrict__ fvtx,
+                              const double* __restrict__ fcen, const double* __restrict__ fdiam,
+                              const double* __restrict__ fe1, const double* __restrict__ fe2,
+                              const double* __restrict__ fnormal, const double* __restrict__ farea,
+                              const double* __restrict__ uq, double* xB) {
+  constexpr int NFD = PK<K>::NFD;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const int f = bface[i];
+  const int fs = fptr[f], nv = fptr[f + 1] - fs;
+  const double fx = fcen[3 * f], fy = fcen[3 * f + 1], fz = fcen[3 * f + 2], ihf = 1.0 / fdiam[f];
+  const double e1x = fe1[3 * f], e1y = fe1[3 * f + 1], e1z = fe1[3 * f + 2];
+  const double e2x = fe2[3 * f], e2y = fe2[3 * f + 1], e2z = fe2[3 * f + 2];
+  const double nx0 = fnormal[3 * f], ny0 = fnormal[3 * f + 1], nz0 = fnormal[3 * f + 2];
+  double acc[NFD];
+  for (int d = 0; d < NFD; ++d) acc[d] = 0.0;
+  int64_t q = (int64_t)btp[i] * npts;
+  const int v0 = fvtx[fs];
+  const double Ax = xyz[3 * v0], Ay = xyz[3 * v0 + 1], Az = xyz[3 * v0 + 2];
+  for (int a = 1; a + 1 < nv; ++a) {
+    const int va = fvtx[fs + a], vb = fvtx[fs + a + 1];
+    const double Bx = xyz[3 * va] - Ax, By = xyz[3 * va + 1] - Ay, Bz = xyz[3 * va + 2] - Az;
+    const double Cx = xyz[3 * vb] - Ax, Cy = xyz[3 * vb + 1] - Ay, Cz = xyz[3 * vb + 2] - Az;
+    const double nx = By * Cz - Bz * Cy, ny = Bz * Cx - Bx * Cz, nz = Bx * Cy - By * Cx;
+    const double a2 = sqrt(nx * nx + ny * ny + nz * nz);
+    for (int r = 0; r < npts; ++r, ++q) {
+      const double xi = ref[2 * r], eta = ref[2 * r + 1];
+      const double dx = Ax + xi * Bx + eta * Cx - fx, dy = Ay + xi * By + eta * Cy - fy,
+                   dz = Az + xi * Bz + eta * Cz - fz;
+      const double s = (dx * e1x + dy * e1y + dz * e1z) * ihf, t = (dx * e2x + dy * e2y + dz * e2z) * ihf;
+      const double un = uq[q] * nx0 + uq[total + q] * ny0 + uq[2 * total + q] * nz0;
+      const double w = a2 * refw[r] * un;
+      for (int d = 0; d < NFD; ++d) {
+        int d1, d2;
+        exp2(d, d1, d2);
+        acc[d] += w * ipow(s, d1) * ipow(t, d2);
+      }
+    }
+  }
+  for (int b = 0; b < NFD; ++b) xB[(int64_t)f * NFD + b] = acc[b] / farea[f];
+}
+
 template <int K>
 void run_loads(const PaperLoadArgs& a) {
   hipStream_t s = a.s;
@@ -650,6 +698,10 @@ void run_loads(const PaperLoadArgs& a) {
     k_pk_bnd_rhs<K><<<g256(a.nb), 256, 0, s>>>(a.nb, a.npts_face, a.ref_face, a.w_face, a.bface, a.btri_ptr, a.xyz,
                                                a.fptr, a.fvtx, a.face_cell, a.fcen, a.fdiam, a.fe1, a.fe2, a.Tf,
                                                a.pq, a.rhs_u);
+  if (a.uq && a.nb > 0)
+    k_pk_bnd_flux<K><<<g256(a.nb), 256, 0, s>>>(a.nb, a.npts_face, a.nq_face_total, a.ref_face, a.w_face, a.bface,
+                                                a.btri_ptr, a.xyz, a.fptr, a.fvtx, a.fcen, a.fdiam, a.fe1, a.fe2,
+                                                a.fnormal, a.farea, a.uq, a.xB);
 }
 
 }  // namespace

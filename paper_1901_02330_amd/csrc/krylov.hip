@@ -230,6 +230,14 @@ __global__ void __launch_bounds__(kThreads) k_update_norm(int64_t n, const doubl
   block_partials<1>(acc, partials);
 }
 
+// out = x - v (dot * inv_vv): x without its component along v (dot = v . x on the device)
+__global__ void k_project(int64_t n, const double* x, const double* __restrict__ v, const double* __restrict__ dot,
+                          double inv_vv, double* out) {
+  const double c = *dot * inv_vv;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = x[i] - v[i] * c;
+}
+
 // x += sum_k Z_k y_k
 template <int K>
 __global__ void __launch_bounds__(kThreads) k_combine(int64_t n, const double* __restrict__ Z, int64_t ldz,
@@ -609,6 +617,11 @@ void launch_update_norm(hipStream_t s, int64_t n, int k, const double* V, int64_
     default: throw Error{VEM_EINVAL, "too many basis vectors"};
   }
   finalize(s, grid, 1, partials, out);
+}
+
+void launch_project(hipStream_t s, int64_t n, const double* x, const double* v, const double* dot, double inv_vv,
+                    double* out) {
+  if (n > 0) k_project<<<stream_grid(n), kThreads, 0, s>>>(n, x, v, dot, inv_vv, out);
 }
 
 void launch_combine(hipStream_t s, int64_t n, int k, const double* Z, int64_t ldz, const double* y, double* x) {

@@ -346,7 +346,41 @@ __global__ void k_bnd_rhs(int nb, int npts, const double* __restrict__ refw, con
   rhs_u[f] = -sg * acc;
 }
 
+// Prescribed boundary fluxes (flux boundary data): the DOF of boundary face f is
+// (1/|f|) int_f u.n_f, from u at the face points (structure of arrays, `total` points).
+__global__ void k_bnd_flux(int nb, int npts, int64_t total, const double* __restrict__ refw,
+                           const int* __restrict__ bface, const int* __restrict__ btp, const double* __restrict__ xyz,
+                           const int* __restrict__ fptr, const int* __restrict__ fvtx,
+                           const double* __restrict__ fnormal, const double* __restrict__ farea,
+                           const double* __restrict__ uq, double* xB) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  int f = bface[i];
+  int fs = fptr[f], n = fptr[f + 1] - fs;
+  int64_t q = (int64_t)btp[i] * npts;
+  const V3 nf = ld3(fnormal, f);
+  V3 A = ld3(xyz, fvtx[fs]);
+  double acc = 0.0;
+  for (int a = 1; a + 1 < n; ++a) {
+    V3 B = ld3(xyz, fvtx[fs + a]), C = ld3(xyz, fvtx[fs + a + 1]);
+    double a2 = norm(cross(B - A, C - A));
+    double s = 0.0;
+    for (int r = 0; r < npts; ++r, ++q)
+      s += refw[r] * (uq[q] * nf.x + uq[total + q] * nf.y + uq[2 * total + q] * nf.z);
+    acc += a2 * s;
+  }
+  xB[f] = acc / farea[f];
+}
+
 }  // namespace
+
+void launch_bnd_flux(hipStream_t s, int nb, int npts, int64_t total, const double* refw, const int* bface,
+                     const int* btri_ptr, const double* xyz, const int* fptr, const int* fvtx, const double* fnormal,
+                     const double* farea, const double* uq, double* xB) {
+  if (nb > 0)
+    k_bnd_flux<<<nblocks(nb), kThreads, 0, s>>>(nb, npts, total, refw, bface, btri_ptr, xyz, fptr, fvtx, fnormal,
+                                                farea, uq, xB);
+}
 
 void launch_check_mesh(hipStream_t s, int nv, int nf, int nc, const int* fptr, const int* fvtx, const int* cptr,
                        const int* cface, const int8_t* csign, int* face_cnt, int* face_cell, int* face_lidx,

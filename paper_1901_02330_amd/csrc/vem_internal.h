@@ -166,6 +166,10 @@ void launch_qp_cell(hipStream_t s, int64_t ntet, int npts, const double* ref, co
                     const double* xref, double* qp);
 void launch_qp_face(hipStream_t s, int nb, int npts, int64_t total, const double* ref, const int* bface,
                     const int* btri_ptr, const double* xyz, const int* fptr, const int* fvtx, double* qp);
+// prescribed boundary fluxes (1/|f|) int_f u.n_f of the lowest-order element, into xB[f]
+void launch_bnd_flux(hipStream_t s, int nb, int npts, int64_t total, const double* refw, const int* bface,
+                     const int* btri_ptr, const double* xyz, const int* fptr, const int* fvtx, const double* fnormal,
+                     const double* farea, const double* uq, double* xB);
 void launch_load_tets(hipStream_t s, int64_t ntet, int npts, const double* refw, const int* tet_inc,
                       const int* tet_a, const int* inc_cell, const double* xyz, const int* fptr, const int* fvtx,
                       const int* cface, const int8_t* csign, const double* xref, const double* fq,
@@ -211,6 +215,11 @@ struct PaperLoadArgs {
   const double *xyz, *xref, *ccen, *cdiam, *cvol, *cmom, *fcen, *fdiam, *fe1, *fe2, *Tf;
   const double *fq, *pq;
   double *tet_sum, *rhs_p, *rhs_u;
+  // flux boundary data: u at the boundary-face points (structure of arrays, nq_face_total points)
+  // gives the prescribed face moments xB (indexed by global flux DOF); uq == nullptr skips them
+  const double *uq, *fnormal, *farea;
+  int64_t nq_face_total;
+  double* xB;
 };
 void launch_paper_loads(int k, const PaperLoadArgs& a);
 
@@ -234,12 +243,24 @@ void launch_coef_grad(hipStream_t s, DofLayout L, const int* cptr, const int* cf
 void launch_values(hipStream_t s, DofLayout L, const int* cptr, const int* cface, const int8_t* csign,
                    const int* ldof_ptr, const int* sorted_gid, const int* sorted_l, const int* face_cell,
                    const int* face_lidx, const int64_t* lmat_ptr, const double* M1, const int64_t* lb_ptr,
-                   const double* Bdiv1, const double* nu, double inv_gamma, const int* Kptr, double* Kval,
-                   const int* Aptr, double* Aval);
+                   const double* Bdiv1, const double* nu, double inv_gamma, const int* bnd, const int* Kptr,
+                   double* Kval, const int* Aptr, double* Aval);
+// flux boundary data: out = b - K xB on the free rows, xB on the prescribed ones
+void launch_flux_rhs(hipStream_t s, DofLayout L, const int* cptr, const int* cface, const int8_t* csign,
+                     const int* face_cell, const int* face_lidx, const int64_t* lmat_ptr, const double* M1,
+                     const int64_t* lb_ptr, const double* Bdiv1, const double* nu, const int* bnd, const double* xB,
+                     const double* b, double* out);
+// the discrete constant pressure and the mean weights (cmom == nullptr: one pressure DOF per cell)
+void launch_pressure_constants(hipStream_t s, DofLayout L, int nsm, const double* cmom, const double* cvol,
+                               double* np, double* w);
+// out = x - v (dot * inv_vv), dot a device scalar (out may be x)
+void launch_project(hipStream_t s, int64_t n, const double* x, const double* v, const double* dot, double inv_vv,
+                    double* out);
 void launch_diag_inv(hipStream_t s, int64_t n, const int* diagpos, const double* val, double* d, double* dinv);
 void launch_schur_values(hipStream_t s, DofLayout L, const int* cptr, const int* cface, const int8_t* csign,
                          const int* ldof_ptr, const int* face_cell, const int* face_lidx, const int64_t* lb_ptr,
-                         const double* Bdiv1, const double* dM, const int* Sptr, const int* Scol, double* Sval);
+                         const double* Bdiv1, const double* dM, const int* bnd, const int* Sptr, const int* Scol,
+                         double* Sval);
 void launch_rhs_from_moments(hipStream_t s, int64_t Nu, int64_t Np, double* rhs);
 
 // sparse/Krylov

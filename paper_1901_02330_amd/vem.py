@@ -89,6 +89,8 @@ def load():
         "vem_time_kernel": ([H, c_int, c_int, POINTER(c_double), POINTER(c_double)], c_int),
         "vem_solve_rhs": ([H, POINTER(SolveOpts), P, P, P, POINTER(SolveInfo)], c_int),
         "vem_coefficient_gradient": ([H, P, P, P], c_int),
+        "vem_set_boundary": ([H, c_int], c_int),
+        "vem_set_rhs_flux": ([H, P, P], c_int),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -118,6 +120,7 @@ class Solver:
         self.h = c_void_p()
         self._check(self.lib.vem_create(byref(self.h), c_void_p(s.cuda_stream)))
         self._sizes = None
+        self.boundary = "pressure"
 
     # -- helpers
     def _check(self, code):
@@ -187,13 +190,31 @@ class Solver:
         pD = None if pD_qp is None else self._dev(pD_qp, self.torch.float64)
         self._check(self.lib.vem_set_rhs(self.h, _ptr(f_qp), _ptr(pD) if pD is not None and pD.numel() else None))
 
-    def set_rhs_functions(self, f, pD=None):
-        """Evaluate f (and p_D) with torch at the library's quadrature points, then load them."""
+    def set_boundary(self, kind):
+        """'pressure' (p_D given, the default) or 'flux' (u.n given and zero-mean pressure, the paper's
+        model problem)."""
+        self._check(self.lib.vem_set_boundary(self.h, {"pressure": 0, "flux": 1}[kind]))
+        self.boundary = kind
+
+    def set_rhs_flux(self, f_qp, u_qp):
+        """f at the cell points and the flux field u (n_qp_face, 3) at the boundary points."""
+        f_qp = self._dev(f_qp, self.torch.float64)
+        u = self._dev(u_qp, self.torch.float64).t().contiguous()  # x, y, z components as separate arrays
+        self._check(self.lib.vem_set_rhs_flux(self.h, _ptr(f_qp), _ptr(u) if u.numel() else None))
+
+    def set_rhs_functions(self, f, g=None):
+        """Evaluate f, and g at the boundary points, with torch at the library's quadrature points, then
+        load them: g is p_D with pressure data, the flux field u (returning (n, 3)) with flux data."""
         qc, qf = self.quadrature()
         fv = f(qc)
-        pv = None if pD is None else pD(qf)
+        gv = None if g is None else g(qf)
         del qc, qf
-        self.set_rhs(fv, pv)
+        if self.boundary == "flux":
+            if gv is None:
+                raise ValueError("flux boundary data need the flux field u")
+            self.set_rhs_flux(fv, gv)
+        else:
+            self.set_rhs(fv, gv)
 
     def solve(self, precond="schur", tol=1e-8, restart=30, maxit=5000, inner_tol=1e-6, inner_maxit=5000,
               inner_check=32, gamma=0.0, x0=None, precision="fp64", rhs=None, graphs=True):
@@ -287,5 +308,5 @@ EXPORTED = [
     "vem_solve_opts_default", "vem_create", "vem_destroy", "vem_set_mesh", "vem_discretize", "vem_get_sizes",
     "vem_get_quadrature", "vem_set_coefficient", "vem_set_rhs", "vem_solve", "vem_apply", "vem_export_csr",
     "vem_get_rhs", "vem_get_geometry", "vem_status_string", "vem_last_error", "vem_time_kernel",
-    "vem_solve_rhs", "vem_coefficient_gradient",
+    "vem_solve_rhs", "vem_coefficient_gradient", "vem_set_boundary", "vem_set_rhs_flux",
 ]
