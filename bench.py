@@ -105,20 +105,29 @@ def summarize(prefix: str):
     print("\n".join(out))
 
 
+KERNEL_SRC = ("pcg.hip", "krylov_device.h")  # the dominant kernel's source, for the traffic record
+
+
+def kernel_src_digest():
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in KERNEL_SRC:
+        h.update(open(os.path.join(ROOT, "paper_1901_02330_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def traffic_from_profiles():
     """HBM bytes per launch of the dominant kernel from the committed counter summary, if it was
     taken on the current kernel source (its hash is recorded there); else None."""
-    import hashlib
-
     path = os.path.join(ROOT, "profiles", "traffic_k_ppcg_iter_cube64_lo.md")
-    src = os.path.join(ROOT, "paper_1901_02330_amd", "csrc", "krylov.hip")
     if not os.path.exists(path):
         return None
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    digest = kernel_src_digest()
     for line in open(path):
         if line.startswith("{") and '"traffic"' in line:
             rec = json.loads(line)
-            if rec.get("krylov_hip_sha256_16") == digest:
+            if rec.get("kernel_src_sha256_16") == digest:
                 return rec["traffic"]
     return None
 
@@ -192,7 +201,6 @@ def summarize_pmc(fetch_dir: str, write_dir: str):
     probe's plain 512 MiB elementwise copy."""
     import csv
     import glob
-    import hashlib
     import statistics
 
     def per_kernel(d, counter):
@@ -233,12 +241,11 @@ def summarize_pmc(fetch_dir: str, write_dir: str):
     it = sorted((k for k in rows if k[0].startswith("k_ppcg_iter<double, false")), key=lambda k: -k[1])
     fm, wm = rows[it[0]]
     alg = probe["kernels"]["cg_reg"]["algorithmic_bytes"]
-    src = os.path.join(ROOT, "paper_1901_02330_amd", "csrc", "krylov.hip")
     rec = {"traffic": {"bytes_per_launch": fm + wm, "fetch_bytes": fm, "write_bytes": wm,
                        "algorithmic_bytes": alg, "ratio_to_algorithmic": (fm + wm) / alg,
                        "note": "FETCH_SIZE + WRITE_SIZE of k_ppcg_iter on M + B^T B/gamma, cube 64^3 LO, "
                                "scaled by a 512 MiB copy; counts L2-to-fabric traffic (MALL hits included)"},
-           "krylov_hip_sha256_16": hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]}
+           "kernel_src_sha256_16": kernel_src_digest()}
     out += ["", f"Algorithmic bytes per launch of the dominant kernel: {alg / 1e6:.1f} MB; measured "
             f"{(fm + wm) / 1e6:.1f} MB ({(fm + wm) / alg:.3f}x).", "", json.dumps(rec)]
     print("\n".join(out))

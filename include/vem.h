@@ -121,7 +121,9 @@ typedef struct {
   int32_t precision;   /* VEM_FP64 or VEM_MIXED */
   int32_t use_graphs;  /* nonzero: replay the inner-CG iterations as a captured HIP graph (same
                           kernels and arguments, identical results; a cap > 64 may be passed
-                          by up to 7 iterations, as graphs run 8 at a time) */
+                          by up to 7 iterations, as graphs run 8 at a time).  Default 0: on
+                          gfx950 each replay boundary leaves the GPU idle for about 8 us,
+                          more than the host's launch cost it saves */
 } vem_solve_opts;
 
 typedef struct {

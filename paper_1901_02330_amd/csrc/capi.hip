@@ -13,6 +13,8 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <map>
+#include <mutex>
 #include <new>
 
 #include "vem_internal.h"
@@ -73,6 +75,9 @@ struct vem_ctx {
   int64_t ntet = 0, nbf = 0, nbtri = 0;
   DBuf<int> cell_tet_ptr, tet_inc, tet_a, bface, btri_ptr;
   DBuf<double> qref_cell, qw_cell, qref_face, qw_face;
+  int qrule_n = 0;   // the n whose reference rules are on the device (0: none)
+  DBuf<double> pk_trip;  // triangle rule (points, weight) of the order-k face integrals
+  int pk_trip_nq = 0;
   int npts_cell = 0, npts_face = 0;
 
   // discretisation
@@ -148,8 +153,34 @@ void jacobi_eval(int n, double a, double b, double x, double& p) {
 
 namespace vem {
 
+namespace {
 // Nodes and weights of int_0^1 (1 - t)^alpha g(t) dt, exact for degree 2n - 1.
+void gauss_jacobi01_compute(int n, int alpha, double* t, double* w);
+}  // namespace
+
+// The rules depend on (n, alpha) only; each is computed once per process (the root search
+// costs a few hundred microseconds) and copied out of a table afterwards.
 void gauss_jacobi01(int n, int alpha, double* t, double* w) {
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, std::vector<double>> memo;  // n nodes, then n weights
+  std::vector<double> tw;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = memo.find({n, alpha});
+    if (it != memo.end()) tw = it->second;
+  }
+  if (tw.empty()) {
+    tw.resize(2 * (size_t)n);
+    gauss_jacobi01_compute(n, alpha, tw.data(), tw.data() + n);
+    std::lock_guard<std::mutex> lock(mu);
+    memo.emplace(std::make_pair(n, alpha), tw);
+  }
+  std::copy(tw.begin(), tw.begin() + n, t);
+  std::copy(tw.begin() + n, tw.end(), w);
+}
+
+namespace {
+void gauss_jacobi01_compute(int n, int alpha, double* t, double* w) {
   const double a = alpha, b = 0.0;
   std::vector<double> roots;
   const int grid = 20000;
@@ -192,6 +223,7 @@ void gauss_jacobi01(int n, int alpha, double* t, double* w) {
     w[i] = wi / std::pow(2.0, a + 1.0);
   }
 }
+}  // namespace
 
 void tet_reference_rule(int n, std::vector<double>& pts, std::vector<double>& w) {
   std::vector<double> a(n), wa(n), b(n), wb(n), c(n), wc(n);
@@ -268,35 +300,56 @@ void fill_i32(hipStream_t s, int64_t n, int v, int* p) {
 
 namespace vem {
 
-int64_t scan_i64(hipStream_t s, Scratch& tmp, const int64_t* len, int64_t n, int64_t* ptr) {
+void scan_reserve(Scratch& tmp, int64_t n) {
+  size_t b64 = 0, b32 = 0;
+  const int64_t* l64 = nullptr;
+  int64_t* p64 = nullptr;
+  hipcub::TransformInputIterator<int64_t, ToI64, const int*> it(nullptr, ToI64());
+  VEM_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, b64, l64, p64, (int)n, (hipStream_t)0));
+  VEM_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, b32, it, p64, (int)n, (hipStream_t)0));
+  const size_t bytes = b64 > b32 ? b64 : b32;
+  tmp.cub.reserve(bytes > 0 ? bytes : 1);
+  tmp.tot.alloc(8);
+}
+
+void scan_i64_async(hipStream_t s, Scratch& tmp, const int64_t* len, int64_t n, int64_t* ptr, int slot) {
   size_t bytes = 0;
   VEM_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, len, ptr, (int)n, s));
-  tmp.cub.reserve(bytes > 0 ? bytes : 1);
+  VEM_REQUIRE(bytes <= tmp.cub.n && tmp.tot.p && slot >= 0 && slot < 8, VEM_EINVAL, "scan scratch not reserved");
   VEM_HIP(hipcub::DeviceScan::ExclusiveSum(tmp.cub.p, bytes, len, ptr, (int)n, s));
   k_scan_tail<<<1, 1, 0, s>>>(n, len, ptr);  // ptr[n] = ptr[n-1] + len[n-1]
   VEM_HIP(hipGetLastError());
-  int64_t total = 0;
-  VEM_HIP(hipMemcpyAsync(&total, ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  VEM_HIP(hipStreamSynchronize(s));
-  return total;
+  VEM_HIP(hipMemcpyAsync(tmp.tot.p + slot, ptr + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
 }
 
-int64_t scan_i32(hipStream_t s, Scratch& tmp, const int* len, int64_t n, int* ptr) {
-  DBuf<int64_t>& p64 = tmp.i64[3];
+void scan_i32_async(hipStream_t s, Scratch& tmp, const int* len, int64_t n, int* ptr, DBuf<int64_t>& p64,
+                    int slot) {
   p64.reserve(n + 1);
   hipcub::TransformInputIterator<int64_t, ToI64, const int*> it(len, ToI64());
   size_t bytes = 0;
   VEM_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, it, p64.p, (int)n, s));
-  tmp.cub.reserve(bytes > 0 ? bytes : 1);
+  VEM_REQUIRE(bytes <= tmp.cub.n && tmp.tot.p && slot >= 0 && slot < 8, VEM_EINVAL, "scan scratch not reserved");
   VEM_HIP(hipcub::DeviceScan::ExclusiveSum(tmp.cub.p, bytes, it, p64.p, (int)n, s));
   k_scan_tail<<<1, 1, 0, s>>>(n, it, p64.p);
   VEM_HIP(hipGetLastError());
-  int64_t total = 0;
-  VEM_HIP(hipMemcpyAsync(&total, p64.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  VEM_HIP(hipStreamSynchronize(s));
-  VEM_REQUIRE(total <= INT_MAX, VEM_ENOMEM, "more than 2^31-1 entries in a sparse pattern");
-  k_narrow<<<grid_of(n + 1), 256, 0, s>>>(n + 1, p64.p, ptr);
+  VEM_HIP(hipMemcpyAsync(tmp.tot.p + slot, p64.p + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  k_narrow<<<grid_of(n + 1), 256, 0, s>>>(n + 1, p64.p, ptr);  // a total past 2^31-1 is rejected by the caller
   VEM_HIP(hipGetLastError());
+}
+
+int64_t scan_i64(hipStream_t s, Scratch& tmp, const int64_t* len, int64_t n, int64_t* ptr) {
+  scan_reserve(tmp, n);
+  scan_i64_async(s, tmp, len, n, ptr, 0);
+  VEM_HIP(hipStreamSynchronize(s));
+  return tmp.tot.p[0];
+}
+
+int64_t scan_i32(hipStream_t s, Scratch& tmp, const int* len, int64_t n, int* ptr) {
+  scan_reserve(tmp, n);
+  scan_i32_async(s, tmp, len, n, ptr, tmp.i64[3], 0);
+  VEM_HIP(hipStreamSynchronize(s));
+  const int64_t total = tmp.tot.p[0];
+  VEM_REQUIRE(total <= INT_MAX, VEM_ENOMEM, "more than 2^31-1 entries in a sparse pattern");
   return total;
 }
 
@@ -673,7 +726,7 @@ void vem_solve_opts_default(vem_solve_opts* o) {
   o->inner_check = 32;
   o->gamma = 0.0;
   o->precision = VEM_FP64;
-  o->use_graphs = 1;
+  o->use_graphs = 0;
 }
 
 vem_status vem_create(vem_handle* out, void* stream) {
@@ -832,7 +885,8 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
 
     // ---- quadrature support: tetrahedra of the cells, triangles of the boundary faces
     h->load_n = load_points;
-    {
+    if (h->qrule_n != load_points) {  // the reference rules depend on n only
+      h->qrule_n = 0;
       std::vector<double> p, w;
       tet_reference_rule(load_points, p, w);
       h->npts_cell = (int)w.size();
@@ -848,6 +902,7 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
       VEM_HIP(hipMemcpyAsync(h->qref_face.p, p.data(), p.size() * sizeof(double), hipMemcpyHostToDevice, s));
       VEM_HIP(hipMemcpyAsync(h->qw_face.p, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, s));
       sync(h);
+      h->qrule_n = load_points;
     }
     {
       DBuf<int>& cnt = h->tmp.i32[1];
@@ -855,14 +910,20 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
       launch_tet_counts(s, nc, h->fptr, h->cptr, h->cface, cnt);
       check_launch();
       h->cell_tet_ptr.alloc(nc + 1);
-      h->ntet = scan_i32(s, h->tmp, cnt, nc, h->cell_tet_ptr);
+      DBuf<int>& pos = h->tmp.i32[2];
+      pos.reserve(nf + 1);
+      // tetrahedron offsets and boundary-face positions: one synchronisation for both totals
+      scan_reserve(h->tmp, std::max(nc, nf));
+      scan_i32_async(s, h->tmp, cnt, nc, h->cell_tet_ptr, h->tmp.i64[3], 0);
+      scan_i32_async(s, h->tmp, h->is_bnd, nf, pos, h->tmp.i64[2], 1);
+      sync(h);
+      VEM_REQUIRE(h->tmp.tot.p[0] <= INT_MAX, VEM_ENOMEM, "more than 2^31-1 quadrature tetrahedra");
+      h->ntet = h->tmp.tot.p[0];
+      h->nbf = h->tmp.tot.p[1];
       h->tet_inc.alloc(h->ntet);
       h->tet_a.alloc(h->ntet);
       launch_tets(s, nc, h->fptr, h->cptr, h->cface, h->cell_tet_ptr, h->tet_inc, h->tet_a);
       check_launch();
-      DBuf<int>& pos = h->tmp.i32[2];
-      pos.reserve(nf + 1);
-      h->nbf = scan_i32(s, h->tmp, h->is_bnd, nf, pos);
       h->bface.alloc(h->nbf > 0 ? h->nbf : 1);
       launch_compact_flags(s, nf, h->is_bnd, pos, h->bface);
       DBuf<int>& tc = h->tmp.i32[3];
@@ -904,15 +965,19 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
       check_launch();
       DBuf<int64_t>& p64 = h->tmp.i64[3];
       p64.reserve(nc + 1);
-      int64_t tot = scan_i64(s, h->tmp, nd, nc, p64);
+      h->lmat_ptr.alloc(nc + 1);
+      h->lb_ptr.alloc(nc + 1);
+      // local DOF, matrix and divergence-block offsets: one synchronisation for the three totals
+      scan_reserve(h->tmp, nc);
+      scan_i64_async(s, h->tmp, nd, nc, p64, 0);
+      scan_i64_async(s, h->tmp, nm, nc, h->lmat_ptr, 1);
+      scan_i64_async(s, h->tmp, nb, nc, h->lb_ptr, 2);
+      sync(h);
+      const int64_t tot = h->tmp.tot.p[0], nmat = h->tmp.tot.p[1], nbd = h->tmp.tot.p[2];
       VEM_REQUIRE(tot <= INT_MAX, VEM_ENOMEM, "too many local DOFs");
       tot_ldof = tot;
       h->ldof_ptr.alloc(nc + 1);
       k_narrow<<<grid_of(nc + 1), 256, 0, s>>>(nc + 1, p64.p, h->ldof_ptr.p);
-      h->lmat_ptr.alloc(nc + 1);
-      int64_t nmat = scan_i64(s, h->tmp, nm, nc, h->lmat_ptr);
-      h->lb_ptr.alloc(nc + 1);
-      int64_t nbd = scan_i64(s, h->tmp, nb, nc, h->lb_ptr);
       h->M1.alloc(nmat);
       h->Bdiv1.alloc(nbd);
       h->sorted_gid.alloc(tot);
@@ -923,22 +988,27 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
                       h->c_vol, h->c_cen, h->lmat_ptr, h->M1, h->lb_ptr, h->Bdiv1);
     } else {
       PaperSizes z = paper_sizes(k);
-      std::vector<double> p2, w2, trip;
-      tri_reference_rule(z.nq, p2, w2);
-      for (size_t r = 0; r < w2.size(); ++r) {
-        trip.push_back(p2[2 * r]);
-        trip.push_back(p2[2 * r + 1]);
-        trip.push_back(w2[r]);
+      if (h->pk_trip_nq != z.nq) {
+        h->pk_trip_nq = 0;
+        std::vector<double> p2, w2, trip;
+        tri_reference_rule(z.nq, p2, w2);
+        for (size_t r = 0; r < w2.size(); ++r) {
+          trip.push_back(p2[2 * r]);
+          trip.push_back(p2[2 * r + 1]);
+          trip.push_back(w2[r]);
+        }
+        h->pk_trip.alloc(trip.size());
+        VEM_HIP(hipMemcpyAsync(h->pk_trip.p, trip.data(), trip.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        sync(h);  // `trip` is released at the end of this scope
+        h->pk_trip_nq = z.nq;
       }
-      DBuf<double>& tri = h->tmp.f64[0];
+      DBuf<double>& tri = h->pk_trip;
       DBuf<double>& FP = h->tmp.f64[1];
       DBuf<double>& FM = h->tmp.f64[2];
       DBuf<double>& Dg = h->tmp.f64[3];
       DBuf<double>& Pg = h->tmp.f64[4];
       DBuf<double>& Xg = h->tmp.f64[5];
       DBuf<double>& Cg = h->tmp.f64[6];
-      tri.reserve(trip.size());
-      VEM_HIP(hipMemcpyAsync(tri.p, trip.data(), trip.size() * sizeof(double), hipMemcpyHostToDevice, s));
       FP.reserve((size_t)h->ncf * z.nsm);
       FM.reserve((size_t)h->ncf * z.nfm);
       h->pk_Tf.alloc((size_t)nf * z.nfd * z.nfd);
@@ -984,7 +1054,6 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
       a.Bdiv1 = h->Bdiv1;
       launch_paper_local(k, a);
       check_launch();
-      sync(h);  // the host-side table `trip` is released at the end of this scope
     }
     launch_ldof_sort(s, L, h->cptr, h->cface, h->ldof_ptr, h->sorted_gid, h->sorted_l);
     check_launch();
@@ -1007,9 +1076,17 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
       h->K.rowptr.alloc(N + 1);
       h->A.rowptr.alloc(L.Nu + 1);
       h->S.rowptr.alloc(L.Np + 1);
-      h->K.nnz = scan_i32(s, h->tmp, lenK, N, h->K.rowptr);
-      h->A.nnz = scan_i32(s, h->tmp, lenA, L.Nu, h->A.rowptr);
-      h->S.nnz = scan_i32(s, h->tmp, lenS, L.Np, h->S.rowptr);
+      // row offsets of K, A_gamma and S: one synchronisation for the three totals
+      scan_reserve(h->tmp, N);
+      scan_i32_async(s, h->tmp, lenK, N, h->K.rowptr, h->tmp.i64[0], 0);
+      scan_i32_async(s, h->tmp, lenA, L.Nu, h->A.rowptr, h->tmp.i64[1], 1);
+      scan_i32_async(s, h->tmp, lenS, L.Np, h->S.rowptr, h->tmp.i64[2], 2);
+      sync(h);
+      for (int m = 0; m < 3; ++m)
+        VEM_REQUIRE(h->tmp.tot.p[m] <= INT_MAX, VEM_ENOMEM, "more than 2^31-1 entries in a sparse pattern");
+      h->K.nnz = h->tmp.tot.p[0];
+      h->A.nnz = h->tmp.tot.p[1];
+      h->S.nnz = h->tmp.tot.p[2];
     }
     h->K.col.alloc(h->K.nnz);
     h->K.val.alloc(h->K.nnz);
@@ -1024,9 +1101,11 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
                          h->K.rowptr, h->K.col, h->Kdiag, h->A.rowptr, h->A.col, h->Adiag, h->S.rowptr, h->S.col,
                          h->Sdiag);
     check_launch();
-    build_sell(s, h->tmp, h->K, h->Ks);
-    build_sell(s, h->tmp, h->A, h->As);
-    build_sell(s, h->tmp, h->S, h->Ss);
+    {
+      const Csr* csr[3] = {&h->K, &h->A, &h->S};
+      Sell* sell[3] = {&h->Ks, &h->As, &h->Ss};
+      build_sells(s, h->tmp, csr, sell, 3);
+    }
     h->dM.alloc(L.Nu);
     h->dMinv.alloc(L.Nu);
     h->dAinv.alloc(L.Nu);
@@ -1311,7 +1390,7 @@ static vem_status solve_impl(vem_handle h, const vem_solve_opts* opts, const dou
     double* x = h->xw;
     double* dh = h->scal.p;                 // h = V^T w          (<= kMaxDots)
     double* dh2 = h->scal.p + kMaxDots;     // reorthogonalisation + ||w'||^2
-    double* dn = h->scal.p + 2 * kMaxDots;  // ||w''||^2, ||r||^2
+    double* dn = h->scal.p + 2 * kMaxDots;  // ||r||^2
     double* dy = h->scal.p + 3 * kMaxDots;  // combination coefficients
     double* hb = h->hbuf.p;
 
@@ -1366,10 +1445,10 @@ static vem_status solve_impl(vem_handle h, const vem_solve_opts* opts, const dou
         // classical Gram-Schmidt, twice
         launch_dots(s, N, j + 1, V, N, w, h->partials, dh);
         launch_update_dots(s, N, j + 1, V, N, dh, w, h->partials, dh2);
-        launch_update_norm(s, N, j + 1, V, N, dh2, w, h->partials, dn);
-        launch_scale_to(s, N, w, dn, w);
+        launch_update_normalize(s, N, j + 1, V, N, dh2, w);
         check_launch();
-        // h, its correction and ||w||^2 sit at scal[0], scal[kMaxDots], scal[2 kMaxDots]
+        // h at scal[0], its correction at scal[kMaxDots], ||w||^2 between the passes at
+        // scal[kMaxDots + j + 1]
         VEM_HIP(hipMemcpyAsync(h->hcol.p + (size_t)j * kColSlot, dh, kColSlot * sizeof(double),
                                hipMemcpyDeviceToHost, s));
         VEM_HIP(hipEventRecord(h->step_done[j & 1], s));
@@ -1379,8 +1458,14 @@ static vem_status solve_impl(vem_handle h, const vem_solve_opts* opts, const dou
         if (j + 1 < m && its + 1 < o.maxit) enqueue_step(j + 1);
         VEM_HIP(hipEventSynchronize(h->step_done[j & 1]));
         const double* col = h->hcol.p + (size_t)j * kColSlot;
-        for (int i = 0; i <= j; ++i) Hc(i, j) = col[i] + col[kMaxDots + i];
-        double hn = std::sqrt(col[2 * kMaxDots]);
+        double hh = 0.0;
+        for (int i = 0; i <= j; ++i) {
+          Hc(i, j) = col[i] + col[kMaxDots + i];
+          hh += col[kMaxDots + i] * col[kMaxDots + i];
+        }
+        // the norm the device divided by: ||w||^2 - |V^T w|^2 of the second pass
+        const double hn2 = col[kMaxDots + j + 1] - hh;
+        double hn = std::isfinite(hn2) ? std::sqrt(hn2 > 0.0 ? hn2 : 0.0) : hn2;
         Hc(j + 1, j) = hn;
         for (int i = 0; i <= j + 1; ++i)
           if (!std::isfinite(Hc(i, j))) nan_seen = true;

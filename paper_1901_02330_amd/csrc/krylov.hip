@@ -1,112 +1,15 @@
-// Sparse matrix-vector products and the vector kernels of flexible GMRES and
-// of the inner Jacobi-preconditioned conjugate gradients.
+// Sparse matrix-vector products, the vector kernels of flexible GMRES, and the
+// classical FP32 conjugate gradients of mixed-precision inner solves (the pipelined
+// FP64 inner CG is in pcg.hip).
 //
 // Reductions are deterministic and use neither atomics nor fences: every block
 // writes its partial sums, and a later kernel on the same stream adds them in
 // block order (a one-block finalize kernel, or every block of the consumer
 // kernel itself for the inner CG).  Every kernel here is bandwidth bound.
-#include "vem_internal.h"
+#include "krylov_device.h"
 
 namespace vem {
 namespace {
-
-constexpr int kThreads = kRedThreads;
-constexpr int kMaxWaves = 16;
-
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  return v;
-}
-
-// Workgroups are dealt round-robin to the eight XCDs, each with its own L2.  The
-// inner-CG kernels take their rows from this logical block number instead: XCD x
-// runs chunks x, x+8, x+16, ... of C consecutive blocks (C blocks = 16384 rows), so
-// that the vector entries gathered around a chunk are fetched into one L2, while all
-// eight XCDs still advance through the rows together.  Blocks past the last whole
-// round of 8 chunks keep their own number.  (Measured on the 64^3 cube: 1.5% off the
-// A_gamma iteration, 3.5% off the S iteration.  The saddle SpMV keeps the hardware
-// order: its flux and pressure rows differ in cost, and contiguous bands per XCD
-// left it 10% slower.)
-__device__ inline int64_t xcd_block() {
-  const int b = blockIdx.x, P = gridDim.x;
-  const int C = (16384 / (int)blockDim.x) > 0 ? (16384 / (int)blockDim.x) : 1;
-  const int full = P / (8 * C) * (8 * C);
-  if (b >= full) return b;
-  const int x = b & 7, i = b >> 3, j = i / C, off = i % C;
-  return (int64_t)(j * 8 + x) * C + off;
-}
-
-// Block-reduce K accumulators and store this block's partial sums at
-// partials[blockIdx.x * K + k].  No atomics and no fences: the consumer is a
-// later kernel on the same stream, and the kernel boundary makes the partials
-// visible to every XCD.
-template <int K>
-__device__ inline void block_partials(const double (&acc)[K], double* partials) {
-  __shared__ double sh[kMaxWaves][K];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-  for (int i = 0; i < K; ++i) {
-    double v = wave_sum(acc[i]);
-    if (lane == 0) sh[wid][i] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < K) {
-    double s = 0.0;
-    for (int w = 0; w < nw; ++w) s += sh[w][threadIdx.x];
-    partials[(size_t)blockIdx.x * K + threadIdx.x] = s;
-  }
-}
-
-// Sum of nparts partials (stride K, component k) by the whole block, in a fixed
-// order: every block that calls it obtains the same bits.
-__device__ inline double block_sum_partials(const double* __restrict__ partials, int nparts, int K, int k) {
-  __shared__ double sh[kMaxWaves];
-  __shared__ double total;
-  double s = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += blockDim.x) s += partials[(size_t)b * K + k];
-  s = wave_sum(s);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  if (lane == 0) sh[wid] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < nw; ++w) t += sh[w];
-    total = t;
-  }
-  __syncthreads();
-  double r = total;
-  __syncthreads();
-  return r;
-}
-
-// Both components of nparts (gamma, delta) partial pairs, summed by the whole block
-// in one pass, in a fixed order (every block obtains the same bits).
-__device__ inline void block_sum_partials2(const double* __restrict__ partials, int nparts, double (&out)[2]) {
-  __shared__ double sh[kMaxWaves][2];
-  __shared__ double total[2];
-  double g = 0.0, d = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
-    g += partials[2 * (size_t)b];
-    d += partials[2 * (size_t)b + 1];
-  }
-  g = wave_sum(g);
-  d = wave_sum(d);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  if (lane == 0) {
-    sh[wid][0] = g;
-    sh[wid][1] = d;
-  }
-  __syncthreads();
-  if (threadIdx.x < 2) {
-    double t = 0.0;
-    for (int w = 0; w < nw; ++w) t += sh[w][threadIdx.x];
-    total[threadIdx.x] = t;
-  }
-  __syncthreads();
-  out[0] = total[0];
-  out[1] = total[1];
-}
 
 // out[k] = sum over nparts partials; block k handles component k
 __global__ void __launch_bounds__(kThreads) k_finalize(int nparts, int K, const double* __restrict__ partials,
@@ -122,31 +25,6 @@ inline int red_grid(int64_t n) {
 }
 
 // ---- SELL-64 SpMV: one thread per row -------------------------------------------------------
-template <typename T>
-struct SellViewT {
-  int64_t rows;
-  const int* __restrict__ slice_ptr;
-  const int* __restrict__ slice_len;
-  const int* __restrict__ col;
-  const T* __restrict__ val;
-};
-using SellView = SellViewT<double>;
-
-inline SellView view(const Sell& A) { return {A.rows, A.slice_ptr, A.slice_len, A.col, A.val}; }
-
-// Whole waves share a slice because every block size here is a multiple of 64.
-// The product is formed in the matrix's precision T from x of type X.
-template <typename T, typename X>
-__device__ inline T sell_dot(const SellViewT<T>& A, int64_t row, const X* __restrict__ x) {
-  const int64_t s = row >> 6;
-  const int64_t base = A.slice_ptr[s] + (row & 63);
-  const int len = A.slice_len[s];
-  T acc = T(0);
-#pragma unroll 4
-  for (int k = 0; k < len; ++k) acc += A.val[base + 64 * k] * (T)x[A.col[base + 64 * k]];
-  return acc;
-}
-
 __global__ void __launch_bounds__(kThreads) k_spmv(SellView A, const double* __restrict__ x, double* __restrict__ y) {
   for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < A.rows;
        row += (int64_t)gridDim.x * blockDim.x)
@@ -211,23 +89,29 @@ __global__ void __launch_bounds__(kThreads) k_update_dots(int64_t n, const doubl
   block_partials<K + 1>(acc, partials);
 }
 
-// w -= V h; partials of ||w||^2
+// Second Gram-Schmidt pass fused with the normalisation.  h holds V^T w and ||w||^2 from
+// the kernel before; with V orthonormal, ||w - V V^T w||^2 = ||w||^2 - |V^T w|^2, so the
+// new basis vector (w - V h) / sqrt(||w||^2 - |h|^2) is written in place with no reduction
+// of its own.  After a first pass |h| is small against ||w||, so the difference loses no
+// accuracy.  A difference <= 0 (breakdown) writes zeros.
 template <int K>
-__global__ void __launch_bounds__(kThreads) k_update_norm(int64_t n, const double* __restrict__ V, int64_t ldv,
-                                                          const double* __restrict__ h, double* __restrict__ w,
-                                                          double* partials) {
+__global__ void __launch_bounds__(kThreads) k_update_normalize(int64_t n, const double* __restrict__ V, int64_t ldv,
+                                                               const double* __restrict__ h, double* __restrict__ w) {
   double hk[K];
+  double hh = 0.0;
 #pragma unroll
-  for (int k = 0; k < K; ++k) hk[k] = h[k];
-  double acc[1] = {0.0};
+  for (int k = 0; k < K; ++k) {
+    hk[k] = h[k];
+    hh += hk[k] * hk[k];
+  }
+  const double nn = h[K] - hh;
+  const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     double wi = w[i];
 #pragma unroll
     for (int k = 0; k < K; ++k) wi -= V[k * ldv + i] * hk[k];
-    w[i] = wi;
-    acc[0] += wi * wi;
+    w[i] = wi * inv;
   }
-  block_partials<1>(acc, partials);
 }
 
 // out = x - v (dot * inv_vv): x without its component along v (dot = v . x on the device)
@@ -276,148 +160,6 @@ __global__ void k_sum(int64_t n, const double* __restrict__ x, double* partials)
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     acc[0] += x[i];
   block_partials<1>(acc, partials);
-}
-
-// ---- inner Jacobi-preconditioned CG, pipelined: one kernel per iteration ------------------
-// Pipelined CG (Ghysels & Vanroose) overlaps the two dot products of an
-// iteration with its matrix-vector product, so one kernel per iteration
-// suffices: it sums the dot-product partials that the previous kernel left
-// (every block in the same order, hence the same scalars everywhere), forms
-// alpha and beta, performs the product and every vector update, and writes
-// the partials of the next iteration's dots.  With the Jacobi preconditioner
-// D^{-1} the preconditioned vectors are diagonal scalings (u = D^{-1} r,
-// q = D^{-1} s, m = D^{-1} w), and the product A D^{-1} w uses the
-// column-scaled copy A D^{-1}, so only r, w, s, z, p, x are stored; w
-// alternates between two buffers because neighbours read it while its owner
-// updates it.  Iteration i, with gamma = r.D^{-1}r, delta = w.D^{-1}r:
-//   beta = gamma_i / gamma_{i-1},  alpha = gamma_i / (delta - beta gamma_i / alpha_{i-1})
-//   n = (A D^{-1}) w,  z = n + beta z,  s = w + beta s,  p = D^{-1} r + beta p,
-//   x += alpha p,  r -= alpha s,  w -= alpha z.
-// The stopping test is gamma_i <= tol^2 gamma_0, as for the plain algorithm.
-template <typename T>
-struct PcgViewT {
-  T* __restrict__ x;
-  T* __restrict__ r;
-  T* __restrict__ z;
-  T* __restrict__ s;
-  T* __restrict__ p;
-  T* __restrict__ w0;
-  T* __restrict__ w1;
-  const T* __restrict__ dinv;
-};
-
-// w = (A D^{-1}) b, x = 0, r = b; partials of gamma_0, delta_0 (slot 0).  b is FP64 and is
-// rounded to T element by element (also where it is gathered).
-template <typename T, int kBlock>
-__global__ void __launch_bounds__(kBlock) k_ppcg_init(SellViewT<T> Ac, PcgViewT<T> v,
-                                                           const double* __restrict__ b, PcgState* st, double tol2,
-                                                           int maxit, double* __restrict__ part) {
-  double acc[2] = {0.0, 0.0};
-  for (int64_t row = xcd_block() * blockDim.x + threadIdx.x; row < Ac.rows;
-       row += (int64_t)gridDim.x * blockDim.x) {
-    const T bi = (T)b[row], di = v.dinv[row];
-    const T wi = sell_dot(Ac, row, b);
-    v.x[row] = T(0);
-    v.r[row] = bi;
-    v.w0[row] = wi;
-    acc[0] += (double)bi * (double)bi * (double)di;
-    acc[1] += (double)wi * (double)bi * (double)di;
-  }
-  block_partials<2>(acc, part);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    st->gamma[0] = st->gamma[1] = 0.0;
-    st->alpha[0] = st->alpha[1] = 0.0;
-    st->gamma0 = 0.0;
-    st->tol2 = tol2;
-    st->count = 0;
-    st->maxit = maxit;
-    st->done = maxit <= 0 ? 1 : 0;
-  }
-}
-
-// One pipelined CG iteration.  Vectors and matrix values in T; scalars and dot products in FP64.
-template <typename T, bool kFirst, int kBlock>
-__global__ void __launch_bounds__(kBlock) k_ppcg_iter(int parity, SellViewT<T> Ac, PcgViewT<T> v, PcgState* st,
-                                                           double* __restrict__ part) {
-  const int P = gridDim.x;
-  const int cur = parity;
-  const T* __restrict__ win = cur ? v.w1 : v.w0;
-  T* __restrict__ wout = cur ? v.w0 : v.w1;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t row = xcd_block() * blockDim.x + threadIdx.x;
-  // The product and the old vector entries do not depend on this iteration's
-  // scalars: their loads are issued first and are in flight while the block sums
-  // the partials of gamma and delta left by the previous iteration.
-  T n = T(0), wi = T(0), di = T(0), ri = T(0), zo = T(0), so = T(0), po = T(0), xo = T(0);
-  auto load = [&](int64_t i) {
-    n = sell_dot(Ac, i, win);
-    wi = win[i];
-    di = v.dinv[i];
-    ri = v.r[i];
-    xo = v.x[i];
-    if (!kFirst) {
-      zo = v.z[i];
-      so = v.s[i];
-      po = v.p[i];
-    }
-  };
-  if (row < Ac.rows) load(row);
-  const int was_done = st->done;
-  double gd[2];
-  block_sum_partials2(part + (size_t)cur * 2 * P, P, gd);
-  if (was_done) return;
-  const double gamma = gd[0], delta = gd[1];
-  double gamma0, beta, alpha;
-  if (kFirst) {
-    gamma0 = gamma;
-    beta = 0.0;
-    alpha = gamma / delta;
-  } else {
-    gamma0 = st->gamma0;
-    beta = gamma / st->gamma[1 - cur];
-    alpha = gamma / (delta - beta * gamma / st->alpha[1 - cur]);
-  }
-  int done = 0;
-  if (!(gamma > st->tol2 * gamma0)) done = 1;
-  else if (!(alpha > 0.0) || !isfinite(alpha)) done = 2;  // loss of positivity: keep the iterate
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (kFirst) st->gamma0 = gamma0;
-    st->gamma[cur] = gamma;
-    st->alpha[cur] = alpha;
-    if (done) st->done = done;
-  }
-  if (done) return;
-  const T a = (T)alpha, bt = (T)beta;
-  double acc[2] = {0.0, 0.0};
-  while (row < Ac.rows) {
-    T zz, ss, pp;
-    if (kFirst) {
-      zz = n;
-      ss = wi;
-      pp = di * ri;
-    } else {
-      zz = n + bt * zo;
-      ss = wi + bt * so;
-      pp = di * ri + bt * po;
-    }
-    v.z[row] = zz;
-    v.s[row] = ss;
-    v.p[row] = pp;
-    v.x[row] = xo + a * pp;
-    const T rn = ri - a * ss;
-    const T wn = wi - a * zz;
-    v.r[row] = rn;
-    wout[row] = wn;
-    acc[0] += (double)rn * (double)rn * (double)di;
-    acc[1] += (double)wn * (double)rn * (double)di;
-    row += stride;
-    if (row < Ac.rows) load(row);
-  }
-  block_partials<2>(acc, part + (size_t)(1 - cur) * 2 * P);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    st->count += 1;
-    st->total += 1;
-  }
 }
 
 // ---- classical Jacobi-PCG in FP32 (mixed-precision inner solves) --------------------------
@@ -551,12 +293,6 @@ inline int stream_grid(int64_t n) {
   return (int)(b < cap ? (b < 1 ? 1 : b) : cap);
 }
 
-inline int pcg_grid(int64_t n, int block = kPcgThreads) {
-  const int64_t cap = kPcgMaxThreads / block;
-  int64_t b = (n + block - 1) / block;
-  return (int)(b < cap ? (b < 1 ? 1 : b) : cap);
-}
-
 #define VEM_K_CASES(X) \
   X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20) \
   X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
@@ -606,17 +342,16 @@ void launch_update_dots(hipStream_t s, int64_t n, int k, const double* V, int64_
   finalize(s, grid, k + 1, partials, out);
 }
 
-void launch_update_norm(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* h, double* w,
-                        double* partials, double* out) {
-  int grid = red_grid(n);
+void launch_update_normalize(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* h,
+                             double* w) {
+  int grid = stream_grid(n);
   switch (k) {
 #define X(K) \
-  case K: k_update_norm<K><<<grid, kThreads, 0, s>>>(n, V, ldv, h, w, partials); break;
+  case K: k_update_normalize<K><<<grid, kThreads, 0, s>>>(n, V, ldv, h, w); break;
     VEM_K_CASES(X)
 #undef X
     default: throw Error{VEM_EINVAL, "too many basis vectors"};
   }
-  finalize(s, grid, 1, partials, out);
 }
 
 void launch_project(hipStream_t s, int64_t n, const double* x, const double* v, const double* dot, double inv_vv,
@@ -660,13 +395,6 @@ void launch_col_scale(hipStream_t s, Sell& A, const double* dinv) {
   k_col_scale<<<stream_grid(A.nnz), kThreads, 0, s>>>(A.nnz, A.col, A.val, dinv, A.val_cs);
 }
 
-template <typename T>
-static PcgViewT<T> pview(const PcgWorkT<T>& w) {
-  return {w.x, w.r, w.z, w.s, w.p, w.w0, w.w1, w.dinv};
-}
-
-static SellView view_cs(const Sell& A) { return {A.rows, A.slice_ptr, A.slice_len, A.col, A.val_cs}; }
-static SellViewT<float> view32(const Sell& A) { return {A.rows, A.slice_ptr, A.slice_len, A.col, A.val32}; }
 
 void launch_col_scale32(hipStream_t s, Sell& A, const double* dinv, float* dinv32) {
   if (A.nnz <= 0) return;
@@ -677,37 +405,6 @@ void launch_col_scale32(hipStream_t s, Sell& A, const double* dinv, float* dinv3
 
 void launch_to_f64(hipStream_t s, int64_t n, const float* x, double* y) {
   if (n > 0) k_to_f64<<<stream_grid(n), kThreads, 0, s>>>(n, x, y);
-}
-
-template <int kBlock>
-void pcg_init_as(hipStream_t s, const Sell& A, const PcgWork& w, const double* b, PcgState* st, double tol, int maxit,
-                 double* part) {
-  k_ppcg_init<double, kBlock><<<pcg_grid(A.rows, kBlock), kBlock, 0, s>>>(view_cs(A), pview(w), b, st, tol * tol,
-                                                                           maxit, part);
-}
-
-template <int kBlock>
-void pcg_iter_as(hipStream_t s, int i, const Sell& A, const PcgWork& w, PcgState* st, double* part) {
-  const int P = pcg_grid(A.rows, kBlock);
-  if (i == 0)
-    k_ppcg_iter<double, true, kBlock><<<P, kBlock, 0, s>>>(0, view_cs(A), pview(w), st, part);
-  else
-    k_ppcg_iter<double, false, kBlock><<<P, kBlock, 0, s>>>(i & 1, view_cs(A), pview(w), st, part);
-}
-
-void launch_pcg_init(hipStream_t s, const Sell& A, const PcgWork& w, const double* b, PcgState* st, double tol,
-                     int maxit, double* part) {
-  if (A.rows > kPcgMaxThreads)  // threads loop over rows
-    pcg_init_as<256>(s, A, w, b, st, tol, maxit, part);
-  else
-    pcg_init_as<1024>(s, A, w, b, st, tol, maxit, part);
-}
-
-void launch_pcg_iter(hipStream_t s, int i, const Sell& A, const PcgWork& w, PcgState* st, double* part) {
-  if (A.rows > kPcgMaxThreads)  // threads loop over rows
-    pcg_iter_as<256>(s, i, A, w, st, part);
-  else
-    pcg_iter_as<1024>(s, i, A, w, st, part);
 }
 
 void launch_pcg_init32(hipStream_t s, const Sell& A, const PcgWork32& w, const double* b, PcgState* st, double tol,

@@ -223,20 +223,26 @@ __global__ void k_bnd_tri_counts(int nb, const int* __restrict__ bface, const in
   cnt[i] = fptr[f + 1] - fptr[f] - 2;
 }
 
-// One thread per quadrature point: x = O + xi (v0 - O) + eta (v_a - O) + zeta (v_{a+1} - O).
-// A block maps kThreads consecutive points; the corners of the (at most kThreads + 1)
-// tetrahedra they belong to are fetched once into LDS instead of once per point.
-__global__ void __launch_bounds__(kThreads) k_qp_cell(int64_t total, int npts, const double* __restrict__ ref,
+// Points x = O + xi (v0 - O) + eta (v_a - O) + zeta (v_{a+1} - O).  A block takes a run of
+// whole tetrahedra (about 2048 points, at most kQpTets tetrahedra): their corners are fetched
+// once into LDS by one thread each, then the block's threads write the run's points in
+// order, so that consecutive threads store consecutive entries of each coordinate array.
+constexpr int kQpTets = 256;
+inline int qp_tets_per_block(int npts) {
+  const int t = 2048 / (npts > 0 ? npts : 1);
+  return t < 1 ? 1 : (t > kQpTets ? kQpTets : t);
+}
+
+__global__ void __launch_bounds__(kThreads) k_qp_cell(int64_t ntet, int npts, int tets_per_block,
+                                                      const double* __restrict__ ref,
                                                       const int* __restrict__ tet_inc, const int* __restrict__ tet_a,
                                                       const int* __restrict__ inc_cell, const double* __restrict__ xyz,
                                                       const int* __restrict__ fptr, const int* __restrict__ fvtx,
                                                       const int* __restrict__ cface, const double* __restrict__ xref,
                                                       double* qp) {
-  __shared__ double corner[kThreads + 1][12];  // O, v0, v_a, v_{a+1}
-  const int64_t g0 = (int64_t)blockIdx.x * kThreads;
-  const int64_t gl = (g0 + kThreads < total ? g0 + kThreads : total) - 1;
-  const int64_t t0 = g0 / npts;
-  const int nt = (int)(gl / npts - t0 + 1);
+  __shared__ double corner[kQpTets][12];  // O, v0, v_a, v_{a+1}
+  const int64_t t0 = (int64_t)blockIdx.x * tets_per_block;
+  const int nt = (int)(ntet - t0 < tets_per_block ? ntet - t0 : tets_per_block);
   for (int i = threadIdx.x; i < nt; i += kThreads) {
     const int64_t t = t0 + i;
     const int j = tet_inc[t], a = tet_a[t];
@@ -249,14 +255,15 @@ __global__ void __launch_bounds__(kThreads) k_qp_cell(int64_t total, int npts, c
     }
   }
   __syncthreads();
-  const int64_t g = g0 + threadIdx.x;
-  if (g >= total) return;
-  const int64_t t = g / npts;
-  const int r = (int)(g - t * npts);
-  const double* c = corner[t - t0];
-  const V3 O{c[0], c[1], c[2]}, A{c[3], c[4], c[5]}, B{c[6], c[7], c[8]}, C{c[9], c[10], c[11]};
-  const double xi = ref[3 * r], eta = ref[3 * r + 1], zeta = ref[3 * r + 2];
-  st3_soa(qp, total, g, O + xi * (A - O) + eta * (B - O) + zeta * (C - O));
+  const int64_t total = ntet * npts, q0 = t0 * npts;
+  const int np = nt * npts;
+  for (int q = threadIdx.x; q < np; q += kThreads) {
+    const int i = q / npts, r = q - i * npts;
+    const double* c = corner[i];
+    const V3 O{c[0], c[1], c[2]}, A{c[3], c[4], c[5]}, B{c[6], c[7], c[8]}, C{c[9], c[10], c[11]};
+    const double xi = ref[3 * r], eta = ref[3 * r + 1], zeta = ref[3 * r + 2];
+    st3_soa(qp, total, q0 + q, O + xi * (A - O) + eta * (B - O) + zeta * (C - O));
+  }
 }
 
 // Boundary-face points: triangles (v0, v_a, v_{a+1}), x = v0 + xi (v_a - v0) + eta (v_{a+1} - v0).
@@ -275,10 +282,18 @@ __global__ void k_qp_face(int nb, int npts, int64_t total, const double* __restr
   }
 }
 
-// Per tetrahedron: sigma det * sum_r w_r f(x_r).  A block takes kThreads consecutive
-// tetrahedra; their point values are contiguous and are read in coalesced chunks
-// through LDS, each thread summing its own points in order.
-__global__ void __launch_bounds__(kThreads) k_load_tets(int64_t ntet, int npts, const double* __restrict__ refw,
+// Per tetrahedron: sigma det * sum_r w_r f(x_r).  A block takes a run of whole tetrahedra
+// (at most kThreads of them, at most kLoadPts points): their point values are contiguous,
+// are read into LDS with coalesced loads all in flight at once, and each thread then sums
+// its own tetrahedron's points in order.
+constexpr int kLoadPts = 4096;
+inline int load_tets_per_block(int npts) {
+  const int t = kLoadPts / (npts > 0 ? npts : 1);
+  return t < 1 ? 1 : (t > kThreads ? kThreads : t);
+}
+
+__global__ void __launch_bounds__(kThreads) k_load_tets(int64_t ntet, int npts, int tets_per_block,
+                                                        const double* __restrict__ refw,
                                                         const int* __restrict__ tet_inc, const int* __restrict__ tet_a,
                                                         const int* __restrict__ inc_cell,
                                                         const double* __restrict__ xyz, const int* __restrict__ fptr,
@@ -286,32 +301,27 @@ __global__ void __launch_bounds__(kThreads) k_load_tets(int64_t ntet, int npts, 
                                                         const int8_t* __restrict__ csign,
                                                         const double* __restrict__ xref, const double* __restrict__ fq,
                                                         double* tet_sum) {
-  constexpr int kChunk = 2048;
-  __shared__ double chunk[kChunk];
-  const int64_t t0 = (int64_t)blockIdx.x * kThreads;
-  const int64_t tend = t0 + kThreads < ntet ? t0 + kThreads : ntet;
-  const int64_t t = t0 + threadIdx.x;
-  const int64_t q1 = tend * npts;
-  const int64_t my0 = t * npts, my1 = my0 + npts;
-  double acc = 0.0;
-  for (int64_t c0 = t0 * npts; c0 < q1; c0 += kChunk) {
-    const int64_t c1 = c0 + kChunk < q1 ? c0 + kChunk : q1;
-    __syncthreads();  // the previous chunk has been read
-    for (int64_t q = c0 + threadIdx.x; q < c1; q += kThreads) chunk[q - c0] = fq[q];
-    __syncthreads();
-    if (t < tend) {
-      const int64_t a = my0 > c0 ? my0 : c0, b = my1 < c1 ? my1 : c1;
-      for (int64_t q = a; q < b; ++q) acc += refw[q - my0] * chunk[q - c0];
-    }
+  __shared__ double vals[kLoadPts];
+  const int64_t t0 = (int64_t)blockIdx.x * tets_per_block;
+  const int nt = (int)(ntet - t0 < tets_per_block ? ntet - t0 : tets_per_block);
+  const int np = nt * npts;
+  const int64_t q0 = t0 * npts;
+  for (int q = threadIdx.x; q < np; q += kThreads) vals[q] = fq[q0 + q];
+  double det = 0.0;
+  const int i = threadIdx.x;
+  if (i < nt) {
+    const int64_t t = t0 + i;
+    const int j = tet_inc[t], a = tet_a[t];
+    const int fs = fptr[cface[j]];
+    const V3 O = ld3(xref, inc_cell[j]);
+    const V3 A = ld3(xyz, fvtx[fs]), B = ld3(xyz, fvtx[fs + a]), C = ld3(xyz, fvtx[fs + a + 1]);
+    det = dot(A - O, cross(B - O, C - O)) * (double)csign[j];
   }
-  if (t >= tend) return;
-  int j = tet_inc[t], a = tet_a[t];
-  int f = cface[j];
-  int fs = fptr[f];
-  V3 O = ld3(xref, inc_cell[j]);
-  V3 A = ld3(xyz, fvtx[fs]), B = ld3(xyz, fvtx[fs + a]), C = ld3(xyz, fvtx[fs + a + 1]);
-  double det = dot(A - O, cross(B - O, C - O)) * (double)csign[j];
-  tet_sum[t] = det * acc;
+  __syncthreads();
+  if (i >= nt) return;
+  double acc = 0.0;
+  for (int r = 0; r < npts; ++r) acc += refw[r] * vals[i * npts + r];
+  tet_sum[t0 + i] = det * acc;
 }
 
 __global__ void k_load_cells(int nc, const int* __restrict__ ctp, const double* __restrict__ tet_sum,
@@ -417,10 +427,11 @@ void launch_bnd_tri_counts(hipStream_t s, int nb, const int* bface, const int* f
 void launch_qp_cell(hipStream_t s, int64_t ntet, int npts, const double* ref, const int* tet_inc, const int* tet_a,
                     const int* inc_cell, const double* xyz, const int* fptr, const int* fvtx, const int* cface,
                     const double* xref, double* qp) {
-  int64_t total = ntet * npts;
-  if (total > 0)
-    k_qp_cell<<<nblocks(total), kThreads, 0, s>>>(total, npts, ref, tet_inc, tet_a, inc_cell, xyz, fptr, fvtx,
-                                                  cface, xref, qp);
+  if (ntet > 0 && npts > 0) {
+    const int tpb = qp_tets_per_block(npts);
+    k_qp_cell<<<(int)((ntet + tpb - 1) / tpb), kThreads, 0, s>>>(ntet, npts, tpb, ref, tet_inc, tet_a, inc_cell,
+                                                                   xyz, fptr, fvtx, cface, xref, qp);
+  }
 }
 void launch_qp_face(hipStream_t s, int nb, int npts, int64_t total, const double* ref, const int* bface,
                     const int* btri_ptr, const double* xyz, const int* fptr, const int* fvtx, double* qp) {
@@ -431,9 +442,11 @@ void launch_load_tets(hipStream_t s, int64_t ntet, int npts, const double* refw,
                       const int* tet_a, const int* inc_cell, const double* xyz, const int* fptr, const int* fvtx,
                       const int* cface, const int8_t* csign, const double* xref, const double* fq,
                       double* tet_sum) {
-  if (ntet > 0)
-    k_load_tets<<<nblocks(ntet), kThreads, 0, s>>>(ntet, npts, refw, tet_inc, tet_a, inc_cell, xyz, fptr, fvtx,
-                                                   cface, csign, xref, fq, tet_sum);
+  if (ntet > 0 && npts > 0) {
+    const int tpb = load_tets_per_block(npts);
+    k_load_tets<<<(int)((ntet + tpb - 1) / tpb), kThreads, 0, s>>>(ntet, npts, tpb, refw, tet_inc, tet_a, inc_cell,
+                                                                     xyz, fptr, fvtx, cface, csign, xref, fq, tet_sum);
+  }
 }
 void launch_load_cells(hipStream_t s, int nc, const int* cell_tet_ptr, const double* tet_sum, double* rhs_p) {
   k_load_cells<<<nblocks(nc), kThreads, 0, s>>>(nc, cell_tet_ptr, tet_sum, rhs_p);

@@ -1,0 +1,188 @@
+// The inner Jacobi-preconditioned conjugate gradients of the block preconditioners,
+// pipelined so that one kernel performs one iteration.
+#include "krylov_device.h"
+
+namespace vem {
+namespace {
+
+// ---- inner Jacobi-preconditioned CG, pipelined: one kernel per iteration ------------------
+// Pipelined CG (Ghysels & Vanroose) overlaps the two dot products of an
+// iteration with its matrix-vector product, so one kernel per iteration
+// suffices: it sums the dot-product partials that the previous kernel left
+// (every block in the same order, hence the same scalars everywhere), forms
+// alpha and beta, performs the product and every vector update, and writes
+// the partials of the next iteration's dots.  With the Jacobi preconditioner
+// D^{-1} the preconditioned vectors are diagonal scalings (u = D^{-1} r,
+// q = D^{-1} s, m = D^{-1} w), and the product A D^{-1} w uses the
+// column-scaled copy A D^{-1}, so only r, w, s, z, p, x are stored; w
+// alternates between two buffers because neighbours read it while its owner
+// updates it.  Iteration i, with gamma = r.D^{-1}r, delta = w.D^{-1}r:
+//   beta = gamma_i / gamma_{i-1},  alpha = gamma_i / (delta - beta gamma_i / alpha_{i-1})
+//   n = (A D^{-1}) w,  z = n + beta z,  s = w + beta s,  p = D^{-1} r + beta p,
+//   x += alpha p,  r -= alpha s,  w -= alpha z.
+// The stopping test is gamma_i <= tol^2 gamma_0, as for the plain algorithm.
+template <typename T>
+struct PcgViewT {
+  T* __restrict__ x;
+  T* __restrict__ r;
+  T* __restrict__ z;
+  T* __restrict__ s;
+  T* __restrict__ p;
+  T* __restrict__ w0;
+  T* __restrict__ w1;
+  const T* __restrict__ dinv;
+};
+
+// w = (A D^{-1}) b, x = 0, r = b; partials of gamma_0, delta_0 (slot 0).  b is FP64 and is
+// rounded to T element by element (also where it is gathered).
+template <typename T, int kBlock>
+__global__ void __launch_bounds__(kBlock) k_ppcg_init(SellViewT<T> Ac, PcgViewT<T> v,
+                                                           const double* __restrict__ b, PcgState* st, double tol2,
+                                                           int maxit, double* __restrict__ part) {
+  double acc[2] = {0.0, 0.0};
+  for (int64_t row = xcd_block() * blockDim.x + threadIdx.x; row < Ac.rows;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    const T bi = (T)b[row], di = v.dinv[row];
+    const T wi = sell_dot(Ac, row, b);
+    v.x[row] = T(0);
+    v.r[row] = bi;
+    v.w0[row] = wi;
+    acc[0] += (double)bi * (double)bi * (double)di;
+    acc[1] += (double)wi * (double)bi * (double)di;
+  }
+  block_partials<2>(acc, part);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->gamma[0] = st->gamma[1] = 0.0;
+    st->alpha[0] = st->alpha[1] = 0.0;
+    st->gamma0 = 0.0;
+    st->tol2 = tol2;
+    st->count = 0;
+    st->maxit = maxit;
+    st->done = maxit <= 0 ? 1 : 0;
+  }
+}
+
+// One pipelined CG iteration.  Vectors and matrix values in T; scalars and dot products in FP64.
+template <typename T, bool kFirst, int kBlock>
+__global__ void __launch_bounds__(kBlock) k_ppcg_iter(int parity, SellViewT<T> Ac, PcgViewT<T> v, PcgState* st,
+                                                           double* __restrict__ part) {
+  const int P = gridDim.x;
+  const int cur = parity;
+  const T* __restrict__ win = cur ? v.w1 : v.w0;
+  T* __restrict__ wout = cur ? v.w0 : v.w1;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t row = xcd_block() * blockDim.x + threadIdx.x;
+  // The product and the old vector entries do not depend on this iteration's
+  // scalars: their loads are issued first and are in flight while the block sums
+  // the partials of gamma and delta left by the previous iteration.
+  T n = T(0), wi = T(0), di = T(0), ri = T(0), zo = T(0), so = T(0), po = T(0), xo = T(0);
+  auto load = [&](int64_t i) {
+    n = sell_dot(Ac, i, win);
+    wi = win[i];
+    di = v.dinv[i];
+    ri = v.r[i];
+    xo = v.x[i];
+    if (!kFirst) {
+      zo = v.z[i];
+      so = v.s[i];
+      po = v.p[i];
+    }
+  };
+  if (row < Ac.rows) load(row);
+  const int was_done = st->done;
+  double gd[2];
+  block_sum_partials2(part + (size_t)cur * 2 * P, P, gd);
+  if (was_done) return;
+  const double gamma = gd[0], delta = gd[1];
+  double gamma0, beta, alpha;
+  if (kFirst) {
+    gamma0 = gamma;
+    beta = 0.0;
+    alpha = gamma / delta;
+  } else {
+    gamma0 = st->gamma0;
+    beta = gamma / st->gamma[1 - cur];
+    alpha = gamma / (delta - beta * gamma / st->alpha[1 - cur]);
+  }
+  int done = 0;
+  if (!(gamma > st->tol2 * gamma0)) done = 1;
+  else if (!(alpha > 0.0) || !isfinite(alpha)) done = 2;  // loss of positivity: keep the iterate
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (kFirst) st->gamma0 = gamma0;
+    st->gamma[cur] = gamma;
+    st->alpha[cur] = alpha;
+    if (done) st->done = done;
+  }
+  if (done) return;
+  const T a = (T)alpha, bt = (T)beta;
+  double acc[2] = {0.0, 0.0};
+  while (row < Ac.rows) {
+    T zz, ss, pp;
+    if (kFirst) {
+      zz = n;
+      ss = wi;
+      pp = di * ri;
+    } else {
+      zz = n + bt * zo;
+      ss = wi + bt * so;
+      pp = di * ri + bt * po;
+    }
+    v.z[row] = zz;
+    v.s[row] = ss;
+    v.p[row] = pp;
+    v.x[row] = xo + a * pp;
+    const T rn = ri - a * ss;
+    const T wn = wi - a * zz;
+    v.r[row] = rn;
+    wout[row] = wn;
+    acc[0] += (double)rn * (double)rn * (double)di;
+    acc[1] += (double)wn * (double)rn * (double)di;
+    row += stride;
+    if (row < Ac.rows) load(row);
+  }
+  block_partials<2>(acc, part + (size_t)(1 - cur) * 2 * P);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->count += 1;
+    st->total += 1;
+  }
+}
+
+template <typename T>
+PcgViewT<T> pview(const PcgWorkT<T>& w) {
+  return {w.x, w.r, w.z, w.s, w.p, w.w0, w.w1, w.dinv};
+}
+
+template <int kBlock>
+void pcg_init_as(hipStream_t s, const Sell& A, const PcgWork& w, const double* b, PcgState* st, double tol, int maxit,
+                 double* part) {
+  k_ppcg_init<double, kBlock><<<pcg_grid(A.rows, kBlock), kBlock, 0, s>>>(view_cs(A), pview(w), b, st, tol * tol,
+                                                                           maxit, part);
+}
+
+template <int kBlock>
+void pcg_iter_as(hipStream_t s, int i, const Sell& A, const PcgWork& w, PcgState* st, double* part) {
+  const int P = pcg_grid(A.rows, kBlock);
+  if (i == 0)
+    k_ppcg_iter<double, true, kBlock><<<P, kBlock, 0, s>>>(0, view_cs(A), pview(w), st, part);
+  else
+    k_ppcg_iter<double, false, kBlock><<<P, kBlock, 0, s>>>(i & 1, view_cs(A), pview(w), st, part);
+}
+
+}  // namespace
+
+void launch_pcg_init(hipStream_t s, const Sell& A, const PcgWork& w, const double* b, PcgState* st, double tol,
+                     int maxit, double* part) {
+  if (A.rows > kPcgMaxThreads)  // threads loop over rows
+    pcg_init_as<256>(s, A, w, b, st, tol, maxit, part);
+  else
+    pcg_init_as<1024>(s, A, w, b, st, tol, maxit, part);
+}
+
+void launch_pcg_iter(hipStream_t s, int i, const Sell& A, const PcgWork& w, PcgState* st, double* part) {
+  if (A.rows > kPcgMaxThreads)  // threads loop over rows
+    pcg_iter_as<256>(s, i, A, w, st, part);
+  else
+    pcg_iter_as<1024>(s, i, A, w, st, part);
+}
+
+}  // namespace vem

@@ -73,28 +73,40 @@ inline int grid256(int64_t n) { return (int)((n + 255) / 256); }
 
 }  // namespace
 
-void build_sell(hipStream_t s, Scratch& tmp, const Csr& A, Sell& S) {
-  S.rows = A.rows;
-  S.nslices = (A.rows + 63) / 64;
-  S.slice_len.alloc(S.nslices);
-  DBuf<int64_t>& sz = tmp.i64[0];
-  DBuf<int64_t>& ptr = tmp.i64[1];
-  sz.reserve(S.nslices + 1);
-  ptr.reserve(S.nslices + 1);
-  k_sell_len<<<grid256(S.nslices), 256, 0, s>>>(A.rows, S.nslices, A.rowptr, S.slice_len, sz);
-  VEM_HIP(hipGetLastError());
-  int64_t total = scan_i64(s, tmp, sz, S.nslices, ptr);
-  VEM_REQUIRE(total < INT32_MAX, VEM_ENOMEM, "padded matrix exceeds 2^31-1 entries");
-  S.nnz = total;
-  S.slice_ptr.alloc(S.nslices + 1);
-  k_narrow64<<<grid256(S.nslices + 1), 256, 0, s>>>(S.nslices + 1, ptr, S.slice_ptr);
-  S.col.alloc(total);
-  S.src.alloc(total);
-  S.val.alloc(total);
-  int64_t nrow_pad = S.nslices * 64;
-  k_sell_fill<<<grid256(nrow_pad), 256, 0, s>>>(A.rows, A.rowptr, A.col, ptr, S.slice_len, S.col, S.src);
-  VEM_HIP(hipGetLastError());
+void build_sells(hipStream_t s, Scratch& tmp, const Csr* const* A, Sell* const* S, int count) {
+  VEM_REQUIRE(count >= 0 && count <= 3, VEM_EINVAL, "at most three SELL builds at once");
+  int64_t maxsl = 1;
+  for (int m = 0; m < count; ++m) maxsl = std::max<int64_t>(maxsl, (A[m]->rows + 63) / 64);
+  scan_reserve(tmp, maxsl);
+  for (int m = 0; m < count; ++m) {
+    Sell& B = *S[m];
+    B.rows = A[m]->rows;
+    B.nslices = (B.rows + 63) / 64;
+    B.slice_len.alloc(B.nslices);
+    DBuf<int64_t>& sz = tmp.i64[2 * m];
+    DBuf<int64_t>& ptr = tmp.i64[2 * m + 1];
+    sz.reserve(B.nslices + 1);
+    ptr.reserve(B.nslices + 1);
+    k_sell_len<<<grid256(B.nslices), 256, 0, s>>>(B.rows, B.nslices, A[m]->rowptr, B.slice_len, sz);
+    VEM_HIP(hipGetLastError());
+    scan_i64_async(s, tmp, sz, B.nslices, ptr, m);
+  }
   VEM_HIP(hipStreamSynchronize(s));
+  for (int m = 0; m < count; ++m) {
+    Sell& B = *S[m];
+    const int64_t total = tmp.tot.p[m];
+    VEM_REQUIRE(total < INT32_MAX, VEM_ENOMEM, "padded matrix exceeds 2^31-1 entries");
+    DBuf<int64_t>& ptr = tmp.i64[2 * m + 1];
+    B.nnz = total;
+    B.slice_ptr.alloc(B.nslices + 1);
+    k_narrow64<<<grid256(B.nslices + 1), 256, 0, s>>>(B.nslices + 1, ptr, B.slice_ptr);
+    B.col.alloc(total);
+    B.src.alloc(total);
+    B.val.alloc(total);
+    const int64_t nrow_pad = B.nslices * 64;
+    k_sell_fill<<<grid256(nrow_pad), 256, 0, s>>>(B.rows, A[m]->rowptr, A[m]->col, ptr, B.slice_len, B.col, B.src);
+    VEM_HIP(hipGetLastError());
+  }
 }
 
 void refresh_sell(hipStream_t s, const Csr& A, Sell& S) {

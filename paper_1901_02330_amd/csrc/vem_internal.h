@@ -62,16 +62,6 @@ struct DBuf {
   operator T*() const { return p; }
 };
 
-// Grow-only device scratch owned by a handle, for the temporaries of the set-up calls:
-// a hipMalloc/hipFree pair per call synchronises the device and costs 0.1-0.5 ms.
-// Slots are handed out by the caller; no two live temporaries share a slot.
-struct Scratch {
-  DBuf<unsigned char> cub;  // hipcub temporary storage
-  DBuf<int64_t> i64[4];
-  DBuf<int> i32[4];
-  DBuf<double> f64[8];
-};
-
 // Pinned host buffer.
 template <class T>
 struct HBuf {
@@ -91,6 +81,17 @@ struct HBuf {
     n = count;
   }
   T& operator[](size_t i) { return p[i]; }
+};
+
+// Grow-only device scratch owned by a handle, for the temporaries of the set-up calls:
+// a hipMalloc/hipFree pair per call synchronises the device and costs 0.1-0.5 ms.
+// Slots are handed out by the caller; no two live temporaries share a slot.
+struct Scratch {
+  DBuf<unsigned char> cub;  // hipcub temporary storage
+  DBuf<int64_t> i64[8];
+  DBuf<int> i32[4];
+  DBuf<double> f64[8];
+  HBuf<int64_t> tot;        // pinned landing slots for the totals of asynchronous scans
 };
 
 // Reduction scratch: per-block partial sums.
@@ -141,7 +142,9 @@ struct Sell {
   DBuf<double> val_cs;   // column-scaled copy A D^{-1} (inner CG matrices only)
   DBuf<float> val32;     // FP32 rounding of val (mixed-precision inner solves)
 };
-void build_sell(hipStream_t s, Scratch& tmp, const Csr& A, Sell& S);
+// SELL copies of `count` (<= 3) CSR matrices, with one host synchronisation for all of
+// their padded sizes (uses tmp.i64[2m], tmp.i64[2m+1] for matrix m and slots 0..count-1).
+void build_sells(hipStream_t s, Scratch& tmp, const Csr* const* A, Sell* const* S, int count);
 void refresh_sell(hipStream_t s, const Csr& A, Sell& S);
 
 // ---- launchers (one translation unit each; all take the handle's stream) ----
@@ -271,8 +274,9 @@ void launch_dots(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, 
                  double* out);
 void launch_update_dots(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* h, double* w,
                         double* partials, double* out);
-void launch_update_norm(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* h, double* w,
-                        double* partials, double* out);
+// w = (w - V h) / sqrt(h[k] - |h[0..k)|^2) in place (h from launch_update_dots)
+void launch_update_normalize(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* h,
+                             double* w);
 void launch_scale_to(hipStream_t s, int64_t n, const double* w, const double* norm2, double* dst);
 void launch_scale_by(hipStream_t s, int64_t n, const double* x, const double* d, double c, double* y);
 void launch_combine(hipStream_t s, int64_t n, int k, const double* Z, int64_t ldz, const double* y, double* x);
@@ -296,9 +300,17 @@ void launch_to_f64(hipStream_t s, int64_t n, const float* x, double* y);
 void gauss_jacobi01(int n, int alpha, double* t, double* w);  // int_0^1 (1-t)^alpha g(t) dt
 void tet_reference_rule(int n, std::vector<double>& pts, std::vector<double>& w);
 void tri_reference_rule(int n, std::vector<double>& pts, std::vector<double>& w);
-// ptr[0..n] = exclusive prefix sums of len[0..n-1]; returns the total (synchronises)
-// Exclusive prefix sums with the total appended (ptr has n+1 entries); return the total
-// (synchronises).  The temporaries come from `tmp` (scan_i32 uses tmp.i64[3]).
+// Exclusive prefix sums with the total appended (ptr has n+1 entries).
+//  - scan_*_async enqueue the scan and a copy of the total into the pinned slot
+//    tmp.tot[slot] (0 <= slot < 8) without waiting: several scans then share one host
+//    synchronisation.  Call scan_reserve(tmp, n) first with the largest n of the group,
+//    so that no scan of the group reallocates the shared hipcub storage.
+//  - scan_i32_async goes through the 64-bit buffer p64 (n + 1 entries); a total beyond
+//    2^31 - 1 is the caller's to reject once it has synchronised.
+//  - scan_i32 / scan_i64 synchronise and return the total (scan_i32 uses tmp.i64[3]).
+void scan_reserve(Scratch& tmp, int64_t n);
+void scan_i64_async(hipStream_t s, Scratch& tmp, const int64_t* len, int64_t n, int64_t* ptr, int slot);
+void scan_i32_async(hipStream_t s, Scratch& tmp, const int* len, int64_t n, int* ptr, DBuf<int64_t>& p64, int slot);
 int64_t scan_i32(hipStream_t s, Scratch& tmp, const int* len, int64_t n, int* ptr);
 int64_t scan_i64(hipStream_t s, Scratch& tmp, const int64_t* len, int64_t n, int64_t* ptr);
 void launch_compact_flags(hipStream_t s, int64_t n, const int* flag, const int* pos, int* out);

@@ -217,7 +217,7 @@ class Solver:
             self.set_rhs(fv, gv)
 
     def solve(self, precond="schur", tol=1e-8, restart=30, maxit=5000, inner_tol=1e-6, inner_maxit=5000,
-              inner_check=32, gamma=0.0, x0=None, precision="fp64", rhs=None, graphs=True):
+              inner_check=32, gamma=0.0, x0=None, precision="fp64", rhs=None, graphs=False):
         t = self.torch
         sz = self.sizes()
         o = SolveOpts()
