@@ -230,8 +230,10 @@ __global__ void k_values(DofLayout L, const int* __restrict__ cptr, const int* _
                          const int64_t* __restrict__ lmat_ptr, const double* __restrict__ M1,
                          const int64_t* __restrict__ lb_ptr, const double* __restrict__ Bdiv1,
                          const double* __restrict__ nu, double inv_gamma, const int* __restrict__ bnd,
-                         const int* __restrict__ Kptr, double* Kval, const int* __restrict__ Aptr, double* Aval) {
+                         const int* __restrict__ Kslice, double* Kval, const int* __restrict__ Aslice, double* Aval) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // entry k of row r sits at slot slice_ptr[r/64] + r%64 + 64k of the SELL arrays: the
+  // stores of a wave's 64 rows are contiguous for each k.  Aval null: K only.
   // prescribed flux DOFs: identity rows and columns in K and A_gamma
   const bool fixed_row = r < L.Nu && fixed_dof(L, bnd, r);
   if (r < L.Nu) {
@@ -247,7 +249,9 @@ __global__ void k_values(DofLayout L, const int* __restrict__ cptr, const int* _
       Mrow[s] = M1 + lmat_ptr[P[s]] + (int64_t)l[s] * nd[s];
       Bp[s] = Bdiv1 + lb_ptr[P[s]];
     }
-    int k = Kptr[r], a = Aptr[r];
+    const int64_t kb = (int64_t)Kslice[r >> 6] + (r & 63);
+    const int64_t ab = Aval ? (int64_t)Aslice[r >> 6] + (r & 63) : 0;
+    int k = 0, a = 0;
     const int* A = sorted_gid + ldof_ptr[P[0]];
     const int* Al = sorted_l + ldof_ptr[P[0]];
     int na = ldof_ptr[P[0] + 1] - ldof_ptr[P[0]];
@@ -263,38 +267,45 @@ __global__ void k_values(DofLayout L, const int* __restrict__ cptr, const int* _
         int lg = Al[ia];
         double ss = sr[0] * ldof_sign(L, cptr, csign, P[0], lg);
         mv += nu[P[0]] * ss * Mrow[0][lg];
-        double t = 0.0;
-        for (int q = 0; q < L.npd; ++q) t += Bp[0][q * nd[0] + l[0]] * Bp[0][q * nd[0] + lg];
-        bb += ss * t;
+        if (Aval) {
+          double t = 0.0;
+          for (int q = 0; q < L.npd; ++q) t += Bp[0][q * nd[0] + l[0]] * Bp[0][q * nd[0] + lg];
+          bb += ss * t;
+        }
         ++ia;
       }
       if (gb == g) {
         int lg = Bl[ib];
         double ss = sr[1] * ldof_sign(L, cptr, csign, P[1], lg);
         mv += nu[P[1]] * ss * Mrow[1][lg];
-        double t = 0.0;
-        for (int q = 0; q < L.npd; ++q) t += Bp[1][q * nd[1] + l[1]] * Bp[1][q * nd[1] + lg];
-        bb += ss * t;
+        if (Aval) {
+          double t = 0.0;
+          for (int q = 0; q < L.npd; ++q) t += Bp[1][q * nd[1] + l[1]] * Bp[1][q * nd[1] + lg];
+          bb += ss * t;
+        }
         ++ib;
       }
       if (fixed_row || fixed_dof(L, bnd, g)) {
         mv = g == r ? 1.0 : 0.0;
         bb = 0.0;
       }
-      Kval[k++] = mv;
-      Aval[a++] = mv + inv_gamma * bb;
+      Kval[kb + 64 * (int64_t)(k++)] = mv;
+      if (Aval) Aval[ab + 64 * (int64_t)(a++)] = mv + inv_gamma * bb;
     }
     for (int s = 0; s < nc; ++s)
-      for (int q = 0; q < L.npd; ++q) Kval[k++] = fixed_row ? 0.0 : -sr[s] * Bp[s][q * nd[s] + l[s]];
+      for (int q = 0; q < L.npd; ++q)
+        Kval[kb + 64 * (int64_t)(k++)] = fixed_row ? 0.0 : -sr[s] * Bp[s][q * nd[s] + l[s]];
   } else if (r < L.Nu + L.Np) {
     int64_t q = r - L.Nu;
     int P = (int)(q / L.npd), g = (int)(q - (int64_t)P * L.npd);
     int nd = ndof_of(L, cptr, P);
     const double* Bp = Bdiv1 + lb_ptr[P] + (int64_t)g * nd;
-    int k = Kptr[r];
+    const int64_t kb = (int64_t)Kslice[r >> 6] + (r & 63);
+    int k = 0;
     for (int i = ldof_ptr[P]; i < ldof_ptr[P + 1]; ++i) {
       int lg = sorted_l[i];
-      Kval[k++] = fixed_dof(L, bnd, sorted_gid[i]) ? 0.0 : -ldof_sign(L, cptr, csign, P, lg) * Bp[lg];
+      Kval[kb + 64 * (int64_t)(k++)] =
+          fixed_dof(L, bnd, sorted_gid[i]) ? 0.0 : -ldof_sign(L, cptr, csign, P, lg) * Bp[lg];
     }
   }
 }
@@ -314,13 +325,16 @@ __global__ void k_schur_values(DofLayout L, const int* __restrict__ cptr, const 
                                const int* __restrict__ face_cell, const int* __restrict__ face_lidx,
                                const int64_t* __restrict__ lb_ptr, const double* __restrict__ Bdiv1,
                                const double* __restrict__ dM, const int* __restrict__ bnd,
-                               const int* __restrict__ Sptr, const int* __restrict__ Scol, double* Sval) {
+                               const int* __restrict__ Sptr, const int* __restrict__ Scol,
+                               const int* __restrict__ Sslice, double* Sval) {
   int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= L.Np) return;
   int P = (int)(q / L.npd), g = (int)(q - (int64_t)P * L.npd);
   int s = cptr[P], F = cptr[P + 1] - s;
   int ndP = F * L.nfd + L.nint;
   const double* BP = Bdiv1 + lb_ptr[P];
+  // CSR entry k of this row goes to SELL slot sb + 64k
+  const int64_t sb = (int64_t)Sslice[q >> 6] + (q & 63) - 64 * (int64_t)Sptr[q];
   for (int k = Sptr[q]; k < Sptr[q + 1]; ++k) {
     int c = Scol[k];
     int Q = c / L.npd, e = c - Q * L.npd;
@@ -348,7 +362,7 @@ __global__ void k_schur_values(DofLayout L, const int* __restrict__ cptr, const 
         }
       }
     }
-    Sval[k] = v;
+    Sval[sb + 64 * (int64_t)k] = v;
   }
 }
 
@@ -485,11 +499,11 @@ void launch_fill_patterns(hipStream_t s, DofLayout L, const int* cptr, const int
 void launch_values(hipStream_t s, DofLayout L, const int* cptr, const int* cface, const int8_t* csign,
                    const int* ldof_ptr, const int* sorted_gid, const int* sorted_l, const int* face_cell,
                    const int* face_lidx, const int64_t* lmat_ptr, const double* M1, const int64_t* lb_ptr,
-                   const double* Bdiv1, const double* nu, double inv_gamma, const int* bnd, const int* Kptr,
-                   double* Kval, const int* Aptr, double* Aval) {
+                   const double* Bdiv1, const double* nu, double inv_gamma, const int* bnd, const int* Kslice,
+                   double* Kval, const int* Aslice, double* Aval) {
   k_values<<<nblocks(L.Nu + L.Np), kThreads, 0, s>>>(L, cptr, cface, csign, ldof_ptr, sorted_gid, sorted_l,
                                                      face_cell, face_lidx, lmat_ptr, M1, lb_ptr, Bdiv1, nu,
-                                                     inv_gamma, bnd, Kptr, Kval, Aptr, Aval);
+                                                     inv_gamma, bnd, Kslice, Kval, Aslice, Aval);
 }
 void launch_flux_rhs(hipStream_t s, DofLayout L, const int* cptr, const int* cface, const int8_t* csign,
                      const int* face_cell, const int* face_lidx, const int64_t* lmat_ptr, const double* M1,
@@ -508,9 +522,9 @@ void launch_diag_inv(hipStream_t s, int64_t n, const int* diagpos, const double*
 void launch_schur_values(hipStream_t s, DofLayout L, const int* cptr, const int* cface, const int8_t* csign,
                          const int* ldof_ptr, const int* face_cell, const int* face_lidx, const int64_t* lb_ptr,
                          const double* Bdiv1, const double* dM, const int* bnd, const int* Sptr, const int* Scol,
-                         double* Sval) {
+                         const int* Sslice, double* Sval) {
   k_schur_values<<<nblocks(L.Np), kThreads, 0, s>>>(L, cptr, cface, csign, ldof_ptr, face_cell, face_lidx, lb_ptr,
-                                                    Bdiv1, dM, bnd, Sptr, Scol, Sval);
+                                                    Bdiv1, dM, bnd, Sptr, Scol, Sslice, Sval);
 }
 
 }  // namespace vem

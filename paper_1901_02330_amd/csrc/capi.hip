@@ -98,10 +98,10 @@ struct vem_ctx {
   DBuf<double> dM, dMinv, dAinv, dSinv;
   DBuf<float> dAinv32, dSinv32;
   double gamma_A = 0.0;
-  // the coefficient-dependent values (K, A_gamma, S, diagonals, SELL copies) are built on first use
-  // after vem_discretize / vem_set_coefficient, so that a coefficient set right after discretising
-  // costs one build
-  bool values_ready = false;
+  // the coefficient-dependent values are built on first use after vem_discretize /
+  // vem_set_coefficient / vem_set_boundary, and only those a call needs: K and diag(M) (k_ready),
+  // S (s_ready, Block-Schur), A_gamma at gamma_A (a_ready, Block-Reg), FP32 shadows (s32, a32)
+  bool k_ready = false, s_ready = false, a_ready = false, s32_ready = false, a32_ready = false;
   int expect_S = 0, expect_A = 0;  // last inner-CG iteration counts (chunk sizing)
 
   // solver workspace
@@ -429,34 +429,52 @@ double device_sum(vem_handle h, const double* x, int64_t n) {
 }
 
 // ----- rebuild every coefficient-dependent value: K, A_gamma, diagonals, S -----
-void rebuild_values(vem_handle h, double gamma) {
-  hipStream_t s = h->stream;
-  DofLayout L = h->L;
-  const int* bnd = h->bc == VEM_BC_FLUX ? h->is_bnd.p : nullptr;
-  launch_values(s, L, h->cptr, h->cface, h->csign, h->ldof_ptr, h->sorted_gid, h->sorted_l, h->face_cell,
-                h->face_lidx, h->lmat_ptr, h->M1, h->lb_ptr, h->Bdiv1, h->nu, 1.0 / gamma, bnd, h->K.rowptr,
-                h->K.val, h->A.rowptr, h->A.val);
-  check_launch();
-  launch_diag_inv(s, L.Nu, h->Kdiag, h->K.val, h->dM, h->dMinv);
-  launch_diag_inv(s, L.Nu, h->Adiag, h->A.val, nullptr, h->dAinv);
-  launch_schur_values(s, L, h->cptr, h->cface, h->csign, h->ldof_ptr, h->face_cell, h->face_lidx, h->lb_ptr,
-                      h->Bdiv1, h->dM, bnd, h->S.rowptr, h->S.col, h->S.val);
-  launch_diag_inv(s, L.Np, h->Sdiag, h->S.val, nullptr, h->dSinv);
-  refresh_sell(s, h->K, h->Ks);
-  refresh_sell(s, h->A, h->As);
-  refresh_sell(s, h->S, h->Ss);
-  launch_col_scale(s, h->As, h->dAinv);
-  launch_col_scale(s, h->Ss, h->dSinv);
-  launch_col_scale32(s, h->As, h->dAinv, h->dAinv32);
-  launch_col_scale32(s, h->Ss, h->dSinv, h->dSinv32);
-  check_launch();
-  h->gamma_A = gamma;
-  h->values_ready = true;
+void invalidate_values(vem_handle h) {
+  h->k_ready = h->s_ready = h->a_ready = h->s32_ready = h->a32_ready = false;
 }
 
-void ensure_values(vem_handle h) {
-  if (!h->values_ready) rebuild_values(h, h->gamma_A > 0 ? h->gamma_A : h->gamma_default);
+// Builds the coefficient-dependent values a call needs and that are not current: K and diag(M)
+// always, S when needS, A_gamma at gamma when needA, their FP32 shadows when f32.  The value
+// kernels write the SELL copies directly; the CSR arrays are filled only for an export.
+void ensure_values(vem_handle h, bool needS, bool needA, bool f32, double gamma) {
+  hipStream_t s = h->stream;
+  const DofLayout L = h->L;
+  const int* bnd = h->bc == VEM_BC_FLUX ? h->is_bnd.p : nullptr;
+  const bool redoA = needA && (!h->a_ready || gamma != h->gamma_A);
+  if (!h->k_ready || redoA) {
+    launch_values(s, L, h->cptr, h->cface, h->csign, h->ldof_ptr, h->sorted_gid, h->sorted_l, h->face_cell,
+                  h->face_lidx, h->lmat_ptr, h->M1, h->lb_ptr, h->Bdiv1, h->nu, redoA ? 1.0 / gamma : 0.0, bnd,
+                  h->Ks.slice_ptr, h->Ks.val, h->As.slice_ptr, redoA ? h->As.val.p : nullptr);
+    launch_diag_inv(s, L.Nu, h->Kdiag, h->Ks.val, h->dM, h->dMinv);
+    h->k_ready = true;
+    if (redoA) {
+      launch_diag_inv(s, L.Nu, h->Adiag, h->As.val, nullptr, h->dAinv);
+      launch_col_scale(s, h->As, h->dAinv);
+      h->gamma_A = gamma;
+      h->a_ready = true;
+      h->a32_ready = false;
+    }
+  }
+  if (needS && !h->s_ready) {
+    launch_schur_values(s, L, h->cptr, h->cface, h->csign, h->ldof_ptr, h->face_cell, h->face_lidx, h->lb_ptr,
+                        h->Bdiv1, h->dM, bnd, h->S.rowptr, h->S.col, h->Ss.slice_ptr, h->Ss.val);
+    launch_diag_inv(s, L.Np, h->Sdiag, h->Ss.val, nullptr, h->dSinv);
+    launch_col_scale(s, h->Ss, h->dSinv);
+    h->s_ready = true;
+    h->s32_ready = false;
+  }
+  if (f32 && needS && !h->s32_ready) {
+    launch_col_scale32(s, h->Ss, h->dSinv, h->dSinv32);
+    h->s32_ready = true;
+  }
+  if (f32 && needA && !h->a32_ready) {
+    launch_col_scale32(s, h->As, h->dAinv, h->dAinv32);
+    h->a32_ready = true;
+  }
+  check_launch();
 }
+
+void ensure_k(vem_handle h) { ensure_values(h, false, false, false, h->gamma_A); }
 
 void ensure_workspace(vem_handle h, int m) {
   int64_t N = h->L.Nu + h->L.Np;
@@ -624,7 +642,7 @@ void apply_prec(vem_handle h, const vem_solve_opts& o, const double* v, double* 
 const double* flux_rhs(vem_handle h) {
   hipStream_t s = h->stream;
   const DofLayout L = h->L;
-  ensure_values(h);
+  ensure_k(h);
   launch_flux_rhs(s, L, h->cptr, h->cface, h->csign, h->face_cell, h->face_lidx, h->lmat_ptr, h->M1, h->lb_ptr,
                   h->Bdiv1, h->nu, h->is_bnd, h->xB, h->rhs, h->rhs_flux);
   double* d = h->scal.p + 4 * kMaxDots;
@@ -1105,6 +1123,11 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
       const Csr* csr[3] = {&h->K, &h->A, &h->S};
       Sell* sell[3] = {&h->Ks, &h->As, &h->Ss};
       build_sells(s, h->tmp, csr, sell, 3);
+      // the diagonals are read from the SELL values
+      sell_diag_slots(s, L.Nu, h->K, h->Ks, h->Kdiag);  // K: the flux rows only
+      sell_diag_slots(s, L.Nu, h->A, h->As, h->Adiag);
+      sell_diag_slots(s, L.Np, h->S, h->Ss, h->Sdiag);
+      check_launch();
     }
     h->dM.alloc(L.Nu);
     h->dMinv.alloc(L.Nu);
@@ -1137,7 +1160,7 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
       h->np_wn = two[1];
     }
     h->gamma_A = h->gamma_default;
-    h->values_ready = false;
+    invalidate_values(h);
     sync(h);
     h->has_disc = true;
   });
@@ -1186,7 +1209,7 @@ vem_status vem_set_coefficient(vem_handle h, const double* nu) {
   return guarded(h, [&] {
     require_disc(h);
     VEM_HIP(hipMemcpyAsync(h->nu.p, nu, h->nc * sizeof(double), hipMemcpyDefault, h->stream));
-    h->values_ready = false;
+    invalidate_values(h);
     sync(h);
   });
 }
@@ -1197,7 +1220,7 @@ vem_status vem_set_boundary(vem_handle h, int kind) {
     VEM_REQUIRE(kind == VEM_BC_PRESSURE || kind == VEM_BC_FLUX, VEM_EINVAL, "unknown boundary data kind");
     if (kind != h->bc) {
       h->bc = kind;
-      h->values_ready = false;
+      invalidate_values(h);
       if (h->has_disc) {
         launch_fill(h->stream, h->L.Nu + h->L.Np, 0.0, h->rhs);
         launch_fill(h->stream, h->L.Nu, 0.0, h->xB);
@@ -1230,7 +1253,7 @@ vem_status vem_apply(vem_handle h, const double* x, double* y) {
   if (!h || !x || !y) return VEM_EINVAL;
   return guarded(h, [&] {
     require_disc(h);
-    ensure_values(h);
+    ensure_k(h);
     launch_spmv(h->stream, h->Ks, x, y);
     check_launch();
   });
@@ -1240,10 +1263,12 @@ vem_status vem_export_csr(vem_handle h, int which, int32_t* rowptr, int32_t* col
   if (!h) return VEM_EINVAL;
   return guarded(h, [&] {
     require_disc(h);
-    ensure_values(h);
-    const Csr* M = which == VEM_MAT_K ? &h->K : which == VEM_MAT_SCHUR ? &h->S : which == VEM_MAT_REG ? &h->A : nullptr;
+    Csr* M = which == VEM_MAT_K ? &h->K : which == VEM_MAT_SCHUR ? &h->S : which == VEM_MAT_REG ? &h->A : nullptr;
+    const Sell* Ms = which == VEM_MAT_K ? &h->Ks : which == VEM_MAT_SCHUR ? &h->Ss : &h->As;
     VEM_REQUIRE(M, VEM_EINVAL, "unknown matrix");
+    ensure_values(h, which == VEM_MAT_SCHUR, which == VEM_MAT_REG, false, h->gamma_A);
     hipStream_t s = h->stream;
+    if (val) sell_to_csr(s, *Ms, *M);
     if (rowptr)
       VEM_HIP(hipMemcpyAsync(rowptr, M->rowptr.p, (M->rows + 1) * sizeof(int), hipMemcpyDefault, s));
     if (col) VEM_HIP(hipMemcpyAsync(col, M->col.p, M->nnz * sizeof(int), hipMemcpyDefault, s));
@@ -1284,8 +1309,10 @@ vem_status vem_time_kernel(vem_handle h, int which, int reps, double* avg_ms, do
   if (!h || !avg_ms || reps < 1) return VEM_EINVAL;
   return guarded(h, [&] {
     require_disc(h);
-    ensure_values(h);
     VEM_REQUIRE(which >= VEM_KERNEL_SPMV && which <= VEM_KERNEL_CG_REG32, VEM_EINVAL, "unknown kernel");
+    ensure_values(h, which == VEM_KERNEL_CG_SCHUR || which == VEM_KERNEL_CG_SCHUR32,
+                  which == VEM_KERNEL_CG_REG || which == VEM_KERNEL_CG_REG32,
+                  which == VEM_KERNEL_CG_SCHUR32 || which == VEM_KERNEL_CG_REG32, h->gamma_A);
     hipStream_t s = h->stream;
     ensure_workspace(h, std::max(1, h->ws_m));
     const int64_t Nu = h->L.Nu, Np = h->L.Np, N = Nu + Np;
@@ -1378,11 +1405,8 @@ static vem_status solve_impl(vem_handle h, const vem_solve_opts* opts, const dou
     hipStream_t s = h->stream;
     const int m = o.restart;
     const int64_t Nu = h->L.Nu, Np = h->L.Np, N = Nu + Np;
-    if (o.precond == VEM_PREC_REG) {
-      double g = o.gamma > 0 ? o.gamma : h->gamma_default;
-      if (g != h->gamma_A || !h->values_ready) rebuild_values(h, g);
-    }
-    ensure_values(h);
+    ensure_values(h, o.precond == VEM_PREC_SCHUR, o.precond == VEM_PREC_REG, o.precision == VEM_MIXED,
+                  o.gamma > 0 ? o.gamma : h->gamma_default);
     if (!user_rhs && h->bc == VEM_BC_FLUX) rhs = flux_rhs(h);
     ensure_workspace(h, m);
     double* V = h->Vb;

@@ -5,11 +5,12 @@
 // contiguous 512-byte load of values and a 256-byte load of column indices.
 // A thread owns a row; its loads do not depend on a row pointer and are
 // independent of each other, which keeps many loads in flight per wave.
-// Padding entries carry value 0 and the row's own column.  The CSR matrix
-// stays the assembly target: src[] maps every SELL slot to its CSR entry
-// (-1 for padding) so that new values (a new coefficient) are copied over
-// without rebuilding the layout.  Entries of a row keep their CSR order, so
-// a row's sum is formed in the same order as a sequential CSR product.
+// Padding entries carry value 0 and the row's own column.  The CSR pattern
+// is built first; the value kernels then write straight into the SELL slots
+// (entry k of row r at slice_ptr[r/64] + r%64 + 64k: coalesced across a
+// wave), and src[] maps every slot back to its CSR entry (-1 for padding)
+// for the CSR export.  Entries of a row keep their CSR order, so a row's sum
+// is formed in the same order as a sequential CSR product.
 #include "vem_internal.h"
 
 namespace vem {
@@ -31,7 +32,7 @@ __global__ void k_sell_len(int64_t rows, int64_t nslices, const int* __restrict_
 
 __global__ void k_sell_fill(int64_t rows, const int* __restrict__ rowptr, const int* __restrict__ col,
                             const int64_t* __restrict__ slice_ptr, const int* __restrict__ slice_len, int* scol,
-                            int* src) {
+                            int* src, double* sval) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t nrow_pad = ((rows + 63) / 64) * 64;
   if (r >= nrow_pad) return;
@@ -52,16 +53,26 @@ __global__ void k_sell_fill(int64_t rows, const int* __restrict__ rowptr, const 
     } else {
       scol[o] = r < rows ? (int)r : 0;
       src[o] = -1;
+      sval[o] = 0.0;  // padding: the value kernels write only the real entries
     }
   }
 }
 
-__global__ void k_sell_vals(int64_t n, const int* __restrict__ src, const double* __restrict__ val,
-                            double* __restrict__ sval) {
+// CSR values from the SELL slots (for the export)
+__global__ void k_sell_to_csr(int64_t n, const int* __restrict__ src, const double* __restrict__ sval,
+                              double* __restrict__ val) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  int j = src[i];
-  sval[i] = j >= 0 ? val[j] : 0.0;
+  const int j = src[i];
+  if (j >= 0) val[j] = sval[i];
+}
+
+// CSR positions of the diagonal entries -> their SELL slots, in place
+__global__ void k_sell_diag(int64_t rows, const int* __restrict__ rowptr, const int* __restrict__ slice_ptr,
+                            int* diag) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  diag[r] = slice_ptr[r >> 6] + (int)(r & 63) + 64 * (diag[r] - rowptr[r]);
 }
 
 __global__ void k_narrow64(int64_t n, const int64_t* __restrict__ in, int* __restrict__ out) {
@@ -104,13 +115,19 @@ void build_sells(hipStream_t s, Scratch& tmp, const Csr* const* A, Sell* const* 
     B.src.alloc(total);
     B.val.alloc(total);
     const int64_t nrow_pad = B.nslices * 64;
-    k_sell_fill<<<grid256(nrow_pad), 256, 0, s>>>(B.rows, A[m]->rowptr, A[m]->col, ptr, B.slice_len, B.col, B.src);
+    k_sell_fill<<<grid256(nrow_pad), 256, 0, s>>>(B.rows, A[m]->rowptr, A[m]->col, ptr, B.slice_len, B.col, B.src,
+                                                   B.val);
     VEM_HIP(hipGetLastError());
   }
 }
 
-void refresh_sell(hipStream_t s, const Csr& A, Sell& S) {
-  if (S.nnz > 0) k_sell_vals<<<grid256(S.nnz), 256, 0, s>>>(S.nnz, S.src, A.val, S.val);
+void sell_to_csr(hipStream_t s, const Sell& S, Csr& A) {
+  if (S.nnz > 0) k_sell_to_csr<<<grid256(S.nnz), 256, 0, s>>>(S.nnz, S.src, S.val, A.val);
+}
+
+void sell_diag_slots(hipStream_t s, int64_t ndiag, const Csr& A, const Sell& S, int* diag) {
+  VEM_REQUIRE(ndiag >= 0 && ndiag <= A.rows, VEM_EINVAL, "more diagonal entries than rows");
+  if (ndiag > 0) k_sell_diag<<<grid256(ndiag), 256, 0, s>>>(ndiag, A.rowptr, S.slice_ptr, diag);
 }
 
 }  // namespace vem

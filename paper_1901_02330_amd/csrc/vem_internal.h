@@ -145,7 +145,11 @@ struct Sell {
 // SELL copies of `count` (<= 3) CSR matrices, with one host synchronisation for all of
 // their padded sizes (uses tmp.i64[2m], tmp.i64[2m+1] for matrix m and slots 0..count-1).
 void build_sells(hipStream_t s, Scratch& tmp, const Csr* const* A, Sell* const* S, int count);
-void refresh_sell(hipStream_t s, const Csr& A, Sell& S);
+// A.val from the SELL values (A shares S's pattern)
+void sell_to_csr(hipStream_t s, const Sell& S, Csr& A);
+// diag[r] (the CSR position of row r's diagonal) becomes its SELL slot, for the first ndiag rows
+// (the rows that have a diagonal entry: K's flux rows; every row of A_gamma and S)
+void sell_diag_slots(hipStream_t s, int64_t ndiag, const Csr& A, const Sell& S, int* diag);
 
 // ---- launchers (one translation unit each; all take the handle's stream) ----
 
@@ -246,8 +250,8 @@ void launch_coef_grad(hipStream_t s, DofLayout L, const int* cptr, const int* cf
 void launch_values(hipStream_t s, DofLayout L, const int* cptr, const int* cface, const int8_t* csign,
                    const int* ldof_ptr, const int* sorted_gid, const int* sorted_l, const int* face_cell,
                    const int* face_lidx, const int64_t* lmat_ptr, const double* M1, const int64_t* lb_ptr,
-                   const double* Bdiv1, const double* nu, double inv_gamma, const int* bnd, const int* Kptr,
-                   double* Kval, const int* Aptr, double* Aval);
+                   const double* Bdiv1, const double* nu, double inv_gamma, const int* bnd, const int* Kslice,
+                   double* Kval, const int* Aslice, double* Aval);
 // flux boundary data: out = b - K xB on the free rows, xB on the prescribed ones
 void launch_flux_rhs(hipStream_t s, DofLayout L, const int* cptr, const int* cface, const int8_t* csign,
                      const int* face_cell, const int* face_lidx, const int64_t* lmat_ptr, const double* M1,
@@ -263,7 +267,7 @@ void launch_diag_inv(hipStream_t s, int64_t n, const int* diagpos, const double*
 void launch_schur_values(hipStream_t s, DofLayout L, const int* cptr, const int* cface, const int8_t* csign,
                          const int* ldof_ptr, const int* face_cell, const int* face_lidx, const int64_t* lb_ptr,
                          const double* Bdiv1, const double* dM, const int* bnd, const int* Sptr, const int* Scol,
-                         double* Sval);
+                         const int* Sslice, double* Sval);
 void launch_rhs_from_moments(hipStream_t s, int64_t Nu, int64_t Np, double* rhs);
 
 // sparse/Krylov
