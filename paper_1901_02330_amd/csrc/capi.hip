@@ -805,42 +805,61 @@ vem_status vem_set_mesh(vem_handle h, int64_t nv, const double* xyz, int64_t nf,
     hipStream_t s = h->stream;
     h->has_mesh = false;
     h->has_disc = false;
-    // offsets to the host for validation
-    h->h_fptr.resize(nf + 1);
-    h->h_cptr.resize(nc + 1);
     if (mem_kind == VEM_MEM_HOST) {
-      std::memcpy(h->h_fptr.data(), face_ptr, (nf + 1) * sizeof(int));
-      std::memcpy(h->h_cptr.data(), cell_ptr, (nc + 1) * sizeof(int));
+      // offsets validated on the host
+      h->h_fptr.assign(face_ptr, face_ptr + nf + 1);
+      h->h_cptr.assign(cell_ptr, cell_ptr + nc + 1);
+      VEM_REQUIRE(h->h_fptr[0] == 0 && h->h_cptr[0] == 0, VEM_EBADMESH, "offset arrays must start at 0");
+      for (int64_t i = 0; i < nf; ++i)
+        VEM_REQUIRE(h->h_fptr[i + 1] >= h->h_fptr[i], VEM_EBADMESH, "face_ptr not monotone");
+      int maxcf = 0;
+      for (int64_t i = 0; i < nc; ++i) {
+        VEM_REQUIRE(h->h_cptr[i + 1] >= h->h_cptr[i], VEM_EBADMESH, "cell_ptr not monotone");
+        maxcf = std::max(maxcf, h->h_cptr[i + 1] - h->h_cptr[i]);
+      }
+      h->nfv = h->h_fptr[nf];
+      h->ncf = h->h_cptr[nc];
+      h->max_cell_faces = maxcf;
+      h->fptr.alloc(nf + 1);
+      h->cptr.alloc(nc + 1);
+      VEM_HIP(hipMemcpyAsync(h->fptr.p, h->h_fptr.data(), (nf + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+      VEM_HIP(hipMemcpyAsync(h->cptr.p, h->h_cptr.data(), (nc + 1) * sizeof(int), hipMemcpyHostToDevice, s));
     } else {
-      VEM_HIP(hipMemcpyAsync(h->h_fptr.data(), face_ptr, (nf + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
-      VEM_HIP(hipMemcpyAsync(h->h_cptr.data(), cell_ptr, (nc + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
+      // offsets validated on the device: no copy of the arrays to the host
+      h->fptr.alloc(nf + 1);
+      h->cptr.alloc(nc + 1);
+      VEM_HIP(hipMemcpyAsync(h->fptr.p, face_ptr, (nf + 1) * sizeof(int), hipMemcpyDefault, s));
+      VEM_HIP(hipMemcpyAsync(h->cptr.p, cell_ptr, (nc + 1) * sizeof(int), hipMemcpyDefault, s));
+      DBuf<int>& chk = h->tmp.i32[0];
+      chk.reserve(2);
+      fill_i32(s, 2, 0, chk);
+      launch_check_offsets(s, nf, h->fptr, nc, h->cptr, chk);
+      check_launch();
+      h->tmp.ti.alloc(8);
+      int* r = h->tmp.ti.p;
+      VEM_HIP(hipMemcpyAsync(r, chk.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+      VEM_HIP(hipMemcpyAsync(r + 2, h->fptr.p + nf, sizeof(int), hipMemcpyDeviceToHost, s));
+      VEM_HIP(hipMemcpyAsync(r + 3, h->cptr.p + nc, sizeof(int), hipMemcpyDeviceToHost, s));
       sync(h);
-    }
-    VEM_REQUIRE(h->h_fptr[0] == 0 && h->h_cptr[0] == 0, VEM_EBADMESH, "offset arrays must start at 0");
-    for (int64_t i = 0; i < nf; ++i)
-      VEM_REQUIRE(h->h_fptr[i + 1] >= h->h_fptr[i], VEM_EBADMESH, "face_ptr not monotone");
-    int maxcf = 0;
-    for (int64_t i = 0; i < nc; ++i) {
-      VEM_REQUIRE(h->h_cptr[i + 1] >= h->h_cptr[i], VEM_EBADMESH, "cell_ptr not monotone");
-      maxcf = std::max(maxcf, h->h_cptr[i + 1] - h->h_cptr[i]);
+      VEM_REQUIRE(!(r[0] & 4), VEM_EBADMESH, "offset arrays must start at 0");
+      VEM_REQUIRE(!(r[0] & 1), VEM_EBADMESH, "face_ptr not monotone");
+      VEM_REQUIRE(!(r[0] & 2), VEM_EBADMESH, "cell_ptr not monotone");
+      h->nfv = r[2];
+      h->ncf = r[3];
+      h->max_cell_faces = r[1];
+      h->h_fptr.clear();
+      h->h_cptr.clear();
     }
     h->nv = (int)nv;
     h->nf = (int)nf;
     h->nc = (int)nc;
-    h->nfv = h->h_fptr[nf];
-    h->ncf = h->h_cptr[nc];
-    h->max_cell_faces = maxcf;
     h->xyz.alloc(3 * nv);
-    h->fptr.alloc(nf + 1);
     h->fvtx.alloc(h->nfv);
-    h->cptr.alloc(nc + 1);
     h->cface.alloc(h->ncf);
     h->csign.alloc(h->ncf);
     h->inc_cell.alloc(h->ncf);
     VEM_HIP(hipMemcpyAsync(h->xyz.p, xyz, 3 * nv * sizeof(double), hipMemcpyDefault, s));
-    VEM_HIP(hipMemcpyAsync(h->fptr.p, h->h_fptr.data(), (nf + 1) * sizeof(int), hipMemcpyHostToDevice, s));
     VEM_HIP(hipMemcpyAsync(h->fvtx.p, face_vtx, h->nfv * sizeof(int), hipMemcpyDefault, s));
-    VEM_HIP(hipMemcpyAsync(h->cptr.p, h->h_cptr.data(), (nc + 1) * sizeof(int), hipMemcpyHostToDevice, s));
     VEM_HIP(hipMemcpyAsync(h->cface.p, cell_face, h->ncf * sizeof(int), hipMemcpyDefault, s));
     VEM_HIP(hipMemcpyAsync(h->csign.p, cell_face_sign, h->ncf * sizeof(int8_t), hipMemcpyDefault, s));
     // face -> (cell, local index) for both orientations, with validation

@@ -35,6 +35,31 @@ __device__ inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.
 __device__ inline double norm(V3 a) { return sqrt(dot(a, a)); }
 
 // --- validation and face -> cell incidence -------------------------------------------------
+// Offset arrays of a mesh handed over in device memory: both start at 0 and never decrease.
+// out[0] collects error bits (1: face_ptr decreases, 2: cell_ptr decreases, 4: a first entry
+// is not 0), out[1] the largest number of faces of a cell; one atomic per wavefront.
+__global__ void k_check_offsets(int64_t nf, const int* __restrict__ fptr, int64_t nc, const int* __restrict__ cptr,
+                                int* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int err = 0, m = 0;
+  if (i < nf && fptr[i + 1] < fptr[i]) err |= 1;
+  if (i < nc) {
+    const int d = cptr[i + 1] - cptr[i];
+    if (d < 0) err |= 2;
+    m = d;
+  }
+  if (i == 0 && (fptr[0] != 0 || cptr[0] != 0)) err |= 4;
+  for (int o = 32; o > 0; o >>= 1) {
+    err |= __shfl_xor(err, o, 64);
+    const int mo = __shfl_xor(m, o, 64);
+    m = mo > m ? mo : m;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (err) atomicOr(out, err);
+    if (m > 0) atomicMax(out + 1, m);
+  }
+}
+
 __global__ void k_check_mesh(int nv, int nf, int nc, const int* __restrict__ fptr, const int* __restrict__ fvtx,
                              const int* __restrict__ cptr, const int* __restrict__ cface,
                              const int8_t* __restrict__ csign, int* face_cnt, int* face_cell, int* face_lidx,
@@ -170,17 +195,23 @@ __global__ void k_cell_geometry(int nc, const double* __restrict__ xyz, const in
       m = m + (t / 4.0) * (O + A + B + C);
     }
   }
-  double dmax = 0.0;
+  // largest vertex-vertex distance; squared distances are compared and one root taken
+  // (the root is monotone and correctly rounded, so this is the same number)
+  double dmax2 = 0.0;
   for (int j = s; j < e; ++j) {
     int f = cface[j];
     for (int q = fptr[f]; q < fptr[f + 1]; ++q) {
       V3 P = ld3(xyz, fvtx[q]);
       for (int j2 = j; j2 < e; ++j2) {
         int f2 = cface[j2];
-        for (int q2 = fptr[f2]; q2 < fptr[f2 + 1]; ++q2) dmax = fmax(dmax, norm(ld3(xyz, fvtx[q2]) - P));
+        for (int q2 = fptr[f2]; q2 < fptr[f2 + 1]; ++q2) {
+          const V3 d = ld3(xyz, fvtx[q2]) - P;
+          dmax2 = fmax(dmax2, dot(d, d));
+        }
       }
     }
   }
+  const double dmax = sqrt(dmax2);
   vol[c] = v;
   st3(cen, c, (1.0 / v) * m);
   diam[c] = dmax;
@@ -398,6 +429,10 @@ void launch_check_mesh(hipStream_t s, int nv, int nf, int nc, const int* fptr, c
   int n = nf > nc ? nf : nc;
   k_check_mesh<<<nblocks(n), kThreads, 0, s>>>(nv, nf, nc, fptr, fvtx, cptr, cface, csign, face_cnt, face_cell,
                                                face_lidx, inc_cell, err);
+}
+void launch_check_offsets(hipStream_t s, int64_t nf, const int* fptr, int64_t nc, const int* cptr, int* out) {
+  const int64_t n = nf > nc ? nf : nc;
+  if (n > 0) k_check_offsets<<<(int)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(nf, fptr, nc, cptr, out);
 }
 void launch_check_faces(hipStream_t s, int nf, const int* face_cnt, const double* area, int* is_bnd, int* err) {
   k_check_faces<<<nblocks(nf), kThreads, 0, s>>>(nf, face_cnt, area, is_bnd, err);

@@ -92,6 +92,7 @@ struct Scratch {
   DBuf<int> i32[4];
   DBuf<double> f64[8];
   HBuf<int64_t> tot;        // pinned landing slots for the totals of asynchronous scans
+  HBuf<int> ti;             // pinned landing slots for small integer results
 };
 
 // Reduction scratch: per-block partial sums.
@@ -162,6 +163,8 @@ void launch_cell_geometry(hipStream_t s, int nc, const double* xyz, const int* f
 void launch_check_mesh(hipStream_t s, int nv, int nf, int nc, const int* fptr, const int* fvtx, const int* cptr,
                        const int* cface, const int8_t* csign, int* face_cnt, int* face_cell, int* face_lidx,
                        int* inc_cell, int* err);
+// out[0] = error bits of the two offset arrays, out[1] = max faces per cell (out zeroed first)
+void launch_check_offsets(hipStream_t s, int64_t nf, const int* fptr, int64_t nc, const int* cptr, int* out);
 void launch_check_faces(hipStream_t s, int nf, const int* face_cnt, const double* area, int* is_bnd, int* err);
 void launch_check_cells(hipStream_t s, int nc, const double* vol, int* err);
 void launch_tets(hipStream_t s, int nc, const int* fptr, const int* cptr, const int* cface, const int* cell_tet_ptr,

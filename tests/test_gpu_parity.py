@@ -157,6 +157,15 @@ def test_error_paths():
     with pytest.raises(VemError) as e:
         s.set_mesh(bad)
     assert e.value.code == -2
+    # offset arrays are checked on the device before anything is indexed through them
+    for key, i, msg in (("face_ptr", 7, "face_ptr not monotone"), ("cell_ptr", 4, "cell_ptr not monotone"),
+                        ("cell_ptr", 0, "start at 0")):
+        bad = dict(m)
+        bad[key] = m[key].copy()
+        bad[key][i] = bad[key][i - 1] - 1 if i > 0 else 1
+        with pytest.raises(VemError) as e:
+            s.set_mesh(bad)
+        assert e.value.code == -2 and msg in str(e.value), (key, i, str(e.value))
     s = gpu_solver(m, rhs=SineSolution())
     u, p, info = s.solve(tol=1e-14, maxit=1)
     assert not info["converged"] and info["iterations"] == 1
