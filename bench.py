@@ -96,7 +96,7 @@ def summarize(prefix: str):
                        f"{statistics.median(w):.2f} |")
         # the live timing loop (vem_time_kernel "cg_reg", 200 launches) runs after the solves: the last
         # 200 launches of the pipelined iteration with the largest grid
-        it = [k for k in by if k[0].startswith("k_ppcg_iter") and "false" in k[0]]
+        it = [k for k in by if k[0].startswith("k_ppcg_iter<double, false")]
         if it:
             key = max(it, key=lambda k: k[1])
             last = by[key][-200:]

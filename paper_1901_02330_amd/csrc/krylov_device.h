@@ -132,6 +132,43 @@ __device__ inline T sell_dot(const SellViewT<T>& A, int64_t row, const X* __rest
   return acc;
 }
 
+// The same product for slices of at most kShortRow entries: all column and value loads are
+// issued first, then all gathers, so a row costs two memory round trips instead of a chain
+// per entry.  The tests on the slice length are uniform over the wave, and the sum is formed
+// in the same order (same bits).
+constexpr int kShortRow = 8;
+template <typename T, typename X>
+__device__ inline T sell_dot_short(const SellViewT<T>& A, int64_t row, const X* __restrict__ x) {
+  const int64_t s = row >> 6;
+  const int64_t base = A.slice_ptr[s] + (row & 63);
+  const int len = A.slice_len[s];
+  int c[kShortRow];
+  T v[kShortRow];
+#pragma unroll
+  for (int u = 0; u < kShortRow; ++u)
+    if (u < len) {
+      c[u] = A.col[base + 64 * u];
+      v[u] = A.val[base + 64 * u];
+    }
+  X g[kShortRow];
+#pragma unroll
+  for (int u = 0; u < kShortRow; ++u)
+    if (u < len) g[u] = x[c[u]];
+  T acc = T(0);
+#pragma unroll
+  for (int u = 0; u < kShortRow; ++u)
+    if (u < len) acc += v[u] * (T)g[u];
+  return acc;
+}
+
+template <bool kShort, typename T, typename X>
+__device__ inline T sell_row(const SellViewT<T>& A, int64_t row, const X* __restrict__ x) {
+  if constexpr (kShort)
+    return sell_dot_short(A, row, x);
+  else
+    return sell_dot(A, row, x);
+}
+
 static SellView view_cs(const Sell& A) { return {A.rows, A.slice_ptr, A.slice_len, A.col, A.val_cs}; }
 static SellViewT<float> view32(const Sell& A) { return {A.rows, A.slice_ptr, A.slice_len, A.col, A.val32}; }
 

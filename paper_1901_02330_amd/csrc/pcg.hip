@@ -35,7 +35,7 @@ struct PcgViewT {
 
 // w = (A D^{-1}) b, x = 0, r = b; partials of gamma_0, delta_0 (slot 0).  b is FP64 and is
 // rounded to T element by element (also where it is gathered).
-template <typename T, int kBlock>
+template <typename T, int kBlock, bool kShort>
 __global__ void __launch_bounds__(kBlock) k_ppcg_init(SellViewT<T> Ac, PcgViewT<T> v,
                                                            const double* __restrict__ b, PcgState* st, double tol2,
                                                            int maxit, double* __restrict__ part) {
@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(kBlock) k_ppcg_init(SellViewT<T> Ac, PcgViewT<
   for (int64_t row = xcd_block() * blockDim.x + threadIdx.x; row < Ac.rows;
        row += (int64_t)gridDim.x * blockDim.x) {
     const T bi = (T)b[row], di = v.dinv[row];
-    const T wi = sell_dot(Ac, row, b);
+    const T wi = sell_row<kShort>(Ac, row, b);
     v.x[row] = T(0);
     v.r[row] = bi;
     v.w0[row] = wi;
@@ -63,7 +63,7 @@ __global__ void __launch_bounds__(kBlock) k_ppcg_init(SellViewT<T> Ac, PcgViewT<
 }
 
 // One pipelined CG iteration.  Vectors and matrix values in T; scalars and dot products in FP64.
-template <typename T, bool kFirst, int kBlock>
+template <typename T, bool kFirst, int kBlock, bool kShort>
 __global__ void __launch_bounds__(kBlock) k_ppcg_iter(int parity, SellViewT<T> Ac, PcgViewT<T> v, PcgState* st,
                                                            double* __restrict__ part) {
   const int P = gridDim.x;
@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(kBlock) k_ppcg_iter(int parity, SellViewT<T> A
   // the partials of gamma and delta left by the previous iteration.
   T n = T(0), wi = T(0), di = T(0), ri = T(0), zo = T(0), so = T(0), po = T(0), xo = T(0);
   auto load = [&](int64_t i) {
-    n = sell_dot(Ac, i, win);
+    n = sell_row<kShort>(Ac, i, win);
     wi = win[i];
     di = v.dinv[i];
     ri = v.r[i];
@@ -152,37 +152,46 @@ PcgViewT<T> pview(const PcgWorkT<T>& w) {
   return {w.x, w.r, w.z, w.s, w.p, w.w0, w.w1, w.dinv};
 }
 
-template <int kBlock>
+template <int kBlock, bool kShort>
 void pcg_init_as(hipStream_t s, const Sell& A, const PcgWork& w, const double* b, PcgState* st, double tol, int maxit,
                  double* part) {
-  k_ppcg_init<double, kBlock><<<pcg_grid(A.rows, kBlock), kBlock, 0, s>>>(view_cs(A), pview(w), b, st, tol * tol,
-                                                                           maxit, part);
+  k_ppcg_init<double, kBlock, kShort><<<pcg_grid(A.rows, kBlock), kBlock, 0, s>>>(view_cs(A), pview(w), b, st,
+                                                                                   tol * tol, maxit, part);
 }
 
-template <int kBlock>
+template <int kBlock, bool kShort>
 void pcg_iter_as(hipStream_t s, int i, const Sell& A, const PcgWork& w, PcgState* st, double* part) {
   const int P = pcg_grid(A.rows, kBlock);
   if (i == 0)
-    k_ppcg_iter<double, true, kBlock><<<P, kBlock, 0, s>>>(0, view_cs(A), pview(w), st, part);
+    k_ppcg_iter<double, true, kBlock, kShort><<<P, kBlock, 0, s>>>(0, view_cs(A), pview(w), st, part);
   else
-    k_ppcg_iter<double, false, kBlock><<<P, kBlock, 0, s>>>(i & 1, view_cs(A), pview(w), st, part);
+    k_ppcg_iter<double, false, kBlock, kShort><<<P, kBlock, 0, s>>>(i & 1, view_cs(A), pview(w), st, part);
 }
 
 }  // namespace
 
+// Launch shape: 1024-thread blocks when every row has a thread, 256-thread blocks when threads
+// loop over rows (their barriers hold fewer waves).  One-row-per-thread launches take the
+// short-row product when no slice is longer than kShortRow (measured on the 64^3 cube: S, 7 per
+// row, 10.95 -> 10.53 us per iteration; rows of 11-13 entries were slower with it, 31.5 ->
+// 33.9 us for A_gamma, so longer rows keep the plain loop).
 void launch_pcg_init(hipStream_t s, const Sell& A, const PcgWork& w, const double* b, PcgState* st, double tol,
                      int maxit, double* part) {
   if (A.rows > kPcgMaxThreads)  // threads loop over rows
-    pcg_init_as<256>(s, A, w, b, st, tol, maxit, part);
+    pcg_init_as<256, false>(s, A, w, b, st, tol, maxit, part);
+  else if (A.max_len <= kShortRow)
+    pcg_init_as<1024, true>(s, A, w, b, st, tol, maxit, part);
   else
-    pcg_init_as<1024>(s, A, w, b, st, tol, maxit, part);
+    pcg_init_as<1024, false>(s, A, w, b, st, tol, maxit, part);
 }
 
 void launch_pcg_iter(hipStream_t s, int i, const Sell& A, const PcgWork& w, PcgState* st, double* part) {
   if (A.rows > kPcgMaxThreads)  // threads loop over rows
-    pcg_iter_as<256>(s, i, A, w, st, part);
+    pcg_iter_as<256, false>(s, i, A, w, st, part);
+  else if (A.max_len <= kShortRow)
+    pcg_iter_as<1024, true>(s, i, A, w, st, part);
   else
-    pcg_iter_as<1024>(s, i, A, w, st, part);
+    pcg_iter_as<1024, false>(s, i, A, w, st, part);
 }
 
 }  // namespace vem

@@ -16,18 +16,25 @@
 namespace vem {
 namespace {
 
+// slice lengths; *max_len (zeroed before) receives the longest, one atomic per wavefront
 __global__ void k_sell_len(int64_t rows, int64_t nslices, const int* __restrict__ rowptr, int* slice_len,
-                           int64_t* slice_sz) {
+                           int64_t* slice_sz, int* max_len) {
   int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nslices) return;
-  int64_t r0 = s * 64, r1 = r0 + 64 < rows ? r0 + 64 : rows;
   int m = 0;
-  for (int64_t r = r0; r < r1; ++r) {
-    int l = rowptr[r + 1] - rowptr[r];
-    m = l > m ? l : m;
+  if (s < nslices) {
+    int64_t r0 = s * 64, r1 = r0 + 64 < rows ? r0 + 64 : rows;
+    for (int64_t r = r0; r < r1; ++r) {
+      int l = rowptr[r + 1] - rowptr[r];
+      m = l > m ? l : m;
+    }
+    slice_len[s] = m;
+    slice_sz[s] = (int64_t)m * 64;
   }
-  slice_len[s] = m;
-  slice_sz[s] = (int64_t)m * 64;
+  for (int o = 32; o > 0; o >>= 1) {
+    const int mo = __shfl_xor(m, o, 64);
+    m = mo > m ? mo : m;
+  }
+  if ((threadIdx.x & 63) == 0 && m > 0) atomicMax(max_len, m);
 }
 
 __global__ void k_sell_fill(int64_t rows, const int* __restrict__ rowptr, const int* __restrict__ col,
@@ -89,6 +96,10 @@ void build_sells(hipStream_t s, Scratch& tmp, const Csr* const* A, Sell* const* 
   int64_t maxsl = 1;
   for (int m = 0; m < count; ++m) maxsl = std::max<int64_t>(maxsl, (A[m]->rows + 63) / 64);
   scan_reserve(tmp, maxsl);
+  DBuf<int>& mlen = tmp.i32[0];
+  mlen.reserve(3);
+  VEM_HIP(hipMemsetAsync(mlen.p, 0, 3 * sizeof(int), s));
+  tmp.ti.alloc(8);
   for (int m = 0; m < count; ++m) {
     Sell& B = *S[m];
     B.rows = A[m]->rows;
@@ -98,11 +109,13 @@ void build_sells(hipStream_t s, Scratch& tmp, const Csr* const* A, Sell* const* 
     DBuf<int64_t>& ptr = tmp.i64[2 * m + 1];
     sz.reserve(B.nslices + 1);
     ptr.reserve(B.nslices + 1);
-    k_sell_len<<<grid256(B.nslices), 256, 0, s>>>(B.rows, B.nslices, A[m]->rowptr, B.slice_len, sz);
+    k_sell_len<<<grid256(B.nslices), 256, 0, s>>>(B.rows, B.nslices, A[m]->rowptr, B.slice_len, sz, mlen.p + m);
     VEM_HIP(hipGetLastError());
     scan_i64_async(s, tmp, sz, B.nslices, ptr, m);
   }
+  VEM_HIP(hipMemcpyAsync(tmp.ti.p, mlen.p, count * sizeof(int), hipMemcpyDeviceToHost, s));
   VEM_HIP(hipStreamSynchronize(s));
+  for (int m = 0; m < count; ++m) S[m]->max_len = tmp.ti.p[m];
   for (int m = 0; m < count; ++m) {
     Sell& B = *S[m];
     const int64_t total = tmp.tot.p[m];

@@ -138,6 +138,7 @@ struct Csr {
 // SELL-64 copy of a CSR matrix (64-row slices, column-major inside a slice).
 struct Sell {
   int64_t rows = 0, nslices = 0, nnz = 0;
+  int max_len = 0;       // longest slice (entries per row after padding)
   DBuf<int> slice_ptr, slice_len, col, src;
   DBuf<double> val;
   DBuf<double> val_cs;   // column-scaled copy A D^{-1} (inner CG matrices only)
