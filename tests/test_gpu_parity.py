@@ -221,3 +221,38 @@ def test_graph_replays_match_eager(precision, cap):
             assert ig["inner_iterations"] == ie["inner_iterations"]
             assert torch.equal(ug, ue) and torch.equal(pg, pe), (precond, rep)
             assert torch.isfinite(y).all()
+
+
+def test_values_follow_coefficient_and_gamma():
+    """The coefficient-dependent values are built lazily, per preconditioner: after a Block-Schur
+    solve, a new coefficient and a Block-Reg solve (which builds K and A_gamma only), S must still
+    come out for the new coefficient, and a Block-Reg solve with another gamma must rebuild
+    A_gamma for that gamma.  Every matrix against the oracle, then a solve."""
+    import scipy.sparse as sp
+
+    _say("lazy values")
+    m = cube_mesh(5, 4, 3)
+    nc = 60
+    nu1, nu2 = 1.0 / lognormal_field(nc, 1.0, 1), 1.0 / lognormal_field(nc, 1.0, 2)
+    s = gpu_solver(m, nu=nu1, rhs=SineSolution())
+    s.solve(precond="schur", tol=1e-10)
+    import torch
+
+    s.set_coefficient(torch.as_tensor(nu2, dtype=torch.float64))
+    s.solve(precond="reg", tol=1e-10, inner_tol=1e-2)
+    d = discretize(m, nu=nu2, rhs=SineSolution())
+    M, B = d["M"].tocsr(), d["B"].tocsr()
+    Nu, Np = M.shape[0], B.shape[0]
+    assert_same_csr(to_scipy(*s.export_csr("K"), (Nu + Np, Nu + Np)), d["K"].tocsr())
+    S = (B @ sp.diags(1.0 / M.diagonal()) @ B.T).tocsr()
+    assert_same_csr(to_scipy(*s.export_csr("schur"), (Np, Np)), S)
+    g0 = s.sizes()["gamma"]
+    assert_same_csr(to_scipy(*s.export_csr("reg"), (Nu, Nu)), (M + B.T @ B / g0).tocsr())
+    g2 = 3.0 * g0
+    s.solve(precond="reg", tol=1e-10, inner_tol=1e-2, gamma=g2)
+    assert_same_csr(to_scipy(*s.export_csr("reg"), (Nu, Nu)), (M + B.T @ B / g2).tocsr())
+    u, p, info = s.solve(precond="schur", tol=1e-13, maxit=2000, inner_tol=1e-12)
+    x = direct_solve(d["K"], d["b"])
+    uo, po = x[:Nu], x[Nu:]
+    assert info["converged"]
+    assert rel(u.cpu().numpy(), uo) < 1e-10 and rel(p.cpu().numpy(), po) < 1e-10
