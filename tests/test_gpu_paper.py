@@ -145,3 +145,4 @@ def test_gpu_sizes_match_the_papers_cube_tables():
         s = solver_for(cube_mesh(n), row["k"])
         assert s.sizes()["n"] + 1 == row["dofs"], (row, s.sizes()["n"])
         s.close()
+
