@@ -8,6 +8,8 @@
  *
  *     nu u + grad p = 0,   div u = f   in Omega,   p = p_D on dOmega,
  *
+ * or, with vem_set_boundary(h, VEM_BC_FLUX), u.n = u_N on dOmega and a pressure
+ * of zero mean (the paper's model problem, Section 3),
  * discretised as in Sections 4.1-4.3 of the paper (face normal-flux moments,
  * L2 projector built through integration by parts, stabilised local forms)
  * and assembled in the symmetric form (Section 5, matrix with blocks A, B^T,
@@ -100,7 +102,7 @@ typedef struct {
   int64_t nnz_schur; /* S = B diag(M)^{-1} B^T */
   int64_t nnz_reg;   /* M + B^T B / gamma */
   int64_t n_qp_cell; /* volume quadrature points (load f) */
-  int64_t n_qp_face; /* boundary-face quadrature points (p_D) */
+  int64_t n_qp_face; /* boundary-face quadrature points (p_D, or the flux field with VEM_BC_FLUX) */
   int32_t load_points; /* quadrature points per direction of the load rule */
   int32_t max_cell_faces;
   double h;          /* mean cell diameter (eq. meshSize) */
@@ -137,7 +139,7 @@ typedef struct {
 
 /* Fill opts with defaults: Block-Schur, m = 30, maxit = 5000, tol = 1e-8,
  * inner_tol = 1e-6, inner_maxit = 5000, inner_check = 32, gamma = h^2, FP64,
- * graphs on. */
+ * graphs off. */
 void vem_solve_opts_default(vem_solve_opts* opts);
 
 /* Create a handle bound to the current HIP device and to `stream`
@@ -151,9 +153,11 @@ vem_status vem_destroy(vem_handle h);
  * global normal n_f.  cell_ptr[nc+1], cell_face, cell_face_sign: the faces of
  * each cell and sigma = +1 if n_f points out of the cell, -1 otherwise.  Every
  * face must bound one cell (boundary) or two cells of opposite sign.  All
- * arrays are host or device memory according to mem_kind.  Errors:
- * VEM_EINVAL (sizes), VEM_EBADMESH (indices out of range, a face used twice
- * with one sign, a face of no cell, zero area, non-positive volume). */
+ * arrays are host or device memory according to mem_kind (device offsets are
+ * checked on the device, never copied to the host).  Errors: VEM_EINVAL
+ * (sizes), VEM_EBADMESH (offset arrays not starting at 0 or decreasing,
+ * indices out of range, a face used twice with one sign, a face of no cell,
+ * zero area, non-positive volume). */
 vem_status vem_set_mesh(vem_handle h, int64_t nv, const double* xyz, int64_t nf, const int32_t* face_ptr,
                         const int32_t* face_vtx, int64_t nc, const int32_t* cell_ptr, const int32_t* cell_face,
                         const int8_t* cell_face_sign, int mem_kind);
@@ -180,10 +184,12 @@ vem_status vem_get_sizes(vem_handle h, vem_sizes* out);
 vem_status vem_get_quadrature(vem_handle h, double* qp_cell, double* qp_face);
 
 /* nu = 1/K per cell (device or host, n_cells doubles, all > 0; copied in).
- * The flux block M (M_P is proportional to nu_P, Section 4.3) and both
- * preconditioners are rebuilt from the stored coefficient-free local
+ * The flux block M (M_P is proportional to nu_P, Section 4.3) and the
+ * preconditioner matrices are rebuilt from the stored coefficient-free local
  * matrices by the next call that uses them (vem_solve, vem_apply,
- * vem_export_csr, vem_time_kernel); the local projectors are not recomputed. */
+ * vem_export_csr, vem_time_kernel), each only when that call needs it (S for
+ * Block-Schur, M + B^T B / gamma for Block-Reg); the local projectors are not
+ * recomputed. */
 vem_status vem_set_coefficient(vem_handle h, const double* nu);
 
 /* Right-hand side from point values (device): f_qp[n_qp_cell] at the points
