@@ -205,69 +205,29 @@ __global__ void k_cell_geometry(int nc, const double* __restrict__ xyz, const in
       m = m + (t / 4.0) * (O + A + B + C);
     }
   }
+  // largest vertex-vertex distance; squared distances are compared and one root taken
+  // (the root is monotone and correctly rounded, so this is the same number).  A wavefront
+  // per cell with the incidences staged in LDS was measured slower (235 us against 258 us
+  // for this whole kernel at 64^3): the chain of dependent index loads dominates, and a
+  // thread per cell overlaps 64 of them per wave.
+  double dmax2 = 0.0;
+  for (int j = s; j < e; ++j) {
+    int f = cface[j];
+    for (int q = fptr[f]; q < fptr[f + 1]; ++q) {
+      V3 P = ld3(xyz, fvtx[q]);
+      for (int j2 = j; j2 < e; ++j2) {
+        int f2 = cface[j2];
+        for (int q2 = fptr[f2]; q2 < fptr[f2 + 1]; ++q2) {
+          const V3 d = ld3(xyz, fvtx[q2]) - P;
+          dmax2 = fmax(dmax2, dot(d, d));
+        }
+      }
+    }
+  }
   vol[c] = v;
   st3(cen, c, (1.0 / v) * m);
+  diam[c] = sqrt(dmax2);
   st3(xref, c, O);
-}
-
-// Cell diameters, the largest distance between two vertices of a cell: one wavefront per
-// cell.  The cell's face-vertex incidences (at most kDiamInc) are staged in LDS, the lanes
-// share the pairs, and a wave maximum of the squared distances gives the result (one root
-// at the end; the root is monotone and correctly rounded, so this is the same number as the
-// largest distance).  A cell with more incidences is done by one lane from global memory.
-constexpr int kDiamInc = 256;
-__global__ void __launch_bounds__(kThreads) k_cell_diam(int nc, const double* __restrict__ xyz,
-                                                        const int* __restrict__ fptr, const int* __restrict__ fvtx,
-                                                        const int* __restrict__ cptr, const int* __restrict__ cface,
-                                                        double* diam) {
-  __shared__ double pts[kThreads / 64][kDiamInc][3];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int c = blockIdx.x * (kThreads / 64) + wv;
-  const bool valid = c < nc;  // no early return: every thread reaches the barrier
-  const int s = valid ? cptr[c] : 0, F = valid ? cptr[c + 1] - s : 0;  // F <= kMaxCellFaces = 64
-  int fs = 0, fn = 0;
-  if (lane < F) {
-    const int f = cface[s + lane];
-    fs = fptr[f];
-    fn = fptr[f + 1] - fs;
-  }
-  int off = fn;  // inclusive prefix of the face sizes over the lanes
-  for (int o = 1; o < 64; o <<= 1) {
-    const int t = __shfl_up(off, o, 64);
-    if (lane >= o) off += t;
-  }
-  const int n = __shfl(off, 63, 64);
-  off -= fn;
-  const bool staged = n <= kDiamInc;
-  if (staged && lane < F)
-    for (int q = 0; q < fn; ++q) {
-      const V3 P = ld3(xyz, fvtx[fs + q]);
-      pts[wv][off + q][0] = P.x;
-      pts[wv][off + q][1] = P.y;
-      pts[wv][off + q][2] = P.z;
-    }
-  __syncthreads();
-  double m = 0.0;
-  if (valid && staged) {
-    for (int a = lane; a < n; a += 64)
-      for (int b = a + 1; b < n; ++b) {
-        const double dx = pts[wv][b][0] - pts[wv][a][0], dy = pts[wv][b][1] - pts[wv][a][1],
-                     dz = pts[wv][b][2] - pts[wv][a][2];
-        m = fmax(m, dx * dx + dy * dy + dz * dz);
-      }
-  } else if (valid && lane == 0) {
-    for (int j = s; j < s + F; ++j)
-      for (int q = fptr[cface[j]]; q < fptr[cface[j] + 1]; ++q) {
-        const V3 P = ld3(xyz, fvtx[q]);
-        for (int j2 = j; j2 < s + F; ++j2)
-          for (int q2 = fptr[cface[j2]]; q2 < fptr[cface[j2] + 1]; ++q2) {
-            const V3 d = ld3(xyz, fvtx[q2]) - P;
-            m = fmax(m, dot(d, d));
-          }
-      }
-  }
-  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-  if (valid && lane == 0) diam[c] = sqrt(m);
 }
 
 // --- tetrahedra and quadrature --------------------------------------------------------------
@@ -500,7 +460,6 @@ void launch_cell_geometry(hipStream_t s, int nc, const double* xyz, const int* f
                           const int* cptr, const int* cface, const int8_t* csign, double* vol, double* cen,
                           double* diam, double* xref) {
   k_cell_geometry<<<nblocks(nc), kThreads, 0, s>>>(nc, xyz, fptr, fvtx, cptr, cface, csign, vol, cen, diam, xref);
-  k_cell_diam<<<nblocks(nc, kThreads / 64), kThreads, 0, s>>>(nc, xyz, fptr, fvtx, cptr, cface, diam);
 }
 void launch_tet_counts(hipStream_t s, int nc, const int* fptr, const int* cptr, const int* cface, int* cnt) {
   k_tet_counts<<<nblocks(nc), kThreads, 0, s>>>(nc, fptr, cptr, cface, cnt);
