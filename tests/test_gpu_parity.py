@@ -166,6 +166,17 @@ def test_error_paths():
         with pytest.raises(VemError) as e:
             s.set_mesh(bad)
         assert e.value.code == -2 and msg in str(e.value), (key, i, str(e.value))
+    # an empty mesh is rejected before anything runs on the device
+    empty = {k: m[k][:0] for k in ("xyz", "face_vtx", "cell_face", "cell_face_sign")}
+    empty["face_ptr"] = m["face_ptr"][:1]
+    empty["cell_ptr"] = m["cell_ptr"][:1]
+    with pytest.raises(VemError) as e:
+        s.set_mesh(empty)
+    assert e.value.code == -1
+    # solving before a discretisation is a call-order error
+    with pytest.raises(VemError) as e:
+        Solver().solve()
+    assert e.value.code == -1
     s = gpu_solver(m, rhs=SineSolution())
     u, p, info = s.solve(tol=1e-14, maxit=1)
     assert not info["converged"] and info["iterations"] == 1
