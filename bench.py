@@ -508,7 +508,7 @@ def main():
     dom = kern["cg_reg"]
     sz = solver.sizes()
     line = {
-        "metric": "solve time to rel. residual 1e-8 (s) + HBM GB/s in SpMV/precond",
+        "metric": "solve time to rel. residual 1e-8 (s) + HBM GB/s in SpMV/precond; adjoint/fwd",
         "value": mean("t_ass") + mean("t_schur"),
         "unit": "s",
         "n_gpus": 1,
@@ -550,6 +550,8 @@ def main():
     if not args.no_extras:
         log("extras ...")
         line["extras"] = extras(args, torch, dev)
+        # the metric's third part: adjoint (backward) time over forward time, 48^3 (extras)
+        line["adjoint_over_forward"] = line["extras"]["adjoint_cube48"]["backward_over_forward"]
     if args.k2_batch > 0:
         log("k=2 batch ...")
         line.setdefault("extras", {})["batch_cube32_k2"] = k2_batch(args.k2_batch, torch, dev)
