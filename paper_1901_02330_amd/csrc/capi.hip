@@ -428,7 +428,7 @@ double device_sum(vem_handle h, const double* x, int64_t n) {
   return v;
 }
 
-// ----- rebuild every coefficient-dependent value: K, A_gamma, diagonals, S -----
+// ----- coefficient-dependent values (K, diagonals, S, A_gamma), built lazily -----
 void invalidate_values(vem_handle h) {
   h->k_ready = h->s_ready = h->a_ready = h->s32_ready = h->a32_ready = false;
 }
@@ -635,14 +635,13 @@ void apply_prec(vem_handle h, const vem_solve_opts& o, const double* v, double* 
   }
 }
 
-// Right-hand side with flux boundary data (needs the values): the known fluxes move to the right, the
-// prescribed rows carry them, and the pressure part is projected off the constant pressure (this
-// removes the quadrature-level mismatch between int f and the boundary flux, so the system is
-// consistent).
+// Right-hand side with flux boundary data (from the coefficient and the coefficient-free local
+// matrices, not from the assembled K): the known fluxes move to the right, the prescribed rows
+// carry them, and the pressure part is projected off the constant pressure (this removes the
+// quadrature-level mismatch between int f and the boundary flux, so the system is consistent).
 const double* flux_rhs(vem_handle h) {
   hipStream_t s = h->stream;
   const DofLayout L = h->L;
-  ensure_k(h);
   launch_flux_rhs(s, L, h->cptr, h->cface, h->csign, h->face_cell, h->face_lidx, h->lmat_ptr, h->M1, h->lb_ptr,
                   h->Bdiv1, h->nu, h->is_bnd, h->xB, h->rhs, h->rhs_flux);
   double* d = h->scal.p + 4 * kMaxDots;
