@@ -28,6 +28,7 @@ import argparse
 import json
 import os
 import re
+import statistics
 import sys
 import time
 
@@ -526,6 +527,9 @@ def main():
             "n_u": sz["n_u"], "n_p": sz["n_p"], "nnz_K": sz["nnz_K"],
         },
         "phases_s": {"assembly": mean("t_ass"), "solve_schur": mean("t_schur"), "solve_reg": mean("t_reg")},
+        "value_per_step_s": {"min": min(r["t_ass"] + r["t_schur"] for r in results),
+                             "median": statistics.median(r["t_ass"] + r["t_schur"] for r in results),
+                             "max": max(r["t_ass"] + r["t_schur"] for r in results)},
         "solves": {
             "schur": {"iterations": results[-1]["info_schur"]["iterations"],
                       "inner_iterations": results[-1]["info_schur"]["inner_iterations"],
