@@ -1456,12 +1456,19 @@ static vem_status solve_impl(vem_handle h, const vem_solve_opts* opts, const dou
     if (bnorm == 0.0) {
       launch_fill(s, N, 0.0, x);
     }
-    // r0 = b - K x0
-    launch_residual(s, h->Ks, x, rhs, V, h->partials, dn);
-    check_launch();
-    VEM_HIP(hipMemcpyAsync(hb, dn, sizeof(double), hipMemcpyDeviceToHost, s));
-    sync(h);
-    double beta = std::sqrt(hb[0]);
+    // r0 = b - K x0.  From x0 = 0 it is b itself, whose norm is known: no product, no second
+    // synchronisation (dn already holds ||b||^2 for the first normalisation).
+    double beta = bnorm;
+    if (o.use_x0) {
+      launch_residual(s, h->Ks, x, rhs, V, h->partials, dn);
+      check_launch();
+      VEM_HIP(hipMemcpyAsync(hb, dn, sizeof(double), hipMemcpyDeviceToHost, s));
+      sync(h);
+      beta = std::sqrt(hb[0]);
+    } else {
+      launch_copy(s, N, rhs, V);
+      check_launch();
+    }
     const double bref = bnorm > 0 ? bnorm : 1.0;
     int its = 0, restarts = 0;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), yv(m);
