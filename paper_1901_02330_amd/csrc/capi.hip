@@ -418,16 +418,6 @@ void ensure_scratch(vem_handle h) {
 }
 
 // total of a device double array (synchronises)
-double device_sum(vem_handle h, const double* x, int64_t n) {
-  ensure_scratch(h);
-  launch_sum(h->stream, n, x, h->partials, h->scal);
-  check_launch();
-  double v = 0.0;
-  VEM_HIP(hipMemcpyAsync(&v, h->scal.p, sizeof(double), hipMemcpyDeviceToHost, h->stream));
-  sync(h);
-  return v;
-}
-
 // ----- coefficient-dependent values (K, diagonals, S, A_gamma), built lazily -----
 void invalidate_values(vem_handle h) {
   h->k_ready = h->s_ready = h->a_ready = h->s32_ready = h->a32_ready = false;
@@ -913,10 +903,17 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
     fill_i32(s, 1, 0, h->is_bnd.p + nf);
     launch_check_faces(s, nf, h->face_cnt, h->f_area, h->is_bnd, derr);
     launch_check_cells(s, nc, h->c_vol, derr);
+    // the error flags and the sum of the cell diameters come back with one synchronisation
+    ensure_scratch(h);
+    launch_sum(s, nc, h->c_diam, h->partials, h->scal);
     check_launch();
-    int e = read_err(h, derr);
+    h->tmp.ti.alloc(8);
+    VEM_HIP(hipMemcpyAsync(h->tmp.ti.p, derr.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    VEM_HIP(hipMemcpyAsync(h->hbuf.p, h->scal.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    sync(h);
+    const int e = h->tmp.ti.p[0];
     VEM_REQUIRE(e == 0, VEM_EBADMESH, mesh_err_text(e));
-    h->h = device_sum(h, h->c_diam, nc) / nc;
+    h->h = h->hbuf.p[0] / nc;
     h->gamma_default = h->h * h->h;
 
     // ---- quadrature support: tetrahedra of the cells, triangles of the boundary faces
@@ -1179,7 +1176,6 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
     }
     h->gamma_A = h->gamma_default;
     invalidate_values(h);
-    sync(h);
     h->has_disc = true;
   });
 }
