@@ -1477,20 +1477,27 @@ static vem_status solve_impl(vem_handle h, const vem_solve_opts* opts, const dou
       std::fill(g.begin(), g.end(), 0.0);
       g[0] = beta;
       int jend = 0;
-      // One Arnoldi step, enqueued without waiting: the next basis vector is normalised on
+      // One Arnoldi step, enqueued without waiting: everything the next step needs stays on
       // the device, so step j+1 is enqueued before the host reads step j's scalars and the
       // device never idles on the host's Givens rotations.  A step enqueued past the
       // convergence point is discarded (its outputs are never read).
+      //   Classical Gram-Schmidt twice, in two passes over V: the first pass of step j also
+      // finishes v_j, i.e. applies step j-1's second projection and normalisation to the w'
+      // that step left in V[j].  The preconditioner of step j therefore takes that w' rather
+      // than v_j; flexible GMRES allows any z_j, since K z_j = V H e_j holds by construction of
+      // the orthogonalisation of K z_j, and w' differs from ||w'|| v_j by a rounding-level
+      // component in span(V).
       auto enqueue_step = [&](int j) {
         double* vj = V + (size_t)j * N;
         double* zj = Z + (size_t)j * N;
         double* w = V + (size_t)(j + 1) * N;
         apply_prec(h, o, vj, zj);
         launch_spmv(s, h->Ks, zj, w);
-        // classical Gram-Schmidt, twice
-        launch_dots(s, N, j + 1, V, N, w, h->partials, dh);
+        if (j == 0)
+          launch_dots(s, N, 1, V, N, w, h->partials, dh);
+        else
+          launch_dots_fix(s, N, j + 1, V, N, dh2, w, h->partials, dh);
         launch_update_dots(s, N, j + 1, V, N, dh, w, h->partials, dh2);
-        launch_update_normalize(s, N, j + 1, V, N, dh2, w);
         check_launch();
         // h at scal[0], its correction at scal[kMaxDots], ||w||^2 between the passes at
         // scal[kMaxDots + j + 1]

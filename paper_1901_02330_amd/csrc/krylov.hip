@@ -63,6 +63,45 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1
   block_partials<K>(acc, partials);
 }
 
+// First Gram-Schmidt pass of Arnoldi step j (K = j + 1 >= 2 basis vectors) with the previous
+// step's second pass folded in.  V[K-1] still holds w' of step j-1 (after its first projection,
+// neither re-orthogonalised nor normalised), and hp holds that step's V^T w' (K-1 values) and
+// ||w'||^2.  With V orthonormal, ||w' - V hp||^2 = ||w'||^2 - |hp|^2, so the pass finishes the
+// basis vector v = (w' - V hp) / sqrt(||w'||^2 - |hp|^2) (written back, zeros if the difference
+// is <= 0), then forms the partials of V_k . w with the finished vectors.  V[0..K-2] are read once
+// for both jobs.
+template <int K>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))) k_dots_fix(int64_t n, double* __restrict__ V, int64_t ldv,
+                                                       const double* __restrict__ hp, const double* __restrict__ w,
+                                                       double* partials) {
+  double hk[K - 1];
+  double hh = 0.0;
+#pragma unroll
+  for (int k = 0; k < K - 1; ++k) {
+    hk[k] = hp[k];
+    hh += hk[k] * hk[k];
+  }
+  const double nn = hp[K - 1] - hh;
+  const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+  double acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double wi = w[i];
+    double t = V[(K - 1) * ldv + i];
+#pragma unroll
+    for (int k = 0; k < K - 1; ++k) {
+      const double vk = V[k * ldv + i];
+      t -= vk * hk[k];
+      acc[k] += vk * wi;
+    }
+    t *= inv;
+    V[(K - 1) * ldv + i] = t;
+    acc[K - 1] += t * wi;
+  }
+  block_partials<K>(acc, partials);
+}
+
 // w -= V h; partials of V_k . w (k < K) and of ||w||^2 (component K)
 template <int K>
 __global__ void __launch_bounds__(kThreads) k_update_dots(int64_t n, const double* __restrict__ V, int64_t ldv,
@@ -89,31 +128,6 @@ __global__ void __launch_bounds__(kThreads) k_update_dots(int64_t n, const doubl
     acc[K] += wi * wi;
   }
   block_partials<K + 1>(acc, partials);
-}
-
-// Second Gram-Schmidt pass fused with the normalisation.  h holds V^T w and ||w||^2 from
-// the kernel before; with V orthonormal, ||w - V V^T w||^2 = ||w||^2 - |V^T w|^2, so the
-// new basis vector (w - V h) / sqrt(||w||^2 - |h|^2) is written in place with no reduction
-// of its own.  After a first pass |h| is small against ||w||, so the difference loses no
-// accuracy.  A difference <= 0 (breakdown) writes zeros.
-template <int K>
-__global__ void __launch_bounds__(kThreads) k_update_normalize(int64_t n, const double* __restrict__ V, int64_t ldv,
-                                                               const double* __restrict__ h, double* __restrict__ w) {
-  double hk[K];
-  double hh = 0.0;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    hk[k] = h[k];
-    hh += hk[k] * hk[k];
-  }
-  const double nn = h[K] - hh;
-  const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    double wi = w[i];
-#pragma unroll
-    for (int k = 0; k < K; ++k) wi -= V[k * ldv + i] * hk[k];
-    w[i] = wi * inv;
-  }
 }
 
 // out = x - v (dot * inv_vv): x without its component along v (dot = v . x on the device)
@@ -295,9 +309,10 @@ inline int stream_grid(int64_t n) {
   return (int)(b < cap ? (b < 1 ? 1 : b) : cap);
 }
 
-#define VEM_K_CASES(X) \
-  X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20) \
+#define VEM_K_CASES_FROM2(X) \
+  X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18) X(19) X(20) \
   X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
+#define VEM_K_CASES(X) X(1) VEM_K_CASES_FROM2(X)
 
 void finalize(hipStream_t s, int nparts, int K, const double* partials, double* out) {
   k_finalize<<<K, kThreads, 0, s>>>(nparts, K, partials, out);
@@ -344,16 +359,17 @@ void launch_update_dots(hipStream_t s, int64_t n, int k, const double* V, int64_
   finalize(s, grid, k + 1, partials, out);
 }
 
-void launch_update_normalize(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* h,
-                             double* w) {
-  int grid = stream_grid(n);
+void launch_dots_fix(hipStream_t s, int64_t n, int k, double* V, int64_t ldv, const double* hp, const double* w,
+                     double* partials, double* out) {
+  int grid = red_grid(n);
   switch (k) {
 #define X(K) \
-  case K: k_update_normalize<K><<<grid, kThreads, 0, s>>>(n, V, ldv, h, w); break;
-    VEM_K_CASES(X)
+  case K: k_dots_fix<K><<<grid, kThreads, 0, s>>>(n, V, ldv, hp, w, partials); break;
+    VEM_K_CASES_FROM2(X)
 #undef X
-    default: throw Error{VEM_EINVAL, "too many basis vectors"};
+    default: throw Error{VEM_EINVAL, "the folded first pass needs 2 to 32 basis vectors"};
   }
+  finalize(s, grid, k, partials, out);
 }
 
 void launch_project(hipStream_t s, int64_t n, const double* x, const double* v, const double* dot, double inv_vv,

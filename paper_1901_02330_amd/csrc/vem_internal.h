@@ -282,9 +282,10 @@ void launch_dots(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, 
                  double* out);
 void launch_update_dots(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* h, double* w,
                         double* partials, double* out);
-// w = (w - V h) / sqrt(h[k] - |h[0..k)|^2) in place (h from launch_update_dots)
-void launch_update_normalize(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* h,
-                             double* w);
+// First Gram-Schmidt pass with the previous step's second pass folded in: V[k-1] = (V[k-1] -
+// V[0..k-1) hp) / sqrt(hp[k-1] - |hp[0..k-1)|^2) in place, then out[0..k) = V^T w (k >= 2)
+void launch_dots_fix(hipStream_t s, int64_t n, int k, double* V, int64_t ldv, const double* hp, const double* w,
+                     double* partials, double* out);
 void launch_scale_to(hipStream_t s, int64_t n, const double* w, const double* norm2, double* dst);
 void launch_scale_by(hipStream_t s, int64_t n, const double* x, const double* d, double c, double* y);
 void launch_combine(hipStream_t s, int64_t n, int k, const double* Z, int64_t ldz, const double* y, double* x);
