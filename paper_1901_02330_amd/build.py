@@ -3,6 +3,8 @@
 Usage: python -m paper_1901_02330_amd.build  (or __graft_entry__.build()).
 Each .hip source is compiled to an object under _build/ (in parallel), then
 linked into one shared library exporting the C ABI declared in include/vem.h.
+The plain-C test program of that ABI (tests/capi_c/cube_solve) is then built
+against it with gcc.
 """
 
 from __future__ import annotations
@@ -57,6 +59,26 @@ def _compile(src: str) -> str:
     return obj
 
 
+def build_c_driver(verbose: bool = True) -> str:
+    """Compile tests/capi_c/cube_solve.c, a plain-C test program of the ABI, with gcc against the
+    built library (the library is found next to the package through the binary's run path)."""
+    src = os.path.join(ROOT, "tests", "capi_c", "cube_solve.c")
+    out = os.path.join(ROOT, "tests", "capi_c", "cube_solve")
+    tmp = out + ".tmp"
+    cmd = ["gcc", "-std=c11", "-O2", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__", f"-I{INCLUDE}",
+           "-I/opt/rocm/include", src, "-o", tmp, f"-L{PKG}", "-l:libvem_mi355x.so", "-L/opt/rocm/lib",
+           "-lamdhip64", "-lm", "-Wl,-rpath,$ORIGIN/../../paper_1901_02330_amd", "-Wl,-rpath,/opt/rocm/lib"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("gcc failed for the C driver:\n" + r.stderr)
+    if r.stderr.strip():
+        sys.stderr.write(r.stderr)
+    os.replace(tmp, out)
+    if verbose:
+        print(f"built {out}")
+    return out
+
+
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), 8)) as ex:
@@ -70,6 +92,7 @@ def build(verbose: bool = True) -> str:
     os.replace(tmp, LIB)
     if verbose:
         print(f"built {LIB}")
+    build_c_driver(verbose)
     return LIB
 
 
