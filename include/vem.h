@@ -189,7 +189,8 @@ vem_status vem_get_quadrature(vem_handle h, double* qp_cell, double* qp_face);
  * matrices by the next call that uses them (vem_solve, vem_apply,
  * vem_export_csr, vem_time_kernel), each only when that call needs it (S for
  * Block-Schur, M + B^T B / gamma for Block-Reg); the local projectors are not
- * recomputed. */
+ * recomputed.  Errors: VEM_EINVAL if a value is not positive and finite
+ * (checked on the device; the previous coefficient stays in place). */
 vem_status vem_set_coefficient(vem_handle h, const double* nu);
 
 /* Right-hand side from point values (device): f_qp[n_qp_cell] at the points

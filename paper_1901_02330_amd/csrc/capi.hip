@@ -1222,9 +1222,23 @@ vem_status vem_set_coefficient(vem_handle h, const double* nu) {
   if (!h || !nu) return VEM_EINVAL;
   return guarded(h, [&] {
     require_disc(h);
-    VEM_HIP(hipMemcpyAsync(h->nu.p, nu, h->nc * sizeof(double), hipMemcpyDefault, h->stream));
-    invalidate_values(h);
+    hipStream_t s = h->stream;
+    // staged and checked first, so that a rejected field leaves the previous coefficient in place
+    DBuf<double>& stage = h->tmp.f64[7];
+    stage.reserve(h->nc);
+    VEM_HIP(hipMemcpyAsync(stage.p, nu, h->nc * sizeof(double), hipMemcpyDefault, s));
+    DBuf<int>& bad = h->tmp.i32[0];
+    bad.reserve(1);
+    fill_i32(s, 1, 0, bad);
+    launch_check_cells(s, (int)h->nc, stage.p, bad);  // flags a value that is not positive and finite
+    check_launch();
+    h->tmp.ti.alloc(8);
+    VEM_HIP(hipMemcpyAsync(h->tmp.ti.p, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
     sync(h);
+    VEM_REQUIRE(h->tmp.ti.p[0] == 0, VEM_EINVAL, "coefficient nu must be positive and finite in every cell");
+    // stream-ordered: the caller's array has been read by now
+    VEM_HIP(hipMemcpyAsync(h->nu.p, stage.p, h->nc * sizeof(double), hipMemcpyDeviceToDevice, s));
+    invalidate_values(h);
   });
 }
 

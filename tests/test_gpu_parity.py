@@ -186,6 +186,19 @@ def test_error_paths():
     with pytest.raises(VemError) as e:
         s.solve()
     assert e.value.code == -6
+    # a coefficient that is not positive and finite is rejected on the device, and the previous
+    # coefficient stays in place (host and device arrays)
+    nu = 1.0 / lognormal_field(27, 1.0, 4)
+    s = gpu_solver(m, nu=nu, rhs=SineSolution())
+    u0, p0, _ = s.solve(tol=1e-12)
+    for v, dev in ((0.0, "cpu"), (-1.0, "cuda"), (float("nan"), "cpu"), (float("inf"), "cuda")):
+        nu_bad = nu.copy()
+        nu_bad[13] = v
+        with pytest.raises(VemError) as e:
+            s.set_coefficient(torch.as_tensor(nu_bad, device=dev))
+        assert e.value.code == -1 and "positive and finite" in str(e.value), str(e.value)
+    u1, p1, _ = s.solve(tol=1e-12)
+    assert torch.equal(u0, u1) and torch.equal(p0, p1)
 
 
 @pytest.mark.parametrize("precond", ["schur", "reg"])
