@@ -103,7 +103,42 @@ def summarize(prefix: str):
             last = by[key][-200:]
             out += ["", f"Last {len(last)} launches of `{key[0]}` at grid {key[1]} (the timing loop): "
                     f"mean {sum(last) / len(last):.2f} us, median {statistics.median(last):.2f} us."]
+        out += schur_window(trace)
     print("\n".join(out))
+
+
+def schur_window(trace: str):
+    """Kernel time inside the first Block-Schur solve of a traced step: from its value build (the
+    first k_schur_values) to the last launch before the Block-Reg solve's first inner-CG init.
+    Template arguments that only count Krylov vectors are folded into one row."""
+    import csv
+
+    rows = sorted(csv.DictReader(open(trace)), key=lambda r: int(r["Start_Timestamp"]))
+    names = [r["Kernel_Name"] for r in rows]
+    try:
+        s = next(i for i, n in enumerate(names) if "k_schur_values" in n)
+        e = next(i for i in range(s, len(names)) if "k_ppcg_init<double, 256" in names[i])
+    except StopIteration:
+        return []
+    seg = rows[s:e]
+    busy, calls = {}, {}
+    for r in seg:
+        mt = re.search(r"(k_[A-Za-z0-9_]+(?:<[^>]*>)?)\(", r["Kernel_Name"])
+        name = mt.group(1) if mt else r["Kernel_Name"].split("(")[0][:40]
+        name = re.sub(r"^(k_(?:dots|dots_fix|update_dots|combine))<\d+>$", r"\1<j>", name)
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        busy[name] = busy.get(name, 0.0) + d
+        calls[name] = calls.get(name, 0) + 1
+    span = (int(seg[-1]["End_Timestamp"]) - int(seg[0]["Start_Timestamp"])) / 1e3
+    total = sum(busy.values())
+    out = ["", f"First Block-Schur solve of the step (value build included): {len(seg)} launches, "
+           f"{total / 1e3:.2f} ms of kernel time in a {span / 1e3:.2f} ms span (the traced run is the "
+           "first, cold step: the span also holds first-use allocations and tracer gaps).", "",
+           "| kernel | launches | total ms | avg us | % of kernel time |", "|---|---|---|---|---|"]
+    for name, t in sorted(busy.items(), key=lambda x: -x[1])[:14]:
+        out.append(f"| `{name}` | {calls[name]} | {t / 1e3:.2f} | {t / calls[name]:.2f} | "
+                   f"{100.0 * t / total:.1f} |")
+    return out
 
 
 KERNEL_SRC = ("pcg.hip", "krylov_device.h")  # the dominant kernel's source, for the traffic record
