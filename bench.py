@@ -538,7 +538,7 @@ def main():
 
     # dominant kernel: one pipelined inner-CG iteration; the Block-Reg one carries most of the step
     kern = {}
-    for which in ("cg_reg", "cg_schur", "spmv"):
+    for which in ("cg_reg", "cg_schur", "spmv", "cg_schur32p"):
         ms, nbytes = solver.time_kernel(which, reps=200)
         kern[which] = {"avg_us": ms * 1e3, "bytes": nbytes, "gbs": nbytes / (ms * 1e-3) / 1e9}
     dom = kern["cg_reg"]

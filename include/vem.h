@@ -255,14 +255,17 @@ vem_status vem_get_geometry(vem_handle h, double* face_area, double* face_normal
 
 /* Hot kernels that vem_time_kernel can time. */
 enum { VEM_KERNEL_SPMV = 0, VEM_KERNEL_CG_SCHUR = 1, VEM_KERNEL_CG_REG = 2, VEM_KERNEL_CG_SCHUR32 = 3,
-       VEM_KERNEL_CG_REG32 = 4 };
+       VEM_KERNEL_CG_REG32 = 4, VEM_KERNEL_CG_SCHUR32P = 5, VEM_KERNEL_CG_REG32P = 6 };
 
 /* Measurement hook for benchmarks: time `reps` back-to-back launches of one
  * hot kernel with HIP events recorded on the handle's stream.
  *   VEM_KERNEL_SPMV:     the saddle product y = K x;
  *   VEM_KERNEL_CG_SCHUR: one pipelined inner-CG iteration on S (Block-Schur);
  *   VEM_KERNEL_CG_REG:   one pipelined inner-CG iteration on M + B^T B / gamma;
- *   VEM_KERNEL_CG_SCHUR32, VEM_KERNEL_CG_REG32: the same in FP32 (VEM_MIXED).
+ *   VEM_KERNEL_CG_SCHUR32, VEM_KERNEL_CG_REG32: one classical FP32 iteration (two
+ *                        launches; VEM_MIXED with an inner cap above 64);
+ *   VEM_KERNEL_CG_SCHUR32P, VEM_KERNEL_CG_REG32P: one pipelined FP32 iteration
+ *                        (VEM_MIXED with an inner cap of 64 or less).
  * avg_ms receives the mean duration of one launch; bytes (may be NULL) the
  * algorithmic bytes one launch moves (every matrix entry and every vector
  * element read or written once).  Uses the solver workspace; the results of

@@ -485,11 +485,20 @@ void ensure_workspace(vem_handle h, int m) {
   h->ws_m = m;
 }
 
+// FP32 inner iteration: pipelined (pipe) or classical
+void iter32(hipStream_t s, bool pipe, int i, const Sell& A, const PcgWork32& w32, PcgState* st, double* part) {
+  if (pipe)
+    launch_pcg_iter32p(s, i, A, w32, st, part);
+  else
+    launch_pcg_iter32(s, i, A, w32, st, part);
+}
+
 // The graph of kGraphIters iterations (2 .. 2+kGraphIters-1) for this matrix and precision,
 // captured on the private stream on first use or when a referenced buffer moved.
 hipGraphExec_t inner_graph(vem_handle h, const Sell& A, const PcgWork& w, const PcgWork32& w32, bool mixed,
-                           InnerGraph& g) {
-  const void* key[8] = {mixed ? (const void*)A.val32.p : (const void*)A.val_cs.p, A.col.p, h->pr.p, h->pcg.p,
+                           bool pipe32, InnerGraph& g) {
+  const void* vals = !mixed ? (const void*)A.val_cs.p : pipe32 ? (const void*)A.val32_cs.p : (const void*)A.val32.p;
+  const void* key[8] = {vals, A.col.p, h->pr.p, h->pcg.p,
                         mixed ? (const void*)h->px32.p : (const void*)w.x, mixed ? (const void*)w32.dinv : w.dinv,
                         (const void*)(intptr_t)A.rows, (const void*)(intptr_t)A.nnz};
   if (g.exec && std::equal(key, key + 8, g.key)) return g.exec;
@@ -500,7 +509,7 @@ hipGraphExec_t inner_graph(vem_handle h, const Sell& A, const PcgWork& w, const 
   try {
     for (int t = 0; t < kGraphIters; ++t) {
       if (mixed)
-        launch_pcg_iter32(h->cap, 2 + t, A, w32, h->pcg, h->pcgpart);
+        iter32(h->cap, pipe32, 2 + t, A, w32, h->pcg, h->pcgpart);
       else
         launch_pcg_iter(h->cap, 2 + t, A, w, h->pcg, h->pcgpart);
     }
@@ -520,7 +529,10 @@ hipGraphExec_t inner_graph(vem_handle h, const Sell& A, const PcgWork& w, const 
   return g.exec;
 }
 
-// Inner Jacobi-CG: x ~ A^{-1} b to inner_tol (pipelined in FP64, classical in FP32).
+// Inner Jacobi-CG: x ~ A^{-1} b to inner_tol (pipelined in FP64; in FP32 pipelined when the
+// iterations are capped at kBlindInner or fewer, classical otherwise: over hundreds of FP32
+// iterations the pipelined recurrences lose positivity, while a capped solve that meets that
+// guard simply stops with its iterate, which flexible GMRES accepts like any inexact solve).
 // Iterations are enqueued in chunks between convergence checks; the first
 // chunk is sized from the previous solve on the same matrix so that few
 // launches find the solve already converged.  With graphs, iterations 0 and
@@ -532,20 +544,23 @@ void inner_pcg(vem_handle h, const Sell& A, const double* dinv, const float* din
                const vem_solve_opts& o, int& expect, InnerGraph& g64, InnerGraph& g32) {
   hipStream_t s = h->stream;
   const bool mixed = o.precision == VEM_MIXED;
+  const bool pipe32 = mixed && o.inner_maxit <= kBlindInner;
   const bool graphs = o.use_graphs != 0;
   PcgWork w{graphs ? h->pxw.p : x, h->pr, h->pz, h->ps, h->pp, h->pw0, h->pw1, dinv};
   // FP32 vectors live in the first half of the FP64 work buffers
   PcgWork32 w32{h->px32, (float*)h->pr.p, (float*)h->pz.p, (float*)h->ps.p, (float*)h->pp.p, (float*)h->pw0.p,
                 (float*)h->pw1.p, dinv32};
-  hipGraphExec_t exec = graphs ? inner_graph(h, A, w, w32, mixed, mixed ? g32 : g64) : nullptr;
-  if (mixed)
+  hipGraphExec_t exec = graphs ? inner_graph(h, A, w, w32, mixed, pipe32, mixed ? g32 : g64) : nullptr;
+  if (pipe32)
+    launch_pcg_init32p(s, A, w32, b, h->pcg, o.inner_tol, o.inner_maxit, h->pcgpart);
+  else if (mixed)
     launch_pcg_init32(s, A, w32, b, h->pcg, o.inner_tol, o.inner_maxit, h->pcgpart);
   else
     launch_pcg_init(s, A, w, b, h->pcg, o.inner_tol, o.inner_maxit, h->pcgpart);
   check_launch();
   auto one = [&](int i) {
     if (mixed)
-      launch_pcg_iter32(s, i, A, w32, h->pcg, h->pcgpart);
+      iter32(s, pipe32, i, A, w32, h->pcg, h->pcgpart);
     else
       launch_pcg_iter(s, i, A, w, h->pcg, h->pcgpart);
   };
@@ -1337,10 +1352,12 @@ vem_status vem_time_kernel(vem_handle h, int which, int reps, double* avg_ms, do
   if (!h || !avg_ms || reps < 1) return VEM_EINVAL;
   return guarded(h, [&] {
     require_disc(h);
-    VEM_REQUIRE(which >= VEM_KERNEL_SPMV && which <= VEM_KERNEL_CG_REG32, VEM_EINVAL, "unknown kernel");
-    ensure_values(h, which == VEM_KERNEL_CG_SCHUR || which == VEM_KERNEL_CG_SCHUR32,
-                  which == VEM_KERNEL_CG_REG || which == VEM_KERNEL_CG_REG32,
-                  which == VEM_KERNEL_CG_SCHUR32 || which == VEM_KERNEL_CG_REG32, h->gamma_A);
+    VEM_REQUIRE(which >= VEM_KERNEL_SPMV && which <= VEM_KERNEL_CG_REG32P, VEM_EINVAL, "unknown kernel");
+    const bool pipe32 = which == VEM_KERNEL_CG_SCHUR32P || which == VEM_KERNEL_CG_REG32P;
+    const bool f32 = pipe32 || which == VEM_KERNEL_CG_SCHUR32 || which == VEM_KERNEL_CG_REG32;
+    const bool schur =
+        which == VEM_KERNEL_CG_SCHUR || which == VEM_KERNEL_CG_SCHUR32 || which == VEM_KERNEL_CG_SCHUR32P;
+    ensure_values(h, which != VEM_KERNEL_SPMV && schur, which != VEM_KERNEL_SPMV && !schur, f32, h->gamma_A);
     hipStream_t s = h->stream;
     ensure_workspace(h, std::max(1, h->ws_m));
     const int64_t Nu = h->L.Nu, Np = h->L.Np, N = Nu + Np;
@@ -1356,8 +1373,6 @@ vem_status vem_time_kernel(vem_handle h, int which, int reps, double* avg_ms, do
         VEM_HIP(hipEventRecord(e1, s));
         b = 12.0 * h->K.nnz + 8.0 * N + 8.0 * N;  // matrix, x once, y once
       } else {
-        const bool schur = which == VEM_KERNEL_CG_SCHUR || which == VEM_KERNEL_CG_SCHUR32;
-        const bool f32 = which == VEM_KERNEL_CG_SCHUR32 || which == VEM_KERNEL_CG_REG32;
         Sell& A = schur ? h->Ss : h->As;
         const Csr& C = schur ? h->S : h->A;
         const double* dinv = schur ? h->dSinv.p : h->dAinv.p;
@@ -1369,7 +1384,16 @@ vem_status vem_time_kernel(vem_handle h, int which, int reps, double* avg_ms, do
         PcgWork32 w32{h->px32, (float*)h->pr.p, (float*)h->pz.p, (float*)h->ps.p, (float*)h->pp.p,
                       (float*)h->pw0.p, (float*)h->pw1.p, dinv32};
         // tol = 0: the solve never stops, every timed launch does a full iteration
-        if (f32) {
+        if (pipe32) {
+          launch_pcg_init32p(s, A, w32, rhs, h->pcg, 0.0, INT_MAX, h->pcgpart);
+          launch_pcg_iter32p(s, 0, A, w32, h->pcg, h->pcgpart);
+          launch_pcg_iter32p(s, 1, A, w32, h->pcg, h->pcgpart);
+          VEM_HIP(hipEventRecord(e0, s));
+          for (int r = 0; r < reps; ++r) launch_pcg_iter32p(s, 2 + r, A, w32, h->pcg, h->pcgpart);
+          VEM_HIP(hipEventRecord(e1, s));
+          // as the FP64 iteration below, with 4-byte values and vector elements
+          b = 8.0 * C.nnz + 4.0 * C.rows * 13.0;
+        } else if (f32) {
           launch_pcg_init32(s, A, w32, rhs, h->pcg, 0.0, INT_MAX, h->pcgpart);
           launch_pcg_iter32(s, 0, A, w32, h->pcg, h->pcgpart);
           launch_pcg_iter32(s, 1, A, w32, h->pcg, h->pcgpart);

@@ -417,7 +417,9 @@ void launch_col_scale(hipStream_t s, Sell& A, const double* dinv) {
 void launch_col_scale32(hipStream_t s, Sell& A, const double* dinv, float* dinv32) {
   if (A.nnz <= 0) return;
   A.val32.alloc(A.nnz);
+  A.val32_cs.alloc(A.nnz);
   k_to_f32<<<stream_grid(A.nnz), kThreads, 0, s>>>(A.nnz, A.val, A.val32);
+  k_to_f32<<<stream_grid(A.nnz), kThreads, 0, s>>>(A.nnz, A.val_cs, A.val32_cs);
   k_to_f32<<<stream_grid(A.rows), kThreads, 0, s>>>(A.rows, dinv, dinv32);
 }
 

@@ -171,6 +171,9 @@ __device__ inline T sell_row(const SellViewT<T>& A, int64_t row, const X* __rest
 
 static SellView view_cs(const Sell& A) { return {A.rows, A.slice_ptr, A.slice_len, A.col, A.val_cs}; }
 static SellViewT<float> view32(const Sell& A) { return {A.rows, A.slice_ptr, A.slice_len, A.col, A.val32}; }
+static SellViewT<float> view_cs32(const Sell& A) {
+  return {A.rows, A.slice_ptr, A.slice_len, A.col, A.val32_cs};
+}
 
 // Grid of the inner-CG kernels: one resident round at most (kPcgMaxThreads threads);
 // larger systems loop over rows.

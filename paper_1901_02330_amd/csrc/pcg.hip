@@ -152,46 +152,67 @@ PcgViewT<T> pview(const PcgWorkT<T>& w) {
   return {w.x, w.r, w.z, w.s, w.p, w.w0, w.w1, w.dinv};
 }
 
-template <int kBlock, bool kShort>
-void pcg_init_as(hipStream_t s, const Sell& A, const PcgWork& w, const double* b, PcgState* st, double tol, int maxit,
-                 double* part) {
-  k_ppcg_init<double, kBlock, kShort><<<pcg_grid(A.rows, kBlock), kBlock, 0, s>>>(view_cs(A), pview(w), b, st,
-                                                                                   tol * tol, maxit, part);
+template <typename T, int kBlock, bool kShort>
+void pcg_init_as(hipStream_t s, SellViewT<T> Av, const PcgWorkT<T>& w, const double* b, PcgState* st, double tol,
+                 int maxit, double* part) {
+  k_ppcg_init<T, kBlock, kShort><<<pcg_grid(Av.rows, kBlock), kBlock, 0, s>>>(Av, pview(w), b, st, tol * tol, maxit,
+                                                                              part);
 }
 
-template <int kBlock, bool kShort>
-void pcg_iter_as(hipStream_t s, int i, const Sell& A, const PcgWork& w, PcgState* st, double* part) {
-  const int P = pcg_grid(A.rows, kBlock);
+template <typename T, int kBlock, bool kShort>
+void pcg_iter_as(hipStream_t s, int i, SellViewT<T> Av, const PcgWorkT<T>& w, PcgState* st, double* part) {
+  const int P = pcg_grid(Av.rows, kBlock);
   if (i == 0)
-    k_ppcg_iter<double, true, kBlock, kShort><<<P, kBlock, 0, s>>>(0, view_cs(A), pview(w), st, part);
+    k_ppcg_iter<T, true, kBlock, kShort><<<P, kBlock, 0, s>>>(0, Av, pview(w), st, part);
   else
-    k_ppcg_iter<double, false, kBlock, kShort><<<P, kBlock, 0, s>>>(i & 1, view_cs(A), pview(w), st, part);
+    k_ppcg_iter<T, false, kBlock, kShort><<<P, kBlock, 0, s>>>(i & 1, Av, pview(w), st, part);
 }
-
-}  // namespace
 
 // Launch shape: 1024-thread blocks when every row has a thread, 256-thread blocks when threads
 // loop over rows (their barriers hold fewer waves).  One-row-per-thread launches take the
 // short-row product when no slice is longer than kShortRow (measured on the 64^3 cube: S, 7 per
 // row, 10.95 -> 10.53 us per iteration; rows of 11-13 entries were slower with it, 31.5 ->
 // 33.9 us for A_gamma, so longer rows keep the plain loop).
+template <typename T>
+void pcg_init_sel(hipStream_t s, const Sell& A, SellViewT<T> Av, const PcgWorkT<T>& w, const double* b,
+                  PcgState* st, double tol, int maxit, double* part) {
+  if (A.rows > kPcgMaxThreads)  // threads loop over rows
+    pcg_init_as<T, 256, false>(s, Av, w, b, st, tol, maxit, part);
+  else if (A.max_len <= kShortRow)
+    pcg_init_as<T, 1024, true>(s, Av, w, b, st, tol, maxit, part);
+  else
+    pcg_init_as<T, 1024, false>(s, Av, w, b, st, tol, maxit, part);
+}
+
+template <typename T>
+void pcg_iter_sel(hipStream_t s, int i, const Sell& A, SellViewT<T> Av, const PcgWorkT<T>& w, PcgState* st,
+                  double* part) {
+  if (A.rows > kPcgMaxThreads)
+    pcg_iter_as<T, 256, false>(s, i, Av, w, st, part);
+  else if (A.max_len <= kShortRow)
+    pcg_iter_as<T, 1024, true>(s, i, Av, w, st, part);
+  else
+    pcg_iter_as<T, 1024, false>(s, i, Av, w, st, part);
+}
+
+}  // namespace
+
 void launch_pcg_init(hipStream_t s, const Sell& A, const PcgWork& w, const double* b, PcgState* st, double tol,
                      int maxit, double* part) {
-  if (A.rows > kPcgMaxThreads)  // threads loop over rows
-    pcg_init_as<256, false>(s, A, w, b, st, tol, maxit, part);
-  else if (A.max_len <= kShortRow)
-    pcg_init_as<1024, true>(s, A, w, b, st, tol, maxit, part);
-  else
-    pcg_init_as<1024, false>(s, A, w, b, st, tol, maxit, part);
+  pcg_init_sel<double>(s, A, view_cs(A), w, b, st, tol, maxit, part);
 }
 
 void launch_pcg_iter(hipStream_t s, int i, const Sell& A, const PcgWork& w, PcgState* st, double* part) {
-  if (A.rows > kPcgMaxThreads)  // threads loop over rows
-    pcg_iter_as<256, false>(s, i, A, w, st, part);
-  else if (A.max_len <= kShortRow)
-    pcg_iter_as<1024, true>(s, i, A, w, st, part);
-  else
-    pcg_iter_as<1024, false>(s, i, A, w, st, part);
+  pcg_iter_sel<double>(s, i, A, view_cs(A), w, st, part);
+}
+
+void launch_pcg_init32p(hipStream_t s, const Sell& A, const PcgWork32& w, const double* b, PcgState* st, double tol,
+                        int maxit, double* part) {
+  pcg_init_sel<float>(s, A, view_cs32(A), w, b, st, tol, maxit, part);
+}
+
+void launch_pcg_iter32p(hipStream_t s, int i, const Sell& A, const PcgWork32& w, PcgState* st, double* part) {
+  pcg_iter_sel<float>(s, i, A, view_cs32(A), w, st, part);
 }
 
 }  // namespace vem

@@ -143,6 +143,7 @@ struct Sell {
   DBuf<double> val;
   DBuf<double> val_cs;   // column-scaled copy A D^{-1} (inner CG matrices only)
   DBuf<float> val32;     // FP32 rounding of val (mixed-precision inner solves)
+  DBuf<float> val32_cs;  // FP32 rounding of val_cs (mixed-precision pipelined inner solves)
 };
 // SELL copies of `count` (<= 3) CSR matrices, with one host synchronisation for all of
 // their padded sizes (uses tmp.i64[2m], tmp.i64[2m+1] for matrix m and slots 0..count-1).
@@ -303,6 +304,10 @@ void launch_col_scale32(hipStream_t s, Sell& A, const double* dinv, float* dinv3
 void launch_pcg_init32(hipStream_t s, const Sell& A, const PcgWork32& w, const double* b, PcgState* st, double tol,
                        int maxit, double* part);
 void launch_pcg_iter32(hipStream_t s, int i, const Sell& A, const PcgWork32& w, PcgState* st, double* part);
+// the pipelined iteration in FP32 (vectors and column-scaled values; dot products in FP64)
+void launch_pcg_init32p(hipStream_t s, const Sell& A, const PcgWork32& w, const double* b, PcgState* st, double tol,
+                        int maxit, double* part);
+void launch_pcg_iter32p(hipStream_t s, int i, const Sell& A, const PcgWork32& w, PcgState* st, double* part);
 void launch_to_f64(hipStream_t s, int64_t n, const float* x, double* y);
 
 // host utilities

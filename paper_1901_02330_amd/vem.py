@@ -281,7 +281,8 @@ class Solver:
 
     def time_kernel(self, which="cg_schur", reps=50):
         """Mean duration (ms) of one launch of a hot kernel, timed with HIP events, and its algorithmic bytes."""
-        code = {"spmv": 0, "cg_schur": 1, "cg_reg": 2, "cg_schur32": 3, "cg_reg32": 4}[which]
+        code = {"spmv": 0, "cg_schur": 1, "cg_reg": 2, "cg_schur32": 3, "cg_reg32": 4, "cg_schur32p": 5,
+                "cg_reg32p": 6}[which]
         ms, nb = c_double(), c_double()
         self._check(self.lib.vem_time_kernel(self.h, code, int(reps), byref(ms), byref(nb)))
         return ms.value, nb.value

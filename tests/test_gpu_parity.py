@@ -222,6 +222,32 @@ def test_mixed_precision_inner_solves(precond):
     assert rel(xg[d["Nu"]:], x[d["Nu"]:]) <= 1e-7
 
 
+@pytest.mark.parametrize("precond,cap,inner_tol", [("schur", 24, 1e-12), ("reg", 64, 1e-1)])
+def test_mixed_precision_capped_inner_solves(precond, cap, inner_tol):
+    """Capped FP32 inner solves take the pipelined iteration (FP32 vectors and column-scaled
+    values, FP64 dot products); the FP64 outer solve still meets its tolerance and matches the
+    oracle's direct solve to the tolerance times the conditioning."""
+    _say("mixed capped", precond, cap)
+    m = cube_mesh(6, 7, 5)
+    nu = 1.0 / lognormal_field(210, 2.0, 0)
+    s = gpu_solver(m, nu=nu, rhs=SineSolution())
+    kw = dict(precond=precond, tol=1e-10, maxit=3000, inner_tol=inner_tol, inner_maxit=cap)
+    u, p, info = s.solve(precision="mixed", **kw)
+    _, _, info64 = s.solve(**kw)
+    assert info["converged"], info
+    assert info["inner_iterations"] <= cap * (info["iterations"] + 1)
+    d = discretize(m, nu=nu, rhs=SineSolution())
+    xg = np.concatenate([u.cpu().numpy(), p.cpu().numpy()])
+    berr = np.linalg.norm(d["b"] - d["K"] @ xg) / np.linalg.norm(d["b"])
+    assert berr <= 1.01e-10
+    x = direct_solve(d["K"], d["b"])
+    _say(info, info64["iterations"], berr, rel(xg[: d["Nu"]], x[: d["Nu"]]), rel(xg[d["Nu"]:], x[d["Nu"]:]))
+    assert rel(xg[: d["Nu"]], x[: d["Nu"]]) <= 1e-7
+    assert rel(xg[d["Nu"]:], x[d["Nu"]:]) <= 1e-7
+    # FP32 inner solves should cost few extra outer iterations
+    assert info["iterations"] <= 1.5 * info64["iterations"] + 5
+
+
 @pytest.mark.parametrize("cap", [5000, 20])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_graph_replays_match_eager(precision, cap):
