@@ -85,9 +85,11 @@ enum { VEM_BC_PRESSURE = 0, VEM_BC_FLUX = 1 };
 /* Arithmetic of the inner preconditioner solves.  VEM_FP64: everything in
  * FP64.  VEM_MIXED: the inner Jacobi-CG of either block preconditioner runs
  * with FP32 vectors and FP32 matrix values (dot products accumulated in
- * FP64); the outer FGMRES, its residuals, Gram-Schmidt and all assembly stay
- * FP64, so the outer tolerance is met in FP64 (flexible GMRES absorbs the
- * FP32 preconditioner as it absorbs any inexact inner solve). */
+ * FP64): the one-kernel pipelined iteration when inner_maxit <= 64, the
+ * classical two-kernel one otherwise.  The outer FGMRES, its residuals,
+ * Gram-Schmidt and all assembly stay FP64, so the outer tolerance is met in
+ * FP64 (flexible GMRES absorbs the FP32 preconditioner as it absorbs any
+ * inexact inner solve). */
 enum { VEM_FP64 = 0, VEM_MIXED = 1 };
 
 /* matrices for vem_export_csr */
