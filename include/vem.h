@@ -92,6 +92,13 @@ enum { VEM_BC_PRESSURE = 0, VEM_BC_FLUX = 1 };
  * inexact inner solve). */
 enum { VEM_FP64 = 0, VEM_MIXED = 1 };
 
+/* Form of the inner Jacobi-CG.  VEM_INNER_PIPELINED (the default): one kernel per
+ * iteration (Ghysels-Vanroose recurrences).  VEM_INNER_CLASSICAL: the textbook
+ * recurrences in two kernels per iteration; slower, but its residual stays closer to
+ * the true one on very ill-conditioned blocks (the paper's order-3 element, where
+ * the pipelined recurrences stall the outer solve). */
+enum { VEM_INNER_PIPELINED = 0, VEM_INNER_CLASSICAL = 1 };
+
 /* matrices for vem_export_csr */
 enum { VEM_MAT_K = 0, VEM_MAT_SCHUR = 1, VEM_MAT_REG = 2 };
 
@@ -128,6 +135,7 @@ typedef struct {
                           by up to 7 iterations, as graphs run 8 at a time).  Default 0: on
                           gfx950 each replay boundary leaves the GPU idle for about 8 us,
                           more than the host's launch cost it saves */
+  int32_t inner_form;  /* VEM_INNER_PIPELINED (default) or VEM_INNER_CLASSICAL */
 } vem_solve_opts;
 
 typedef struct {
@@ -141,7 +149,7 @@ typedef struct {
 
 /* Fill opts with defaults: Block-Schur, m = 30, maxit = 5000, tol = 1e-8,
  * inner_tol = 1e-6, inner_maxit = 5000, inner_check = 32, gamma = h^2, FP64,
- * graphs off. */
+ * graphs off, pipelined inner CG. */
 void vem_solve_opts_default(vem_solve_opts* opts);
 
 /* Create a handle bound to the current HIP device and to `stream`

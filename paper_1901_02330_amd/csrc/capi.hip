@@ -485,19 +485,29 @@ void ensure_workspace(vem_handle h, int m) {
   h->ws_m = m;
 }
 
-// FP32 inner iteration: pipelined (pipe) or classical
-void iter32(hipStream_t s, bool pipe, int i, const Sell& A, const PcgWork32& w32, PcgState* st, double* part) {
-  if (pipe)
-    launch_pcg_iter32p(s, i, A, w32, st, part);
-  else
-    launch_pcg_iter32(s, i, A, w32, st, part);
+// The four inner iterations: FP64 pipelined (the default), FP64 classical, FP32 classical
+// (mixed precision, uncapped) and FP32 pipelined (mixed precision, capped).
+enum InnerMode { kPipe64 = 0, kClassic64 = 1, kClassic32 = 2, kPipe32 = 3 };
+
+void inner_iter(hipStream_t s, InnerMode mode, int i, const Sell& A, const PcgWork& w, const PcgWork32& w32,
+                PcgState* st, double* part) {
+  switch (mode) {
+    case kPipe64: launch_pcg_iter(s, i, A, w, st, part); break;
+    case kClassic64: launch_pcg_iter64c(s, i, A, w, st, part); break;
+    case kClassic32: launch_pcg_iter32(s, i, A, w32, st, part); break;
+    case kPipe32: launch_pcg_iter32p(s, i, A, w32, st, part); break;
+  }
 }
 
 // The graph of kGraphIters iterations (2 .. 2+kGraphIters-1) for this matrix and precision,
 // captured on the private stream on first use or when a referenced buffer moved.
-hipGraphExec_t inner_graph(vem_handle h, const Sell& A, const PcgWork& w, const PcgWork32& w32, bool mixed,
-                           bool pipe32, InnerGraph& g) {
-  const void* vals = !mixed ? (const void*)A.val_cs.p : pipe32 ? (const void*)A.val32_cs.p : (const void*)A.val32.p;
+hipGraphExec_t inner_graph(vem_handle h, const Sell& A, const PcgWork& w, const PcgWork32& w32, InnerMode mode,
+                           InnerGraph& g) {
+  const bool mixed = mode == kClassic32 || mode == kPipe32;
+  const void* vals = mode == kPipe64      ? (const void*)A.val_cs.p
+                     : mode == kClassic64 ? (const void*)A.val.p
+                     : mode == kPipe32    ? (const void*)A.val32_cs.p
+                                          : (const void*)A.val32.p;
   const void* key[8] = {vals, A.col.p, h->pr.p, h->pcg.p,
                         mixed ? (const void*)h->px32.p : (const void*)w.x, mixed ? (const void*)w32.dinv : w.dinv,
                         (const void*)(intptr_t)A.rows, (const void*)(intptr_t)A.nnz};
@@ -508,10 +518,7 @@ hipGraphExec_t inner_graph(vem_handle h, const Sell& A, const PcgWork& w, const 
   hipGraph_t graph = nullptr;
   try {
     for (int t = 0; t < kGraphIters; ++t) {
-      if (mixed)
-        iter32(h->cap, pipe32, 2 + t, A, w32, h->pcg, h->pcgpart);
-      else
-        launch_pcg_iter(h->cap, 2 + t, A, w, h->pcg, h->pcgpart);
+      inner_iter(h->cap, mode, 2 + t, A, w, w32, h->pcg, h->pcgpart);
     }
   } catch (...) {
     (void)hipStreamEndCapture(h->cap, &graph);
@@ -529,8 +536,9 @@ hipGraphExec_t inner_graph(vem_handle h, const Sell& A, const PcgWork& w, const 
   return g.exec;
 }
 
-// Inner Jacobi-CG: x ~ A^{-1} b to inner_tol (pipelined in FP64; in FP32 pipelined when the
-// iterations are capped at kBlindInner or fewer, classical otherwise: over hundreds of FP32
+// Inner Jacobi-CG: x ~ A^{-1} b to inner_tol.  FP64: pipelined, or classical on request (its
+// residual stays closer to the true one on very ill-conditioned blocks).  FP32: pipelined when
+// the iterations are capped at kBlindInner or fewer, classical otherwise (over hundreds of FP32
 // iterations the pipelined recurrences lose positivity, while a capped solve that meets that
 // guard simply stops with its iterate, which flexible GMRES accepts like any inexact solve).
 // Iterations are enqueued in chunks between convergence checks; the first
@@ -544,26 +552,23 @@ void inner_pcg(vem_handle h, const Sell& A, const double* dinv, const float* din
                const vem_solve_opts& o, int& expect, InnerGraph& g64, InnerGraph& g32) {
   hipStream_t s = h->stream;
   const bool mixed = o.precision == VEM_MIXED;
-  const bool pipe32 = mixed && o.inner_maxit <= kBlindInner;
+  const bool classical = o.inner_form == VEM_INNER_CLASSICAL;
+  const InnerMode mode = !mixed ? (classical ? kClassic64 : kPipe64)
+                                : (o.inner_maxit <= kBlindInner && !classical ? kPipe32 : kClassic32);
   const bool graphs = o.use_graphs != 0;
   PcgWork w{graphs ? h->pxw.p : x, h->pr, h->pz, h->ps, h->pp, h->pw0, h->pw1, dinv};
   // FP32 vectors live in the first half of the FP64 work buffers
   PcgWork32 w32{h->px32, (float*)h->pr.p, (float*)h->pz.p, (float*)h->ps.p, (float*)h->pp.p, (float*)h->pw0.p,
                 (float*)h->pw1.p, dinv32};
-  hipGraphExec_t exec = graphs ? inner_graph(h, A, w, w32, mixed, pipe32, mixed ? g32 : g64) : nullptr;
-  if (pipe32)
-    launch_pcg_init32p(s, A, w32, b, h->pcg, o.inner_tol, o.inner_maxit, h->pcgpart);
-  else if (mixed)
-    launch_pcg_init32(s, A, w32, b, h->pcg, o.inner_tol, o.inner_maxit, h->pcgpart);
-  else
-    launch_pcg_init(s, A, w, b, h->pcg, o.inner_tol, o.inner_maxit, h->pcgpart);
+  hipGraphExec_t exec = graphs ? inner_graph(h, A, w, w32, mode, mixed ? g32 : g64) : nullptr;
+  switch (mode) {
+    case kPipe64: launch_pcg_init(s, A, w, b, h->pcg, o.inner_tol, o.inner_maxit, h->pcgpart); break;
+    case kClassic64: launch_pcg_init64c(s, A, w, b, h->pcg, o.inner_tol, h->pcgpart); break;
+    case kClassic32: launch_pcg_init32(s, A, w32, b, h->pcg, o.inner_tol, o.inner_maxit, h->pcgpart); break;
+    case kPipe32: launch_pcg_init32p(s, A, w32, b, h->pcg, o.inner_tol, o.inner_maxit, h->pcgpart); break;
+  }
   check_launch();
-  auto one = [&](int i) {
-    if (mixed)
-      iter32(s, pipe32, i, A, w32, h->pcg, h->pcgpart);
-    else
-      launch_pcg_iter(s, i, A, w, h->pcg, h->pcgpart);
-  };
+  auto one = [&](int i) { inner_iter(s, mode, i, A, w, w32, h->pcg, h->pcgpart); };
   if (o.inner_maxit <= kBlindInner) {
     // A small cap: enqueue every iteration without looking at the state.  Once the
     // stop test fires, the remaining launches return at once; the iteration count is
@@ -749,6 +754,7 @@ void vem_solve_opts_default(vem_solve_opts* o) {
   o->gamma = 0.0;
   o->precision = VEM_FP64;
   o->use_graphs = 0;
+  o->inner_form = VEM_INNER_PIPELINED;
 }
 
 vem_status vem_create(vem_handle* out, void* stream) {
@@ -1453,6 +1459,8 @@ static vem_status solve_impl(vem_handle h, const vem_solve_opts* opts, const dou
     VEM_REQUIRE(o.precond >= VEM_PREC_SCHUR && o.precond <= VEM_PREC_NONE, VEM_EINVAL, "unknown preconditioner");
     VEM_REQUIRE(o.inner_tol > 0 && o.inner_maxit >= 1, VEM_EINVAL, "inner_tol must be > 0 and inner_maxit >= 1");
     VEM_REQUIRE(o.precision == VEM_FP64 || o.precision == VEM_MIXED, VEM_EINVAL, "unknown precision mode");
+    VEM_REQUIRE(o.inner_form == VEM_INNER_PIPELINED || o.inner_form == VEM_INNER_CLASSICAL, VEM_EINVAL,
+                "unknown inner CG form");
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = h->stream;
     const int m = o.restart;

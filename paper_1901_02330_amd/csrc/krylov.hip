@@ -183,8 +183,8 @@ __global__ void k_sum(int64_t n, const double* __restrict__ x, double* partials)
 // recurrences do not guarantee once FP32 rounding meets an ill-conditioned
 // operator.  Two kernels per iteration; the direction update p = z + beta p
 // is fused into the product through two p buffers, and every kernel sums the
-// partials the previous one left.  Vectors and matrix values in T (FP32),
-// dot products and scalars in FP64.
+// partials the previous one left.  Vectors and matrix values in T (FP32 for mixed
+// precision, FP64 for the classical inner form), dot products and scalars in FP64.
 //   [spmv]   rho_k, beta = rho_k / rho_{k-1}; stop test; p_k = z + beta p_{k-1}; q = A p_k; partials p_k.q
 //   [update] alpha = rho_k / p_k.q; x += alpha p_k; r -= alpha q; z = D^{-1} r; partials rho_{k+1}
 template <typename T>
@@ -431,6 +431,22 @@ void launch_pcg_init32(hipStream_t s, const Sell& A, const PcgWork32& w, const d
                        int maxit, double* part) {
   (void)maxit;
   k_cg_init<float><<<pcg_grid(A.rows), kPcgThreads, 0, s>>>(A.rows, b, w.dinv, w.x, w.r, w.z, st, tol * tol, part);
+}
+
+// The classical iteration in FP64 on the unscaled values (same work layout as the FP32 one below)
+void launch_pcg_init64c(hipStream_t s, const Sell& A, const PcgWork& w, const double* b, PcgState* st, double tol,
+                        double* part) {
+  k_cg_init<double><<<pcg_grid(A.rows), kPcgThreads, 0, s>>>(A.rows, b, w.dinv, w.x, w.r, w.z, st, tol * tol, part);
+}
+
+void launch_pcg_iter64c(hipStream_t s, int i, const Sell& A, const PcgWork& w, PcgState* st, double* part) {
+  const int P = pcg_grid(A.rows);
+  double* prho = part;  // 2 x P slots
+  double* ppq = part + 2 * (size_t)P;
+  double* pold = (i & 1) ? w.p : w.s;
+  double* pnew = (i & 1) ? w.s : w.p;
+  k_cg_spmv<double><<<P, kPcgThreads, 0, s>>>(i, view(A), w.z, pold, pnew, w.w0, st, prho, ppq);
+  k_cg_update<double><<<P, kPcgThreads, 0, s>>>(i, A.rows, w.x, w.r, w.z, w.w0, pnew, w.dinv, st, prho, ppq);
 }
 
 // FP32 work layout: r, z as named; s and p hold the two direction buffers, w0 holds A p

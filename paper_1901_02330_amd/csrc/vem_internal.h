@@ -304,6 +304,10 @@ void launch_col_scale32(hipStream_t s, Sell& A, const double* dinv, float* dinv3
 void launch_pcg_init32(hipStream_t s, const Sell& A, const PcgWork32& w, const double* b, PcgState* st, double tol,
                        int maxit, double* part);
 void launch_pcg_iter32(hipStream_t s, int i, const Sell& A, const PcgWork32& w, PcgState* st, double* part);
+// the classical iteration in FP64 (unscaled values; two kernels per iteration)
+void launch_pcg_init64c(hipStream_t s, const Sell& A, const PcgWork& w, const double* b, PcgState* st, double tol,
+                        double* part);
+void launch_pcg_iter64c(hipStream_t s, int i, const Sell& A, const PcgWork& w, PcgState* st, double* part);
 // the pipelined iteration in FP32 (vectors and column-scaled values; dot products in FP64)
 void launch_pcg_init32p(hipStream_t s, const Sell& A, const PcgWork32& w, const double* b, PcgState* st, double tol,
                         int maxit, double* part);

@@ -43,7 +43,7 @@ class SolveOpts(ctypes.Structure):
         ("precond", ctypes.c_int32), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32),
         ("use_x0", ctypes.c_int32), ("tol", c_double), ("inner_tol", c_double),
         ("inner_maxit", ctypes.c_int32), ("inner_check", ctypes.c_int32), ("gamma", c_double),
-        ("precision", ctypes.c_int32), ("use_graphs", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("use_graphs", ctypes.c_int32), ("inner_form", ctypes.c_int32),
     ]
 
 
@@ -217,7 +217,8 @@ class Solver:
             self.set_rhs(fv, gv)
 
     def solve(self, precond="schur", tol=1e-8, restart=30, maxit=5000, inner_tol=1e-6, inner_maxit=5000,
-              inner_check=32, gamma=0.0, x0=None, precision="fp64", rhs=None, graphs=False):
+              inner_check=32, gamma=0.0, x0=None, precision="fp64", rhs=None, graphs=False,
+              inner_form="pipelined"):
         t = self.torch
         sz = self.sizes()
         o = SolveOpts()
@@ -228,6 +229,7 @@ class Solver:
         o.gamma = float(gamma)
         o.precision = {"fp64": 0, "mixed": 1}[precision]
         o.use_graphs = 1 if graphs else 0
+        o.inner_form = {"pipelined": 0, "classical": 1}[inner_form]
         if x0 is not None:
             u = self._dev(x0[0], t.float64).clone()
             p = self._dev(x0[1], t.float64).clone()

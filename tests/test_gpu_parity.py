@@ -119,6 +119,27 @@ def test_solve_matches_oracle(case, precond):
     assert np.abs(r).max() <= 1e-10 * np.abs(d["F"]).max()
 
 
+@pytest.mark.parametrize("precond", ["schur", "reg"])
+def test_solve_classical_inner_form(precond):
+    """The classical (two-kernel) FP64 inner CG: full solves against the oracle's direct solve, and
+    the same outer iteration count as the pipelined form within a few iterations."""
+    _say("solve classical inner", precond)
+    m = cube_mesh(6, 7, 5)
+    nu = 1.0 / lognormal_field(210, 2.0, 0)
+    s = gpu_solver(m, nu=nu, rhs=SineSolution())
+    kw = dict(precond=precond, tol=1e-13, maxit=3000, inner_tol=1e-10)
+    u, p, info = s.solve(inner_form="classical", **kw)
+    _, _, info_p = s.solve(**kw)
+    assert info["converged"], info
+    d = discretize(m, nu=nu, rhs=SineSolution())
+    x = direct_solve(d["K"], d["b"])
+    u, p = u.cpu().numpy(), p.cpu().numpy()
+    _say(info, info_p["iterations"], rel(u, x[: d["Nu"]]), rel(p, x[d["Nu"]:]))
+    assert rel(u, x[: d["Nu"]]) <= 1e-10
+    assert rel(p, x[d["Nu"]:]) <= 1e-10
+    assert abs(info["iterations"] - info_p["iterations"]) <= 3
+
+
 def test_patch_test_exact_on_gpu():
     _say("patch")
     m = voronoi_mesh(60, seed=8)
