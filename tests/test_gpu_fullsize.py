@@ -43,9 +43,11 @@ def test_cube64_lognormal_matrix_rhs_and_solves():
     assert np.abs(G.data - O.data).max() <= 1e-13 * np.abs(O.data).max()
     b = s.rhs().cpu().numpy()
     assert np.abs(b - d["b"]).max() <= 1e-13 * np.abs(d["b"]).max()
-    # the benchmark's settings: Block-Schur with 24 inner iterations, Block-Reg inner tolerance 1e-1
-    for prec, kw in (("schur", dict(inner_tol=1e-12, inner_maxit=24)), ("reg", dict(inner_tol=1e-1))):
-        _say("solve", prec)
+    # the benchmark's settings: Block-Schur with 24 inner iterations, Block-Reg inner tolerance 1e-1;
+    # and the capped Block-Schur with FP32 inner iterations (the pipelined FP32 form)
+    for prec, kw in (("schur", dict(inner_tol=1e-12, inner_maxit=24)), ("reg", dict(inner_tol=1e-1)),
+                     ("schur", dict(inner_tol=1e-12, inner_maxit=24, precision="mixed"))):
+        _say("solve", prec, kw)
         u, p, info = s.solve(prec, tol=1e-8, maxit=5000, **kw)
         assert info["converged"], info
         x = np.concatenate([u.cpu().numpy(), p.cpu().numpy()])
