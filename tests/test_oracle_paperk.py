@@ -115,6 +115,8 @@ class _Poly:
         v = 0.5 + x - 2 * y + 0.3 * z + x * y - 0.5 * z * z
         if self.k >= 2:
             v = v + x * y * z + 0.25 * y**3
+        if self.k >= 3:
+            v = v + 0.2 * x * x * y * y - 0.1 * x * z**3
         return v
 
     pD = p
@@ -124,6 +126,8 @@ class _Poly:
         g = np.stack([1 + y + 0 * x, -2 + x, 0.3 - z], -1)
         if self.k >= 2:
             g = g + np.stack([y * z, x * z + 0.75 * y**2, x * y], -1)
+        if self.k >= 3:
+            g = g + np.stack([0.4 * x * y * y - 0.1 * z**3, 0.4 * x * x * y, -0.3 * x * z * z], -1)
         return -g
 
     def f(self, X):
@@ -131,15 +135,20 @@ class _Poly:
         v = 1.0 + 0 * y
         if self.k >= 2:
             v = v - 1.5 * y
+        if self.k >= 3:
+            x, z = X[..., 0], X[..., 2]
+            v = v - 0.4 * y * y - 0.4 * x * x + 0.6 * x * z
         return v
 
 
-@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("k", [1, 2, 3])
 @pytest.mark.parametrize("mesh", ["cube", "voronoi"])
 def test_patch_test(k, mesh):
     m = cube_mesh(2, 3, 2) if mesh == "cube" else voronoi_mesh(12, seed=3)
     sol = _Poly(k)
-    d = discretize_paper(m, rhs=sol, k=k)
+    # boundary data p_D in P_{k+1} against face monomials of degree k: the load rule must be exact
+    # to degree 2k + 1, i.e. k + 1 points per direction; k + 2 leaves one to spare
+    d = discretize_paper(m, rhs=sol, k=k, nq_load=max(3, k + 2))
     x = direct_solve(d["K"], d["b"])
     ue, pe = interpolate_paper(m, d, sol)
     assert np.abs(x[: d["Nu"]] - ue).max() < 1e-10
