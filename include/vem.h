@@ -235,8 +235,11 @@ vem_status vem_solve(vem_handle h, const vem_solve_opts* opts, double* u, double
 
 /* Solve K x = rhs for a caller-supplied right-hand side (device, n
  * doubles) instead of the assembled [g; -F]; otherwise as vem_solve.  K is
- * symmetric, so this is also the adjoint solve K^T lambda = dJ/dx of a
- * functional J of the solution (same operator, same preconditioners). */
+ * symmetric (eq. mod_prob_eqDisc in the symmetric form above), so this is also
+ * the adjoint solve K^T lambda = dJ/dx of a functional J of the solution
+ * (same operator, same preconditioners).  Pressure boundary data only:
+ * VEM_EINVAL with VEM_BC_FLUX, where K is singular and its prescribed rows fix
+ * the boundary DOFs. */
 vem_status vem_solve_rhs(vem_handle h, const vem_solve_opts* opts, const double* rhs, double* u, double* p,
                          vem_solve_info* info);
 
@@ -244,7 +247,10 @@ vem_status vem_solve_rhs(vem_handle h, const vem_solve_opts* opts, const double*
  * with nu piecewise constant): g[P] = nu_P lambda_P^T M1_P u_P, with u_P and
  * lambda_P the cell's oriented local flux DOFs of the device vectors u and
  * lam (n_u doubles each).  For nu = exp(-log K) and K x = b, a functional J
- * of x with K lambda = dJ/dx has dJ/d(log K_P) = g[P].  g: device, n_cells. */
+ * of x with K lambda = dJ/dx has dJ/d(log K_P) = g[P].  g: device, n_cells.
+ * Pressure boundary data only: VEM_EINVAL with VEM_BC_FLUX (there the
+ * prescribed boundary fluxes do not depend on K, and the formula would add
+ * their terms). */
 vem_status vem_coefficient_gradient(vem_handle h, const double* u, const double* lam, double* g);
 
 /* y = K x for device vectors of length n (test hook for the saddle SpMV). */

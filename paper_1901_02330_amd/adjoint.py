@@ -14,6 +14,8 @@ import torch
 class FluxPressureFromLogK(torch.autograd.Function):
     @staticmethod
     def forward(ctx, logk, solver, solve_kw):
+        if solver.boundary != "pressure":
+            raise ValueError("the adjoint gradient supports pressure boundary data only")
         solver.set_coefficient(torch.exp(-logk.detach()))
         u, p, info = solver.solve(**solve_kw)
         if not info["converged"]:

@@ -1649,12 +1649,24 @@ vem_status vem_solve(vem_handle h, const vem_solve_opts* opts, double* u, double
 
 vem_status vem_solve_rhs(vem_handle h, const vem_solve_opts* opts, const double* rhs, double* u, double* p,
                          vem_solve_info* info) {
-  if (!rhs) return VEM_EINVAL;
+  if (!h || !rhs) return VEM_EINVAL;
+  // With flux data K is singular (the constant pressure spans its kernel) and its prescribed rows
+  // fix boundary DOFs; a caller right-hand side is neither projected nor meaningful there.
+  if (h->bc == VEM_BC_FLUX) {
+    h->last_error = "vem_solve_rhs supports pressure boundary data only";
+    return VEM_EINVAL;
+  }
   return solve_impl(h, opts, rhs, u, p, info);
 }
 
 vem_status vem_coefficient_gradient(vem_handle h, const double* u, const double* lam, double* g) {
   if (!h || !u || !lam || !g) return VEM_EINVAL;
+  // The gradient formula assumes every flux DOF is free (pressure data): with flux data the
+  // prescribed DOFs would contribute terms that do not depend on the coefficient.
+  if (h->bc == VEM_BC_FLUX) {
+    h->last_error = "vem_coefficient_gradient supports pressure boundary data only";
+    return VEM_EINVAL;
+  }
   return guarded(h, [&] {
     require_disc(h);
     launch_coef_grad(h->stream, h->L, h->cptr, h->cface, h->csign, h->lmat_ptr, h->M1, h->nu, u, lam, g);

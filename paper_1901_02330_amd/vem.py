@@ -1,7 +1,10 @@
 """Python binding of the C ABI in include/vem.h (argument marshalling only).
 
 Device memory and streams come from PyTorch: every device argument is a
-torch CUDA (HIP) tensor and work is enqueued on torch's current stream.  All
+torch CUDA (HIP) tensor.  A Solver is bound to the stream that is current when
+it is created (or the one it is given); each wrapper runs on that stream,
+ordered after the caller's current stream, and the caller's stream then waits
+for it.  All
 numerical work runs in the HIP library; if the library is not built, loading
 fails with an error (there is no fallback).
 """
@@ -9,6 +12,7 @@ fails with an error (there is no fallback).
 from __future__ import annotations
 
 import ctypes
+import functools
 import os
 from ctypes import POINTER, byref, c_char_p, c_double, c_int, c_int64, c_void_p
 
@@ -104,6 +108,29 @@ def _ptr(t):
     return None if t is None else c_void_p(t.data_ptr())
 
 
+def _ordered(method):
+    """Run a wrapper on the handle's stream, ordered after the caller's current stream, and make the
+    caller's stream wait for it afterwards: inputs converted by the caller are complete before the
+    library reads them, and outputs (or temporaries freed on return) are not touched by the caller's
+    later work before the library's kernels finish.  Without this, entry points that return before
+    their kernels end (vem_apply, vem_get_quadrature, ...) could race with a caller on another stream."""
+
+    @functools.wraps(method)
+    def run(self, *args, **kwargs):
+        t = self.torch
+        cur = t.cuda.current_stream(self.device)
+        if cur == self.stream:
+            return method(self, *args, **kwargs)
+        self.stream.wait_stream(cur)
+        try:
+            with t.cuda.stream(self.stream):
+                return method(self, *args, **kwargs)
+        finally:
+            cur.wait_stream(self.stream)
+
+    return run
+
+
 class Solver:
     """One mesh + discretisation + solver state on the current device and stream."""
 
@@ -147,6 +174,7 @@ class Solver:
         return t.as_tensor(a, dtype=dtype, device=self.device).contiguous()
 
     # -- C ABI wrappers
+    @_ordered
     def set_mesh(self, mesh):
         t = self.torch
         xyz = self._dev(mesh["xyz"], t.float64)
@@ -159,11 +187,13 @@ class Solver:
                                           cp.numel() - 1, _ptr(cp), _ptr(cf), _ptr(cs), 1))
         self._sizes = None
 
+    @_ordered
     def discretize(self, family="lo", k=0, load_points=3):
         fam = {"lo": VEM_LO, "paper": VEM_PAPER}[family]
         self._check(self.lib.vem_discretize(self.h, fam, int(k), int(load_points)))
         self._sizes = None
 
+    @_ordered
     def sizes(self):
         if self._sizes is None:
             s = Sizes()
@@ -171,6 +201,7 @@ class Solver:
             self._sizes = {f: getattr(s, f) for f, _ in Sizes._fields_}
         return self._sizes
 
+    @_ordered
     def quadrature(self):
         t = self.torch
         sz = self.sizes()
@@ -181,21 +212,25 @@ class Solver:
                                                 _ptr(qf) if qf.numel() else None))
         return qc.t(), qf.t()
 
+    @_ordered
     def set_coefficient(self, nu):
         nu = self._dev(nu, self.torch.float64)
         self._check(self.lib.vem_set_coefficient(self.h, _ptr(nu)))
 
+    @_ordered
     def set_rhs(self, f_qp, pD_qp=None):
         f_qp = self._dev(f_qp, self.torch.float64)
         pD = None if pD_qp is None else self._dev(pD_qp, self.torch.float64)
         self._check(self.lib.vem_set_rhs(self.h, _ptr(f_qp), _ptr(pD) if pD is not None and pD.numel() else None))
 
+    @_ordered
     def set_boundary(self, kind):
         """'pressure' (p_D given, the default) or 'flux' (u.n given and zero-mean pressure, the paper's
         model problem)."""
         self._check(self.lib.vem_set_boundary(self.h, {"pressure": 0, "flux": 1}[kind]))
         self.boundary = kind
 
+    @_ordered
     def set_rhs_flux(self, f_qp, u_qp):
         """f at the cell points and the flux field u (n_qp_face, 3) at the boundary points."""
         f_qp = self._dev(f_qp, self.torch.float64)
@@ -216,6 +251,7 @@ class Solver:
         else:
             self.set_rhs(fv, gv)
 
+    @_ordered
     def solve(self, precond="schur", tol=1e-8, restart=30, maxit=5000, inner_tol=1e-6, inner_maxit=5000,
               inner_check=32, gamma=0.0, x0=None, precision="fp64", rhs=None, graphs=False,
               inner_form="pipelined"):
@@ -248,6 +284,7 @@ class Solver:
         out["converged"] = code == 0
         return u, p, out
 
+    @_ordered
     def coefficient_gradient(self, u, lam):
         """g[P] = nu_P lambda_P^T M1_P u_P (flux parts u, lam of length n_u)."""
         t = self.torch
@@ -257,6 +294,7 @@ class Solver:
         self._check(self.lib.vem_coefficient_gradient(self.h, _ptr(u), _ptr(lam), _ptr(g)))
         return g
 
+    @_ordered
     def apply(self, x):
         t = self.torch
         x = self._dev(x, t.float64)
@@ -264,6 +302,7 @@ class Solver:
         self._check(self.lib.vem_apply(self.h, _ptr(x), _ptr(y)))
         return y
 
+    @_ordered
     def export_csr(self, which="K"):
         t = self.torch
         sz = self.sizes()
@@ -275,12 +314,14 @@ class Solver:
         self._check(self.lib.vem_export_csr(self.h, MATS[which], _ptr(rp), _ptr(col), _ptr(val)))
         return rp, col, val
 
+    @_ordered
     def rhs(self):
         t = self.torch
         b = t.empty(self.sizes()["n"], dtype=t.float64, device=self.device)
         self._check(self.lib.vem_get_rhs(self.h, _ptr(b)))
         return b
 
+    @_ordered
     def time_kernel(self, which="cg_schur", reps=50):
         """Mean duration (ms) of one launch of a hot kernel, timed with HIP events, and its algorithmic bytes."""
         code = {"spmv": 0, "cg_schur": 1, "cg_reg": 2, "cg_schur32": 3, "cg_reg32": 4, "cg_schur32p": 5,
@@ -289,6 +330,7 @@ class Solver:
         self._check(self.lib.vem_time_kernel(self.h, code, int(reps), byref(ms), byref(nb)))
         return ms.value, nb.value
 
+    @_ordered
     def geometry(self):
         t = self.torch
         sz = self.sizes()

@@ -128,3 +128,28 @@ def test_flux_patch_test_on_gpu(case):
     pe = pe - d["n_p"] * (d["w"] @ pe) / (d["w"] @ d["n_p"])
     assert np.abs(u.cpu().numpy() - ue).max() < 1e-9 * max(1.0, np.abs(ue).max())
     assert np.abs(p.cpu().numpy() - pe).max() < 1e-9 * max(1.0, np.abs(pe).max())
+
+
+def test_adjoint_rejected_with_flux_data():
+    """The adjoint entry points take pressure data only: with flux data K is singular and its
+    prescribed rows fix the boundary DOFs, so vem_solve_rhs and vem_coefficient_gradient return
+    VEM_EINVAL, and the autograd path raises before solving."""
+    import torch
+
+    from paper_1901_02330_amd.adjoint import solve_logk
+    from paper_1901_02330_amd.vem import VemError
+
+    _say("flux adjoint rejected")
+    m = cube_mesh(3)
+    s = _gpu(m, "lo", 0, None, SineSolution())
+    sz = s.sizes()
+    u, p, info = s.solve(precond="schur", tol=1e-10)
+    assert info["converged"]
+    with pytest.raises(VemError) as e:
+        s.solve(rhs=torch.ones(sz["n"], dtype=torch.float64, device=u.device))
+    assert e.value.code == -1 and "pressure boundary data" in str(e.value)
+    with pytest.raises(VemError) as e:
+        s.coefficient_gradient(u, u)
+    assert e.value.code == -1
+    with pytest.raises(ValueError):
+        solve_logk(s, torch.zeros(sz["n_cells"], dtype=torch.float64, device=u.device), tol=1e-10)

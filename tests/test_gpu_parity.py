@@ -90,6 +90,32 @@ def test_spmv():
     assert np.abs(y - yo).max() <= 1e-13 * np.abs(yo).max()
 
 
+def test_spmv_on_a_side_stream():
+    """A Solver bound to a side stream, called while another stream is current: the product is read on
+    the caller's stream right away, with no synchronisation by the caller (the binding orders the two
+    streams both ways)."""
+    import torch
+
+    from paper_1901_02330_amd.vem import Solver
+
+    _say("spmv side stream")
+    m = cube_mesh(12)
+    nu = 1.0 / lognormal_field(12**3, 1.0, 4)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        s = Solver()
+    s.set_mesh(m)
+    s.discretize("lo")
+    s.set_coefficient(torch.as_tensor(nu))
+    d = discretize(m, nu=nu)
+    x = np.random.default_rng(1).standard_normal(d["Nu"] + d["Np"])
+    for _ in range(3):
+        xt = torch.as_tensor(x, device="cuda") * 2.0  # produced on the current stream
+        y = (s.apply(xt) * 0.5).cpu().numpy()  # consumed on the current stream
+        yo = d["K"] @ x
+        assert np.abs(y - yo).max() <= 1e-13 * np.abs(yo).max()
+
+
 @pytest.mark.parametrize("precond", ["schur", "reg"])
 @pytest.mark.parametrize("case", ["cube8_K1", "cube675_lognormal", "voronoi150_lognormal", "tet1"])
 def test_solve_matches_oracle(case, precond):
