@@ -207,6 +207,19 @@ vem_status vem_set_coefficient(vem_handle h, const double* nu);
  * of vem_get_quadrature, pD_qp[n_qp_face] (NULL means p_D = 0). */
 vem_status vem_set_rhs(vem_handle h, const double* f_qp, const double* pD_qp);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): vem_set_rhs with the same arguments, kernels and result,
+ * that calls no hipMalloc, hipFree or allocating library routine.  Its one temporary, the
+ * per-tetrahedron load sums (ntet doubles at the lowest order, ntet * dim P_{k-1} for the order-k
+ * element, ntet = the cell tetrahedra of vem_get_quadrature), lives in a fixed device array of
+ * 4 * 2^20 doubles (32 MiB) that the library holds on each device it runs on until the process
+ * ends.  All handles on one device share that array, and every entry a call reads it writes first;
+ * it keeps the last call's contents.  Two calls that overlap on one device (handles driven from
+ * different host threads) race on it and must be serialised by the caller.  Errors as vem_set_rhs,
+ * and VEM_ENOMEM (nothing changed) when the mesh needs more than the fixed array holds (about
+ * 350,000 hexahedra at the lowest order): use vem_set_rhs there. */
+vem_status vem_set_rhs_noalloc(vem_handle h, const double* f_qp, const double* pD_qp);
+
 /* Select the boundary data: VEM_BC_PRESSURE (the default) or VEM_BC_FLUX, before or after
  * vem_discretize; a change clears the right-hand side.  With VEM_BC_FLUX the DOFs of the
  * boundary faces are prescribed: they hold identity rows and columns in K and A_gamma, B has no

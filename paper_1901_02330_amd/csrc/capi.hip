@@ -41,6 +41,14 @@ struct InnerGraph {
   }
 };
 
+// Device memory behind vem_set_rhs_noalloc, for callers that cannot allocate: the per-tetrahedron
+// load sums of one right-hand side build (ntet doubles at the lowest order, ntet * dim P_{k-1} for
+// the order-k element).  Each device holds its own copy until the process ends; host code never
+// passes this name to a kernel (on the host it is only a stand-in for the symbol), it uses the
+// address that hipGetSymbolAddress returned on that device (noalloc_scratch below).
+constexpr int64_t kNoAllocDoubles = int64_t(4) << 20;  // 32 MiB
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
 struct vem_ctx {
   ~vem_ctx() {
     for (InnerGraph* g : {&gS, &gA, &gS32, &gA32}) g->reset();
@@ -52,6 +60,7 @@ struct vem_ctx {
   hipStream_t cap = nullptr;  // private stream used only to capture graphs
   hipStream_t stream = nullptr;
   int device = 0;
+  double* noalloc = nullptr;  // this device's copy of `scratch` (vem_set_rhs_noalloc)
   std::string last_error;
 
   // mesh (device copies) and host copies of the offsets
@@ -403,6 +412,22 @@ std::string mesh_err_text(int e) {
   return "bad mesh:" + t;
 }
 
+// The device address of `scratch` on the current device, looked up once per device (the symbol
+// has one copy per device, at a different address on each).
+double* noalloc_scratch(int device) {
+  static std::mutex mu;
+  static std::map<int, double*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(device);
+  if (it != addr.end()) return it->second;
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    throw Error{VEM_EHIP, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e)};
+  addr[device] = (double*)p;
+  return (double*)p;
+}
+
 void ensure_scratch(vem_handle h) {
   if (!h->partials.p) {
     h->partials.alloc((size_t)kRedBlocks * kMaxDots);
@@ -664,14 +689,19 @@ const double* flux_rhs(vem_handle h) {
 
 // Loads F from f at the cell points, and either the pressure term g from p_D at the boundary points
 // or the prescribed boundary fluxes xB from u at the boundary points (structure of arrays).
-void set_loads(vem_handle h, const double* f_qp, const double* pD_qp, const double* u_qp) {
+// The per-tetrahedron sums go to `fixed` when given (at least tet_sum_len(h) doubles), else to the
+// handle's grow-only pool.
+int64_t tet_sum_len(vem_handle h) { return h->family == VEM_LO ? h->ntet : h->ntet * h->L.npd; }
+
+void set_loads(vem_handle h, const double* f_qp, const double* pD_qp, const double* u_qp, double* fixed = nullptr) {
     hipStream_t s = h->stream;
     const int64_t nqf = (int64_t)h->nbtri * h->npts_face;
     if (u_qp) launch_fill(s, h->L.Nu, 0.0, h->xB);
     launch_fill(s, h->L.Nu, 0.0, h->rhs);
-    DBuf<double>& tsum = h->tmp.f64[0];
+    DBuf<double>& pool = h->tmp.f64[0];
+    if (!fixed) pool.reserve(tet_sum_len(h));
+    double* tsum = fixed ? fixed : pool.p;
     if (h->family == VEM_LO) {
-      tsum.reserve(h->ntet);
       launch_load_tets(s, h->ntet, h->npts_cell, h->qw_cell, h->tet_inc, h->tet_a, h->inc_cell, h->xyz, h->fptr,
                        h->fvtx, h->cface, h->csign, h->c_xref, f_qp, tsum);
       launch_load_cells(s, h->nc, h->cell_tet_ptr, tsum, h->rhs.p + h->L.Nu);
@@ -682,7 +712,6 @@ void set_loads(vem_handle h, const double* f_qp, const double* pD_qp, const doub
         launch_bnd_flux(s, (int)h->nbf, h->npts_face, nqf, h->qw_face, h->bface, h->btri_ptr, h->xyz, h->fptr,
                         h->fvtx, h->f_normal, h->f_area, u_qp, h->xB);
     } else {
-      tsum.reserve((size_t)h->ntet * h->L.npd);
       PaperLoadArgs a{};
       a.s = s;
       a.nc = h->nc;
@@ -769,6 +798,7 @@ vem_status vem_create(vem_handle* out, void* stream) {
     VEM_HIP(hipGetDevice(&h->device));
     h->stream = (hipStream_t)stream;
     ensure_scratch(h);
+    h->noalloc = noalloc_scratch(h->device);
   });
   if (st != VEM_OK) {
     delete h;
@@ -1286,6 +1316,22 @@ vem_status vem_set_rhs(vem_handle h, const double* f_qp, const double* pD_qp) {
     require_disc(h);
     VEM_REQUIRE(h->bc == VEM_BC_PRESSURE, VEM_EINVAL, "flux boundary data: use vem_set_rhs_flux");
     set_loads(h, f_qp, pD_qp, nullptr);
+  });
+}
+
+vem_status vem_set_rhs_noalloc(vem_handle h, const double* f_qp, const double* pD_qp) {
+  if (!h || !f_qp) return VEM_EINVAL;
+  return guarded(h, [&] {
+    require_disc(h);
+    VEM_REQUIRE(h->bc == VEM_BC_PRESSURE, VEM_EINVAL, "flux boundary data: use vem_set_rhs_flux");
+    VEM_REQUIRE(h->noalloc, VEM_EHIP, "no device scratch bound to this handle");
+    const int64_t need = tet_sum_len(h);
+    VEM_REQUIRE(need <= kNoAllocDoubles, VEM_ENOMEM,
+                "vem_set_rhs_noalloc: the mesh needs " + std::to_string(need) +
+                    " doubles of load scratch, more than its fixed " + std::to_string(kNoAllocDoubles) +
+                    " (use vem_set_rhs)");
+    // every entry the build reads is written by it first: nothing to clear
+    set_loads(h, f_qp, pD_qp, nullptr, h->noalloc);
   });
 }
 

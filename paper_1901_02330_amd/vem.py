@@ -95,6 +95,7 @@ def load():
         "vem_coefficient_gradient": ([H, P, P, P], c_int),
         "vem_set_boundary": ([H, c_int], c_int),
         "vem_set_rhs_flux": ([H, P, P], c_int),
+        "vem_set_rhs_noalloc": ([H, P, P], c_int),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -353,5 +354,5 @@ EXPORTED = [
     "vem_solve_opts_default", "vem_create", "vem_destroy", "vem_set_mesh", "vem_discretize", "vem_get_sizes",
     "vem_get_quadrature", "vem_set_coefficient", "vem_set_rhs", "vem_solve", "vem_apply", "vem_export_csr",
     "vem_get_rhs", "vem_get_geometry", "vem_status_string", "vem_last_error", "vem_time_kernel",
-    "vem_solve_rhs", "vem_coefficient_gradient", "vem_set_boundary", "vem_set_rhs_flux",
+    "vem_solve_rhs", "vem_coefficient_gradient", "vem_set_boundary", "vem_set_rhs_flux", "vem_set_rhs_noalloc",
 ]
