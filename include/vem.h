@@ -99,8 +99,20 @@ enum { VEM_FP64 = 0, VEM_MIXED = 1 };
  * the pipelined recurrences stall the outer solve). */
 enum { VEM_INNER_PIPELINED = 0, VEM_INNER_CLASSICAL = 1 };
 
-/* matrices for vem_export_csr */
-enum { VEM_MAT_K = 0, VEM_MAT_SCHUR = 1, VEM_MAT_REG = 2 };
+/* Preconditioner of Block-Reg's inner CG on A_gamma = M + B^T B / gamma (Section 5, eq.
+ * block_diag, where the paper applies one algebraic multigrid cycle).  VEM_REG_JACOBI: diag(A_gamma)
+ * (the inner_form and use_graphs options apply).  VEM_REG_SCHWARZ: additive Schwarz over the mesh
+ * edges.  Each patch is the set of DOFs of the faces around one edge; these patches hold the local
+ * divergence-free fluxes that dominate the small eigenvalues of A_gamma, which a diagonal
+ * preconditioner never sees.  For the order-k element the interior DOFs of each cell are first
+ * condensed exactly (static condensation), and the CG runs on the face DOFs; two kernels per
+ * iteration; inner_form and use_graphs are ignored. */
+enum { VEM_REG_JACOBI = 0, VEM_REG_SCHWARZ = 1 };
+
+/* matrices for vem_export_csr: the saddle matrix, S, A_gamma; the Block-Reg Schwarz preconditioner's
+ * face system (A_gamma with the cell interiors condensed; A_gamma itself at the lowest order) and its
+ * operator P = sum_e R_e^T F_e^{-1} R_e over the edge patches, both on the face DOFs. */
+enum { VEM_MAT_K = 0, VEM_MAT_SCHUR = 1, VEM_MAT_REG = 2, VEM_MAT_REG_FACE = 3, VEM_MAT_REG_SCHWARZ = 4 };
 
 typedef struct {
   int64_t n_vertices, n_faces, n_cells;
@@ -116,6 +128,7 @@ typedef struct {
   int32_t max_cell_faces;
   double h;          /* mean cell diameter (eq. meshSize) */
   double gamma;      /* default Block-Reg parameter h^2 */
+  int64_t n_face_dofs; /* flux unknowns on faces (the first n_face_dofs of u) */
 } vem_sizes;
 
 typedef struct {
@@ -136,6 +149,7 @@ typedef struct {
                           gfx950 each replay boundary leaves the GPU idle for about 8 us,
                           more than the host's launch cost it saves */
   int32_t inner_form;  /* VEM_INNER_PIPELINED (default) or VEM_INNER_CLASSICAL */
+  int32_t reg_inner;   /* Block-Reg inner preconditioner: VEM_REG_SCHWARZ (default) or VEM_REG_JACOBI */
 } vem_solve_opts;
 
 typedef struct {
@@ -270,7 +284,10 @@ vem_status vem_coefficient_gradient(vem_handle h, const double* u, const double*
 vem_status vem_apply(vem_handle h, const double* x, double* y);
 
 /* Copy a matrix out in CSR form to device buffers rowptr[rows+1], col[nnz],
- * val[nnz]; rows = n (VEM_MAT_K), n_p (VEM_MAT_SCHUR), n_u (VEM_MAT_REG). */
+ * val[nnz]; rows = n (VEM_MAT_K), n_p (VEM_MAT_SCHUR), n_u (VEM_MAT_REG),
+ * n_face_dofs (VEM_MAT_REG_FACE, VEM_MAT_REG_SCHWARZ).  With col and val NULL only rowptr is
+ * written (nnz = rowptr[rows]).  The two Schwarz matrices are built for the default gamma = h^2
+ * if no Block-Reg solve has built them yet, else for the last solve's gamma. */
 vem_status vem_export_csr(vem_handle h, int which, int32_t* rowptr, int32_t* col, double* val);
 
 /* Copy the assembled right-hand side b = [g; -F] (device, n doubles). */
@@ -284,7 +301,8 @@ vem_status vem_get_geometry(vem_handle h, double* face_area, double* face_normal
 
 /* Hot kernels that vem_time_kernel can time. */
 enum { VEM_KERNEL_SPMV = 0, VEM_KERNEL_CG_SCHUR = 1, VEM_KERNEL_CG_REG = 2, VEM_KERNEL_CG_SCHUR32 = 3,
-       VEM_KERNEL_CG_REG32 = 4, VEM_KERNEL_CG_SCHUR32P = 5, VEM_KERNEL_CG_REG32P = 6 };
+       VEM_KERNEL_CG_REG32 = 4, VEM_KERNEL_CG_SCHUR32P = 5, VEM_KERNEL_CG_REG32P = 6,
+       VEM_KERNEL_CG_REG_SCHWARZ = 7, VEM_KERNEL_CG_REG_SCHWARZ32 = 8 };
 
 /* Measurement hook for benchmarks: time `reps` back-to-back launches of one
  * hot kernel with HIP events recorded on the handle's stream.
@@ -294,7 +312,9 @@ enum { VEM_KERNEL_SPMV = 0, VEM_KERNEL_CG_SCHUR = 1, VEM_KERNEL_CG_REG = 2, VEM_
  *   VEM_KERNEL_CG_SCHUR32, VEM_KERNEL_CG_REG32: one classical FP32 iteration (two
  *                        launches; VEM_MIXED with an inner cap above 64);
  *   VEM_KERNEL_CG_SCHUR32P, VEM_KERNEL_CG_REG32P: one pipelined FP32 iteration
- *                        (VEM_MIXED with an inner cap of 64 or less).
+ *                        (VEM_MIXED with an inner cap of 64 or less);
+ *   VEM_KERNEL_CG_REG_SCHWARZ, VEM_KERNEL_CG_REG_SCHWARZ32: one iteration of Block-Reg's inner CG
+ *                        with the edge-patch Schwarz preconditioner (two launches), FP64 / FP32.
  * avg_ms receives the mean duration of one launch; bytes (may be NULL) the
  * algorithmic bytes one launch moves (every matrix entry and every vector
  * element read or written once).  Uses the solver workspace; the results of

@@ -21,7 +21,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libvem_mi355x.so")
-SOURCES = ["mesh.hip", "element_lo.hip", "element_paper.hip", "assemble.hip", "sell.hip", "krylov.hip", "pcg.hip", "capi.hip"]
+SOURCES = ["mesh.hip", "element_lo.hip", "element_paper.hip", "assemble.hip", "sell.hip", "krylov.hip", "pcg.hip", "schwarz.hip", "capi.hip"]
 ARCH = os.environ.get("VEM_OFFLOAD_ARCH", "gfx950")
 
 CFLAGS = [

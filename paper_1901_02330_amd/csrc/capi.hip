@@ -103,6 +103,7 @@ struct vem_ctx {
   // matrices
   Csr K, A, S;
   Sell Ks, As, Ss;
+  Schwarz sz;  // Block-Reg's edge-patch Schwarz preconditioner (built on first use)
   DBuf<int> Kdiag, Adiag, Sdiag;
   DBuf<double> dM, dMinv, dAinv, dSinv;
   DBuf<float> dAinv32, dSinv32;
@@ -446,6 +447,7 @@ void ensure_scratch(vem_handle h) {
 // ----- coefficient-dependent values (K, diagonals, S, A_gamma), built lazily -----
 void invalidate_values(vem_handle h) {
   h->k_ready = h->s_ready = h->a_ready = h->s32_ready = h->a32_ready = false;
+  h->sz.ready = h->sz.ready32 = false;
 }
 
 // Builds the coefficient-dependent values a call needs and that are not current: K and diag(M)
@@ -490,6 +492,29 @@ void ensure_values(vem_handle h, bool needS, bool needA, bool f32, double gamma)
 }
 
 void ensure_k(vem_handle h) { ensure_values(h, false, false, false, h->gamma_A); }
+
+SchwarzMesh schwarz_mesh(vem_handle h) {
+  return {h->nv,        h->nf,       h->nc,           h->fptr,       h->fvtx,       h->cptr, h->cface,
+          h->face_cell, h->face_lidx, h->ldof_ptr,    h->sorted_gid, h->sorted_l,  h->csign};
+}
+
+// Block-Reg's Schwarz preconditioner for gamma: A_gamma's values (the lowest order's face system),
+// the edge patterns on first use, then the face system and the patch inverses when the coefficient,
+// gamma or the boundary data changed; FP32 roundings when f32.
+void ensure_schwarz(vem_handle h, double gamma, bool f32) {
+  const DofLayout L = h->L;
+  ensure_values(h, false, true, f32 && L.nint == 0, gamma);
+  hipStream_t s = h->stream;
+  const SchwarzMesh m = schwarz_mesh(h);
+  if (!h->sz.built) schwarz_build(s, h->tmp, m, L, h->A, h->sz);
+  if (!h->sz.ready || h->sz.gamma != gamma) {
+    const int* bnd = h->bc == VEM_BC_FLUX ? h->is_bnd.p : nullptr;
+    schwarz_values(s, m, L, h->lmat_ptr, h->M1, h->lb_ptr, h->Bdiv1, h->nu, 1.0 / gamma, bnd, h->A, h->As, h->sz);
+    h->sz.gamma = gamma;
+  }
+  if (f32 && !h->sz.ready32) schwarz_round32(s, L, h->sz);
+  check_launch();
+}
 
 void ensure_workspace(vem_handle h, int m) {
   int64_t N = h->L.Nu + h->L.Np;
@@ -642,6 +667,58 @@ void inner_pcg(vem_handle h, const Sell& A, const double* dinv, const float* din
   expect = h->hpcg.p->count;
 }
 
+// Enqueue the iterations of one inner solve (one(i) enqueues iteration i): all of them without
+// polling for a cap of kBlindInner or fewer, else in chunks between convergence checks, the first
+// sized from the previous solve on the same block.
+template <class One>
+void run_inner(vem_handle h, const vem_solve_opts& o, int& expect, One&& one) {
+  if (o.inner_maxit <= kBlindInner) {
+    for (int i = 0; i < o.inner_maxit; ++i) one(i);
+    check_launch();
+    return;
+  }
+  const int step = std::max(1, o.inner_check);
+  int chunk = expect > 4 ? (expect * 7) / 8 : step;
+  int i = 0;
+  for (;;) {
+    const int stop = std::min(o.inner_maxit, i + chunk);
+    while (i < stop) one(i++);
+    check_launch();
+    VEM_HIP(hipMemcpyAsync(h->hpcg.p, h->pcg.p, sizeof(PcgState), hipMemcpyDeviceToHost, h->stream));
+    sync(h);
+    if (h->hpcg.p->done || i >= o.inner_maxit) break;
+    chunk = expect > 4 ? std::max(2, std::min(step, expect / 8)) : step;
+  }
+  expect = h->hpcg.p->count;
+}
+
+// z_u ~ A_gamma^{-1} v_u by CG on the face system preconditioned by the edge-patch Schwarz operator:
+// the interior DOFs condensed into the right-hand side (order k), CG on the face DOFs (FP64, or
+// FP32 with FP64 dot products), then the interior DOFs by back-substitution.
+void schwarz_inner(vem_handle h, const vem_solve_opts& o, const double* v, double* z) {
+  hipStream_t s = h->stream;
+  const DofLayout L = h->L;
+  const Schwarz& X = h->sz;
+  const Sell& F = schwarz_face_sell(X, h->As, L);
+  const SchwarzMesh m = schwarz_mesh(h);
+  const int* bnd = h->bc == VEM_BC_FLUX ? h->is_bnd.p : nullptr;
+  if (o.precision == VEM_MIXED) {
+    PcgWork32 w{h->px32, (float*)h->pr.p, (float*)h->pz.p, (float*)h->ps.p, (float*)h->pp.p, (float*)h->pw0.p,
+                (float*)h->pw1.p, nullptr};
+    launch_schwarz_rhs<float>(s, m, L, X, bnd, v, w.r);
+    launch_scg_init<float>(s, X.Ps, w, h->pcg, o.inner_tol, h->pcgpart);
+    run_inner(h, o, h->expect_A, [&](int i) { launch_scg_iter<float>(s, i, F, X.Ps, w, h->pcg, h->pcgpart); });
+    launch_to_f64(s, X.nF, h->px32, z);
+  } else {
+    PcgWork w{z, h->pr, h->pz, h->ps, h->pp, h->pw0, h->pw1, nullptr};
+    launch_schwarz_rhs<double>(s, m, L, X, bnd, v, w.r);
+    launch_scg_init<double>(s, X.Ps, w, h->pcg, o.inner_tol, h->pcgpart);
+    run_inner(h, o, h->expect_A, [&](int i) { launch_scg_iter<double>(s, i, F, X.Ps, w, h->pcg, h->pcgpart); });
+  }
+  if (L.nint > 0) launch_schwarz_back(s, m, L, X, v, z);
+  check_launch();
+}
+
 // z = P^{-1} v for the chosen block preconditioner
 void apply_prec(vem_handle h, const vem_solve_opts& o, const double* v, double* z) {
   hipStream_t s = h->stream;
@@ -662,7 +739,10 @@ void apply_prec(vem_handle h, const vem_solve_opts& o, const double* v, double* 
       return;
     }
     case VEM_PREC_REG:
-      inner_pcg(h, h->As, h->dAinv, h->dAinv32, v, z, o, h->expect_A, h->gA, h->gA32);
+      if (o.reg_inner == VEM_REG_SCHWARZ)
+        schwarz_inner(h, o, v, z);
+      else
+        inner_pcg(h, h->As, h->dAinv, h->dAinv32, v, z, o, h->expect_A, h->gA, h->gA32);
       launch_scale_by(s, Np, v + Nu, nullptr, 1.0 / h->gamma_A, z + Nu);
       return;
     default:
@@ -784,6 +864,7 @@ void vem_solve_opts_default(vem_solve_opts* o) {
   o->precision = VEM_FP64;
   o->use_graphs = 0;
   o->inner_form = VEM_INNER_PIPELINED;
+  o->reg_inner = VEM_REG_SCHWARZ;
 }
 
 vem_status vem_create(vem_handle* out, void* stream) {
@@ -845,6 +926,7 @@ vem_status vem_set_mesh(vem_handle h, int64_t nv, const double* xyz, int64_t nf,
     hipStream_t s = h->stream;
     h->has_mesh = false;
     h->has_disc = false;
+    h->sz.built = h->sz.ready = h->sz.ready32 = false;
     if (mem_kind == VEM_MEM_HOST) {
       // offsets validated on the host
       h->h_fptr.assign(face_ptr, face_ptr + nf + 1);
@@ -931,6 +1013,7 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
     VEM_REQUIRE(load_points >= 1 && load_points <= 6, VEM_EINVAL, "load_points must be in 1..6");
     hipStream_t s = h->stream;
     h->has_disc = false;
+    h->sz.built = h->sz.ready = h->sz.ready32 = false;
     const int nf = h->nf, nc = h->nc;
     // ---- a1: geometry
     h->f_area.alloc(nf);
@@ -1251,6 +1334,7 @@ vem_status vem_get_sizes(vem_handle h, vem_sizes* o) {
     o->max_cell_faces = h->max_cell_faces;
     o->h = h->h;
     o->gamma = h->gamma_default;
+    o->n_face_dofs = (int64_t)h->L.nf * h->L.nfd;
   });
 }
 
@@ -1358,10 +1442,26 @@ vem_status vem_export_csr(vem_handle h, int which, int32_t* rowptr, int32_t* col
   if (!h) return VEM_EINVAL;
   return guarded(h, [&] {
     require_disc(h);
-    Csr* M = which == VEM_MAT_K ? &h->K : which == VEM_MAT_SCHUR ? &h->S : which == VEM_MAT_REG ? &h->A : nullptr;
-    const Sell* Ms = which == VEM_MAT_K ? &h->Ks : which == VEM_MAT_SCHUR ? &h->Ss : &h->As;
-    VEM_REQUIRE(M, VEM_EINVAL, "unknown matrix");
-    ensure_values(h, which == VEM_MAT_SCHUR, which == VEM_MAT_REG, false, h->gamma_A);
+    VEM_REQUIRE(which >= VEM_MAT_K && which <= VEM_MAT_REG_SCHWARZ, VEM_EINVAL, "unknown matrix");
+    const bool face = which == VEM_MAT_REG_FACE, schw = which == VEM_MAT_REG_SCHWARZ;
+    if (face || schw) {
+      ensure_schwarz(h, h->sz.ready ? h->sz.gamma : h->gamma_A, false);
+    } else {
+      ensure_values(h, which == VEM_MAT_SCHUR, which == VEM_MAT_REG, false, h->gamma_A);
+    }
+    const bool lo_face = face && h->L.nint == 0;  // the lowest order's face system is A_gamma
+    Csr* M = which == VEM_MAT_K       ? &h->K
+             : which == VEM_MAT_SCHUR ? &h->S
+             : which == VEM_MAT_REG   ? &h->A
+             : schw                   ? &h->sz.Pc
+             : lo_face                ? &h->A
+                                      : &h->sz.Fc;
+    const Sell* Ms = which == VEM_MAT_K       ? &h->Ks
+                     : which == VEM_MAT_SCHUR ? &h->Ss
+                     : which == VEM_MAT_REG   ? &h->As
+                     : schw                   ? &h->sz.Ps
+                     : lo_face                ? &h->As
+                                              : &h->sz.Fs;
     hipStream_t s = h->stream;
     if (val) sell_to_csr(s, *Ms, *M);
     if (rowptr)
@@ -1404,12 +1504,14 @@ vem_status vem_time_kernel(vem_handle h, int which, int reps, double* avg_ms, do
   if (!h || !avg_ms || reps < 1) return VEM_EINVAL;
   return guarded(h, [&] {
     require_disc(h);
-    VEM_REQUIRE(which >= VEM_KERNEL_SPMV && which <= VEM_KERNEL_CG_REG32P, VEM_EINVAL, "unknown kernel");
+    VEM_REQUIRE(which >= VEM_KERNEL_SPMV && which <= VEM_KERNEL_CG_REG_SCHWARZ32, VEM_EINVAL, "unknown kernel");
+    const bool schwarz = which == VEM_KERNEL_CG_REG_SCHWARZ || which == VEM_KERNEL_CG_REG_SCHWARZ32;
     const bool pipe32 = which == VEM_KERNEL_CG_SCHUR32P || which == VEM_KERNEL_CG_REG32P;
     const bool f32 = pipe32 || which == VEM_KERNEL_CG_SCHUR32 || which == VEM_KERNEL_CG_REG32;
     const bool schur =
         which == VEM_KERNEL_CG_SCHUR || which == VEM_KERNEL_CG_SCHUR32 || which == VEM_KERNEL_CG_SCHUR32P;
     ensure_values(h, which != VEM_KERNEL_SPMV && schur, which != VEM_KERNEL_SPMV && !schur, f32, h->gamma_A);
+    if (schwarz) ensure_schwarz(h, h->gamma_A, which == VEM_KERNEL_CG_REG_SCHWARZ32);
     hipStream_t s = h->stream;
     ensure_workspace(h, std::max(1, h->ws_m));
     const int64_t Nu = h->L.Nu, Np = h->L.Np, N = Nu + Np;
@@ -1424,6 +1526,38 @@ vem_status vem_time_kernel(vem_handle h, int which, int reps, double* avg_ms, do
         for (int r = 0; r < reps; ++r) launch_spmv(s, h->Ks, h->rhs, h->Vb);
         VEM_HIP(hipEventRecord(e1, s));
         b = 12.0 * h->K.nnz + 8.0 * N + 8.0 * N;  // matrix, x once, y once
+      } else if (schwarz) {
+        const DofLayout L = h->L;
+        const Schwarz& X = h->sz;
+        const Sell& F = schwarz_face_sell(X, h->As, L);
+        const Csr& Fc = L.nint > 0 ? X.Fc : h->A;
+        const SchwarzMesh m = schwarz_mesh(h);
+        launch_fill(s, L.Nu, 1.0, h->Vb);  // a constant right-hand side
+        const double nF = (double)X.nF;
+        if (which == VEM_KERNEL_CG_REG_SCHWARZ32) {
+          PcgWork32 w{h->px32, (float*)h->pr.p, (float*)h->pz.p, (float*)h->ps.p, (float*)h->pp.p, (float*)h->pw0.p,
+                      (float*)h->pw1.p, nullptr};
+          launch_schwarz_rhs<float>(s, m, L, X, nullptr, h->Vb, w.r);
+          launch_scg_init<float>(s, X.Ps, w, h->pcg, 0.0, h->pcgpart);
+          launch_scg_iter<float>(s, 0, F, X.Ps, w, h->pcg, h->pcgpart);
+          launch_scg_iter<float>(s, 1, F, X.Ps, w, h->pcg, h->pcgpart);
+          VEM_HIP(hipEventRecord(e0, s));
+          for (int r = 0; r < reps; ++r) launch_scg_iter<float>(s, 2 + r, F, X.Ps, w, h->pcg, h->pcgpart);
+          VEM_HIP(hipEventRecord(e1, s));
+          b = 8.0 * (Fc.nnz + X.Pc.nnz) + 4.0 * nF * 11.0;
+        } else {
+          PcgWork w{h->xw.p, h->pr, h->pz, h->ps, h->pp, h->pw0, h->pw1, nullptr};
+          launch_schwarz_rhs<double>(s, m, L, X, nullptr, h->Vb, w.r);
+          launch_scg_init<double>(s, X.Ps, w, h->pcg, 0.0, h->pcgpart);
+          launch_scg_iter<double>(s, 0, F, X.Ps, w, h->pcg, h->pcgpart);
+          launch_scg_iter<double>(s, 1, F, X.Ps, w, h->pcg, h->pcgpart);
+          VEM_HIP(hipEventRecord(e0, s));
+          for (int r = 0; r < reps; ++r) launch_scg_iter<double>(s, 2 + r, F, X.Ps, w, h->pcg, h->pcgpart);
+          VEM_HIP(hipEventRecord(e1, s));
+          // both matrices once; [product] z and p_old gathered, p and q written; [update] r and q
+          // gathered, r written, x read and written, p read, z written: 11 vector accesses per row
+          b = 12.0 * (Fc.nnz + X.Pc.nnz) + 8.0 * nF * 11.0;
+        }
       } else {
         Sell& A = schur ? h->Ss : h->As;
         const Csr& C = schur ? h->S : h->A;
@@ -1507,12 +1641,15 @@ static vem_status solve_impl(vem_handle h, const vem_solve_opts* opts, const dou
     VEM_REQUIRE(o.precision == VEM_FP64 || o.precision == VEM_MIXED, VEM_EINVAL, "unknown precision mode");
     VEM_REQUIRE(o.inner_form == VEM_INNER_PIPELINED || o.inner_form == VEM_INNER_CLASSICAL, VEM_EINVAL,
                 "unknown inner CG form");
+    VEM_REQUIRE(o.reg_inner == VEM_REG_JACOBI || o.reg_inner == VEM_REG_SCHWARZ, VEM_EINVAL,
+                "unknown Block-Reg inner preconditioner");
     auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = h->stream;
     const int m = o.restart;
     const int64_t Nu = h->L.Nu, Np = h->L.Np, N = Nu + Np;
-    ensure_values(h, o.precond == VEM_PREC_SCHUR, o.precond == VEM_PREC_REG, o.precision == VEM_MIXED,
-                  o.gamma > 0 ? o.gamma : h->gamma_default);
+    const double gam = o.gamma > 0 ? o.gamma : h->gamma_default;
+    ensure_values(h, o.precond == VEM_PREC_SCHUR, o.precond == VEM_PREC_REG, o.precision == VEM_MIXED, gam);
+    if (o.precond == VEM_PREC_REG && o.reg_inner == VEM_REG_SCHWARZ) ensure_schwarz(h, gam, o.precision == VEM_MIXED);
     if (!user_rhs && h->bc == VEM_BC_FLUX) rhs = flux_rhs(h);
     ensure_workspace(h, m);
     double* V = h->Vb;

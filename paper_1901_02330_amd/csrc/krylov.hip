@@ -287,6 +287,88 @@ __global__ void __launch_bounds__(kPcgThreads) k_cg_update(int k, int64_t n, T* 
   }
 }
 
+// ---- CG on the face system F with the edge-patch Schwarz operator P (Block-Reg) -------------
+// The update kernel forms z = P r_new with r_new = r - alpha q gathered at the neighbouring rows
+// (r and q are complete when it starts), so the preconditioner costs no kernel of its own; the
+// residual is double-buffered by parity, since rows read their neighbours' old residual while
+// their own new one is written.
+//   [init]    z = P r0; x = 0; partials r0.z
+//   [product] k_cg_spmv: rho, beta = rho / rho_old; stop test; p = z + beta p_old; q = F p; partials p.q
+//   [update]  alpha = rho / p.q; x += alpha p; r_new = r - alpha q; z = P r_new; partials r_new.z
+template <typename T>
+__global__ void __launch_bounds__(kPcgThreads) k_scg_init(SellViewT<T> P, const T* __restrict__ r0,
+                                                          T* __restrict__ x, T* __restrict__ z, PcgState* st,
+                                                          double tol2, double* __restrict__ prho0) {
+  double acc[1] = {0.0};
+  for (int64_t row = xcd_block() * blockDim.x + threadIdx.x; row < P.rows;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    const T zi = sell_dot(P, row, r0);
+    z[row] = zi;
+    x[row] = T(0);
+    acc[0] += (double)r0[row] * (double)zi;
+  }
+  block_partials<1>(acc, prho0);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->gamma[0] = st->gamma[1] = 0.0;
+    st->gamma0 = 0.0;
+    st->tol2 = tol2;
+    st->count = 0;
+    st->done = 0;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kPcgThreads) k_scg_update(int k, SellViewT<T> P, T* __restrict__ x,
+                                                            const T* __restrict__ rold, T* __restrict__ rnew,
+                                                            T* __restrict__ z, const T* __restrict__ q,
+                                                            const T* __restrict__ p, PcgState* st,
+                                                            double* __restrict__ prho, const double* __restrict__ ppq) {
+  if (st->done) return;
+  const int G = gridDim.x;
+  const int cur = k & 1;
+  const double rho = block_sum_partials(prho + (size_t)cur * G, G, 1, 0);
+  const double pq = block_sum_partials(ppq, G, 1, 0);
+  if (!(pq > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->done = 2;
+    return;
+  }
+  const T a = (T)(rho / pq);
+  double acc[1] = {0.0};
+  for (int64_t row = xcd_block() * blockDim.x + threadIdx.x; row < P.rows;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t sl = row >> 6;
+    const int64_t base = P.slice_ptr[sl] + (row & 63);
+    const int len = P.slice_len[sl];
+    T sum = T(0);
+#pragma unroll 4
+    for (int j = 0; j < len; ++j) {
+      const int c = P.col[base + 64 * j];
+      sum += P.val[base + 64 * j] * (rold[c] - a * q[c]);
+    }
+    const T rn = rold[row] - a * q[row];
+    rnew[row] = rn;
+    x[row] += a * p[row];
+    z[row] = sum;
+    acc[0] += (double)rn * (double)sum;
+  }
+  block_partials<1>(acc, prho + (size_t)(1 - cur) * G);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->count += 1;
+    st->total += 1;
+  }
+}
+
+template <typename T>
+SellViewT<T> values_view(const Sell& A);
+template <>
+SellViewT<double> values_view<double>(const Sell& A) {
+  return view(A);
+}
+template <>
+SellViewT<float> values_view<float>(const Sell& A) {
+  return view32(A);
+}
+
 __global__ void k_to_f32(int64_t n, const double* __restrict__ x, float* __restrict__ y) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = (float)x[i];
@@ -459,5 +541,32 @@ void launch_pcg_iter32(hipStream_t s, int i, const Sell& A, const PcgWork32& w, 
   k_cg_spmv<float><<<P, kPcgThreads, 0, s>>>(i, view32(A), w.z, pold, pnew, w.w0, st, prho, ppq);
   k_cg_update<float><<<P, kPcgThreads, 0, s>>>(i, A.rows, w.x, w.r, w.z, w.w0, pnew, w.dinv, st, prho, ppq);
 }
+
+template <typename T>
+void launch_scg_init(hipStream_t s, const Sell& P, const PcgWorkT<T>& w, PcgState* st, double tol, double* part) {
+  k_scg_init<T><<<pcg_grid(P.rows), kPcgThreads, 0, s>>>(values_view<T>(P), w.r, w.x, w.z, st, tol * tol, part);
+}
+
+// work layout: x; r and w1 the two residual buffers; z; s and p the two direction buffers; w0 = q
+template <typename T>
+void launch_scg_iter(hipStream_t s, int i, const Sell& F, const Sell& P, const PcgWorkT<T>& w, PcgState* st,
+                     double* part) {
+  const int G = pcg_grid(F.rows);
+  double* prho = part;  // 2 x G slots
+  double* ppq = part + 2 * (size_t)G;
+  T* pold = (i & 1) ? w.p : w.s;
+  T* pnew = (i & 1) ? w.s : w.p;
+  T* rold = (i & 1) ? w.w1 : w.r;
+  T* rnew = (i & 1) ? w.r : w.w1;
+  k_cg_spmv<T><<<G, kPcgThreads, 0, s>>>(i, values_view<T>(F), w.z, pold, pnew, w.w0, st, prho, ppq);
+  k_scg_update<T><<<G, kPcgThreads, 0, s>>>(i, values_view<T>(P), w.x, rold, rnew, w.z, w.w0, pnew, st, prho, ppq);
+}
+
+template void launch_scg_init<double>(hipStream_t, const Sell&, const PcgWorkT<double>&, PcgState*, double, double*);
+template void launch_scg_init<float>(hipStream_t, const Sell&, const PcgWorkT<float>&, PcgState*, double, double*);
+template void launch_scg_iter<double>(hipStream_t, int, const Sell&, const Sell&, const PcgWorkT<double>&, PcgState*,
+                                      double*);
+template void launch_scg_iter<float>(hipStream_t, int, const Sell&, const Sell&, const PcgWorkT<float>&, PcgState*,
+                                     double*);
 
 }  // namespace vem

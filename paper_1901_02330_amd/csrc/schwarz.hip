@@ -1,0 +1,636 @@
+// Edge-patch additive Schwarz preconditioner for the regularised block of Block-Reg
+// (Section 5, eq. block_diag: A_gamma = M + B^T B / gamma).
+//
+// gamma^{-1} B^T B dominates A_gamma (B^T B / gamma ~ h^2 against M ~ h^3 per entry), and it
+// vanishes on divergence-free fluxes, so the small eigenvalues of A_gamma belong to fluxes that
+// circulate.  A flux through the faces around one mesh edge, turning about the edge, is
+// divergence-free in every cell it touches: the patches of faces that share an edge carry these
+// local circulations, and a Jacobi scaling (one DOF at a time) never sees them.
+//
+// Set-up (this file):
+//  - the mesh edges, as the distinct vertex pairs of the face loops (a stable radix sort of the
+//    pair keys; each edge lists its faces in ascending order);
+//  - order k: the interior DOFs of a cell couple only to that cell's DOFs (A_gamma is a sum of
+//    cell matrices), so they are condensed cell by cell: F = A_ff - A_fi A_ii^{-1} A_if on the
+//    face DOFs, with W = A_fi A_ii^{-1} and A_ii^{-1} kept for the right-hand side and the
+//    back-substitution.  At the lowest order there are no interior DOFs and F = A_gamma;
+//  - per edge e, the inverse of F restricted to the DOFs of its faces (dense, Gauss-Jordan in
+//    LDS, one wavefront per edge);
+//  - P = sum_e R_e^T F_e^{-1} R_e assembled by gathering: each row sums the inverses of the
+//    edges of its face, in the face loop's order (no atomics, same bits every run).
+// The CG on F preconditioned by P is in krylov.hip.
+#include <hipcub/hipcub.hpp>
+
+#include <climits>
+
+#include "vem_internal.h"
+
+namespace vem {
+namespace {
+
+constexpr int kT = 256;
+inline int grid(int64_t n) { return (int)((n + kT - 1) / kT); }
+// faces that share an edge with one face (its own included); more is rejected
+constexpr int kMaxNb = 160;
+// DOFs of one edge patch (faces around the edge times face DOFs); more is rejected
+constexpr int kMaxPatchDof = 80;
+
+__global__ void k_inc_face(int nf, const int* __restrict__ fptr, int* __restrict__ inc_face) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  for (int i = fptr[f]; i < fptr[f + 1]; ++i) inc_face[i] = f;
+}
+
+// key of the loop edge (v_a, v_{a+1}) of every face-loop incidence: min * nv + max
+__global__ void k_loop_keys(int nf, int nv, const int* __restrict__ fptr, const int* __restrict__ fvtx,
+                            unsigned long long* __restrict__ keys, int* __restrict__ vals) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  const int b = fptr[f], n = fptr[f + 1] - b;
+  for (int a = 0; a < n; ++a) {
+    const int v = fvtx[b + a], w = fvtx[b + (a + 1 == n ? 0 : a + 1)];
+    const unsigned long long lo = v < w ? v : w, hi = v < w ? w : v;
+    keys[b + a] = lo * (unsigned long long)nv + hi;
+    vals[b + a] = b + a;
+  }
+}
+
+__global__ void k_edge_flags(int64_t n, const unsigned long long* __restrict__ keys, int* __restrict__ flag) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) flag[j] = (j == 0 || keys[j] != keys[j - 1]) ? 1 : 0;
+}
+
+// edge ids from the flags' exclusive sum; faces of each edge; edge of each incidence
+__global__ void k_edge_lists(int64_t n, const int* __restrict__ flag, const int* __restrict__ pos,
+                             const int* __restrict__ vals, const int* __restrict__ inc_face, int* __restrict__ edge_ptr,
+                             int* __restrict__ edge_face, int* __restrict__ face_edge, int ne) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int e = pos[j] + flag[j] - 1;
+  if (flag[j]) edge_ptr[e] = (int)j;
+  const int i = vals[j];
+  edge_face[j] = inc_face[i];
+  face_edge[i] = e;
+  if (j == n - 1) edge_ptr[ne] = (int)n;
+}
+
+__global__ void k_max_patch(int ne, const int* __restrict__ edge_ptr, int* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  int m = e < ne ? edge_ptr[e + 1] - edge_ptr[e] : 0;
+  for (int o = 32; o > 0; o >>= 1) {
+    const int t = __shfl_xor(m, o, 64);
+    m = t > m ? t : m;
+  }
+  if ((threadIdx.x & 63) == 0 && m > 0) atomicMax(out, m);
+}
+
+// Faces sharing an edge with face f (f included), ascending and unique; returns the count, or -1
+// past kMaxNb.
+__device__ inline int face_nbrs(int f, const int* __restrict__ fptr, const int* __restrict__ face_edge,
+                                const int* __restrict__ edge_ptr, const int* __restrict__ edge_face, int* nb) {
+  int n = 0;
+  for (int i = fptr[f]; i < fptr[f + 1]; ++i) {
+    const int e = face_edge[i];
+    for (int j = edge_ptr[e]; j < edge_ptr[e + 1]; ++j) {
+      const int g = edge_face[j];
+      int k = n;
+      bool dup = false;
+      for (int q = 0; q < n; ++q)
+        if (nb[q] == g) dup = true;
+      if (dup) continue;
+      if (n == kMaxNb) return -1;
+      while (k > 0 && nb[k - 1] > g) {
+        nb[k] = nb[k - 1];
+        --k;
+      }
+      nb[k] = g;
+      ++n;
+    }
+  }
+  return n;
+}
+
+__global__ void k_p_rowlen(int nf, int nfd, const int* __restrict__ fptr, const int* __restrict__ face_edge,
+                           const int* __restrict__ edge_ptr, const int* __restrict__ edge_face, int* __restrict__ len,
+                           int* __restrict__ err) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  int nb[kMaxNb];
+  const int n = face_nbrs(f, fptr, face_edge, edge_ptr, edge_face, nb);
+  if (n < 0) *err = 1;
+  for (int b = 0; b < nfd; ++b) len[(int64_t)f * nfd + b] = n < 0 ? 0 : n * nfd;
+}
+
+__global__ void k_p_cols(int nf, int nfd, const int* __restrict__ fptr, const int* __restrict__ face_edge,
+                         const int* __restrict__ edge_ptr, const int* __restrict__ edge_face,
+                         const int* __restrict__ rowptr, int* __restrict__ col) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  int nb[kMaxNb];
+  const int n = face_nbrs(f, fptr, face_edge, edge_ptr, edge_face, nb);
+  if (n < 0) return;
+  for (int b = 0; b < nfd; ++b) {
+    int o = rowptr[(int64_t)f * nfd + b];
+    for (int t = 0; t < n; ++t)
+      for (int c = 0; c < nfd; ++c) col[o++] = nb[t] * nfd + c;
+  }
+}
+
+__global__ void k_patch_size(int ne, int nfd, const int* __restrict__ edge_ptr, int64_t* __restrict__ sz) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const int64_t n = (int64_t)(edge_ptr[e + 1] - edge_ptr[e]) * nfd;
+  sz[e] = n * n;
+}
+
+// face system pattern (order k): the face-DOF columns of A_gamma's face-DOF rows (interior DOFs are
+// numbered after every face DOF, so they end each row)
+__device__ inline int lower_bound_i32(const int* __restrict__ a, int n, int v) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] < v)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__global__ void k_fc_rowlen(int64_t nF, const int* __restrict__ Aptr, const int* __restrict__ Acol,
+                            int* __restrict__ len) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nF) return;
+  len[r] = lower_bound_i32(Acol + Aptr[r], Aptr[r + 1] - Aptr[r], (int)nF);
+}
+
+__global__ void k_fc_cols(int64_t nF, const int* __restrict__ Aptr, const int* __restrict__ Acol,
+                          const int* __restrict__ Fptr, int* __restrict__ Fcol) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nF) return;
+  const int n = Fptr[r + 1] - Fptr[r];
+  for (int k = 0; k < n; ++k) Fcol[Fptr[r] + k] = Acol[Aptr[r] + k];
+}
+
+// ---- values ----------------------------------------------------------------------------------
+
+__device__ inline bool fixed_face_dof(const int* bnd, int nfd, int64_t gid) { return bnd && bnd[gid / nfd]; }
+
+// Local A_gamma entry (i, j) of cell P in the cell's outward orientation:
+// nu_P M1_P[i][j] + gamma^{-1} sum_q B_P[q][i] B_P[q][j].
+__device__ inline double local_a(const double* __restrict__ M, const double* __restrict__ Bp, int nd, int npd,
+                                 double nu, double ig, int i, int j) {
+  double t = 0.0;
+  for (int q = 0; q < npd; ++q) t += Bp[q * nd + i] * Bp[q * nd + j];
+  return nu * M[(int64_t)i * nd + j] + ig * t;
+}
+
+// In-place inverse of the SPD n x n matrix a (row-major, in LDS) by Gauss-Jordan elimination
+// without pivoting; rk, ck: scratch rows of n.  All threads of the block take part.
+__device__ inline void gj_invert(double* a, double* rk, double* ck, int n) {
+  for (int k = 0; k < n; ++k) {
+    __syncthreads();
+    const double p = 1.0 / a[k * n + k];
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+      rk[t] = a[k * n + t] * p;
+      ck[t] = a[t * n + k];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+      const int i = t / n, j = t - i * n;
+      if (i == k && j == k)
+        a[t] = p;
+      else if (i == k)
+        a[t] = rk[j];
+      else if (j == k)
+        a[t] = -ck[i] * p;
+      else
+        a[t] -= ck[i] * rk[j];
+    }
+  }
+  __syncthreads();
+}
+
+// Per cell (one block): A_ii^{-1} and W = A_fi A_ii^{-1} (rows of prescribed face DOFs zero: A_gamma
+// holds identity rows and columns there).  LDS: nint^2 + 2 nint doubles.
+__global__ void k_cell_condense(DofLayout L, const int* __restrict__ cptr, const int* __restrict__ cface,
+                                const int64_t* __restrict__ lmat_ptr, const double* __restrict__ M1,
+                                const int64_t* __restrict__ lb_ptr, const double* __restrict__ Bdiv1,
+                                const double* __restrict__ nu, double ig, const int* __restrict__ bnd,
+                                const int* __restrict__ ldof_ptr, double* __restrict__ Aiinv,
+                                double* __restrict__ W) {
+  extern __shared__ double sh[];
+  const int P = blockIdx.x;
+  const int ni = L.nint;
+  double* a = sh;
+  double* rk = sh + ni * ni;
+  double* ck = rk + ni;
+  const int F = cptr[P + 1] - cptr[P], Fn = F * L.nfd, nd = Fn + ni;
+  const double* M = M1 + lmat_ptr[P];
+  const double* Bp = Bdiv1 + lb_ptr[P];
+  const double nuP = nu[P];
+  for (int t = threadIdx.x; t < ni * ni; t += blockDim.x) {
+    const int i = t / ni, j = t - i * ni;
+    a[t] = local_a(M, Bp, nd, L.npd, nuP, ig, Fn + i, Fn + j);
+  }
+  gj_invert(a, rk, ck, ni);
+  for (int t = threadIdx.x; t < ni * ni; t += blockDim.x) Aiinv[(int64_t)P * ni * ni + t] = a[t];
+  const int64_t wo = ((int64_t)ldof_ptr[P] - (int64_t)P * ni) * ni;
+  for (int l = threadIdx.x; l < Fn; l += blockDim.x) {
+    const int j = l / L.nfd;
+    const bool fixed = bnd && bnd[cface[cptr[P] + j]];
+    double af[64];
+    for (int b = 0; b < ni; ++b) af[b] = fixed ? 0.0 : local_a(M, Bp, nd, L.npd, nuP, ig, l, Fn + b);
+    for (int c = 0; c < ni; ++c) {
+      double t = 0.0;
+      for (int b = 0; b < ni; ++b) t += af[b] * a[b * ni + c];
+      W[wo + (int64_t)l * ni + c] = t;
+    }
+  }
+}
+
+// Face system values (order k): row r (face DOF) of F = sum over its cells of
+// sigma_r sigma_g (A_ff - W A_if)[l_r][l_g], written to the SELL slots in column order.
+__global__ void k_fc_values(DofLayout L, const int* __restrict__ cptr, const int* __restrict__ cface,
+                            const int8_t* __restrict__ csign, const int* __restrict__ ldof_ptr,
+                            const int* __restrict__ sorted_gid, const int* __restrict__ sorted_l,
+                            const int* __restrict__ face_cell, const int* __restrict__ face_lidx,
+                            const int64_t* __restrict__ lmat_ptr, const double* __restrict__ M1,
+                            const int64_t* __restrict__ lb_ptr, const double* __restrict__ Bdiv1,
+                            const double* __restrict__ nu, double ig, const int* __restrict__ bnd,
+                            const double* __restrict__ W, const int* __restrict__ Fslice, double* __restrict__ Fval) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nF = (int64_t)L.nf * L.nfd;
+  if (r >= nF) return;
+  const int f = (int)(r / L.nfd), beta = (int)(r - (int64_t)f * L.nfd);
+  const bool fixed_row = bnd && bnd[f];
+  int P[2], lr[2], n = 0;
+  for (int side = 0; side < 2; ++side) {
+    const int c = face_cell[2 * f + side];
+    if (c >= 0) {
+      P[n] = c;
+      lr[n] = face_lidx[2 * f + side] * L.nfd + beta;
+      ++n;
+    }
+  }
+  if (n == 2 && P[0] > P[1]) {
+    int t = P[0];
+    P[0] = P[1];
+    P[1] = t;
+    t = lr[0];
+    lr[0] = lr[1];
+    lr[1] = t;
+  }
+  int nd[2], Fn[2], na[2];
+  double sr[2];
+  const int* gl[2];
+  const int* ll[2];
+  int64_t wo[2];
+  for (int c = 0; c < n; ++c) {
+    const int F = cptr[P[c] + 1] - cptr[P[c]];
+    Fn[c] = F * L.nfd;
+    nd[c] = Fn[c] + L.nint;
+    sr[c] = (double)csign[cptr[P[c]] + lr[c] / L.nfd];
+    gl[c] = sorted_gid + ldof_ptr[P[c]];
+    ll[c] = sorted_l + ldof_ptr[P[c]];
+    na[c] = Fn[c];  // the face DOFs come first in the sorted list
+    wo[c] = ((int64_t)ldof_ptr[P[c]] - (int64_t)P[c] * L.nint) * L.nint;
+  }
+  const int64_t base = (int64_t)Fslice[r >> 6] + (r & 63);
+  int k = 0, ia = 0, ib = 0;
+  const int nb = n == 2 ? na[1] : 0;
+  while (ia < na[0] || ib < nb) {
+    const int ga = ia < na[0] ? gl[0][ia] : INT_MAX, gb = ib < nb ? gl[1][ib] : INT_MAX;
+    const int g = ga < gb ? ga : gb;
+    double v = 0.0;
+    for (int c = 0; c < n; ++c) {
+      int idx;
+      if (c == 0) {
+        if (ga != g) continue;
+        idx = ia;
+      } else {
+        if (gb != g) continue;
+        idx = ib;
+      }
+      const int lg = ll[c][idx];
+      const double sg = (double)csign[cptr[P[c]] + lg / L.nfd];
+      const double* M = M1 + lmat_ptr[P[c]];
+      const double* Bp = Bdiv1 + lb_ptr[P[c]];
+      const double nuP = nu[P[c]];
+      double t = local_a(M, Bp, nd[c], L.npd, nuP, ig, lr[c], lg);
+      const bool fixed_col = bnd && bnd[g / L.nfd];
+      if (!fixed_row && !fixed_col) {
+        const double* Wr = W + wo[c] + (int64_t)lr[c] * L.nint;
+        for (int a = 0; a < L.nint; ++a) t -= Wr[a] * local_a(M, Bp, nd[c], L.npd, nuP, ig, lg, Fn[c] + a);
+      }
+      v += sr[c] * sg * t;
+    }
+    if (ga == g) ++ia;
+    if (gb == g) ++ib;
+    if (fixed_row || (bnd && bnd[g / L.nfd])) v = (g == r) ? 1.0 : 0.0;
+    Fval[base + 64 * (int64_t)(k++)] = v;
+  }
+}
+
+// Entry (r, c) of a matrix given by its CSR pattern (sorted columns) and SELL values; 0 where the
+// pattern has none.
+__device__ inline double csr_sell_entry(const int* __restrict__ rowptr, const int* __restrict__ col,
+                                        const int* __restrict__ slice_ptr, const double* __restrict__ val, int64_t r,
+                                        int c) {
+  const int b = rowptr[r], n = rowptr[r + 1] - b;
+  const int k = lower_bound_i32(col + b, n, c);
+  if (k >= n || col[b + k] != c) return 0.0;
+  return val[(int64_t)slice_ptr[r >> 6] + (r & 63) + 64 * (int64_t)k];
+}
+
+// One block per edge: the face system restricted to the DOFs of the edge's faces, inverted.
+__global__ void k_edge_inv(int ne, int nfd, const int* __restrict__ edge_ptr, const int* __restrict__ edge_face,
+                           const int* __restrict__ Fptr, const int* __restrict__ Fcol,
+                           const int* __restrict__ Fslice, const double* __restrict__ Fval,
+                           const int64_t* __restrict__ einv_ptr, double* __restrict__ einv) {
+  extern __shared__ double sh[];
+  const int e = blockIdx.x;
+  if (e >= ne) return;
+  const int m = edge_ptr[e + 1] - edge_ptr[e], n = m * nfd;
+  const int* fe = edge_face + edge_ptr[e];
+  double* a = sh;
+  double* rk = sh + n * n;
+  double* ck = rk + n;
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) {
+    const int i = t / n, j = t - i * n;
+    const int64_t gi = (int64_t)fe[i / nfd] * nfd + i % nfd;
+    const int gj = fe[j / nfd] * nfd + j % nfd;
+    a[t] = csr_sell_entry(Fptr, Fcol, Fslice, Fval, gi, gj);
+  }
+  gj_invert(a, rk, ck, n);
+  double* out = einv + einv_ptr[e];
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) out[t] = a[t];
+}
+
+// P row r = (f, beta): the edges of f in loop order, each adding its inverse's row for (f, beta).
+__global__ void k_p_values(int nf, int nfd, const int* __restrict__ fptr, const int* __restrict__ face_edge,
+                           const int* __restrict__ edge_ptr, const int* __restrict__ edge_face,
+                           const int64_t* __restrict__ einv_ptr, const double* __restrict__ einv,
+                           const int* __restrict__ Pptr, const int* __restrict__ Pcol,
+                           const int* __restrict__ Pslice, double* __restrict__ Pval) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= (int64_t)nf * nfd) return;
+  const int f = (int)(r / nfd), beta = (int)(r - (int64_t)f * nfd);
+  const int rb = Pptr[r], rn = Pptr[r + 1] - rb;
+  const int64_t base = (int64_t)Pslice[r >> 6] + (r & 63);
+  for (int k = 0; k < rn; ++k) Pval[base + 64 * (int64_t)k] = 0.0;
+  for (int i = fptr[f]; i < fptr[f + 1]; ++i) {
+    const int e = face_edge[i];
+    const int* fe = edge_face + edge_ptr[e];
+    const int m = edge_ptr[e + 1] - edge_ptr[e], n = m * nfd;
+    int pf = 0;
+    while (fe[pf] != f) ++pf;
+    const double* inv = einv + einv_ptr[e] + (int64_t)(pf * nfd + beta) * n;
+    for (int j = 0; j < m; ++j) {
+      const int k0 = lower_bound_i32(Pcol + rb, rn, fe[j] * nfd);
+      for (int c = 0; c < nfd; ++c) Pval[base + 64 * (int64_t)(k0 + c)] += inv[j * nfd + c];
+    }
+  }
+}
+
+__global__ void k_round32(int64_t n, const double* __restrict__ x, float* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+
+// ---- inner solve: right-hand side and back-substitution --------------------------------------
+
+template <typename T>
+__global__ void k_schwarz_rhs(DofLayout L, const int* __restrict__ cptr, const int8_t* __restrict__ csign,
+                              const int* __restrict__ face_cell, const int* __restrict__ face_lidx,
+                              const int* __restrict__ ldof_ptr, const double* __restrict__ W,
+                              const double* __restrict__ v, T* __restrict__ r0) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nF = (int64_t)L.nf * L.nfd;
+  if (r >= nF) return;
+  double t = v[r];
+  if (L.nint > 0) {
+    const int f = (int)(r / L.nfd), beta = (int)(r - (int64_t)f * L.nfd);
+    for (int side = 0; side < 2; ++side) {
+      const int P = face_cell[2 * f + side];
+      if (P < 0) continue;
+      const int j = face_lidx[2 * f + side];
+      const int l = j * L.nfd + beta;
+      const double s = (double)csign[cptr[P] + j];
+      const double* Wr = W + ((int64_t)ldof_ptr[P] - (int64_t)P * L.nint) * L.nint + (int64_t)l * L.nint;
+      const double* vi = v + nF + (int64_t)P * L.nint;
+      double u = 0.0;
+      for (int a = 0; a < L.nint; ++a) u += Wr[a] * vi[a];
+      t -= s * u;
+    }
+  }
+  r0[r] = (T)t;
+}
+
+__global__ void k_schwarz_back(DofLayout L, const int* __restrict__ cptr, const int* __restrict__ cface,
+                               const int8_t* __restrict__ csign, const int* __restrict__ ldof_ptr,
+                               const double* __restrict__ Aiinv, const double* __restrict__ W,
+                               const double* __restrict__ v, double* __restrict__ z) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nF = (int64_t)L.nf * L.nfd;
+  if (t >= (int64_t)L.nc * L.nint) return;
+  const int P = (int)(t / L.nint), a = (int)(t - (int64_t)P * L.nint);
+  const double* vi = v + nF + (int64_t)P * L.nint;
+  const double* Ai = Aiinv + (int64_t)P * L.nint * L.nint + (int64_t)a * L.nint;
+  double acc = 0.0;
+  for (int b = 0; b < L.nint; ++b) acc += Ai[b] * vi[b];
+  const int s0 = cptr[P], F = cptr[P + 1] - s0;
+  const double* Wc = W + ((int64_t)ldof_ptr[P] - (int64_t)P * L.nint) * L.nint + a;
+  for (int j = 0; j < F; ++j) {
+    const double s = (double)csign[s0 + j];
+    const int64_t g0 = (int64_t)cface[s0 + j] * L.nfd;
+    for (int b = 0; b < L.nfd; ++b) acc -= Wc[(int64_t)(j * L.nfd + b) * L.nint] * s * z[g0 + b];
+  }
+  z[nF + t] = acc;
+}
+
+}  // namespace
+
+void schwarz_build(hipStream_t s, Scratch& tmp, const SchwarzMesh& m, const DofLayout& L, const Csr& A,
+                   Schwarz& X) {
+  X.built = X.ready = X.ready32 = false;
+  // incidences of the face loops
+  int64_t ninc = 0;
+  {
+    int h_last = 0;
+    VEM_HIP(hipMemcpyAsync(&h_last, m.fptr + m.nf, sizeof(int), hipMemcpyDeviceToHost, s));
+    VEM_HIP(hipStreamSynchronize(s));
+    ninc = h_last;
+  }
+  VEM_REQUIRE(ninc > 0, VEM_EINVAL, "mesh without face loops");
+  DBuf<unsigned long long> keys, keys_out;
+  DBuf<int> vals, vals_out, inc_face, flag, pos;
+  keys.alloc(ninc);
+  keys_out.alloc(ninc);
+  vals.alloc(ninc);
+  vals_out.alloc(ninc);
+  inc_face.alloc(ninc);
+  flag.alloc(ninc + 1);
+  pos.alloc(ninc + 1);
+  k_inc_face<<<grid(m.nf), kT, 0, s>>>(m.nf, m.fptr, inc_face);
+  k_loop_keys<<<grid(m.nf), kT, 0, s>>>(m.nf, m.nv, m.fptr, m.fvtx, keys, vals);
+  VEM_HIP(hipGetLastError());
+  int end_bit = 1;
+  const unsigned long long kmax = (unsigned long long)m.nv * (unsigned long long)m.nv;
+  while (end_bit < 64 && (1ULL << end_bit) <= kmax) ++end_bit;
+  // the hipcub storage is sized for the sort and for every later scan before the sort is enqueued,
+  // so that no scan reallocates it while the sort may still run
+  const int64_t nF = (int64_t)L.nf * L.nfd;
+  scan_reserve(tmp, std::max<int64_t>(ninc, nF));
+  size_t bytes = 0;
+  VEM_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, keys.p, keys_out.p, vals.p, vals_out.p, (int)ninc, 0,
+                                             end_bit, s));
+  tmp.cub.reserve(bytes > 0 ? bytes : 1);
+  VEM_HIP(hipcub::DeviceRadixSort::SortPairs(tmp.cub.p, bytes, keys.p, keys_out.p, vals.p, vals_out.p, (int)ninc, 0,
+                                             end_bit, s));
+  k_edge_flags<<<grid(ninc), kT, 0, s>>>(ninc, keys_out, flag);
+  VEM_HIP(hipGetLastError());
+  const int64_t ne = scan_i32(s, tmp, flag, ninc, pos);
+  X.ne = ne;
+  X.edge_ptr.alloc(ne + 1);
+  X.edge_face.alloc(ninc);
+  X.face_edge.alloc(ninc);
+  k_edge_lists<<<grid(ninc), kT, 0, s>>>(ninc, flag, pos, vals_out, inc_face, X.edge_ptr, X.edge_face, X.face_edge,
+                                          (int)ne);
+  VEM_HIP(hipGetLastError());
+  // largest patch
+  {
+    DBuf<int> mx;
+    mx.alloc(2);
+    VEM_HIP(hipMemsetAsync(mx.p, 0, 2 * sizeof(int), s));
+    k_max_patch<<<grid(ne), kT, 0, s>>>((int)ne, X.edge_ptr, mx.p);
+    VEM_HIP(hipGetLastError());
+    int h_mx = 0;
+    VEM_HIP(hipMemcpyAsync(&h_mx, mx.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    VEM_HIP(hipStreamSynchronize(s));
+    X.max_patch = h_mx;
+  }
+  VEM_REQUIRE(X.max_patch * L.nfd <= kMaxPatchDof, VEM_EINVAL,
+              "edge patch of " + std::to_string(X.max_patch) + " faces exceeds the Schwarz preconditioner's limit");
+  // pattern of P on the face DOFs
+  X.nF = nF;
+  {
+    DBuf<int> len, err;
+    len.alloc(nF + 1);
+    err.alloc(1);
+    VEM_HIP(hipMemsetAsync(err.p, 0, sizeof(int), s));
+    k_p_rowlen<<<grid(m.nf), kT, 0, s>>>(m.nf, L.nfd, m.fptr, X.face_edge, X.edge_ptr, X.edge_face, len, err);
+    VEM_HIP(hipGetLastError());
+    X.Pc.rows = nF;
+    X.Pc.rowptr.alloc(nF + 1);
+    X.Pc.nnz = scan_i32(s, tmp, len, nF, X.Pc.rowptr);
+    int h_err = 0;
+    VEM_HIP(hipMemcpyAsync(&h_err, err.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    VEM_HIP(hipStreamSynchronize(s));
+    VEM_REQUIRE(h_err == 0, VEM_EINVAL, "a face shares edges with more faces than the Schwarz preconditioner holds");
+    X.Pc.col.alloc(X.Pc.nnz);
+    X.Pc.val.alloc(X.Pc.nnz);
+    k_p_cols<<<grid(m.nf), kT, 0, s>>>(m.nf, L.nfd, m.fptr, X.face_edge, X.edge_ptr, X.edge_face, X.Pc.rowptr,
+                                        X.Pc.col);
+    VEM_HIP(hipGetLastError());
+  }
+  // the order-k face system: face-DOF part of A_gamma's pattern
+  if (L.nint > 0) {
+    DBuf<int> len;
+    len.alloc(nF + 1);
+    k_fc_rowlen<<<grid(nF), kT, 0, s>>>(nF, A.rowptr, A.col, len);
+    VEM_HIP(hipGetLastError());
+    X.Fc.rows = nF;
+    X.Fc.rowptr.alloc(nF + 1);
+    X.Fc.nnz = scan_i32(s, tmp, len, nF, X.Fc.rowptr);
+    X.Fc.col.alloc(X.Fc.nnz);
+    X.Fc.val.alloc(X.Fc.nnz);
+    k_fc_cols<<<grid(nF), kT, 0, s>>>(nF, A.rowptr, A.col, X.Fc.rowptr, X.Fc.col);
+    VEM_HIP(hipGetLastError());
+    const Csr* csr[2] = {&X.Fc, &X.Pc};
+    Sell* sell[2] = {&X.Fs, &X.Ps};
+    build_sells(s, tmp, csr, sell, 2);
+    X.Aiinv.alloc((size_t)m.nc * L.nint * L.nint);
+    // W: (sum of face DOFs over the cells) x nint
+    int h_ld = 0;
+    VEM_HIP(hipMemcpyAsync(&h_ld, m.ldof_ptr + m.nc, sizeof(int), hipMemcpyDeviceToHost, s));
+    VEM_HIP(hipStreamSynchronize(s));
+    X.W.alloc(((size_t)h_ld - (size_t)m.nc * L.nint) * L.nint);
+  } else {
+    const Csr* csr[1] = {&X.Pc};
+    Sell* sell[1] = {&X.Ps};
+    build_sells(s, tmp, csr, sell, 1);
+  }
+  // patch inverse offsets
+  {
+    DBuf<int64_t> sz;
+    sz.alloc(ne + 1);
+    k_patch_size<<<grid(ne), kT, 0, s>>>((int)ne, L.nfd, X.edge_ptr, sz);
+    VEM_HIP(hipGetLastError());
+    X.einv_ptr.alloc(ne + 1);
+    const int64_t tot = scan_i64(s, tmp, sz, ne, X.einv_ptr);
+    X.einv.alloc(tot);
+  }
+  VEM_HIP(hipStreamSynchronize(s));  // the local temporaries above are freed on return
+  X.built = true;
+}
+
+void schwarz_values(hipStream_t s, const SchwarzMesh& m, const DofLayout& L, const int64_t* lmat_ptr,
+                    const double* M1, const int64_t* lb_ptr, const double* Bdiv1, const double* nu,
+                    double inv_gamma, const int* bnd, const Csr& A, const Sell& As, Schwarz& X) {
+  VEM_REQUIRE(X.built, VEM_EINVAL, "Schwarz pattern not built");
+  const Csr& F = L.nint > 0 ? X.Fc : A;
+  const Sell& Fs = schwarz_face_sell(X, As, L);
+  if (L.nint > 0) {
+    const size_t lds = ((size_t)L.nint * L.nint + 2 * L.nint) * sizeof(double);
+    k_cell_condense<<<m.nc, 64, lds, s>>>(L, m.cptr, m.cface, lmat_ptr, M1, lb_ptr, Bdiv1, nu, inv_gamma, bnd,
+                                          m.ldof_ptr, X.Aiinv, X.W);
+    VEM_HIP(hipGetLastError());
+    k_fc_values<<<grid(X.nF), kT, 0, s>>>(L, m.cptr, m.cface, m.csign, m.ldof_ptr, m.sorted_gid, m.sorted_l,
+                                           m.face_cell, m.face_lidx, lmat_ptr, M1, lb_ptr, Bdiv1, nu, inv_gamma, bnd,
+                                           X.W, X.Fs.slice_ptr, X.Fs.val);
+    VEM_HIP(hipGetLastError());
+  }
+  const int n = X.max_patch * L.nfd;
+  const size_t lds = ((size_t)n * n + 2 * n) * sizeof(double);
+  if (X.ne > 0)
+    k_edge_inv<<<(int)X.ne, 64, lds, s>>>((int)X.ne, L.nfd, X.edge_ptr, X.edge_face, F.rowptr, F.col, Fs.slice_ptr,
+                                           Fs.val, X.einv_ptr, X.einv);
+  VEM_HIP(hipGetLastError());
+  k_p_values<<<grid(X.nF), kT, 0, s>>>(m.nf, L.nfd, m.fptr, X.face_edge, X.edge_ptr, X.edge_face, X.einv_ptr, X.einv,
+                                        X.Pc.rowptr, X.Pc.col, X.Ps.slice_ptr, X.Ps.val);
+  VEM_HIP(hipGetLastError());
+  X.ready = true;
+  X.ready32 = false;
+}
+
+void schwarz_round32(hipStream_t s, const DofLayout& L, Schwarz& X) {
+  X.Ps.val32.alloc(X.Ps.nnz);
+  k_round32<<<1024, kT, 0, s>>>(X.Ps.nnz, X.Ps.val, X.Ps.val32);
+  if (L.nint > 0) {
+    X.Fs.val32.alloc(X.Fs.nnz);
+    k_round32<<<1024, kT, 0, s>>>(X.Fs.nnz, X.Fs.val, X.Fs.val32);
+  }
+  VEM_HIP(hipGetLastError());
+  X.ready32 = true;
+}
+
+template <typename T>
+void launch_schwarz_rhs(hipStream_t s, const SchwarzMesh& m, const DofLayout& L, const Schwarz& X, const int* bnd,
+                        const double* v, T* r0) {
+  (void)bnd;  // W rows of prescribed DOFs are zero
+  k_schwarz_rhs<T><<<grid(X.nF), kT, 0, s>>>(L, m.cptr, m.csign, m.face_cell, m.face_lidx, m.ldof_ptr, X.W, v, r0);
+}
+template void launch_schwarz_rhs<double>(hipStream_t, const SchwarzMesh&, const DofLayout&, const Schwarz&,
+                                         const int*, const double*, double*);
+template void launch_schwarz_rhs<float>(hipStream_t, const SchwarzMesh&, const DofLayout&, const Schwarz&,
+                                        const int*, const double*, float*);
+
+void launch_schwarz_back(hipStream_t s, const SchwarzMesh& m, const DofLayout& L, const Schwarz& X,
+                         const double* v, double* z) {
+  const int64_t n = (int64_t)L.nc * L.nint;
+  if (n > 0)
+    k_schwarz_back<<<grid(n), kT, 0, s>>>(L, m.cptr, m.cface, m.csign, m.ldof_ptr, X.Aiinv, X.W, v, z);
+}
+
+}  // namespace vem

@@ -314,6 +314,66 @@ void launch_pcg_init32p(hipStream_t s, const Sell& A, const PcgWork32& w, const 
 void launch_pcg_iter32p(hipStream_t s, int i, const Sell& A, const PcgWork32& w, PcgState* st, double* part);
 void launch_to_f64(hipStream_t s, int64_t n, const float* x, double* y);
 
+// ---- edge-patch additive Schwarz for the regularised block (Block-Reg) ----
+// Face system: the lowest order uses A_gamma itself; the order-k element condenses the interior
+// DOFs of each cell (A_gamma is a sum of cell matrices and an interior DOF belongs to one cell),
+// leaving F = A_ff - A_fi A_ii^{-1} A_if on the face DOFs.  The preconditioner of the CG on F is
+// P = sum_e R_e^T F_e^{-1} R_e over the mesh edges e, R_e restricting to the DOFs of the faces
+// that contain e (the patches that hold the local divergence-free fields).
+struct Schwarz {
+  bool built = false;  // pattern of the current discretisation
+  bool ready = false;  // values for the current coefficient, gamma and boundary data
+  bool ready32 = false;
+  double gamma = 0.0;
+  int64_t ne = 0, nF = 0;
+  int max_patch = 0;                 // largest number of faces around an edge
+  DBuf<int> edge_ptr, edge_face;     // faces of each edge, ascending
+  DBuf<int> face_edge;               // edge of each face-loop incidence (face_ptr order)
+  DBuf<int64_t> einv_ptr;            // offsets of the patch inverses
+  DBuf<double> einv;
+  Csr Fc;                            // face system (order k only; the lowest order uses A)
+  Sell Fs;
+  Csr Pc;                            // the Schwarz operator on the face DOFs
+  Sell Ps;
+  DBuf<int64_t> w_ptr;               // order k: per cell W = A_fi A_ii^{-1} (face DOFs x nint)
+  DBuf<double> W, Aiinv;             // and A_ii^{-1} (nint x nint)
+};
+struct SchwarzMesh {
+  int nv, nf, nc;
+  const int *fptr, *fvtx, *cptr, *cface, *face_cell, *face_lidx, *ldof_ptr, *sorted_gid, *sorted_l;
+  const int8_t* csign;
+};
+// edges and patterns (coefficient-free; synchronises)
+void schwarz_build(hipStream_t s, Scratch& tmp, const SchwarzMesh& m, const DofLayout& L, const Csr& A,
+                   Schwarz& X);
+// values for nu and gamma (A / As: the assembled A_gamma, used directly at the lowest order)
+void schwarz_values(hipStream_t s, const SchwarzMesh& m, const DofLayout& L, const int64_t* lmat_ptr,
+                    const double* M1, const int64_t* lb_ptr, const double* Bdiv1, const double* nu,
+                    double inv_gamma, const int* bnd, const Csr& A, const Sell& As, Schwarz& X);
+// FP32 roundings of P and (order k) of the face system, for mixed-precision inner solves
+void schwarz_round32(hipStream_t s, const DofLayout& L, Schwarz& X);
+// the face system's SELL (As at the lowest order) and CSR pattern
+inline const Sell& schwarz_face_sell(const Schwarz& X, const Sell& As, const DofLayout& L) {
+  return L.nint > 0 ? X.Fs : As;
+}
+// r0 = v_f - sum_P sigma W_P v_{i,P} (order k) or v_f (lowest order), in T
+template <typename T>
+void launch_schwarz_rhs(hipStream_t s, const SchwarzMesh& m, const DofLayout& L, const Schwarz& X, const int* bnd,
+                        const double* v, T* r0);
+// z_i = A_ii^{-1} v_i - W^T sigma x_f on the interior DOFs (order k only)
+void launch_schwarz_back(hipStream_t s, const SchwarzMesh& m, const DofLayout& L, const Schwarz& X,
+                         const double* v, double* z);
+// CG on the face system F with the Schwarz operator P, two kernels per iteration:
+//   [product] beta, stop test; p = z + beta p_old; q = F p; partials p.q
+//   [update]  alpha; x += alpha p; r_new = r - alpha q; z = P (r - alpha q); partials r_new.z
+// Work layout: x, r (and w1: the two residual buffers), z, s/p (the two direction buffers),
+// w0 = q.  T = double, or float with FP64 dot products.
+template <typename T>
+void launch_scg_init(hipStream_t s, const Sell& P, const PcgWorkT<T>& w, PcgState* st, double tol, double* part);
+template <typename T>
+void launch_scg_iter(hipStream_t s, int i, const Sell& F, const Sell& P, const PcgWorkT<T>& w, PcgState* st,
+                     double* part);
+
 // host utilities
 void gauss_jacobi01(int n, int alpha, double* t, double* w);  // int_0^1 (1-t)^alpha g(t) dt
 void tet_reference_rule(int n, std::vector<double>& pts, std::vector<double>& w);

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvem_mi35
 
 VEM_LO, VEM_PAPER = 0, 1
 PREC = {"schur": 0, "reg": 1, "none": 2}
-MATS = {"K": 0, "schur": 1, "reg": 2}
+MATS = {"K": 0, "schur": 1, "reg": 2, "reg_face": 3, "reg_schwarz": 4}
 STATUS = {0: "VEM_OK", 1: "VEM_NOT_CONVERGED", -1: "VEM_EINVAL", -2: "VEM_EBADMESH", -3: "VEM_ENOMEM",
           -4: "VEM_EHIP", -5: "VEM_EBREAKDOWN", -6: "VEM_ENAN"}
 
@@ -38,7 +38,7 @@ class Sizes(ctypes.Structure):
         ("nnz_K", c_int64), ("nnz_schur", c_int64), ("nnz_reg", c_int64),
         ("n_qp_cell", c_int64), ("n_qp_face", c_int64),
         ("load_points", ctypes.c_int32), ("max_cell_faces", ctypes.c_int32),
-        ("h", c_double), ("gamma", c_double),
+        ("h", c_double), ("gamma", c_double), ("n_face_dofs", c_int64),
     ]
 
 
@@ -48,6 +48,7 @@ class SolveOpts(ctypes.Structure):
         ("use_x0", ctypes.c_int32), ("tol", c_double), ("inner_tol", c_double),
         ("inner_maxit", ctypes.c_int32), ("inner_check", ctypes.c_int32), ("gamma", c_double),
         ("precision", ctypes.c_int32), ("use_graphs", ctypes.c_int32), ("inner_form", ctypes.c_int32),
+        ("reg_inner", ctypes.c_int32),
     ]
 
 
@@ -255,7 +256,7 @@ class Solver:
     @_ordered
     def solve(self, precond="schur", tol=1e-8, restart=30, maxit=5000, inner_tol=1e-6, inner_maxit=5000,
               inner_check=32, gamma=0.0, x0=None, precision="fp64", rhs=None, graphs=False,
-              inner_form="pipelined"):
+              inner_form="pipelined", reg_inner="schwarz"):
         t = self.torch
         sz = self.sizes()
         o = SolveOpts()
@@ -267,6 +268,7 @@ class Solver:
         o.precision = {"fp64": 0, "mixed": 1}[precision]
         o.use_graphs = 1 if graphs else 0
         o.inner_form = {"pipelined": 0, "classical": 1}[inner_form]
+        o.reg_inner = {"jacobi": 0, "schwarz": 1}[reg_inner]
         if x0 is not None:
             u = self._dev(x0[0], t.float64).clone()
             p = self._dev(x0[1], t.float64).clone()
@@ -307,9 +309,15 @@ class Solver:
     def export_csr(self, which="K"):
         t = self.torch
         sz = self.sizes()
-        rows = {"K": sz["n"], "schur": sz["n_p"], "reg": sz["n_u"]}[which]
-        nnz = {"K": sz["nnz_K"], "schur": sz["nnz_schur"], "reg": sz["nnz_reg"]}[which]
+        rows = {"K": sz["n"], "schur": sz["n_p"], "reg": sz["n_u"], "reg_face": sz["n_face_dofs"],
+                "reg_schwarz": sz["n_face_dofs"]}[which]
         rp = t.empty(rows + 1, dtype=t.int32, device=self.device)
+        if which in ("reg_face", "reg_schwarz"):
+            # the Schwarz patterns are built on first use: the row offsets give their size
+            self._check(self.lib.vem_export_csr(self.h, MATS[which], _ptr(rp), None, None))
+            nnz = int(rp[-1].item())
+        else:
+            nnz = {"K": sz["nnz_K"], "schur": sz["nnz_schur"], "reg": sz["nnz_reg"]}[which]
         col = t.empty(nnz, dtype=t.int32, device=self.device)
         val = t.empty(nnz, dtype=t.float64, device=self.device)
         self._check(self.lib.vem_export_csr(self.h, MATS[which], _ptr(rp), _ptr(col), _ptr(val)))
@@ -326,7 +334,7 @@ class Solver:
     def time_kernel(self, which="cg_schur", reps=50):
         """Mean duration (ms) of one launch of a hot kernel, timed with HIP events, and its algorithmic bytes."""
         code = {"spmv": 0, "cg_schur": 1, "cg_reg": 2, "cg_schur32": 3, "cg_reg32": 4, "cg_schur32p": 5,
-                "cg_reg32p": 6}[which]
+                "cg_reg32p": 6, "cg_reg_schwarz": 7, "cg_reg_schwarz32": 8}[which]
         ms, nb = c_double(), c_double()
         self._check(self.lib.vem_time_kernel(self.h, code, int(reps), byref(ms), byref(nb)))
         return ms.value, nb.value

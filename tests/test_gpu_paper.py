@@ -103,7 +103,8 @@ def test_paper_order3_solve_with_classical_inner_cg():
     m = cube_mesh(3, 2, 2)
     nu = 1.0 / lognormal_field(12, 1.0, 7)
     s = solver_for(m, 3, nu=nu, rhs=SineSolution())
-    u, p, info = s.solve(precond="reg", tol=1e-10, maxit=500, inner_tol=1e-4, inner_form="classical")
+    u, p, info = s.solve(precond="reg", tol=1e-10, maxit=500, inner_tol=1e-4, inner_form="classical",
+                         reg_inner="jacobi")
     assert info["converged"], info
     d = discretize_paper(m, nu=nu, rhs=SineSolution(), k=3)
     u, p = u.cpu().numpy(), p.cpu().numpy()

@@ -278,7 +278,8 @@ def test_mixed_precision_capped_inner_solves(precond, cap, inner_tol):
     m = cube_mesh(6, 7, 5)
     nu = 1.0 / lognormal_field(210, 2.0, 0)
     s = gpu_solver(m, nu=nu, rhs=SineSolution())
-    kw = dict(precond=precond, tol=1e-10, maxit=3000, inner_tol=inner_tol, inner_maxit=cap)
+    # the Jacobi inner preconditioner (the FP32 pipelined iteration is its form)
+    kw = dict(precond=precond, tol=1e-10, maxit=3000, inner_tol=inner_tol, inner_maxit=cap, reg_inner="jacobi")
     u, p, info = s.solve(precision="mixed", **kw)
     _, _, info64 = s.solve(**kw)
     assert info["converged"], info
@@ -308,7 +309,8 @@ def test_graph_replays_match_eager(precision, cap):
     nu = 1.0 / lognormal_field(9 * 8 * 7, 2.0, 3)
     s = gpu_solver(m, nu=nu, rhs=SineSolution())
     for precond in ("schur", "reg"):
-        kw = dict(precond=precond, tol=1e-10, inner_tol=1e-4, inner_maxit=cap, precision=precision)
+        kw = dict(precond=precond, tol=1e-10, inner_tol=1e-4, inner_maxit=cap, precision=precision,
+                  reg_inner="jacobi")  # graphs replay the Jacobi inner iterations
         ue, pe, ie = s.solve(graphs=False, **kw)
         for rep in range(3):
             y = s.apply(torch.cat([ue, pe]))  # eager work between replays
