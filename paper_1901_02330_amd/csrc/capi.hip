@@ -1544,7 +1544,7 @@ vem_status vem_time_kernel(vem_handle h, int which, int reps, double* avg_ms, do
           VEM_HIP(hipEventRecord(e0, s));
           for (int r = 0; r < reps; ++r) launch_scg_iter<float>(s, 2 + r, F, X.Ps, w, h->pcg, h->pcgpart);
           VEM_HIP(hipEventRecord(e1, s));
-          b = 8.0 * (Fc.nnz + X.Pc.nnz) + 4.0 * nF * 11.0;
+          b = 8.0 * (Fc.nnz + X.Pc.nnz) + 4.0 * nF * 13.0;
         } else {
           PcgWork w{h->xw.p, h->pr, h->pz, h->ps, h->pp, h->pw0, h->pw1, nullptr};
           launch_schwarz_rhs<double>(s, m, L, X, nullptr, h->Vb, w.r);
@@ -1554,9 +1554,9 @@ vem_status vem_time_kernel(vem_handle h, int which, int reps, double* avg_ms, do
           VEM_HIP(hipEventRecord(e0, s));
           for (int r = 0; r < reps; ++r) launch_scg_iter<double>(s, 2 + r, F, X.Ps, w, h->pcg, h->pcgpart);
           VEM_HIP(hipEventRecord(e1, s));
-          // both matrices once; [product] z and p_old gathered, p and q written; [update] r and q
-          // gathered, r written, x read and written, p read, z written: 11 vector accesses per row
-          b = 12.0 * (Fc.nnz + X.Pc.nnz) + 8.0 * nF * 11.0;
+          // both matrices once; [product] z gathered, p and q read and written; [update] q gathered,
+          // r, z and x read and written, p read: 13 vector accesses per row
+          b = 12.0 * (Fc.nnz + X.Pc.nnz) + 8.0 * nF * 13.0;
         }
       } else {
         Sell& A = schur ? h->Ss : h->As;

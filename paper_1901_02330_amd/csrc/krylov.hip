@@ -288,13 +288,17 @@ __global__ void __launch_bounds__(kPcgThreads) k_cg_update(int k, int64_t n, T* 
 }
 
 // ---- CG on the face system F with the edge-patch Schwarz operator P (Block-Reg) -------------
-// The update kernel forms z = P r_new with r_new = r - alpha q gathered at the neighbouring rows
-// (r and q are complete when it starts), so the preconditioner costs no kernel of its own; the
-// residual is double-buffered by parity, since rows read their neighbours' old residual while
-// their own new one is written.
+// Two kernels per iteration, each one sparse product with a single gathered vector.  The products
+// F p and P r are carried by recurrences, as F p_new = F z + beta F p_old and
+// P r_new = P r_old - alpha P q: the product kernel gathers only z and the update kernel only q
+// (gathering z and p, or r and q, doubled the gathers per matrix entry).  Every vector is then read
+// and written at its own row only, except the gathered one, which the kernel does not write, so no
+// vector needs a second buffer.  The recurrences equal the direct products in exact arithmetic;
+// over the few dozen iterations of one inner solve their rounding stays far below the inner
+// tolerance, and the outer flexible GMRES accepts any inner result.
 //   [init]    z = P r0; x = 0; partials r0.z
-//   [product] k_cg_spmv: rho, beta = rho / rho_old; stop test; p = z + beta p_old; q = F p; partials p.q
-//   [update]  alpha = rho / p.q; x += alpha p; r_new = r - alpha q; z = P r_new; partials r_new.z
+//   [product] rho, beta = rho / rho_old; stop test; p = z + beta p; q = F z + beta q; partials p.q
+//   [update]  alpha = rho / p.q; x += alpha p; r -= alpha q; z -= alpha P q; partials r.z
 template <typename T>
 __global__ void __launch_bounds__(kPcgThreads) k_scg_init(SellViewT<T> P, const T* __restrict__ r0,
                                                           T* __restrict__ x, T* __restrict__ z, PcgState* st,
@@ -318,11 +322,42 @@ __global__ void __launch_bounds__(kPcgThreads) k_scg_init(SellViewT<T> P, const 
 }
 
 template <typename T>
+__global__ void __launch_bounds__(kPcgThreads) k_scg_prod(int k, SellViewT<T> F, const T* __restrict__ z,
+                                                          T* __restrict__ p, T* __restrict__ q, PcgState* st,
+                                                          const double* __restrict__ prho, double* __restrict__ ppq) {
+  if (st->done) return;
+  const int G = gridDim.x;
+  const int cur = k & 1;
+  const double rho = block_sum_partials(prho + (size_t)cur * G, G, 1, 0);
+  const double rho0 = k == 0 ? rho : st->gamma0;
+  const double beta = k == 0 ? 0.0 : rho / st->gamma[1 - cur];
+  const bool done = !(rho > st->tol2 * rho0);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (k == 0) st->gamma0 = rho0;
+    st->gamma[cur] = rho;
+    if (done) st->done = 1;
+  }
+  if (done) return;
+  const T bt = (T)beta;
+  double acc[1] = {0.0};
+  for (int64_t row = xcd_block() * blockDim.x + threadIdx.x; row < F.rows;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    const T fz = sell_dot(F, row, z);
+    const T pn = k == 0 ? z[row] : z[row] + bt * p[row];
+    const T qn = k == 0 ? fz : fz + bt * q[row];
+    p[row] = pn;
+    q[row] = qn;
+    acc[0] += (double)pn * (double)qn;
+  }
+  block_partials<1>(acc, ppq);
+}
+
+template <typename T>
 __global__ void __launch_bounds__(kPcgThreads) k_scg_update(int k, SellViewT<T> P, T* __restrict__ x,
-                                                            const T* __restrict__ rold, T* __restrict__ rnew,
-                                                            T* __restrict__ z, const T* __restrict__ q,
-                                                            const T* __restrict__ p, PcgState* st,
-                                                            double* __restrict__ prho, const double* __restrict__ ppq) {
+                                                            T* __restrict__ r, T* __restrict__ z,
+                                                            const T* __restrict__ q, const T* __restrict__ p,
+                                                            PcgState* st, double* __restrict__ prho,
+                                                            const double* __restrict__ ppq) {
   if (st->done) return;
   const int G = gridDim.x;
   const int cur = k & 1;
@@ -336,20 +371,13 @@ __global__ void __launch_bounds__(kPcgThreads) k_scg_update(int k, SellViewT<T> 
   double acc[1] = {0.0};
   for (int64_t row = xcd_block() * blockDim.x + threadIdx.x; row < P.rows;
        row += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t sl = row >> 6;
-    const int64_t base = P.slice_ptr[sl] + (row & 63);
-    const int len = P.slice_len[sl];
-    T sum = T(0);
-#pragma unroll 4
-    for (int j = 0; j < len; ++j) {
-      const int c = P.col[base + 64 * j];
-      sum += P.val[base + 64 * j] * (rold[c] - a * q[c]);
-    }
-    const T rn = rold[row] - a * q[row];
-    rnew[row] = rn;
+    const T pqr = sell_dot(P, row, q);
+    const T rn = r[row] - a * q[row];
+    const T zn = z[row] - a * pqr;
+    r[row] = rn;
+    z[row] = zn;
     x[row] += a * p[row];
-    z[row] = sum;
-    acc[0] += (double)rn * (double)sum;
+    acc[0] += (double)rn * (double)zn;
   }
   block_partials<1>(acc, prho + (size_t)(1 - cur) * G);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -547,19 +575,15 @@ void launch_scg_init(hipStream_t s, const Sell& P, const PcgWorkT<T>& w, PcgStat
   k_scg_init<T><<<pcg_grid(P.rows), kPcgThreads, 0, s>>>(values_view<T>(P), w.r, w.x, w.z, st, tol * tol, part);
 }
 
-// work layout: x; r and w1 the two residual buffers; z; s and p the two direction buffers; w0 = q
+// work layout: x, r, z, p as named, w0 = q (s and w1 unused)
 template <typename T>
 void launch_scg_iter(hipStream_t s, int i, const Sell& F, const Sell& P, const PcgWorkT<T>& w, PcgState* st,
                      double* part) {
   const int G = pcg_grid(F.rows);
   double* prho = part;  // 2 x G slots
   double* ppq = part + 2 * (size_t)G;
-  T* pold = (i & 1) ? w.p : w.s;
-  T* pnew = (i & 1) ? w.s : w.p;
-  T* rold = (i & 1) ? w.w1 : w.r;
-  T* rnew = (i & 1) ? w.r : w.w1;
-  k_cg_spmv<T><<<G, kPcgThreads, 0, s>>>(i, values_view<T>(F), w.z, pold, pnew, w.w0, st, prho, ppq);
-  k_scg_update<T><<<G, kPcgThreads, 0, s>>>(i, values_view<T>(P), w.x, rold, rnew, w.z, w.w0, pnew, st, prho, ppq);
+  k_scg_prod<T><<<G, kPcgThreads, 0, s>>>(i, values_view<T>(F), w.z, w.p, w.w0, st, prho, ppq);
+  k_scg_update<T><<<G, kPcgThreads, 0, s>>>(i, values_view<T>(P), w.x, w.r, w.z, w.w0, w.p, st, prho, ppq);
 }
 
 template void launch_scg_init<double>(hipStream_t, const Sell&, const PcgWorkT<double>&, PcgState*, double, double*);

@@ -363,11 +363,11 @@ void launch_schwarz_rhs(hipStream_t s, const SchwarzMesh& m, const DofLayout& L,
 // z_i = A_ii^{-1} v_i - W^T sigma x_f on the interior DOFs (order k only)
 void launch_schwarz_back(hipStream_t s, const SchwarzMesh& m, const DofLayout& L, const Schwarz& X,
                          const double* v, double* z);
-// CG on the face system F with the Schwarz operator P, two kernels per iteration:
-//   [product] beta, stop test; p = z + beta p_old; q = F p; partials p.q
-//   [update]  alpha; x += alpha p; r_new = r - alpha q; z = P (r - alpha q); partials r_new.z
-// Work layout: x, r (and w1: the two residual buffers), z, s/p (the two direction buffers),
-// w0 = q.  T = double, or float with FP64 dot products.
+// CG on the face system F with the Schwarz operator P, two kernels per iteration (the products
+// F p and P r carried by recurrences, one gathered vector per kernel):
+//   [product] beta, stop test; p = z + beta p; q = F z + beta q; partials p.q
+//   [update]  alpha; x += alpha p; r -= alpha q; z -= alpha P q; partials r.z
+// Work layout: x, r, z, p, w0 = q.  T = double, or float with FP64 dot products.
 template <typename T>
 void launch_scg_init(hipStream_t s, const Sell& P, const PcgWorkT<T>& w, PcgState* st, double tol, double* part);
 template <typename T>
