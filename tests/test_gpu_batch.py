@@ -1,5 +1,5 @@
 """Batched solves over many coefficient fields, run concurrently on separate streams, give the same
-bits as one-at-a-time solves."""
+bits as one-at-a-time solves, and the first field's solution matches the oracle's direct solve."""
 import sys
 
 import numpy as np
@@ -34,3 +34,17 @@ def test_batch_matches_sequential():
         assert torch.equal(us[b], u) and torch.equal(ps[b], p)
     print(percentiles(infos), flush=True)
     bs.close()
+    # field 0 against the oracle: backward error in the oracle's K within the tolerance, and the
+    # solution within the tolerance times this small system's conditioning
+    from oracle.assemble import discretize
+    from oracle.solvers import direct_solve
+
+    d = discretize(m, nu=nus[0].cpu().numpy(), rhs=SineSolution())
+    xg = np.concatenate([us[0].cpu().numpy(), ps[0].cpu().numpy()])
+    berr = np.linalg.norm(d["b"] - d["K"] @ xg) / np.linalg.norm(d["b"])
+    x = direct_solve(d["K"], d["b"])
+    eu = np.linalg.norm(xg[: d["Nu"]] - x[: d["Nu"]]) / np.linalg.norm(x[: d["Nu"]])
+    ep = np.linalg.norm(xg[d["Nu"]:] - x[d["Nu"]:]) / np.linalg.norm(x[d["Nu"]:])
+    print("field 0 vs oracle: backward error", berr, "u", eu, "p", ep, flush=True)
+    assert berr <= 1.01e-10
+    assert eu <= 1e-7 and ep <= 1e-7

@@ -135,22 +135,27 @@ def test_paper_patch_test_on_gpu(k):
 @pytest.mark.parametrize("precond", ["schur", "reg"])
 def test_paper_mixed_precision_voronoi(precond):
     """Voronoi mesh, k = 2, per-cell log-normal K (sigma = 1), mixed precision (FP32 inner CG, FP64
-    outer FGMRES): the FP64 residual reaches the tolerance; the error against the oracle's FP64
-    direct solve is reported and bounded by the tolerance times the system's conditioning."""
+    outer FGMRES): the FP64 residual reaches the tolerance, and the error against the oracle's FP64
+    direct solve is within the bound that the tolerance and the system's conditioning give,
+    ||x - x*|| / ||x*|| <= cond_2(K) * ||b - K x|| / ||b|| (cond_2 computed densely here), and within
+    1e-6.  Block-Schur with B_1 = diag(M) converges slowly on this element, so it runs more
+    iterations to the same tolerance."""
     _say("paper mixed", precond)
     m = voronoi_mesh(40, seed=0)
     nu = 1.0 / lognormal_field(40, 1.0, 0)
     s = solver_for(m, 2, nu=nu, rhs=SineSolution())
-    tol = 1e-10 if precond == "reg" else 1e-4
-    u, p, info = s.solve(precond=precond, tol=tol, maxit=3000, inner_tol=1e-3, precision="mixed")
+    tol = 1e-10
+    u, p, info = s.solve(precond=precond, tol=tol, maxit=20000, inner_tol=1e-3, precision="mixed")
     assert info["converged"], info
     d = discretize_paper(m, nu=nu, rhs=SineSolution(), k=2)
     xg = np.concatenate([u.cpu().numpy(), p.cpu().numpy()])
     berr = np.linalg.norm(d["b"] - d["K"] @ xg) / np.linalg.norm(d["b"])
     x = direct_solve(d["K"], d["b"])
     eu, ep = rel(xg[: d["Nu"]], x[: d["Nu"]]), rel(xg[d["Nu"]:], x[d["Nu"]:])
-    _say(info, "backward error", berr, "error vs FP64 oracle: u", eu, "p", ep)
+    cond = np.linalg.cond(d["K"].toarray())
+    _say(info, "backward error", berr, "error vs FP64 oracle: u", eu, "p", ep, "cond(K)", cond)
     assert berr <= 1.5 * tol
+    assert eu <= min(cond * berr, 1e-6) and ep <= min(cond * berr, 1e-6)
 
 
 def test_gpu_sizes_match_the_papers_cube_tables():
