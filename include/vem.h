@@ -92,12 +92,14 @@ enum { VEM_BC_PRESSURE = 0, VEM_BC_FLUX = 1 };
  * inexact inner solve). */
 enum { VEM_FP64 = 0, VEM_MIXED = 1 };
 
-/* Form of the inner Jacobi-CG.  VEM_INNER_PIPELINED (the default): one kernel per
- * iteration (Ghysels-Vanroose recurrences).  VEM_INNER_CLASSICAL: the textbook
- * recurrences in two kernels per iteration; slower, but its residual stays closer to
- * the true one on very ill-conditioned blocks (the paper's order-3 element, where
- * the pipelined recurrences stall the outer solve). */
-enum { VEM_INNER_PIPELINED = 0, VEM_INNER_CLASSICAL = 1 };
+/* Form of the inner Jacobi-preconditioned iteration.  VEM_INNER_PIPELINED (the default): CG, one
+ * kernel per iteration (Ghysels-Vanroose recurrences).  VEM_INNER_CLASSICAL: CG with the textbook
+ * recurrences in two kernels per iteration; slower, but its residual stays closer to the true one
+ * on very ill-conditioned blocks (the paper's order-3 element, where the pipelined recurrences
+ * stall the outer solve).  VEM_INNER_CHEBYSHEV: the Chebyshev iteration on D^{-1}A over the
+ * interval [cheb_lo * hi, hi], hi the Gershgorin bound of D^{-1}A: a fixed polynomial of degree
+ * inner_maxit, one kernel per degree and no reductions (inner_tol and use_graphs do not apply). */
+enum { VEM_INNER_PIPELINED = 0, VEM_INNER_CLASSICAL = 1, VEM_INNER_CHEBYSHEV = 2 };
 
 /* Preconditioner of Block-Reg's inner CG on A_gamma = M + B^T B / gamma (Section 5, eq.
  * block_diag, where the paper applies one algebraic multigrid cycle).  VEM_REG_JACOBI: diag(A_gamma)
@@ -150,6 +152,8 @@ typedef struct {
                           more than the host's launch cost it saves */
   int32_t inner_form;  /* VEM_INNER_PIPELINED (default) or VEM_INNER_CLASSICAL */
   int32_t reg_inner;   /* Block-Reg inner preconditioner: VEM_REG_SCHWARZ (default) or VEM_REG_JACOBI */
+  double cheb_lo;      /* VEM_INNER_CHEBYSHEV: lower end of the interval over the upper, in (0, 1);
+                          <= 0 selects 1/200 */
 } vem_solve_opts;
 
 typedef struct {
@@ -302,7 +306,8 @@ vem_status vem_get_geometry(vem_handle h, double* face_area, double* face_normal
 /* Hot kernels that vem_time_kernel can time. */
 enum { VEM_KERNEL_SPMV = 0, VEM_KERNEL_CG_SCHUR = 1, VEM_KERNEL_CG_REG = 2, VEM_KERNEL_CG_SCHUR32 = 3,
        VEM_KERNEL_CG_REG32 = 4, VEM_KERNEL_CG_SCHUR32P = 5, VEM_KERNEL_CG_REG32P = 6,
-       VEM_KERNEL_CG_REG_SCHWARZ = 7, VEM_KERNEL_CG_REG_SCHWARZ32 = 8 };
+       VEM_KERNEL_CG_REG_SCHWARZ = 7, VEM_KERNEL_CG_REG_SCHWARZ32 = 8, VEM_KERNEL_CHEB_SCHUR = 9,
+       VEM_KERNEL_CHEB_SCHUR32 = 10 };
 
 /* Measurement hook for benchmarks: time `reps` back-to-back launches of one
  * hot kernel with HIP events recorded on the handle's stream.
@@ -314,7 +319,9 @@ enum { VEM_KERNEL_SPMV = 0, VEM_KERNEL_CG_SCHUR = 1, VEM_KERNEL_CG_REG = 2, VEM_
  *   VEM_KERNEL_CG_SCHUR32P, VEM_KERNEL_CG_REG32P: one pipelined FP32 iteration
  *                        (VEM_MIXED with an inner cap of 64 or less);
  *   VEM_KERNEL_CG_REG_SCHWARZ, VEM_KERNEL_CG_REG_SCHWARZ32: one iteration of Block-Reg's inner CG
- *                        with the edge-patch Schwarz preconditioner (two launches), FP64 / FP32.
+ *                        with the edge-patch Schwarz preconditioner (two launches), FP64 / FP32;
+ *   VEM_KERNEL_CHEB_SCHUR, VEM_KERNEL_CHEB_SCHUR32: one Chebyshev-Jacobi product on S (the
+ *                        VEM_INNER_CHEBYSHEV form), FP64 / FP32.
  * avg_ms receives the mean duration of one launch; bytes (may be NULL) the
  * algorithmic bytes one launch moves (every matrix entry and every vector
  * element read or written once).  Uses the solver workspace; the results of

@@ -106,6 +106,7 @@ struct vem_ctx {
   Schwarz sz;  // Block-Reg's edge-patch Schwarz preconditioner (built on first use)
   DBuf<int> Kdiag, Adiag, Sdiag;
   DBuf<double> dM, dMinv, dAinv, dSinv;
+  DBuf<double> cheb;  // 1 / Gershgorin bound of D^{-1}S [0] and of D^{-1}A_gamma [1] (Chebyshev inner form)
   DBuf<float> dAinv32, dSinv32;
   double gamma_A = 0.0;
   // the coefficient-dependent values are built on first use after vem_discretize /
@@ -467,6 +468,7 @@ void ensure_values(vem_handle h, bool needS, bool needA, bool f32, double gamma)
     if (redoA) {
       launch_diag_inv(s, L.Nu, h->Adiag, h->As.val, nullptr, h->dAinv);
       launch_col_scale(s, h->As, h->dAinv);
+      launch_gershgorin(s, h->As, h->dAinv, h->partials, h->cheb.p + 1);
       h->gamma_A = gamma;
       h->a_ready = true;
       h->a32_ready = false;
@@ -477,6 +479,7 @@ void ensure_values(vem_handle h, bool needS, bool needA, bool f32, double gamma)
                         h->Bdiv1, h->dM, bnd, h->S.rowptr, h->S.col, h->Ss.slice_ptr, h->Ss.val);
     launch_diag_inv(s, L.Np, h->Sdiag, h->Ss.val, nullptr, h->dSinv);
     launch_col_scale(s, h->Ss, h->dSinv);
+    launch_gershgorin(s, h->Ss, h->dSinv, h->partials, h->cheb.p);
     h->s_ready = true;
     h->s32_ready = false;
   }
@@ -601,6 +604,22 @@ hipGraphExec_t inner_graph(vem_handle h, const Sell& A, const PcgWork& w, const 
 void inner_pcg(vem_handle h, const Sell& A, const double* dinv, const float* dinv32, const double* b, double* x,
                const vem_solve_opts& o, int& expect, InnerGraph& g64, InnerGraph& g32) {
   hipStream_t s = h->stream;
+  if (o.inner_form == VEM_INNER_CHEBYSHEV) {
+    // a fixed polynomial of degree inner_maxit on [cheb_lo hi, hi]; inner_tol and graphs do not apply
+    const double c = o.cheb_lo > 0.0 ? o.cheb_lo : 1.0 / 200.0;
+    const double* inv_hi = h->cheb.p + (&A == &h->Ss ? 0 : 1);
+    if (o.precision == VEM_MIXED) {
+      PcgWork32 w{h->px32, (float*)h->pr.p, (float*)h->pz.p, (float*)h->ps.p, (float*)h->pp.p, (float*)h->pw0.p,
+                  (float*)h->pw1.p, dinv32};
+      launch_cheb<float>(s, A, w, b, inv_hi, c, o.inner_maxit, h->pcg);
+      launch_to_f64(s, A.rows, h->px32, x);
+    } else {
+      PcgWork w{x, h->pr, h->pz, h->ps, h->pp, h->pw0, h->pw1, dinv};
+      launch_cheb<double>(s, A, w, b, inv_hi, c, o.inner_maxit, h->pcg);
+    }
+    check_launch();
+    return;
+  }
   const bool mixed = o.precision == VEM_MIXED;
   const bool classical = o.inner_form == VEM_INNER_CLASSICAL;
   const InnerMode mode = !mixed ? (classical ? kClassic64 : kPipe64)
@@ -865,6 +884,7 @@ void vem_solve_opts_default(vem_solve_opts* o) {
   o->use_graphs = 0;
   o->inner_form = VEM_INNER_PIPELINED;
   o->reg_inner = VEM_REG_SCHWARZ;
+  o->cheb_lo = 0.0;
 }
 
 vem_status vem_create(vem_handle* out, void* stream) {
@@ -1284,6 +1304,7 @@ vem_status vem_discretize(vem_handle h, int family, int k, int load_points) {
     h->dSinv.alloc(L.Np);
     h->dAinv32.alloc(L.Nu);
     h->dSinv32.alloc(L.Np);
+    h->cheb.alloc(2);
     h->nu.alloc(nc);
     launch_fill(s, nc, 1.0, h->nu);
     h->rhs.alloc(N);
@@ -1504,12 +1525,14 @@ vem_status vem_time_kernel(vem_handle h, int which, int reps, double* avg_ms, do
   if (!h || !avg_ms || reps < 1) return VEM_EINVAL;
   return guarded(h, [&] {
     require_disc(h);
-    VEM_REQUIRE(which >= VEM_KERNEL_SPMV && which <= VEM_KERNEL_CG_REG_SCHWARZ32, VEM_EINVAL, "unknown kernel");
+    VEM_REQUIRE(which >= VEM_KERNEL_SPMV && which <= VEM_KERNEL_CHEB_SCHUR32, VEM_EINVAL, "unknown kernel");
+    const bool cheb = which == VEM_KERNEL_CHEB_SCHUR || which == VEM_KERNEL_CHEB_SCHUR32;
     const bool schwarz = which == VEM_KERNEL_CG_REG_SCHWARZ || which == VEM_KERNEL_CG_REG_SCHWARZ32;
     const bool pipe32 = which == VEM_KERNEL_CG_SCHUR32P || which == VEM_KERNEL_CG_REG32P;
-    const bool f32 = pipe32 || which == VEM_KERNEL_CG_SCHUR32 || which == VEM_KERNEL_CG_REG32;
-    const bool schur =
-        which == VEM_KERNEL_CG_SCHUR || which == VEM_KERNEL_CG_SCHUR32 || which == VEM_KERNEL_CG_SCHUR32P;
+    const bool f32 = pipe32 || which == VEM_KERNEL_CG_SCHUR32 || which == VEM_KERNEL_CG_REG32 ||
+                     which == VEM_KERNEL_CHEB_SCHUR32;
+    const bool schur = which == VEM_KERNEL_CG_SCHUR || which == VEM_KERNEL_CG_SCHUR32 ||
+                       which == VEM_KERNEL_CG_SCHUR32P || cheb;
     ensure_values(h, which != VEM_KERNEL_SPMV && schur, which != VEM_KERNEL_SPMV && !schur, f32, h->gamma_A);
     if (schwarz) ensure_schwarz(h, h->gamma_A, which == VEM_KERNEL_CG_REG_SCHWARZ32);
     hipStream_t s = h->stream;
@@ -1526,6 +1549,26 @@ vem_status vem_time_kernel(vem_handle h, int which, int reps, double* avg_ms, do
         for (int r = 0; r < reps; ++r) launch_spmv(s, h->Ks, h->rhs, h->Vb);
         VEM_HIP(hipEventRecord(e1, s));
         b = 12.0 * h->K.nnz + 8.0 * N + 8.0 * N;  // matrix, x once, y once
+      } else if (cheb) {
+        // one Chebyshev product kernel: reps products (plus the one initial scaling) averaged
+        launch_fill(s, h->L.Np, 1.0, h->Vb);
+        if (which == VEM_KERNEL_CHEB_SCHUR32) {
+          PcgWork32 w{h->px32, (float*)h->pr.p, (float*)h->pz.p, (float*)h->ps.p, (float*)h->pp.p,
+                      (float*)h->pw0.p, (float*)h->pw1.p, h->dSinv32};
+          launch_cheb<float>(s, h->Ss, w, h->Vb, h->cheb.p, 1.0 / 400.0, 2, h->pcg);
+          VEM_HIP(hipEventRecord(e0, s));
+          launch_cheb<float>(s, h->Ss, w, h->Vb, h->cheb.p, 1.0 / 400.0, reps, h->pcg);
+          VEM_HIP(hipEventRecord(e1, s));
+          b = 8.0 * h->S.nnz + 4.0 * h->S.rows * 7.0;
+        } else {
+          PcgWork w{h->xw.p, h->pr, h->pz, h->ps, h->pp, h->pw0, h->pw1, h->dSinv};
+          launch_cheb<double>(s, h->Ss, w, h->Vb, h->cheb.p, 1.0 / 400.0, 2, h->pcg);
+          VEM_HIP(hipEventRecord(e0, s));
+          launch_cheb<double>(s, h->Ss, w, h->Vb, h->cheb.p, 1.0 / 400.0, reps, h->pcg);
+          VEM_HIP(hipEventRecord(e1, s));
+          // S once; d gathered; D^{-1} read; r and x read and written; the next d written
+          b = 12.0 * h->S.nnz + 8.0 * h->S.rows * 7.0;
+        }
       } else if (schwarz) {
         const DofLayout L = h->L;
         const Schwarz& X = h->sz;
@@ -1639,8 +1682,11 @@ static vem_status solve_impl(vem_handle h, const vem_solve_opts* opts, const dou
     VEM_REQUIRE(o.precond >= VEM_PREC_SCHUR && o.precond <= VEM_PREC_NONE, VEM_EINVAL, "unknown preconditioner");
     VEM_REQUIRE(o.inner_tol > 0 && o.inner_maxit >= 1, VEM_EINVAL, "inner_tol must be > 0 and inner_maxit >= 1");
     VEM_REQUIRE(o.precision == VEM_FP64 || o.precision == VEM_MIXED, VEM_EINVAL, "unknown precision mode");
-    VEM_REQUIRE(o.inner_form == VEM_INNER_PIPELINED || o.inner_form == VEM_INNER_CLASSICAL, VEM_EINVAL,
-                "unknown inner CG form");
+    VEM_REQUIRE(o.inner_form == VEM_INNER_PIPELINED || o.inner_form == VEM_INNER_CLASSICAL ||
+                    o.inner_form == VEM_INNER_CHEBYSHEV,
+                VEM_EINVAL, "unknown inner CG form");
+    VEM_REQUIRE(o.inner_form != VEM_INNER_CHEBYSHEV || (o.inner_maxit <= 4096 && o.cheb_lo < 1.0), VEM_EINVAL,
+                "Chebyshev inner form: inner_maxit (the degree) at most 4096 and cheb_lo below 1");
     VEM_REQUIRE(o.reg_inner == VEM_REG_JACOBI || o.reg_inner == VEM_REG_SCHWARZ, VEM_EINVAL,
                 "unknown Block-Reg inner preconditioner");
     auto t0 = std::chrono::steady_clock::now();

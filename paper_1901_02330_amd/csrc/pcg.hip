@@ -1,5 +1,8 @@
 // The inner Jacobi-preconditioned conjugate gradients of the block preconditioners,
 // pipelined so that one kernel performs one iteration.
+#include <algorithm>
+#include <type_traits>
+
 #include "krylov_device.h"
 
 namespace vem {
@@ -195,7 +198,139 @@ void pcg_iter_sel(hipStream_t s, int i, const Sell& A, SellViewT<T> Av, const Pc
     pcg_iter_as<T, 1024, false>(s, i, Av, w, st, part);
 }
 
+// ---- inner Chebyshev-Jacobi: a fixed polynomial in D^{-1}A, no reductions ----------------------
+// Chebyshev iteration for D^{-1}A x = D^{-1}b on [lo, hi] = [c hi, hi], from x = 0:
+//   d_0 = D^{-1}b / theta,  x_{k+1} = x_k + d_k,  r_{k+1} = r_k - A d_k,
+//   rho_{k+1} = 1 / (2 sigma - rho_k),  d_{k+1} = rho_{k+1} rho_k d_k + (2 rho_{k+1} / delta) D^{-1} r_{k+1},
+// theta = (hi + lo) / 2, delta = (hi - lo) / 2, sigma = theta / delta, rho_0 = 1 / sigma.  The
+// rho_k depend on c only, so the host forms every coefficient in units of 1/hi, and the kernels
+// scale them by the device-resident 1/hi (the Gershgorin bound of D^{-1}A, taken when the values
+// are built): nothing is read back.  The last product's kernel also adds d_m, so m products give
+// x_{m+1}, a polynomial of degree m in D^{-1}A applied to D^{-1}b.  d alternates between two
+// buffers (neighbours gather it while its owner writes the next one).
+template <typename T>
+__global__ void __launch_bounds__(1024) k_cheb_init(int64_t n, const double* __restrict__ b,
+                                                    const T* __restrict__ dinv, T* __restrict__ d,
+                                                    const double* __restrict__ inv_hi, double c0, PcgState* st,
+                                                    int m) {
+  const T c = (T)(c0 * inv_hi[0]);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = c * dinv[i] * (T)b[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->count = m;
+    st->total += m;
+    st->done = 0;
+  }
+}
+
+template <typename T, bool kShort, bool kFirst, bool kLast>
+__global__ void __launch_bounds__(1024) k_cheb_iter(SellViewT<T> A, const T* __restrict__ dinv,
+                                                    const double* __restrict__ b, T* __restrict__ x,
+                                                    T* __restrict__ r, const T* __restrict__ dold,
+                                                    T* __restrict__ dnew, const double* __restrict__ inv_hi,
+                                                    double c1, double c2u) {
+  const T c2 = (T)(c2u * inv_hi[0]), t1 = (T)c1;
+  for (int64_t row = xcd_block() * blockDim.x + threadIdx.x; row < A.rows;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    const T ad = sell_row<kShort>(A, row, dold);
+    const T di = dold[row];
+    const T rn = (kFirst ? (T)b[row] : r[row]) - ad;
+    const T dn = t1 * di + c2 * dinv[row] * rn;
+    const T xo = kFirst ? T(0) : x[row];
+    if (kLast) {
+      x[row] = xo + di + dn;
+    } else {
+      x[row] = xo + di;
+      r[row] = rn;
+      dnew[row] = dn;
+    }
+  }
+}
+
+// Gershgorin bound of D^{-1}A (max over rows of sum_j |a_ij| / a_ii): block maxima, then their
+// maximum; out[0] = 1 / bound.
+__global__ void __launch_bounds__(256) k_gersh(SellView A, const double* __restrict__ dinv,
+                                               double* __restrict__ part) {
+  __shared__ double sh[4];
+  double m = 0.0;
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < A.rows;
+       row += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t sl = row >> 6, base = A.slice_ptr[sl] + (row & 63);
+    double t = 0.0;
+    for (int k = 0; k < A.slice_len[sl]; ++k) t += fabs(A.val[base + 64 * k]);
+    t *= fabs(dinv[row]);
+    m = t > m ? t : m;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double q = __shfl_down(m, o, 64);
+    m = q > m ? q : m;
+  }
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = sh[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) b = sh[w] > b ? sh[w] : b;
+    part[blockIdx.x] = b;
+  }
+}
+
+__global__ void k_gersh_final(int nparts, const double* __restrict__ part, double* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double m = 0.0;
+  for (int i = 0; i < nparts; ++i) m = part[i] > m ? part[i] : m;
+  out[0] = m > 0.0 ? 1.0 / m : 0.0;
+}
+
+template <typename T, bool kShort>
+void cheb_iter_as(hipStream_t s, int k, int m, SellViewT<T> Av, const T* dinv, const double* b, T* x, T* r,
+                  const T* dold, T* dnew, const double* inv_hi, double c1, double c2u) {
+  const int G = pcg_grid(Av.rows, 1024);
+  const bool first = k == 0, last = k == m - 1;
+  if (first && last)
+    k_cheb_iter<T, kShort, true, true><<<G, 1024, 0, s>>>(Av, dinv, b, x, r, dold, dnew, inv_hi, c1, c2u);
+  else if (first)
+    k_cheb_iter<T, kShort, true, false><<<G, 1024, 0, s>>>(Av, dinv, b, x, r, dold, dnew, inv_hi, c1, c2u);
+  else if (last)
+    k_cheb_iter<T, kShort, false, true><<<G, 1024, 0, s>>>(Av, dinv, b, x, r, dold, dnew, inv_hi, c1, c2u);
+  else
+    k_cheb_iter<T, kShort, false, false><<<G, 1024, 0, s>>>(Av, dinv, b, x, r, dold, dnew, inv_hi, c1, c2u);
+}
+
 }  // namespace
+
+template <typename T>
+void launch_cheb(hipStream_t s, const Sell& A, const PcgWorkT<T>& w, const double* b, const double* inv_hi,
+                 double c, int m, PcgState* st) {
+  VEM_REQUIRE(c > 0.0 && c < 1.0 && m >= 1, VEM_EINVAL, "Chebyshev interval or degree out of range");
+  SellViewT<T> Av = std::is_same<T, float>::value ? SellViewT<T>{A.rows, A.slice_ptr, A.slice_len, A.col,
+                                                                 (const T*)(const void*)A.val32.p}
+                                                  : SellViewT<T>{A.rows, A.slice_ptr, A.slice_len, A.col,
+                                                                 (const T*)(const void*)A.val.p};
+  const double sigma = (1.0 + c) / (1.0 - c);
+  double rho = 1.0 / sigma;
+  // d_0 = D^{-1} b / theta, theta = hi (1 + c) / 2
+  k_cheb_init<T><<<pcg_grid(A.rows, 1024), 1024, 0, s>>>(A.rows, b, w.dinv, w.p, inv_hi, 2.0 / (1.0 + c), st, m);
+  T* dbuf[2] = {w.p, w.s};
+  for (int k = 0; k < m; ++k) {
+    const double rho1 = 1.0 / (2.0 * sigma - rho);
+    const double c1 = rho1 * rho, c2u = 4.0 * rho1 / (1.0 - c);  // 2 rho_{k+1} / delta, delta = hi (1 - c) / 2
+    if (A.max_len <= kShortRow && A.rows <= kPcgMaxThreads)
+      cheb_iter_as<T, true>(s, k, m, Av, w.dinv, b, w.x, w.r, dbuf[k & 1], dbuf[(k + 1) & 1], inv_hi, c1, c2u);
+    else
+      cheb_iter_as<T, false>(s, k, m, Av, w.dinv, b, w.x, w.r, dbuf[k & 1], dbuf[(k + 1) & 1], inv_hi, c1, c2u);
+    rho = rho1;
+  }
+}
+template void launch_cheb<double>(hipStream_t, const Sell&, const PcgWorkT<double>&, const double*, const double*,
+                                  double, int, PcgState*);
+template void launch_cheb<float>(hipStream_t, const Sell&, const PcgWorkT<float>&, const double*, const double*,
+                                 double, int, PcgState*);
+
+void launch_gershgorin(hipStream_t s, const Sell& A, const double* dinv, double* part, double* inv_hi) {
+  const int G = (int)std::min<int64_t>(1024, (A.rows + 255) / 256);
+  k_gersh<<<G > 0 ? G : 1, 256, 0, s>>>(view(A), dinv, part);
+  k_gersh_final<<<1, 64, 0, s>>>(G > 0 ? G : 1, part, inv_hi);
+}
 
 void launch_pcg_init(hipStream_t s, const Sell& A, const PcgWork& w, const double* b, PcgState* st, double tol,
                      int maxit, double* part) {

@@ -48,7 +48,7 @@ class SolveOpts(ctypes.Structure):
         ("use_x0", ctypes.c_int32), ("tol", c_double), ("inner_tol", c_double),
         ("inner_maxit", ctypes.c_int32), ("inner_check", ctypes.c_int32), ("gamma", c_double),
         ("precision", ctypes.c_int32), ("use_graphs", ctypes.c_int32), ("inner_form", ctypes.c_int32),
-        ("reg_inner", ctypes.c_int32),
+        ("reg_inner", ctypes.c_int32), ("cheb_lo", c_double),
     ]
 
 
@@ -256,7 +256,7 @@ class Solver:
     @_ordered
     def solve(self, precond="schur", tol=1e-8, restart=30, maxit=5000, inner_tol=1e-6, inner_maxit=5000,
               inner_check=32, gamma=0.0, x0=None, precision="fp64", rhs=None, graphs=False,
-              inner_form="pipelined", reg_inner="schwarz"):
+              inner_form="pipelined", reg_inner="schwarz", cheb_lo=0.0):
         t = self.torch
         sz = self.sizes()
         o = SolveOpts()
@@ -267,7 +267,8 @@ class Solver:
         o.gamma = float(gamma)
         o.precision = {"fp64": 0, "mixed": 1}[precision]
         o.use_graphs = 1 if graphs else 0
-        o.inner_form = {"pipelined": 0, "classical": 1}[inner_form]
+        o.inner_form = {"pipelined": 0, "classical": 1, "chebyshev": 2}[inner_form]
+        o.cheb_lo = float(cheb_lo)
         o.reg_inner = {"jacobi": 0, "schwarz": 1}[reg_inner]
         if x0 is not None:
             u = self._dev(x0[0], t.float64).clone()
@@ -334,7 +335,7 @@ class Solver:
     def time_kernel(self, which="cg_schur", reps=50):
         """Mean duration (ms) of one launch of a hot kernel, timed with HIP events, and its algorithmic bytes."""
         code = {"spmv": 0, "cg_schur": 1, "cg_reg": 2, "cg_schur32": 3, "cg_reg32": 4, "cg_schur32p": 5,
-                "cg_reg32p": 6, "cg_reg_schwarz": 7, "cg_reg_schwarz32": 8}[which]
+                "cg_reg32p": 6, "cg_reg_schwarz": 7, "cg_reg_schwarz32": 8, "cheb_schur": 9, "cheb_schur32": 10}[which]
         ms, nb = c_double(), c_double()
         self._check(self.lib.vem_time_kernel(self.h, code, int(reps), byref(ms), byref(nb)))
         return ms.value, nb.value
