@@ -13,13 +13,19 @@ geometry, local matrices, assembly, both preconditioner set-ups
 the library's quadrature points (vem_set_rhs), then a Block-Schur solve and a
 Block-Reg solve (vem_solve), flux and pressure out.
 
+Inner solves: Block-Schur applies S^{-1} by a Chebyshev-Jacobi polynomial of degree 24 on
+[hi/400, hi] (hi the Gershgorin bound of D^{-1}S); Block-Reg applies A_gamma^{-1} by CG with the
+edge-patch Schwarz preconditioner to a relative tolerance of 0.1, capped at 24 iterations.
+
 Printed JSON (one line):
-  value        seconds per step of assembly + the Block-Schur solve (the
-               paper's Schur-complement preconditioner, the faster of the two);
-  ms_per_step  the whole step, both solves included;
-  solves       per-preconditioner solve times, iterations, true residuals;
-  roofline     the dominant kernel, timed live with HIP events;
-  cpu_baseline the FP64 CPU oracle on a bounded sample of the same recipe.
+  value          seconds per step of assembly + the Block-Schur solve (the
+                 paper's Schur-complement preconditioner, the faster of the two);
+  ms_per_step    the whole step, both solves included;
+  solves         per-preconditioner solve times, iterations, true residuals;
+  roofline       the step's dominant kernel (Block-Reg's inner iteration), timed live with HIP events;
+  roofline_value the kernel that dominates `value` (the Chebyshev product on S);
+  kernels        every hot kernel's live rate, with its algorithmic bytes;
+  cpu_baseline   the FP64 CPU oracle on the same 64^3 workload (assembly + Block-Schur solve).
 """
 
 from __future__ import annotations
@@ -45,9 +51,13 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=64, help="cells per direction of the Cube mesh")
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--schur-inner-tol", type=float, default=1e-12)
-    ap.add_argument("--schur-inner-maxit", type=int, default=24)
+    ap.add_argument("--schur-inner-form", default="chebyshev", choices=("chebyshev", "pipelined", "classical"))
+    ap.add_argument("--schur-inner-tol", type=float, default=1e-12, help="CG inner forms only")
+    ap.add_argument("--schur-inner-maxit", type=int, default=24, help="degree (Chebyshev) or iteration cap (CG)")
+    ap.add_argument("--cheb-lo", type=float, default=1.0 / 400.0)
     ap.add_argument("--reg-inner-tol", type=float, default=1e-1)
+    ap.add_argument("--reg-inner-maxit", type=int, default=24)
+    ap.add_argument("--reg-inner", default="schwarz", choices=("schwarz", "jacobi"))
     ap.add_argument("--no-extras", action="store_true", help="skip the adjoint / mixed / batch / 128^3 measurements")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="short run for rocprofv3 --pmc: discretize, 20 launches of each hot kernel, and a plain "
@@ -56,7 +66,7 @@ def parse():
                     help="also time FIELDS log-normal fields (sigma 1.5, seeds 0..) on the Cube 32^3 k=2 mesh: "
                          "Block-Reg with FP32 inner solves, sequential and on FIELDS concurrent lanes (minutes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=40, help="Cube size of the CPU oracle sample")
+    ap.add_argument("--cpu-n", type=int, default=0, help="Cube size of the CPU oracle run (default: the workload's)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
                     help="print the HBM-traffic summary of two rocprofv3 --pmc runs of --pmc-probe and exit")
     ap.add_argument("--summarize", metavar="PREFIX", default=None,
@@ -79,30 +89,39 @@ def summarize(prefix: str):
                    f"`{r['Name'][:80]}` |")
     trace = prefix + "_kernel_trace.csv"
     if os.path.exists(trace):
-        out += ["", "Per launch grid (threads) of the hot kernels; 'working' excludes launches under 5 us. A launch",
-                "enqueued after its inner solve converged still loads its operands before it reads the stop",
-                "flag, so such launches take 7-12 us and are counted as working:", "",
+        out += ["", "Per launch grid (threads) of the hot kernels; 'working' excludes launches under 3 us (launches",
+                "enqueued after their inner solve converged return at once):", "",
                 "| kernel | grid | launches | working | avg working us | median us |", "|---|---|---|---|---|---|"]
         by = {}
         for r in csv.DictReader(open(trace)):
             mt = re.search(r"(k_[A-Za-z0-9_]+(?:<[^>]*>)?)\(", r["Kernel_Name"])
             name = mt.group(1) if mt else r["Kernel_Name"][:40]
-            if not any(k in name for k in ("k_ppcg_iter", "k_spmv")):
+            if not any(k in name for k in ("k_ppcg_iter", "k_spmv", "k_scg_", "k_cheb_iter")):
                 continue
             d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
             by.setdefault((name, int(r["Grid_Size_X"])), []).append(d)
         for (name, g), ds in sorted(by.items()):
-            w = [d for d in ds if d > 5.0] or ds
+            w = [d for d in ds if d > 3.0] or ds
             out.append(f"| `{name}` | {g} | {len(ds)} | {len(w)} | {sum(w) / len(w):.2f} | "
                        f"{statistics.median(w):.2f} |")
-        # the live timing loop (vem_time_kernel "cg_reg", 200 launches) runs after the solves: the last
-        # 200 launches of the pipelined iteration with the largest grid
-        it = [k for k in by if k[0].startswith("k_ppcg_iter<double, false")]
-        if it:
+        # the live timing loops (vem_time_kernel, 200 launches each) run after the solves: the last 200
+        # launches of each roofline kernel (FP64), the Chebyshev product's middle variant
+        out += ["", "The live timing loops (the last 200 launches of each roofline kernel, FP64):", "",
+                "| kernel | grid | mean us | median us |", "|---|---|---|---|"]
+        pair = 0.0
+        for pref in ("k_scg_prod<double,", "k_scg_update<double,", "k_cheb_iter<double, true, false, false>",
+                     "k_cheb_iter<double, false, false, false>"):
+            it = [k for k in by if k[0].startswith(pref)]
+            if not it:
+                continue
             key = max(it, key=lambda k: k[1])
             last = by[key][-200:]
-            out += ["", f"Last {len(last)} launches of `{key[0]}` at grid {key[1]} (the timing loop): "
-                    f"mean {sum(last) / len(last):.2f} us, median {statistics.median(last):.2f} us."]
+            mean = sum(last) / len(last)
+            if pref.startswith("k_scg_"):
+                pair += mean
+            out.append(f"| `{key[0]}` | {key[1]} | {mean:.2f} | {statistics.median(last):.2f} |")
+        if pair:
+            out += ["", f"One Schwarz-CG iteration (k_scg_prod + k_scg_update): {pair:.2f} us."]
         out += schur_window(trace)
     print("\n".join(out))
 
@@ -117,7 +136,9 @@ def schur_window(trace: str):
     names = [r["Kernel_Name"] for r in rows]
     try:
         s = next(i for i, n in enumerate(names) if "k_schur_values" in n)
-        e = next(i for i in range(s, len(names)) if "k_ppcg_init<double, 256" in names[i])
+        e = next(i for i in range(s, len(names))
+                 if any(k in names[i] for k in ("k_inc_face", "k_cell_condense", "k_edge_inv", "k_schwarz_rhs",
+                                                "k_ppcg_init<double, 256")))
     except StopIteration:
         return []
     seg = rows[s:e]
@@ -141,7 +162,8 @@ def schur_window(trace: str):
     return out
 
 
-KERNEL_SRC = ("pcg.hip", "krylov_device.h")  # the dominant kernel's source, for the traffic record
+KERNEL_SRC = ("krylov.hip", "pcg.hip", "krylov_device.h")  # the measured kernels' sources (traffic record)
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_cube64_lo.md")
 
 
 def kernel_src_digest():
@@ -154,17 +176,16 @@ def kernel_src_digest():
 
 
 def traffic_from_profiles():
-    """HBM bytes per launch of the dominant kernel from the committed counter summary, if it was
-    taken on the current kernel source (its hash is recorded there); else None."""
-    path = os.path.join(ROOT, "profiles", "traffic_k_ppcg_iter_cube64_lo.md")
-    if not os.path.exists(path):
+    """HBM bytes of the two roofline kernels from the committed counter summary, if it was taken on
+    the current kernel sources (their hash is recorded there); else None."""
+    if not os.path.exists(TRAFFIC_PROFILE):
         return None
     digest = kernel_src_digest()
-    for line in open(path):
+    for line in open(TRAFFIC_PROFILE):
         if line.startswith("{") and '"traffic"' in line:
             rec = json.loads(line)
             if rec.get("kernel_src_sha256_16") == digest:
-                return rec["traffic"]
+                return rec
     return None
 
 
@@ -172,36 +193,38 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(n_gpu: int, n_cpu: int):
-    """The oracle (the paper's algorithm: FGMRES + Block-Schur with an exact sparse LU of S) on the
-    n_cpu^3 cube of the same recipe, scaled to the n_gpu^3 workload by the number of unknowns."""
+def cpu_baseline(n: int, args):
+    """The oracle on the workload itself (Cube n^3, the same coefficient and data): its assembly, then
+    FGMRES(30) with its Block-Schur preconditioner to the same tolerance.  The oracle's exact sparse LU
+    of S takes minutes at 64^3 on the host, so its inner Jacobi-CG on S is used, capped at the GPU
+    run's 24 products (the same preconditioner family; the outer iteration count is stated)."""
     import numpy as np
 
     from oracle.assemble import discretize
     from oracle.solvers import block_schur, fgmres
     from paper_1901_02330_amd.inputs import SineSolution, cube_mesh, lognormal_field
 
-    m = cube_mesh(n_cpu)
-    nu = 1.0 / lognormal_field(n_cpu**3, 2.0, 0)
+    m = cube_mesh(n)
+    nu = 1.0 / lognormal_field(n**3, 2.0, 0)
     t0 = time.perf_counter()
     d = discretize(m, nu=nu, rhs=SineSolution())
     t1 = time.perf_counter()
-    pre = block_schur(d["M"], d["B"], inner="exact")
-    x, info = fgmres(d["K"], d["b"], pre, m=30, tol=1e-8)
+    Nu = d["Nu"]
+    K = d["K"].tocsr()
+    pre = block_schur(K[:Nu, :Nu], K[Nu:, :Nu], inner="cg", tol=1e-12, maxit=args.schur_inner_maxit)
+    x, info = fgmres(K, d["b"], pre, m=30, tol=args.tol)
     t2 = time.perf_counter()
-    n_small = d["Nu"] + d["Np"]
-    n_big = 3 * n_gpu * n_gpu * (n_gpu + 1) + n_gpu**3
-    scale = n_big / n_small
+    threads = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
     return {
-        "value": (t2 - t0) * scale,
+        "value": t2 - t0,
         "unit": "s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"oracle FP64 (NumPy/SciPy, single-threaded sparse phases) on the {n_cpu}^3 cube of the same "
-                   f"recipe ({n_small} unknowns): assembly {t1 - t0:.2f} s + FGMRES(30)/Block-Schur with exact "
-                   f"sparse LU of S {t2 - t1:.2f} s ({info['iterations']} iterations, relres "
-                   f"{info['relres']:.1e}); scaled x{scale:.2f} to {n_big} unknowns by unknown count "
-                   f"(a lower bound: the LU grows faster than linearly)"),
+        "sample": (f"the whole {n}^3 workload ({Nu + d['Np']} unknowns), unscaled: oracle FP64 (NumPy/SciPy) "
+                   f"assembly {t1 - t0:.2f} s + FGMRES(30)/Block-Schur with the oracle's inner Jacobi-CG on S "
+                   f"capped at {args.schur_inner_maxit} iterations {t2 - t1:.2f} s ({info['iterations']} "
+                   f"iterations, relres {info['relres']:.1e}); SciPy's sparse products run on one core, dense "
+                   f"NumPy on up to the host's cores (thread variables: {threads})"),
         "host_cpus_available": len(os.sched_getaffinity(0)),
     }
 
@@ -224,7 +247,7 @@ def pmc_probe(mesh, n):
     s.set_coefficient(torch.as_tensor(1.0 / lognormal_field(n**3, 2.0, 0), device="cuda"))
     s.set_rhs_functions(SineSolution.f, SineSolution.pD)
     rec = {"copy_read_bytes": src.numel() * 8, "copy_write_bytes": src.numel() * 8, "kernels": {}}
-    for which in ("cg_reg", "cg_schur", "spmv", "cg_schur32p"):
+    for which in ("cg_reg_schwarz", "cheb_schur", "spmv", "cg_schur", "cg_reg"):
         ms, nb = s.time_kernel(which, reps=20)
         log(f"{which}: {ms * 1e3:.1f} us, algorithmic {nb / 1e6:.1f} MB")
         rec["kernels"][which] = {"avg_us": ms * 1e3, "algorithmic_bytes": nb}
@@ -266,35 +289,41 @@ def summarize_pmc(fetch_dir: str, write_dir: str):
            "|---|---|---|---|---|---|"]
     rows = {}
     for key in sorted(set(fetch) & set(write)):
-        if key[0] == "copy" or not any(k in key[0] for k in ("k_ppcg_iter", "k_spmv", "k_cg_")):
+        if key[0] == "copy" or not any(k in key[0] for k in ("k_ppcg_iter", "k_spmv", "k_scg_", "k_cheb_iter")):
             continue
         fm = statistics.median(fetch[key]) * f_fetch
         wm = statistics.median(write[key]) * f_write
-        rows[key] = (fm, wm)
+        rows[key] = (fm, wm, len(fetch[key]))
         out.append(f"| `{key[0]}` | {key[1]} | {len(fetch[key])} | {fm / 1e6:.1f} | {wm / 1e6:.1f} | "
                    f"{(fm + wm) / 1e6:.1f} |")
-    # measured against algorithmic bytes for the timed iterations (not the first of each solve)
-    which_of = {"k_spmv": "spmv", "k_ppcg_iter<double, false, 256": "cg_reg",
-                "k_ppcg_iter<double, false, 1024": "cg_schur", "k_ppcg_iter<float, false, 1024": "cg_schur32p"}
-    ratios = []
-    for key, (fm, wm) in rows.items():
-        w = next((v for k, v in which_of.items() if key[0].startswith(k)), None)
-        if w and w in probe["kernels"]:
-            alg = probe["kernels"][w]["algorithmic_bytes"]
-            ratios.append(f"| `{key[0]}` | {alg / 1e6:.1f} | {(fm + wm) / 1e6:.1f} | {(fm + wm) / alg:.3f} |")
-    if ratios:
-        out += ["", "| kernel | algorithmic MB | measured MB | ratio |", "|---|---|---|---|"] + sorted(ratios)
-    # the dominant kernel: pipelined CG iteration on M + B^T B / gamma (the larger k_ppcg_iter grid)
-    it = sorted((k for k in rows if k[0].startswith("k_ppcg_iter<double, false")), key=lambda k: -k[1])
-    fm, wm = rows[it[0]]
-    alg = probe["kernels"]["cg_reg"]["algorithmic_bytes"]
-    rec = {"traffic": {"bytes_per_launch": fm + wm, "fetch_bytes": fm, "write_bytes": wm,
-                       "algorithmic_bytes": alg, "ratio_to_algorithmic": (fm + wm) / alg,
-                       "note": "FETCH_SIZE + WRITE_SIZE of k_ppcg_iter on M + B^T B/gamma, cube 64^3 LO, "
-                               "scaled by a 512 MiB copy; counts L2-to-fabric traffic (MALL hits included)"},
+
+    def most(prefix):  # the variant of a kernel with the most dispatches (the timing loop's)
+        ks = [k for k in rows if k[0].startswith(prefix)]
+        return max(ks, key=lambda k: rows[k][2]) if ks else None
+
+    measured = {}
+    for which, prefixes in (("spmv", ["k_spmv"]), ("cheb_schur", ["k_cheb_iter<double"]),
+                            ("cg_schur", ["k_ppcg_iter<double, false, 1024"]),
+                            ("cg_reg", ["k_ppcg_iter<double, false, 256"]),
+                            ("cg_reg_schwarz", ["k_scg_prod<double,", "k_scg_update<double,"])):
+        keys = [most(p) for p in prefixes]
+        if any(k is None for k in keys) or which not in probe["kernels"]:
+            continue
+        fm = sum(rows[k][0] for k in keys)
+        wm = sum(rows[k][1] for k in keys)
+        alg = probe["kernels"][which]["algorithmic_bytes"]
+        measured[which] = {"bytes": fm + wm, "fetch_bytes": fm, "write_bytes": wm, "algorithmic_bytes": alg,
+                           "ratio_to_algorithmic": (fm + wm) / alg, "kernels": [k[0] for k in keys]}
+    out += ["", "Per iteration or launch, against the algorithmic bytes (every matrix entry and vector element "
+            "once):", "", "| timed unit | kernels | algorithmic MB | measured MB | ratio |", "|---|---|---|---|---|"]
+    for which, m in measured.items():
+        out.append(f"| {which} | {', '.join('`' + k + '`' for k in m['kernels'])} | {m['algorithmic_bytes'] / 1e6:.1f} "
+                   f"| {m['bytes'] / 1e6:.1f} | {m['ratio_to_algorithmic']:.3f} |")
+    note = "FETCH_SIZE + WRITE_SIZE, cube 64^3 LO, each scaled by a 512 MiB copy; L2-to-fabric traffic (MALL hits included)"
+    rec = {"traffic": dict(measured.get("cg_reg_schwarz", {}), note=note),
+           "traffic_value": dict(measured.get("cheb_schur", {}), note=note),
            "kernel_src_sha256_16": kernel_src_digest()}
-    out += ["", f"Algorithmic bytes per launch of the dominant kernel: {alg / 1e6:.1f} MB; measured "
-            f"{(fm + wm) / 1e6:.1f} MB ({(fm + wm) / alg:.3f}x).", "", json.dumps(rec)]
+    out += ["", json.dumps(rec)]
     print("\n".join(out))
 
 
@@ -308,13 +337,16 @@ def extras(args, torch, dev):
     from paper_1901_02330_amd.vem import Solver
 
     out = {}
+    sk = dict(inner_form=args.schur_inner_form, inner_tol=args.schur_inner_tol, inner_maxit=args.schur_inner_maxit,
+              cheb_lo=args.cheb_lo)
+    rk = dict(reg_inner=args.reg_inner, inner_tol=args.reg_inner_tol, inner_maxit=args.reg_inner_maxit)
     # adjoint: Cube 48^3, log K ~ N(0,1) seed 0, p_obs from the seed-1 field, J = 1/2 ||p - p_obs||^2
     m48 = cube_mesh(48)
     s = Solver()
     s.set_mesh(m48)
     s.discretize("lo")
     s.set_rhs_functions(SineSolution.f, SineSolution.pD)
-    kw = dict(precond="schur", tol=1e-10, inner_tol=1e-12, inner_maxit=32)
+    kw = dict(precond="schur", tol=1e-10, **sk)
     s.set_coefficient(torch.as_tensor(1.0 / lognormal_field(48**3, 1.0, 1), device=dev))
     _, p_obs, _ = s.solve(**kw)
     logk = torch.tensor(np.log(lognormal_field(48**3, 1.0, 0)), dtype=torch.float64, device=dev,
@@ -336,7 +368,32 @@ def extras(args, torch, dev):
                              "note": "forward = set coefficient + Block-Schur solve to 1e-10; backward = adjoint "
                                      "solve + per-cell gradient kernel"}
     s.close()
-    # mixed precision on the headline workload, error against the FP64 GPU solution
+    # mixed precision against the FP64 oracle's direct solve, Cube 24^3 of the same recipe (the oracle
+    # solves it in seconds); then on the headline workload, against the GPU's FP64 solution (which the
+    # full-size test matches to the oracle's 1e-13 solution within 4e-15)
+    from oracle.assemble import discretize
+    from oracle.solvers import direct_solve
+
+    s = Solver()
+    m24 = cube_mesh(24)
+    nu24 = 1.0 / lognormal_field(24**3, 2.0, 0)
+    s.set_mesh(m24)
+    s.discretize("lo")
+    s.set_coefficient(torch.as_tensor(nu24, device=dev))
+    s.set_rhs_functions(SineSolution.f, SineSolution.pD)
+    d24 = discretize(m24, nu=nu24, rhs=SineSolution())
+    x24 = direct_solve(d24["K"], d24["b"])
+    vs_or = {}
+    for prec, kwp in (("schur", sk), ("reg", rk)):
+        for precision in ("mixed", "fp64"):
+            u, p, info = s.solve(prec, tol=1e-10, precision=precision, maxit=3000, **kwp)
+            uc, pc = u.cpu().numpy(), p.cpu().numpy()
+            vs_or[f"{prec}_{precision}"] = {
+                "iterations": info["iterations"], "relres": info["relres"],
+                "rel_err_u_vs_oracle": float(np.linalg.norm(uc - x24[: d24["Nu"]]) / np.linalg.norm(x24[: d24["Nu"]])),
+                "rel_err_p_vs_oracle": float(np.linalg.norm(pc - x24[d24["Nu"]:]) / np.linalg.norm(x24[d24["Nu"]:]))}
+    out["precision_vs_oracle_cube24_tol1e-10"] = vs_or
+    s.close()
     n = args.n
     s = Solver()
     s.set_mesh(cube_mesh(n))
@@ -344,7 +401,7 @@ def extras(args, torch, dev):
     s.set_coefficient(torch.as_tensor(1.0 / lognormal_field(n**3, 2.0, 0), device=dev))
     s.set_rhs_functions(SineSolution.f, SineSolution.pD)
     mixed = {}
-    for prec, kwp in (("schur", dict(inner_tol=1e-12, inner_maxit=32)), ("reg", dict(inner_tol=1e-1))):
+    for prec, kwp in (("schur", sk), ("reg", rk)):
         u64, p64, i64 = s.solve(prec, tol=1e-10, **kwp)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -366,15 +423,16 @@ def extras(args, torch, dev):
     bat = {}
     for lanes in (1, 8):
         bs = BatchSolver(cube_mesh(n), lanes=lanes, rhs=SineSolution())
-        bs.solve(nus[:lanes], precond="schur", tol=1e-8, inner_tol=1e-12, inner_maxit=32)  # warm-up
+        bs.solve(nus[:lanes], precond="schur", tol=1e-8, **sk)  # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, _, infos = bs.solve(nus, precond="schur", tol=1e-8, inner_tol=1e-12, inner_maxit=32)
+        _, _, infos = bs.solve(nus, precond="schur", tol=1e-8, **sk)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         bat[f"lanes{lanes}"] = {"solves_per_s": len(nus) / wall, "wall_s": wall, **percentiles(infos)}
         bs.close()
     out["batch_cube64_16fields"] = bat
+    out["batch_cube32_k2_64fields"] = k2_fields(args, torch, dev, 64)
     # one 128^3 solve (8.4M unknowns), log-normal sigma 1.5 seed 0
     s = Solver()
     m128 = cube_mesh(128)
@@ -391,7 +449,7 @@ def extras(args, torch, dev):
         s.set_rhs_functions(SineSolution.f, SineSolution.pD)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        u, p, info = s.solve("schur", tol=1e-8, inner_tol=1e-12, inner_maxit=32)
+        u, p, info = s.solve("schur", tol=1e-8, **sk)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         big = {"n_unknowns": s.sizes()["n"], "assembly_s": t1 - t0, "solve_schur_s": t2 - t1,
@@ -407,8 +465,7 @@ def extras(args, torch, dev):
     s.set_coefficient(torch.as_tensor(1.0 / lognormal_field(args.n**3, 2.0, 0), device=dev))
     s.set_rhs_functions(SineSolution.f, SineSolution.u)
     fl = {"boundary_data": "flux, zero-mean pressure"}
-    for prec, kw in (("schur", dict(inner_tol=args.schur_inner_tol, inner_maxit=args.schur_inner_maxit)),
-                     ("reg", dict(inner_tol=args.reg_inner_tol))):
+    for prec, kw in (("schur", sk), ("reg", rk)):
         for rep in range(2):  # the second solve is timed
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -453,6 +510,43 @@ def extras(args, torch, dev):
         tab[f"cube{nn}_k{k}_{bc}"] = row
         s.close()
     out["paper_cube_table1"] = tab
+    return out
+
+
+def k2_fields(args, torch, dev, fields):
+    """The batched workload: `fields` log-normal coefficient fields (log K = 1.5 N(0,1), seeds 0..) on the
+    Cube 32^3 mesh with the paper's k = 2 element, one handle, vem_set_coefficient_batch +
+    vem_solve_batch: Block-Reg (Schwarz inner CG in FP32, FP64 FGMRES) to 1e-8.  Per-system times
+    include each field's value and preconditioner build.  Field 0 is also solved in FP64."""
+    import numpy as np
+
+    from paper_1901_02330_amd.inputs import SineSolution, cube_mesh, lognormal_field
+    from paper_1901_02330_amd.vem import Solver
+
+    s = Solver()
+    s.set_mesh(cube_mesh(32))
+    s.discretize("paper", k=2)
+    s.set_rhs_functions(SineSolution.f, SineSolution.pD)
+    nus = np.stack([1.0 / lognormal_field(32**3, 1.5, sd) for sd in range(fields)])
+    kw = dict(precond="reg", tol=1e-8, maxit=1000, inner_tol=args.reg_inner_tol, inner_maxit=args.reg_inner_maxit,
+              precision="mixed")
+    s.set_coefficient(torch.as_tensor(nus[0], device=dev))
+    u64, p64, i64 = s.solve(**dict(kw, precision="fp64"))  # also builds the Schwarz patterns
+    s.set_coefficient_batch(torch.as_tensor(nus, device=dev))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, p, infos = s.solve_batch(fields, **kw)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = np.array([i["solve_ms"] for i in infos])
+    out = {"fields": fields, "n_unknowns_per_field": s.sizes()["n"], "solves_per_s": fields / wall, "wall_s": wall,
+           "p50_s": float(np.percentile(ms, 50)) / 1e3, "p99_s": float(np.percentile(ms, 99)) / 1e3,
+           "iterations_min_max": [min(i["iterations"] for i in infos), max(i["iterations"] for i in infos)],
+           "all_converged": all(i["converged"] for i in infos),
+           "field0_fp64": {"iterations": i64["iterations"], "relres": i64["relres"]},
+           "field0_rel_err_u_vs_fp64": float(torch.linalg.norm(u[0] - u64) / torch.linalg.norm(u64)),
+           "field0_rel_err_p_vs_fp64": float(torch.linalg.norm(p[0] - p64) / torch.linalg.norm(p64))}
+    s.close()
     return out
 
 
@@ -509,6 +603,9 @@ def main():
             ("xyz", "face_ptr", "face_vtx", "cell_ptr", "cell_face", "cell_face_sign")}
     nu = torch.as_tensor(1.0 / lognormal_field(n**3, 2.0, 0), device=dev)
     solver = Solver()
+    schur_kw = dict(inner_form=args.schur_inner_form, inner_tol=args.schur_inner_tol,
+                    inner_maxit=args.schur_inner_maxit, cheb_lo=args.cheb_lo)
+    reg_kw = dict(reg_inner=args.reg_inner, inner_tol=args.reg_inner_tol, inner_maxit=args.reg_inner_maxit)
 
     def step():
         torch.cuda.synchronize()
@@ -519,11 +616,10 @@ def main():
         solver.set_rhs_functions(SineSolution.f, SineSolution.pD)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        u, p, i_s = solver.solve("schur", tol=args.tol, inner_tol=args.schur_inner_tol,
-                                 inner_maxit=args.schur_inner_maxit)
+        u, p, i_s = solver.solve("schur", tol=args.tol, **schur_kw)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        u2, p2, i_r = solver.solve("reg", tol=args.tol, inner_tol=args.reg_inner_tol, maxit=5000)
+        u2, p2, i_r = solver.solve("reg", tol=args.tol, maxit=5000, **reg_kw)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         return {"t_ass": t1 - t0, "t_schur": t2 - t1, "t_reg": t3 - t2, "info_schur": i_s, "info_reg": i_r}
@@ -547,13 +643,22 @@ def main():
     for r in results:
         assert r["info_schur"]["converged"] and r["info_reg"]["converged"], "solve did not reach the tolerance"
 
-    # dominant kernel: one pipelined inner-CG iteration; the Block-Reg one carries most of the step
-    kern = {}
-    for which in ("cg_reg", "cg_schur", "spmv", "cg_schur32p"):
-        ms, nbytes = solver.time_kernel(which, reps=200)
-        kern[which] = {"avg_us": ms * 1e3, "bytes": nbytes, "gbs": nbytes / (ms * 1e-3) / 1e9}
-    dom = kern["cg_reg"]
+    # live kernel rates (HIP events on the library's stream, 200 back-to-back launches each)
     sz = solver.sizes()
+    kern = {}
+    for which in ("cg_reg_schwarz", "cheb_schur", "spmv", "cg_schur", "cg_reg", "cheb_schur32", "cg_reg_schwarz32",
+                  "cg_schur32p"):
+        ms, nbytes = solver.time_kernel(which, reps=200)
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        kern[which] = {"avg_us": ms * 1e3, "bytes": nbytes, "gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
+    # the pipelined Jacobi-CG iterations also against the blueprint's inner-PCG count, 12 nnz + 68 n
+    # (matrix once, D^{-1}, r, x read and written, z, p, q ... as a textbook PCG step), beside their own
+    # 12 nnz + 104 n (the pipelined form's 13 vector streams)
+    for which, nnz, rows in (("cg_schur", sz["nnz_schur"], sz["n_p"]), ("cg_reg", sz["nnz_reg"], sz["n_u"])):
+        b3 = 12.0 * nnz + 68.0 * rows
+        kern[which]["bytes_pcg_12nnz_68n"] = b3
+        kern[which]["frac_pcg_12nnz_68n"] = b3 / (kern[which]["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS
+    dom, val = kern["cg_reg_schwarz"], kern["cheb_schur"]
     line = {
         "metric": "solve time to rel. residual 1e-8 (s) + HBM GB/s in SpMV/precond; adjoint/fwd",
         "value": mean("t_ass") + mean("t_schur"),
@@ -579,21 +684,36 @@ def main():
         "solves": {
             "schur": {"iterations": results[-1]["info_schur"]["iterations"],
                       "inner_iterations": results[-1]["info_schur"]["inner_iterations"],
-                      "relres": results[-1]["info_schur"]["relres"], "inner_tol": args.schur_inner_tol},
+                      "relres": results[-1]["info_schur"]["relres"], **schur_kw},
             "reg": {"iterations": results[-1]["info_reg"]["iterations"],
                     "inner_iterations": results[-1]["info_reg"]["inner_iterations"],
-                    "relres": results[-1]["info_reg"]["relres"], "inner_tol": args.reg_inner_tol},
+                    "relres": results[-1]["info_reg"]["relres"], **reg_kw},
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_ppcg_iter (pipelined inner CG iteration on M + B^T B/gamma)",
+            "kernel": "k_scg_prod + k_scg_update: one iteration of Block-Reg's inner CG on A_gamma with the "
+                      "edge-patch Schwarz preconditioner (two launches; the step's dominant kernel pair)",
             "achieved": dom["gbs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": dom["gbs"] / HBM_PEAK_GBS,
+            "frac": dom["frac"],
             "traffic": None,
-            "avg_launch_us": dom["avg_us"],
-            "algorithmic_bytes_per_launch": dom["bytes"],
+            "avg_iteration_us": dom["avg_us"],
+            "algorithmic_bytes_per_iteration": dom["bytes"],
+            "bytes_formula": "12 (nnz(A_gamma) + nnz(P)) + 13 * 8 n_u",
+        },
+        "roofline_value": {
+            "bound": "hbm",
+            "kernel": "k_cheb_iter<double>: one Chebyshev-Jacobi product on S (Block-Schur's inner polynomial, "
+                      "the kernel that dominates `value`)",
+            "achieved": val["gbs"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": val["frac"],
+            "traffic": None,
+            "avg_launch_us": val["avg_us"],
+            "algorithmic_bytes_per_launch": val["bytes"],
+            "bytes_formula": "12 nnz(S) + 7 * 8 n_p",
         },
         "kernels": kern,
     }
@@ -607,11 +727,14 @@ def main():
         line.setdefault("extras", {})["batch_cube32_k2"] = k2_batch(args.k2_batch, torch, dev)
     tr = traffic_from_profiles()
     if tr is not None:
-        line["roofline"]["traffic"] = tr["bytes_per_launch"]
-        line["roofline"]["traffic_note"] = tr["note"]
+        for key, obj in (("traffic", "roofline"), ("traffic_value", "roofline_value")):
+            if tr.get(key, {}).get("bytes"):
+                line[obj]["traffic"] = tr[key]["bytes"]
+                line[obj]["traffic_ratio_to_algorithmic"] = tr[key]["ratio_to_algorithmic"]
+                line[obj]["traffic_note"] = tr[key]["note"]
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
-        line["cpu_baseline"] = cpu_baseline(n, args.cpu_n)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_n or n, args)
     print(json.dumps(line), flush=True)
 
 

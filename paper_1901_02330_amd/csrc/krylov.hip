@@ -299,10 +299,13 @@ __global__ void __launch_bounds__(kPcgThreads) k_cg_update(int k, int64_t n, T* 
 //   [init]    z = P r0; x = 0; partials r0.z
 //   [product] rho, beta = rho / rho_old; stop test; p = z + beta p; q = F z + beta q; partials p.q
 //   [update]  alpha = rho / p.q; x += alpha p; r -= alpha q; z -= alpha P q; partials r.z
-template <typename T>
-__global__ void __launch_bounds__(kPcgThreads) k_scg_init(SellViewT<T> P, const T* __restrict__ r0,
-                                                          T* __restrict__ x, T* __restrict__ z, PcgState* st,
-                                                          double tol2, double* __restrict__ prho0) {
+// Each kernel issues its row's product (which does not depend on this iteration's scalars) before
+// it sums the previous kernel's partials, so the product's loads are in flight during that prologue.
+// Block size: 1024 threads when every row has a thread, 256 when threads loop over rows.
+template <typename T, int kBlock>
+__global__ void __launch_bounds__(kBlock) k_scg_init(SellViewT<T> P, const T* __restrict__ r0, T* __restrict__ x,
+                                                     T* __restrict__ z, PcgState* st, double tol2,
+                                                     double* __restrict__ prho0) {
   double acc[1] = {0.0};
   for (int64_t row = xcd_block() * blockDim.x + threadIdx.x; row < P.rows;
        row += (int64_t)gridDim.x * blockDim.x) {
@@ -321,14 +324,27 @@ __global__ void __launch_bounds__(kPcgThreads) k_scg_init(SellViewT<T> P, const 
   }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kPcgThreads) k_scg_prod(int k, SellViewT<T> F, const T* __restrict__ z,
-                                                          T* __restrict__ p, T* __restrict__ q, PcgState* st,
-                                                          const double* __restrict__ prho, double* __restrict__ ppq) {
-  if (st->done) return;
+template <typename T, int kBlock>
+__global__ void __launch_bounds__(kBlock) k_scg_prod(int k, SellViewT<T> F, const T* __restrict__ z,
+                                                     T* __restrict__ p, T* __restrict__ q, PcgState* st,
+                                                     const double* __restrict__ prho, double* __restrict__ ppq) {
   const int G = gridDim.x;
   const int cur = k & 1;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t row = xcd_block() * blockDim.x + threadIdx.x;
+  T fz = T(0), zi = T(0), po = T(0), qo = T(0);
+  auto load = [&](int64_t i) {
+    fz = sell_dot(F, i, z);
+    zi = z[i];
+    if (k > 0) {
+      po = p[i];
+      qo = q[i];
+    }
+  };
+  if (row < F.rows) load(row);
+  const int was_done = st->done;
   const double rho = block_sum_partials(prho + (size_t)cur * G, G, 1, 0);
+  if (was_done) return;
   const double rho0 = k == 0 ? rho : st->gamma0;
   const double beta = k == 0 ? 0.0 : rho / st->gamma[1 - cur];
   const bool done = !(rho > st->tol2 * rho0);
@@ -340,44 +356,57 @@ __global__ void __launch_bounds__(kPcgThreads) k_scg_prod(int k, SellViewT<T> F,
   if (done) return;
   const T bt = (T)beta;
   double acc[1] = {0.0};
-  for (int64_t row = xcd_block() * blockDim.x + threadIdx.x; row < F.rows;
-       row += (int64_t)gridDim.x * blockDim.x) {
-    const T fz = sell_dot(F, row, z);
-    const T pn = k == 0 ? z[row] : z[row] + bt * p[row];
-    const T qn = k == 0 ? fz : fz + bt * q[row];
+  while (row < F.rows) {
+    const T pn = k == 0 ? zi : zi + bt * po;
+    const T qn = k == 0 ? fz : fz + bt * qo;
     p[row] = pn;
     q[row] = qn;
     acc[0] += (double)pn * (double)qn;
+    row += stride;
+    if (row < F.rows) load(row);
   }
   block_partials<1>(acc, ppq);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kPcgThreads) k_scg_update(int k, SellViewT<T> P, T* __restrict__ x,
-                                                            T* __restrict__ r, T* __restrict__ z,
-                                                            const T* __restrict__ q, const T* __restrict__ p,
-                                                            PcgState* st, double* __restrict__ prho,
-                                                            const double* __restrict__ ppq) {
-  if (st->done) return;
+template <typename T, int kBlock>
+__global__ void __launch_bounds__(kBlock) k_scg_update(int k, SellViewT<T> P, T* __restrict__ x,
+                                                       T* __restrict__ r, T* __restrict__ z,
+                                                       const T* __restrict__ q, const T* __restrict__ p,
+                                                       PcgState* st, double* __restrict__ prho,
+                                                       const double* __restrict__ ppq) {
   const int G = gridDim.x;
   const int cur = k & 1;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t row = xcd_block() * blockDim.x + threadIdx.x;
+  T pq_r = T(0), qi = T(0), ri = T(0), zi = T(0), xi = T(0), pi = T(0);
+  auto load = [&](int64_t i) {
+    pq_r = sell_dot(P, i, q);
+    qi = q[i];
+    ri = r[i];
+    zi = z[i];
+    xi = x[i];
+    pi = p[i];
+  };
+  if (row < P.rows) load(row);
+  const int was_done = st->done;
   const double rho = block_sum_partials(prho + (size_t)cur * G, G, 1, 0);
   const double pq = block_sum_partials(ppq, G, 1, 0);
+  if (was_done) return;
   if (!(pq > 0.0)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) st->done = 2;
     return;
   }
   const T a = (T)(rho / pq);
   double acc[1] = {0.0};
-  for (int64_t row = xcd_block() * blockDim.x + threadIdx.x; row < P.rows;
-       row += (int64_t)gridDim.x * blockDim.x) {
-    const T pqr = sell_dot(P, row, q);
-    const T rn = r[row] - a * q[row];
-    const T zn = z[row] - a * pqr;
+  while (row < P.rows) {
+    const T rn = ri - a * qi;
+    const T zn = zi - a * pq_r;
     r[row] = rn;
     z[row] = zn;
-    x[row] += a * p[row];
+    x[row] = xi + a * pi;
     acc[0] += (double)rn * (double)zn;
+    row += stride;
+    if (row < P.rows) load(row);
   }
   block_partials<1>(acc, prho + (size_t)(1 - cur) * G);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -572,18 +601,31 @@ void launch_pcg_iter32(hipStream_t s, int i, const Sell& A, const PcgWork32& w, 
 
 template <typename T>
 void launch_scg_init(hipStream_t s, const Sell& P, const PcgWorkT<T>& w, PcgState* st, double tol, double* part) {
-  k_scg_init<T><<<pcg_grid(P.rows), kPcgThreads, 0, s>>>(values_view<T>(P), w.r, w.x, w.z, st, tol * tol, part);
+  if (P.rows > kPcgMaxThreads)
+    k_scg_init<T, 256><<<pcg_grid(P.rows, 256), 256, 0, s>>>(values_view<T>(P), w.r, w.x, w.z, st, tol * tol, part);
+  else
+    k_scg_init<T, 1024><<<pcg_grid(P.rows, 1024), 1024, 0, s>>>(values_view<T>(P), w.r, w.x, w.z, st, tol * tol,
+                                                                  part);
 }
 
-// work layout: x, r, z, p as named, w0 = q (s and w1 unused)
+// work layout: x, r, z, p as named, w0 = q (s and w1 unused); the init's grid (same rows, same
+// block size) leaves the partials the first product kernel sums
 template <typename T>
 void launch_scg_iter(hipStream_t s, int i, const Sell& F, const Sell& P, const PcgWorkT<T>& w, PcgState* st,
                      double* part) {
-  const int G = pcg_grid(F.rows);
-  double* prho = part;  // 2 x G slots
-  double* ppq = part + 2 * (size_t)G;
-  k_scg_prod<T><<<G, kPcgThreads, 0, s>>>(i, values_view<T>(F), w.z, w.p, w.w0, st, prho, ppq);
-  k_scg_update<T><<<G, kPcgThreads, 0, s>>>(i, values_view<T>(P), w.x, w.r, w.z, w.w0, w.p, st, prho, ppq);
+  if (F.rows > kPcgMaxThreads) {
+    const int G = pcg_grid(F.rows, 256);
+    double* prho = part;  // 2 x G slots
+    double* ppq = part + 2 * (size_t)G;
+    k_scg_prod<T, 256><<<G, 256, 0, s>>>(i, values_view<T>(F), w.z, w.p, w.w0, st, prho, ppq);
+    k_scg_update<T, 256><<<G, 256, 0, s>>>(i, values_view<T>(P), w.x, w.r, w.z, w.w0, w.p, st, prho, ppq);
+  } else {
+    const int G = pcg_grid(F.rows, 1024);
+    double* prho = part;
+    double* ppq = part + 2 * (size_t)G;
+    k_scg_prod<T, 1024><<<G, 1024, 0, s>>>(i, values_view<T>(F), w.z, w.p, w.w0, st, prho, ppq);
+    k_scg_update<T, 1024><<<G, 1024, 0, s>>>(i, values_view<T>(P), w.x, w.r, w.z, w.w0, w.p, st, prho, ppq);
+  }
 }
 
 template void launch_scg_init<double>(hipStream_t, const Sell&, const PcgWorkT<double>&, PcgState*, double, double*);
