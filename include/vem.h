@@ -171,12 +171,15 @@ typedef struct {
 void vem_solve_opts_default(vem_solve_opts* opts);
 
 /* Create a handle bound to the current HIP device and to `stream`
- * (a hipStream_t; NULL = the default stream). */
+ * (a hipStream_t; NULL = the default stream).  The handle carries one instance of the paper's
+ * discrete problem (Section 4.3, eq. mod_prob_eqDisc) and its solver state.  Errors: VEM_EINVAL
+ * (h NULL), VEM_ENOMEM, VEM_EHIP. */
 vem_status vem_create(vem_handle* h, void* stream);
 vem_status vem_destroy(vem_handle h);
 
-/* Set the polyhedral mesh (copied in; the caller may free its arrays on
- * return).  xyz[nv*3]: vertex coordinates.  face_ptr[nf+1], face_vtx: the
+/* Set the polyhedral mesh Omega_h (Section 2: polyhedra P with planar polygonal faces; the
+ * paper's Section 4.4 meshes are of this kind), copied in; the caller may free its arrays on
+ * return.  xyz[nv*3]: vertex coordinates.  face_ptr[nf+1], face_vtx: the
  * vertex loop of each planar convex face, counter-clockwise about the face's
  * global normal n_f.  cell_ptr[nc+1], cell_face, cell_face_sign: the faces of
  * each cell and sigma = +1 if n_f points out of the cell, -1 otherwise.  Every
@@ -201,10 +204,14 @@ vem_status vem_set_mesh(vem_handle h, int64_t nv, const double* xyz, int64_t nf,
  * coefficient is set to nu = 1 and the right-hand side to zero. */
 vem_status vem_discretize(vem_handle h, int family, int k, int load_points);
 
+/* Sizes of the discretisation (DOF counts of Section 4.1's spaces: per face dim P_k(f) moments,
+ * per cell dim P_{k-1} - 1 + dim G_k^oplus interior moments and dim P_{k-1} pressure moments; the
+ * lowest order 1, 0, 1), matrix sizes, quadrature point counts, h and gamma = h^2 (Section 5,
+ * eq. meshSize).  out: host.  Errors: VEM_EINVAL before vem_discretize. */
 vem_status vem_get_sizes(vem_handle h, vem_sizes* out);
 
-/* Write the quadrature points at which the caller evaluates f and p_D
- * (device buffers): qp_cell[3*n_qp_cell] and qp_face[3*n_qp_face] (either
+/* Write the quadrature points at which the caller evaluates f and p_D (the loads of Section 4.3,
+ * which the paper notes depend only on the quadrature formulas used; device buffers): qp_cell[3*n_qp_cell] and qp_face[3*n_qp_face] (either
  * may be NULL to skip), as structures of arrays: all x coordinates, then all
  * y, then all z.  Points are ordered cell by cell, then by the tetrahedra
  * (x_ref, v0, v_a, v_{a+1}) of each face, then by the reference points;
@@ -221,8 +228,37 @@ vem_status vem_get_quadrature(vem_handle h, double* qp_cell, double* qp_face);
  * (checked on the device; the previous coefficient stays in place). */
 vem_status vem_set_coefficient(vem_handle h, const double* nu);
 
-/* Right-hand side from point values (device): f_qp[n_qp_cell] at the points
- * of vem_get_quadrature, pD_qp[n_qp_face] (NULL means p_D = 0). */
+/* Multi-field batch: nbatch coefficient fields nu[nbatch * n_cells] (field b at offset b * n_cells;
+ * host or device; copied in, every value checked positive and finite on the device), for
+ * vem_solve_batch.  The blueprint's nbatch of the coefficient (Section 4.3: M_P = nu_P M1_P, so a field
+ * only rescales the stored coefficient-free local matrices).  Replaces any earlier batch; the handle's
+ * own coefficient (vem_set_coefficient) is unchanged.  Errors: VEM_EINVAL (nothing stored). */
+vem_status vem_set_coefficient_batch(vem_handle h, int64_t nbatch, const double* nu);
+
+/* nbatch right-hand sides from point values, for vem_solve_batch: f_qp[nbatch * n_qp_cell] and
+ * pD_qp[nbatch * n_qp_face] (NULL: p_D = 0), field b at offset b times the point count (device).
+ * Each is loaded as vem_set_rhs loads one; the handle's own right-hand side is unchanged.  Pressure
+ * boundary data only.  Errors: VEM_EINVAL. */
+vem_status vem_set_rhs_batch(vem_handle h, int64_t nbatch, const double* f_qp, const double* pD_qp);
+
+/* Solve nbatch systems of eq. mod_prob_eqDisc: system b takes coefficient field b of
+ * vem_set_coefficient_batch (or the handle's coefficient if no batch of fields is set) and right-hand
+ * side b of vem_set_rhs_batch (or its single right-hand side if one was set, or the handle's
+ * [g; -F] if none).  u[nbatch * n_u], p[nbatch * n_p]: device, system b at offset b * n_u and b * n_p.
+ * info[nbatch] (host, may be NULL).  The systems are solved one after another on the handle's stream
+ * with the same options; each field rebuilds the coefficient-dependent values (K, and S or A_gamma with
+ * its preconditioner) from the stored local matrices.  The handle's coefficient is restored on return.
+ * Returns the first error, else the largest warning (VEM_NOT_CONVERGED if any system missed tol).
+ * Errors: VEM_EINVAL when neither nbatch fields nor nbatch right-hand sides are set, or their counts
+ * differ from nbatch. */
+vem_status vem_solve_batch(vem_handle h, const vem_solve_opts* opts, int64_t nbatch, double* u, double* p,
+                           vem_solve_info* info);
+
+/* Right-hand side [g; -F] of eq. mod_prob_eqDisc from point values (device): F_P = int_P f psi
+ * (Section 4.3) from f_qp[n_qp_cell] at the points of vem_get_quadrature, and the boundary term
+ * g = -int_{dOmega} p_D phi.n from pD_qp[n_qp_face] (NULL means p_D = 0).  Errors: VEM_EINVAL
+ * (before vem_discretize, or with flux boundary data); non-finite values are not checked here, a
+ * later vem_solve reports them (VEM_ENAN). */
 vem_status vem_set_rhs(vem_handle h, const double* f_qp, const double* pD_qp);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
@@ -258,14 +294,16 @@ vem_status vem_set_boundary(vem_handle h, int kind);
  * VEM_BC_FLUX. */
 vem_status vem_set_rhs_flux(vem_handle h, const double* f_qp, const double* u_qp);
 
-/* Solve.  u[n_u], p[n_p]: caller-owned device buffers receiving the flux and
- * pressure unknowns (read as the initial guess when opts->use_x0).  Blocks
- * until the result is known.  Returns VEM_OK, VEM_NOT_CONVERGED (best
- * iterate written), or an error.  info may be NULL. */
+/* Solve the saddle system of eq. mod_prob_eqDisc, [M B^T; B 0][u; p] = [g; -F], by FGMRES with the
+ * block preconditioner opts->precond (Section 5, eqs. block_schur and block_diag).  u[n_u], p[n_p]:
+ * caller-owned device buffers receiving the flux and pressure unknowns (read as the initial guess
+ * when opts->use_x0).  Blocks until the result is known.  Returns VEM_OK, VEM_NOT_CONVERGED (best
+ * iterate written), or an error (VEM_EINVAL for bad options, VEM_ENAN, VEM_EHIP).  info may be
+ * NULL. */
 vem_status vem_solve(vem_handle h, const vem_solve_opts* opts, double* u, double* p, vem_solve_info* info);
 
-/* Solve K x = rhs for a caller-supplied right-hand side (device, n
- * doubles) instead of the assembled [g; -F]; otherwise as vem_solve.  K is
+/* Solve K x = rhs (K the matrix of eq. mod_prob_eqDisc) for a caller-supplied right-hand side
+ * (device, n doubles) instead of the assembled [g; -F]; otherwise as vem_solve.  K is
  * symmetric (eq. mod_prob_eqDisc in the symmetric form above), so this is also
  * the adjoint solve K^T lambda = dJ/dx of a functional J of the solution
  * (same operator, same preconditioners).  Pressure boundary data only:

@@ -135,6 +135,9 @@ struct vem_ctx {
   double np_nn = 1.0, np_wn = 1.0;
   hipEvent_t step_done[2] = {nullptr, nullptr};
   HBuf<PcgState> hpcg;
+  // multi-field batch: nb_nu coefficient fields (nu, cell-major per field) and nb_rhs right-hand sides
+  int64_t nb_nu = 0, nb_rhs = 0;
+  DBuf<double> nu_batch, rhs_batch;
 };
 
 namespace {
@@ -1424,6 +1427,55 @@ vem_status vem_set_rhs(vem_handle h, const double* f_qp, const double* pD_qp) {
   });
 }
 
+vem_status vem_set_coefficient_batch(vem_handle h, int64_t nbatch, const double* nu) {
+  if (!h || !nu || nbatch < 1) return VEM_EINVAL;
+  return guarded(h, [&] {
+    require_disc(h);
+    hipStream_t s = h->stream;
+    const int64_t n = nbatch * h->nc;
+    VEM_REQUIRE(n <= INT_MAX, VEM_EINVAL, "nbatch * n_cells exceeds 2^31 - 1");
+    DBuf<double>& stage = h->tmp.f64[7];
+    stage.reserve(n);
+    VEM_HIP(hipMemcpyAsync(stage.p, nu, n * sizeof(double), hipMemcpyDefault, s));
+    DBuf<int>& bad = h->tmp.i32[0];
+    bad.reserve(1);
+    fill_i32(s, 1, 0, bad);
+    launch_check_cells(s, (int)n, stage.p, bad);  // every value positive and finite
+    check_launch();
+    h->tmp.ti.alloc(8);
+    VEM_HIP(hipMemcpyAsync(h->tmp.ti.p, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    sync(h);
+    VEM_REQUIRE(h->tmp.ti.p[0] == 0, VEM_EINVAL, "coefficient nu must be positive and finite in every cell");
+    h->nu_batch.reserve(n);
+    VEM_HIP(hipMemcpyAsync(h->nu_batch.p, stage.p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    h->nb_nu = nbatch;
+  });
+}
+
+vem_status vem_set_rhs_batch(vem_handle h, int64_t nbatch, const double* f_qp, const double* pD_qp) {
+  if (!h || !f_qp || nbatch < 1) return VEM_EINVAL;
+  return guarded(h, [&] {
+    require_disc(h);
+    VEM_REQUIRE(h->bc == VEM_BC_PRESSURE, VEM_EINVAL, "batched right-hand sides take pressure boundary data");
+    hipStream_t s = h->stream;
+    const int64_t N = h->L.Nu + h->L.Np;
+    const int64_t nqc = h->ntet * h->npts_cell, nqf = h->nbtri * h->npts_face;
+    h->rhs_batch.reserve(nbatch * N);
+    // each load goes through the handle's single right-hand side, which is then restored
+    DBuf<double>& keep = h->tmp.f64[6];
+    keep.reserve(N);
+    launch_copy(s, N, h->rhs, keep);
+    for (int64_t b = 0; b < nbatch; ++b) {
+      set_loads(h, f_qp + b * nqc, pD_qp ? pD_qp + b * nqf : nullptr, nullptr);
+      launch_copy(s, N, h->rhs, h->rhs_batch.p + b * N);
+    }
+    launch_copy(s, N, keep, h->rhs);
+    check_launch();
+    sync(h);
+    h->nb_rhs = nbatch;
+  });
+}
+
 vem_status vem_set_rhs_noalloc(vem_handle h, const double* f_qp, const double* pD_qp) {
   if (!h || !f_qp) return VEM_EINVAL;
   return guarded(h, [&] {
@@ -1886,6 +1938,52 @@ vem_status vem_solve_rhs(vem_handle h, const vem_solve_opts* opts, const double*
     return VEM_EINVAL;
   }
   return solve_impl(h, opts, rhs, u, p, info);
+}
+
+vem_status vem_solve_batch(vem_handle h, const vem_solve_opts* opts, int64_t nbatch, double* u, double* p,
+                           vem_solve_info* info) {
+  if (!h || !u || !p || nbatch < 1) return VEM_EINVAL;
+  if (!h->has_disc || (h->nb_nu != 0 && h->nb_nu != nbatch) || (h->nb_rhs > 1 && h->nb_rhs != nbatch) ||
+      (h->nb_nu == 0 && h->nb_rhs <= 1) || (h->nb_rhs > 0 && h->bc != VEM_BC_PRESSURE)) {
+    h->last_error = "vem_solve_batch: set nbatch coefficient fields and/or nbatch right-hand sides first";
+    return VEM_EINVAL;
+  }
+  const int64_t nc = h->nc, Nu = h->L.Nu, Np = h->L.Np, N = Nu + Np;
+  // the handle's own coefficient is restored afterwards
+  vem_status st = guarded(h, [&] {
+    DBuf<double>& keep = h->tmp.f64[5];
+    keep.reserve(nc);
+    launch_copy(h->stream, nc, h->nu, keep);
+    check_launch();
+  });
+  if (st != VEM_OK) return st;
+  vem_status worst = VEM_OK;
+  for (int64_t b = 0; b < nbatch; ++b) {
+    if (h->nb_nu > 0) {
+      st = guarded(h, [&] {
+        launch_copy(h->stream, nc, h->nu_batch.p + b * nc, h->nu);
+        check_launch();
+        invalidate_values(h);
+      });
+      if (st != VEM_OK) return st;
+    }
+    const double* rhs = h->nb_rhs > 1 ? h->rhs_batch.p + b * N : h->nb_rhs == 1 ? h->rhs_batch.p : nullptr;
+    vem_solve_info inf{};
+    st = solve_impl(h, opts, rhs, u + b * Nu, p + b * Np, &inf);
+    if (info) info[b] = inf;
+    if (st < 0) return st;
+    if (st > worst) worst = st;
+  }
+  if (h->nb_nu > 0) {
+    st = guarded(h, [&] {
+      launch_copy(h->stream, nc, h->tmp.f64[5], h->nu);
+      check_launch();
+      invalidate_values(h);
+      sync(h);
+    });
+    if (st != VEM_OK) return st;
+  }
+  return worst;
 }
 
 vem_status vem_coefficient_gradient(vem_handle h, const double* u, const double* lam, double* g) {

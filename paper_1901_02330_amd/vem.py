@@ -97,6 +97,9 @@ def load():
         "vem_set_boundary": ([H, c_int], c_int),
         "vem_set_rhs_flux": ([H, P, P], c_int),
         "vem_set_rhs_noalloc": ([H, P, P], c_int),
+        "vem_set_coefficient_batch": ([H, c_int64, P], c_int),
+        "vem_set_rhs_batch": ([H, c_int64, P, P], c_int),
+        "vem_solve_batch": ([H, POINTER(SolveOpts), c_int64, P, P, POINTER(SolveInfo)], c_int),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -253,12 +256,9 @@ class Solver:
         else:
             self.set_rhs(fv, gv)
 
-    @_ordered
-    def solve(self, precond="schur", tol=1e-8, restart=30, maxit=5000, inner_tol=1e-6, inner_maxit=5000,
-              inner_check=32, gamma=0.0, x0=None, precision="fp64", rhs=None, graphs=False,
-              inner_form="pipelined", reg_inner="schwarz", cheb_lo=0.0):
-        t = self.torch
-        sz = self.sizes()
+    def _opts(self, precond="schur", tol=1e-8, restart=30, maxit=5000, inner_tol=1e-6, inner_maxit=5000,
+              inner_check=32, gamma=0.0, precision="fp64", graphs=False, inner_form="pipelined",
+              reg_inner="schwarz", cheb_lo=0.0):
         o = SolveOpts()
         self.lib.vem_solve_opts_default(byref(o))
         o.precond = PREC[precond]
@@ -268,8 +268,50 @@ class Solver:
         o.precision = {"fp64": 0, "mixed": 1}[precision]
         o.use_graphs = 1 if graphs else 0
         o.inner_form = {"pipelined": 0, "classical": 1, "chebyshev": 2}[inner_form]
-        o.cheb_lo = float(cheb_lo)
         o.reg_inner = {"jacobi": 0, "schwarz": 1}[reg_inner]
+        o.cheb_lo = float(cheb_lo)
+        return o
+
+    @_ordered
+    def set_coefficient_batch(self, nus):
+        """nbatch coefficient fields (nbatch, n_cells) for solve_batch."""
+        nus = self._dev(nus, self.torch.float64)
+        self._check(self.lib.vem_set_coefficient_batch(self.h, nus.shape[0], _ptr(nus)))
+
+    @_ordered
+    def set_rhs_batch(self, f_qp, pD_qp=None):
+        """nbatch right-hand sides from point values: f_qp (nbatch, n_qp_cell), pD_qp (nbatch, n_qp_face)."""
+        f = self._dev(f_qp, self.torch.float64)
+        pD = None if pD_qp is None else self._dev(pD_qp, self.torch.float64)
+        self._check(self.lib.vem_set_rhs_batch(self.h, f.shape[0], _ptr(f), _ptr(pD) if pD is not None else None))
+
+    @_ordered
+    def solve_batch(self, nbatch, **kw):
+        """Solve the nbatch systems set by set_coefficient_batch / set_rhs_batch: u (nbatch, n_u),
+        p (nbatch, n_p) and one info dict per system."""
+        t = self.torch
+        sz = self.sizes()
+        o = self._opts(**kw)
+        u = t.empty((nbatch, sz["n_u"]), dtype=t.float64, device=self.device)
+        p = t.empty((nbatch, sz["n_p"]), dtype=t.float64, device=self.device)
+        infos = (SolveInfo * nbatch)()
+        self._check(self.lib.vem_solve_batch(self.h, byref(o), nbatch, _ptr(u), _ptr(p), infos))
+        out = []
+        for i in infos:
+            d = {f: getattr(i, f) for f, _ in SolveInfo._fields_}
+            d["converged"] = d["status"] == 0
+            out.append(d)
+        return u, p, out
+
+    @_ordered
+    def solve(self, precond="schur", tol=1e-8, restart=30, maxit=5000, inner_tol=1e-6, inner_maxit=5000,
+              inner_check=32, gamma=0.0, x0=None, precision="fp64", rhs=None, graphs=False,
+              inner_form="pipelined", reg_inner="schwarz", cheb_lo=0.0):
+        t = self.torch
+        sz = self.sizes()
+        o = self._opts(precond=precond, tol=tol, restart=restart, maxit=maxit, inner_tol=inner_tol,
+                       inner_maxit=inner_maxit, inner_check=inner_check, gamma=gamma, precision=precision,
+                       graphs=graphs, inner_form=inner_form, reg_inner=reg_inner, cheb_lo=cheb_lo)
         if x0 is not None:
             u = self._dev(x0[0], t.float64).clone()
             p = self._dev(x0[1], t.float64).clone()
@@ -364,4 +406,5 @@ EXPORTED = [
     "vem_get_quadrature", "vem_set_coefficient", "vem_set_rhs", "vem_solve", "vem_apply", "vem_export_csr",
     "vem_get_rhs", "vem_get_geometry", "vem_status_string", "vem_last_error", "vem_time_kernel",
     "vem_solve_rhs", "vem_coefficient_gradient", "vem_set_boundary", "vem_set_rhs_flux", "vem_set_rhs_noalloc",
+    "vem_set_coefficient_batch", "vem_set_rhs_batch", "vem_solve_batch",
 ]

@@ -11,8 +11,11 @@
  * (p_D = 0), solves with the chosen block preconditioner and writes u then p
  * (FP64, native byte order) to a file.
  *
- * usage: cube_solve n nu_file out_file [schur|reg]
+ * usage: cube_solve n nu_file out_file [schur|reg [batch B]]
  *        prints one line: n_u n_p iterations relres status
+ *        With "batch B", nu_file holds B fields (B n^3 doubles): they are set with
+ *        vem_set_coefficient_batch and solved with vem_solve_batch (one load for all), the B
+ *        solutions are written one after another, and one line per field is printed.
  *        cube_solve --mesh n out_file
  *        writes the mesh arrays only (no GPU call): nv, nf, nc (int64), xyz,
  *        face_ptr, face_vtx, cell_ptr, cell_face (int32), cell_face_sign (int8)
@@ -166,13 +169,19 @@ int main(int argc, char** argv) {
     return 1;
   }
   const int reg = argc > 4 && strcmp(argv[4], "reg") == 0;
+  const int nb = (argc > 6 && strcmp(argv[5], "batch") == 0) ? atoi(argv[6]) : 0;
+  if (argc > 5 && (nb < 1 || nb > 64)) {
+    fprintf(stderr, "batch B: B must be in 1..64\n");
+    return 1;
+  }
   cube_mesh m = make_cube(n);
 
-  /* nu per cell, n^3 doubles */
-  double* nu = xmalloc(sizeof(double) * m.nc);
+  /* nu per cell, n^3 doubles per field */
+  const int64_t nfield = nb > 0 ? nb : 1;
+  double* nu = xmalloc(sizeof(double) * m.nc * nfield);
   FILE* fin = fopen(argv[2], "rb");
-  if (!fin || fread(nu, sizeof(double), (size_t)m.nc, fin) != (size_t)m.nc) {
-    fprintf(stderr, "cannot read %lld coefficients from %s\n", (long long)m.nc, argv[2]);
+  if (!fin || fread(nu, sizeof(double), (size_t)(m.nc * nfield), fin) != (size_t)(m.nc * nfield)) {
+    fprintf(stderr, "cannot read %lld coefficients from %s\n", (long long)(m.nc * nfield), argv[2]);
     return 1;
   }
   fclose(fin);
@@ -207,22 +216,34 @@ int main(int argc, char** argv) {
   o.inner_tol = reg ? 1e-1 : 1e-10;
   o.maxit = 5000;
   double *u_d = NULL, *p_d = NULL;
-  CHECK_HIP(hipMalloc((void**)&u_d, sizeof(double) * sz.n_u));
-  CHECK_HIP(hipMalloc((void**)&p_d, sizeof(double) * sz.n_p));
-  vem_solve_info info;
-  const vem_status st = vem_solve(g_h, &o, u_d, p_d, &info);
+  CHECK_HIP(hipMalloc((void**)&u_d, sizeof(double) * sz.n_u * nfield));
+  CHECK_HIP(hipMalloc((void**)&p_d, sizeof(double) * sz.n_p * nfield));
+  vem_solve_info info[64];
+  vem_status st;
+  if (nb > 0) {
+    /* the fields in host memory; the library copies them in */
+    CHECK_VEM(vem_set_coefficient_batch(g_h, nb, nu));
+    st = vem_solve_batch(g_h, &o, nb, u_d, p_d, info);
+  } else {
+    st = vem_solve(g_h, &o, u_d, p_d, info);
+  }
   CHECK_VEM(st);
 
-  double* x = xmalloc(sizeof(double) * (sz.n_u + sz.n_p));
-  CHECK_HIP(hipMemcpy(x, u_d, sizeof(double) * sz.n_u, hipMemcpyDeviceToHost));
-  CHECK_HIP(hipMemcpy(x + sz.n_u, p_d, sizeof(double) * sz.n_p, hipMemcpyDeviceToHost));
+  const int64_t nx = sz.n_u + sz.n_p;
+  double* x = xmalloc(sizeof(double) * nx * nfield);
+  for (int64_t b = 0; b < nfield; ++b) {
+    CHECK_HIP(hipMemcpy(x + b * nx, u_d + b * sz.n_u, sizeof(double) * sz.n_u, hipMemcpyDeviceToHost));
+    CHECK_HIP(hipMemcpy(x + b * nx + sz.n_u, p_d + b * sz.n_p, sizeof(double) * sz.n_p, hipMemcpyDeviceToHost));
+  }
   FILE* fout = fopen(argv[3], "wb");
-  if (!fout || fwrite(x, sizeof(double), (size_t)(sz.n_u + sz.n_p), fout) != (size_t)(sz.n_u + sz.n_p)) {
+  if (!fout || fwrite(x, sizeof(double), (size_t)(nx * nfield), fout) != (size_t)(nx * nfield)) {
     fprintf(stderr, "cannot write %s\n", argv[3]);
     return 1;
   }
   fclose(fout);
-  printf("%lld %lld %d %.6e %d\n", (long long)sz.n_u, (long long)sz.n_p, info.iterations, info.relres, st);
+  for (int64_t b = 0; b < nfield; ++b)
+    printf("%lld %lld %d %.6e %d\n", (long long)sz.n_u, (long long)sz.n_p, info[b].iterations, info[b].relres,
+           info[b].status);
 
   CHECK_HIP(hipFree(qc_d));
   CHECK_HIP(hipFree(f_d));

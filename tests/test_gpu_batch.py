@@ -48,3 +48,66 @@ def test_batch_matches_sequential():
     print("field 0 vs oracle: backward error", berr, "u", eu, "p", ep, flush=True)
     assert berr <= 1.01e-10
     assert eu <= 1e-7 and ep <= 1e-7
+
+
+def test_native_batch_matches_single_solves_and_oracle():
+    """vem_set_coefficient_batch / vem_set_rhs_batch / vem_solve_batch: each system of the batch gives the
+    same bits as a single solve with that coefficient and right-hand side, the handle's own coefficient
+    and right-hand side are unchanged afterwards, and system 0 matches the oracle's direct solve."""
+    import torch
+
+    from oracle.assemble import discretize
+    from oracle.solvers import direct_solve
+    from paper_1901_02330_amd.inputs import SineSolution, cube_mesh, lognormal_field
+    from paper_1901_02330_amd.vem import Solver
+
+    print("native batch", flush=True)
+    m = cube_mesh(7, 6, 5)
+    nc = 210
+    B = 4
+    nus = np.stack([1.0 / lognormal_field(nc, 1.5, 20 + b) for b in range(B)])
+    s = Solver()
+    s.set_mesh(m)
+    s.discretize("lo")
+    s.set_rhs_functions(SineSolution.f, SineSolution.pD)
+    qc, qf = s.quadrature()
+    scale = torch.arange(1, B + 1, dtype=torch.float64, device=qc.device)[:, None]
+    fb = scale * SineSolution.f(qc)[None, :]          # system b: load (b + 1) f
+    pDb = (qf[:, 0] * qf[:, 1])[None, :] * scale       # and p_D = (b + 1) x y
+    s.set_coefficient_batch(torch.as_tensor(nus))
+    s.set_rhs_batch(fb, pDb)
+    b_before = s.rhs().clone()
+    kw = dict(precond="schur", tol=1e-12, inner_tol=1e-12, inner_maxit=32)
+    ub, pb, infos = s.solve_batch(B, **kw)
+    assert all(i["converged"] for i in infos), infos
+    assert torch.equal(s.rhs(), b_before)
+    ref = Solver()
+    ref.set_mesh(m)
+    ref.discretize("lo")
+    for b in range(B):
+        ref.set_coefficient(torch.as_tensor(nus[b]))
+        ref.set_rhs(fb[b], pDb[b])
+        u, p, info = ref.solve(**kw)
+        assert info["iterations"] == infos[b]["iterations"]
+        assert torch.equal(u, ub[b]) and torch.equal(p, pb[b]), b
+    # system 0 against the oracle (load f, p_D = x y)
+    class Rhs0:
+        f = staticmethod(SineSolution.f)
+
+        @staticmethod
+        def pD(x):
+            return x[..., 0] * x[..., 1]
+
+    d = discretize(m, nu=nus[0], rhs=Rhs0())
+    x = direct_solve(d["K"], d["b"])
+    eu = np.linalg.norm(ub[0].cpu().numpy() - x[: d["Nu"]]) / np.linalg.norm(x[: d["Nu"]])
+    ep = np.linalg.norm(pb[0].cpu().numpy() - x[d["Nu"]:]) / np.linalg.norm(x[d["Nu"]:])
+    print("system 0 vs oracle", eu, ep, flush=True)
+    assert eu <= 1e-9 and ep <= 1e-9
+    # the handle's own coefficient (nu = 1) still solves its own system
+    u1, p1, i1 = s.solve(**kw)
+    d1 = discretize(m, rhs=SineSolution())
+    x1 = direct_solve(d1["K"], d1["b"])
+    assert np.linalg.norm(u1.cpu().numpy() - x1[: d1["Nu"]]) <= 1e-9 * np.linalg.norm(x1[: d1["Nu"]])
+    s.close()
+    ref.close()
