@@ -108,7 +108,9 @@ enum { VEM_INNER_PIPELINED = 0, VEM_INNER_CLASSICAL = 1, VEM_INNER_CHEBYSHEV = 2
  * divergence-free fluxes that dominate the small eigenvalues of A_gamma, which a diagonal
  * preconditioner never sees.  For the order-k element the interior DOFs of each cell are first
  * condensed exactly (static condensation), and the CG runs on the face DOFs; two kernels per
- * iteration; inner_form and use_graphs are ignored. */
+ * iteration; inner_form and use_graphs are ignored.  Limits: at most 80 DOFs per patch (faces around
+ * one edge times face DOFs: 8 faces at k = 3, 13 at k = 2) and 160 faces sharing an edge with one
+ * face; a mesh beyond them makes the Block-Reg solve fail with VEM_EINVAL (use VEM_REG_JACOBI). */
 enum { VEM_REG_JACOBI = 0, VEM_REG_SCHWARZ = 1 };
 
 /* matrices for vem_export_csr: the saddle matrix, S, A_gamma; the Block-Reg Schwarz preconditioner's

@@ -1958,30 +1958,38 @@ vem_status vem_solve_batch(vem_handle h, const vem_solve_opts* opts, int64_t nba
   });
   if (st != VEM_OK) return st;
   vem_status worst = VEM_OK;
-  for (int64_t b = 0; b < nbatch; ++b) {
+  for (int64_t b = 0; b < nbatch && worst >= 0; ++b) {
     if (h->nb_nu > 0) {
       st = guarded(h, [&] {
         launch_copy(h->stream, nc, h->nu_batch.p + b * nc, h->nu);
         check_launch();
         invalidate_values(h);
       });
-      if (st != VEM_OK) return st;
+      if (st != VEM_OK) {
+        worst = st;
+        break;
+      }
     }
     const double* rhs = h->nb_rhs > 1 ? h->rhs_batch.p + b * N : h->nb_rhs == 1 ? h->rhs_batch.p : nullptr;
     vem_solve_info inf{};
     st = solve_impl(h, opts, rhs, u + b * Nu, p + b * Np, &inf);
     if (info) info[b] = inf;
-    if (st < 0) return st;
-    if (st > worst) worst = st;
+    if (st < 0)
+      worst = st;
+    else if (st > worst)
+      worst = st;
   }
+  // the handle's coefficient back in place, also after a failed system
   if (h->nb_nu > 0) {
+    const std::string err = h->last_error;
     st = guarded(h, [&] {
       launch_copy(h->stream, nc, h->tmp.f64[5], h->nu);
       check_launch();
       invalidate_values(h);
       sync(h);
     });
-    if (st != VEM_OK) return st;
+    if (worst < 0) h->last_error = err;  // report the system's error, not the restore's
+    if (st != VEM_OK && worst >= 0) return st;
   }
   return worst;
 }

@@ -111,3 +111,31 @@ def test_native_batch_matches_single_solves_and_oracle():
     assert np.linalg.norm(u1.cpu().numpy() - x1[: d1["Nu"]]) <= 1e-9 * np.linalg.norm(x1[: d1["Nu"]])
     s.close()
     ref.close()
+
+
+def test_native_batch_rejects_mismatched_counts():
+    """vem_solve_batch needs nbatch coefficient fields or nbatch right-hand sides; other counts are
+    rejected with VEM_EINVAL and leave the handle usable."""
+    import torch
+
+    from paper_1901_02330_amd.inputs import SineSolution, cube_mesh, lognormal_field
+    from paper_1901_02330_amd.vem import Solver, VemError
+
+    m = cube_mesh(4)
+    s = Solver()
+    s.set_mesh(m)
+    s.discretize("lo")
+    s.set_rhs_functions(SineSolution.f, SineSolution.pD)
+    with pytest.raises(VemError) as e:
+        s.solve_batch(2, precond="schur", tol=1e-10)  # nothing batched yet
+    assert e.value.code == -1
+    s.set_coefficient_batch(torch.as_tensor(np.stack([1.0 / lognormal_field(64, 1.0, b) for b in range(3)])))
+    with pytest.raises(VemError) as e:
+        s.solve_batch(2, precond="schur", tol=1e-10)  # 3 fields, 2 systems
+    assert e.value.code == -1
+    with pytest.raises(VemError) as e:
+        s.set_coefficient_batch(torch.as_tensor(np.full((2, 64), -1.0)))  # not positive
+    assert e.value.code == -1
+    u, p, infos = s.solve_batch(3, precond="schur", tol=1e-10)
+    assert all(i["converged"] for i in infos)
+    s.close()
