@@ -204,27 +204,29 @@ def cpu_baseline(n: int, args):
     from oracle.solvers import block_schur, fgmres
     from paper_1901_02330_amd.inputs import SineSolution, cube_mesh, lognormal_field
 
+    from threadpoolctl import threadpool_limits
+
     m = cube_mesh(n)
     nu = 1.0 / lognormal_field(n**3, 2.0, 0)
-    t0 = time.perf_counter()
-    d = discretize(m, nu=nu, rhs=SineSolution())
-    t1 = time.perf_counter()
-    Nu = d["Nu"]
-    K = d["K"].tocsr()
-    pre = block_schur(K[:Nu, :Nu], K[Nu:, :Nu], inner="cg", tol=1e-12, maxit=args.schur_inner_maxit)
-    x, info = fgmres(K, d["b"], pre, m=30, tol=args.tol)
-    t2 = time.perf_counter()
-    threads = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    # one thread throughout (SciPy's sparse kernels are single-threaded; BLAS is held to one thread)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        d = discretize(m, nu=nu, rhs=SineSolution())
+        t1 = time.perf_counter()
+        Nu = d["Nu"]
+        K = d["K"].tocsr()
+        pre = block_schur(K[:Nu, :Nu], K[Nu:, :Nu], inner="cg", tol=1e-12, maxit=args.schur_inner_maxit)
+        x, info = fgmres(K, d["b"], pre, m=30, tol=args.tol)
+        t2 = time.perf_counter()
     return {
         "value": t2 - t0,
         "unit": "s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"the whole {n}^3 workload ({Nu + d['Np']} unknowns), unscaled: oracle FP64 (NumPy/SciPy) "
-                   f"assembly {t1 - t0:.2f} s + FGMRES(30)/Block-Schur with the oracle's inner Jacobi-CG on S "
-                   f"capped at {args.schur_inner_maxit} iterations {t2 - t1:.2f} s ({info['iterations']} "
-                   f"iterations, relres {info['relres']:.1e}); SciPy's sparse products run on one core, dense "
-                   f"NumPy on up to the host's cores (thread variables: {threads})"),
+        "sample": (f"the whole {n}^3 workload ({Nu + d['Np']} unknowns), unscaled, on one thread: oracle FP64 "
+                   f"(NumPy/SciPy) assembly {t1 - t0:.2f} s + FGMRES(30)/Block-Schur with the oracle's inner "
+                   f"Jacobi-CG on S capped at {args.schur_inner_maxit} iterations {t2 - t1:.2f} s "
+                   f"({info['iterations']} iterations, relres {info['relres']:.1e})"),
         "host_cpus_available": len(os.sched_getaffinity(0)),
     }
 

@@ -274,11 +274,24 @@ __global__ void __launch_bounds__(256) k_gersh(SellView A, const double* __restr
   }
 }
 
-__global__ void k_gersh_final(int nparts, const double* __restrict__ part, double* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// one 256-thread block: the maximum of the block maxima (a single thread walking 1024 partials took
+// 88 us)
+__global__ void __launch_bounds__(256) k_gersh_final(int nparts, const double* __restrict__ part,
+                                                     double* __restrict__ out) {
+  __shared__ double sh[4];
   double m = 0.0;
-  for (int i = 0; i < nparts; ++i) m = part[i] > m ? part[i] : m;
-  out[0] = m > 0.0 ? 1.0 / m : 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) m = part[i] > m ? part[i] : m;
+  for (int o = 32; o > 0; o >>= 1) {
+    const double q = __shfl_down(m, o, 64);
+    m = q > m ? q : m;
+  }
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = sh[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) b = sh[w] > b ? sh[w] : b;
+    out[0] = b > 0.0 ? 1.0 / b : 0.0;
+  }
 }
 
 template <typename T, bool kShort>
@@ -329,7 +342,7 @@ template void launch_cheb<float>(hipStream_t, const Sell&, const PcgWorkT<float>
 void launch_gershgorin(hipStream_t s, const Sell& A, const double* dinv, double* part, double* inv_hi) {
   const int G = (int)std::min<int64_t>(1024, (A.rows + 255) / 256);
   k_gersh<<<G > 0 ? G : 1, 256, 0, s>>>(view(A), dinv, part);
-  k_gersh_final<<<1, 64, 0, s>>>(G > 0 ? G : 1, part, inv_hi);
+  k_gersh_final<<<1, 256, 0, s>>>(G > 0 ? G : 1, part, inv_hi);
 }
 
 void launch_pcg_init(hipStream_t s, const Sell& A, const PcgWork& w, const double* b, PcgState* st, double tol,

@@ -52,3 +52,52 @@ def test_chebyshev_rejects_bad_interval():
     with pytest.raises(VemError) as e:
         s.solve(precond="schur", inner_form="chebyshev", inner_maxit=24, cheb_lo=1.5)
     assert e.value.code == -1
+
+
+def test_chebyshev_with_flux_boundary_data():
+    """With the paper's flux boundary data S has the constant pressure in its kernel; the Chebyshev
+    polynomial then leaves a constant component in z_p, which the zero-mean shift of the result
+    removes: the solution matches the oracle's augmented direct solve."""
+    import torch
+
+    from oracle.fluxbc import flux_system, solve_flux
+    from paper_1901_02330_amd.vem import Solver
+
+    _say("chebyshev flux data")
+    m = cube_mesh(5, 3, 4)
+    nu = 1.0 / lognormal_field(60, 2.0, 4)
+    s = Solver()
+    s.set_mesh(m)
+    s.discretize("lo", load_points=3)
+    s.set_boundary("flux")
+    s.set_coefficient(torch.as_tensor(nu))
+
+    def ufield(X):
+        return torch.as_tensor(SineSolution.u(X.cpu().numpy()), dtype=torch.float64, device=X.device)
+
+    s.set_rhs_functions(SineSolution.f, ufield)
+    u, p, info = s.solve(precond="schur", tol=1e-13, maxit=3000, inner_form="chebyshev", inner_maxit=24)
+    assert info["converged"], info
+    d = flux_system(m, nu=nu, rhs=SineSolution())
+    uo, po = solve_flux(d)[:2]
+    eu, ep = rel(u.cpu().numpy(), uo), rel(p.cpu().numpy(), po)
+    _say(info, eu, ep)
+    assert eu <= 1e-10 and ep <= 1e-10
+
+
+@pytest.mark.parametrize("which", ["spmv", "cg_schur", "cg_reg", "cg_schur32", "cg_reg32", "cg_schur32p",
+                                   "cg_reg32p", "cg_reg_schwarz", "cg_reg_schwarz32", "cheb_schur",
+                                   "cheb_schur32"])
+def test_time_kernel_hook(which):
+    """Every kernel of the timing hook runs, with a positive time and its algorithmic bytes, and leaves
+    a later solve unchanged."""
+    m = cube_mesh(6, 5, 4)
+    nu = 1.0 / lognormal_field(120, 1.0, 1)
+    s = gpu_solver(m, nu=nu, rhs=SineSolution())
+    u0, p0, _ = s.solve(precond="reg", tol=1e-12)
+    ms, nbytes = s.time_kernel(which, reps=5)
+    assert ms > 0 and nbytes > 0
+    u1, p1, _ = s.solve(precond="reg", tol=1e-12)
+    import torch
+
+    assert torch.equal(u0, u1) and torch.equal(p0, p1)
