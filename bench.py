@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--k2-batch", type=int, default=0, metavar="FIELDS",
                     help="also time FIELDS log-normal fields (sigma 1.5, seeds 0..) on the Cube 32^3 k=2 mesh: "
                          "Block-Reg with FP32 inner solves, sequential and on FIELDS concurrent lanes (minutes)")
+    ap.add_argument("--voronoi-checkerboard", action="store_true",
+                    help="also solve the mixed-precision workload: Random Voronoi 20,000 cells, the paper's k = 2, "
+                         "checkerboard K in {1e-3, 1e3}, Block-Reg with FP32 and FP64 inner solves (minutes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=0, help="Cube size of the CPU oracle run (default: the workload's)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
@@ -512,6 +515,29 @@ def extras(args, torch, dev):
         tab[f"cube{nn}_k{k}_{bc}"] = row
         s.close()
     out["paper_cube_table1"] = tab
+    # the paper's optimality sweep on Cube meshes (its Table 4: k = 2, 512 to 21,952 cells, flux data,
+    # nu = 1, the polynomial solution; the paper's counts at 8 processes are context)
+    paper4 = {8: (19585, 113, 86), 16: (152065, 78, 123), 20: (295201, 76, 145), 24: (508033, 72, 168),
+              28: (804385, 69, 188)}
+    opt = {}
+    for nn, (dofs, its_s, its_r) in paper4.items():
+        s = Solver()
+        s.set_mesh(cube_mesh(nn))
+        s.set_boundary("flux")
+        s.discretize("paper", k=2)
+        s.set_rhs_functions(PolynomialSolution.f, PolynomialSolution.u)
+        row = {"n_unknowns": s.sizes()["n"], "paper": {"dofs": dofs, "schur_its": its_s, "reg_its": its_r}}
+        for prec, kw in (("schur", dict(inner_tol=1e-8, inner_maxit=2000)), ("reg", dict(inner_tol=1e-1))):
+            _, _, info = s.solve(prec, tol=1e-8, maxit=3000, **kw)  # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, info = s.solve(prec, tol=1e-8, maxit=3000, **kw)
+            torch.cuda.synchronize()
+            row[prec] = {"iterations": info["iterations"], "inner_iterations": info["inner_iterations"],
+                         "solve_s": time.perf_counter() - t0}
+        opt[f"cube{nn}_k2_flux"] = row
+        s.close()
+    out["paper_cube_table4_k2"] = opt
     return out
 
 
@@ -549,6 +575,42 @@ def k2_fields(args, torch, dev, fields):
            "field0_fp64": {"iterations": i64["iterations"], "relres": i64["relres"]},
            "field0_rel_err_u_vs_fp64": float(torch.linalg.norm(u[0] - u64) / torch.linalg.norm(u64)),
            "field0_rel_err_p_vs_fp64": float(torch.linalg.norm(p[0] - p64) / torch.linalg.norm(p64))}
+    s.close()
+    return out
+
+
+def voronoi_checkerboard(torch, dev):
+    """The mixed-precision workload: Random Voronoi mesh of 20,000 seeded uniform points, the paper's k = 2,
+    checkerboard K in {1e-3, 1e3} on 4x4x4 blocks, Block-Reg to 1e-8 with FP32 inner Schwarz-CG under FP64
+    FGMRES, then with FP64 inner solves; the difference between the two solutions."""
+    from paper_1901_02330_amd.inputs import SineSolution, checkerboard_field, voronoi_mesh
+    from paper_1901_02330_amd.vem import Solver
+
+    t0 = time.perf_counter()
+    m = voronoi_mesh(20000, seed=0)
+    t_mesh = time.perf_counter() - t0
+    s = Solver()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.set_mesh(m)
+    s.discretize("paper", k=2)
+    s.set_coefficient(torch.as_tensor(1.0 / checkerboard_field(m["seeds"]), device=dev))
+    s.set_rhs_functions(SineSolution.f, SineSolution.pD)
+    torch.cuda.synchronize()
+    out = {"mesh_generation_s": t_mesh, "assembly_s": time.perf_counter() - t0, "n_unknowns": s.sizes()["n"],
+           "nnz_K": s.sizes()["nnz_K"]}
+    xs = {}
+    for prec in ("mixed", "fp64"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, p, info = s.solve("reg", tol=1e-8, maxit=1500, inner_tol=1e-2, precision=prec)
+        torch.cuda.synchronize()
+        out[prec] = {"solve_s": time.perf_counter() - t0, "iterations": info["iterations"],
+                     "inner_iterations": info["inner_iterations"], "relres": info["relres"],
+                     "converged": info["converged"]}
+        xs[prec] = torch.cat([u, p])
+        log(f"voronoi checkerboard {prec}: {out[prec]}")
+    out["rel_diff_mixed_vs_fp64"] = float(torch.linalg.norm(xs["mixed"] - xs["fp64"]) / torch.linalg.norm(xs["fp64"]))
     s.close()
     return out
 
@@ -725,6 +787,9 @@ def main():
         line["extras"] = extras(args, torch, dev)
         # the metric's third part: adjoint (backward) time over forward time, 48^3 (extras)
         line["adjoint_over_forward"] = line["extras"]["adjoint_cube48"]["backward_over_forward"]
+    if args.voronoi_checkerboard:
+        log("voronoi checkerboard ...")
+        line.setdefault("extras", {})["voronoi20k_k2_checkerboard"] = voronoi_checkerboard(torch, dev)
     if args.k2_batch > 0:
         log("k=2 batch ...")
         line.setdefault("extras", {})["batch_cube32_k2"] = k2_batch(args.k2_batch, torch, dev)
