@@ -541,6 +541,18 @@ def extras(args, torch, dev):
     return out
 
 
+def schwarz_rates(s, reps=100):
+    """One Schwarz-CG iteration (both launches), FP64 and FP32: mean time over `reps` back-to-back
+    iterations (HIP events), algorithmic bytes (every stored matrix entry, index and vector element
+    once) and the fraction of the HBM peak."""
+    out = {}
+    for which in ("cg_reg_schwarz", "cg_reg_schwarz32"):
+        ms, nb = s.time_kernel(which, reps=reps)
+        gbs = nb / (ms * 1e-3) / 1e9
+        out[which] = {"avg_us": ms * 1e3, "bytes": nb, "gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
+    return out
+
+
 def k2_fields(args, torch, dev, fields):
     """The batched workload: `fields` log-normal coefficient fields (log K = 1.5 N(0,1), seeds 0..) on the
     Cube 32^3 mesh with the paper's k = 2 element, one handle, vem_set_coefficient_batch +
@@ -575,6 +587,7 @@ def k2_fields(args, torch, dev, fields):
            "field0_fp64": {"iterations": i64["iterations"], "relres": i64["relres"]},
            "field0_rel_err_u_vs_fp64": float(torch.linalg.norm(u[0] - u64) / torch.linalg.norm(u64)),
            "field0_rel_err_p_vs_fp64": float(torch.linalg.norm(p[0] - p64) / torch.linalg.norm(p64))}
+    out["schwarz_iteration"] = schwarz_rates(s)
     s.close()
     return out
 
@@ -611,6 +624,7 @@ def voronoi_checkerboard(torch, dev):
         xs[prec] = torch.cat([u, p])
         log(f"voronoi checkerboard {prec}: {out[prec]}")
     out["rel_diff_mixed_vs_fp64"] = float(torch.linalg.norm(xs["mixed"] - xs["fp64"]) / torch.linalg.norm(xs["fp64"]))
+    out["schwarz_iteration"] = schwarz_rates(s, reps=50)
     s.close()
     return out
 

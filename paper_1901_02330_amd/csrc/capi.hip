@@ -728,14 +728,14 @@ void schwarz_inner(vem_handle h, const vem_solve_opts& o, const double* v, doubl
     PcgWork32 w{h->px32, (float*)h->pr.p, (float*)h->pz.p, (float*)h->ps.p, (float*)h->pp.p, (float*)h->pw0.p,
                 (float*)h->pw1.p, nullptr};
     launch_schwarz_rhs<float>(s, m, L, X, bnd, v, w.r);
-    launch_scg_init<float>(s, X.Ps, w, h->pcg, o.inner_tol, h->pcgpart);
-    run_inner(h, o, h->expect_A, [&](int i) { launch_scg_iter<float>(s, i, F, X.Ps, w, h->pcg, h->pcgpart); });
+    launch_scg_init<float>(s, X, w, h->pcg, o.inner_tol, h->pcgpart);
+    run_inner(h, o, h->expect_A, [&](int i) { launch_scg_iter<float>(s, i, F, X, w, h->pcg, h->pcgpart); });
     launch_to_f64(s, X.nF, h->px32, z);
   } else {
     PcgWork w{z, h->pr, h->pz, h->ps, h->pp, h->pw0, h->pw1, nullptr};
     launch_schwarz_rhs<double>(s, m, L, X, bnd, v, w.r);
-    launch_scg_init<double>(s, X.Ps, w, h->pcg, o.inner_tol, h->pcgpart);
-    run_inner(h, o, h->expect_A, [&](int i) { launch_scg_iter<double>(s, i, F, X.Ps, w, h->pcg, h->pcgpart); });
+    launch_scg_init<double>(s, X, w, h->pcg, o.inner_tol, h->pcgpart);
+    run_inner(h, o, h->expect_A, [&](int i) { launch_scg_iter<double>(s, i, F, X, w, h->pcg, h->pcgpart); });
   }
   if (L.nint > 0) launch_schwarz_back(s, m, L, X, v, z);
   check_launch();
@@ -1536,7 +1536,12 @@ vem_status vem_export_csr(vem_handle h, int which, int32_t* rowptr, int32_t* col
                      : lo_face                ? &h->As
                                               : &h->sz.Fs;
     hipStream_t s = h->stream;
-    if (val) sell_to_csr(s, *Ms, *M);
+    if (val) {
+      if (schw || (face && !lo_face))
+        schwarz_export(s, h->sz, face, *M);
+      else
+        sell_to_csr(s, *Ms, *M);
+    }
     if (rowptr)
       VEM_HIP(hipMemcpyAsync(rowptr, M->rowptr.p, (M->rows + 1) * sizeof(int), hipMemcpyDefault, s));
     if (col) VEM_HIP(hipMemcpyAsync(col, M->col.p, M->nnz * sizeof(int), hipMemcpyDefault, s));
@@ -1633,25 +1638,30 @@ vem_status vem_time_kernel(vem_handle h, int which, int reps, double* avg_ms, do
           PcgWork32 w{h->px32, (float*)h->pr.p, (float*)h->pz.p, (float*)h->ps.p, (float*)h->pp.p, (float*)h->pw0.p,
                       (float*)h->pw1.p, nullptr};
           launch_schwarz_rhs<float>(s, m, L, X, nullptr, h->Vb, w.r);
-          launch_scg_init<float>(s, X.Ps, w, h->pcg, 0.0, h->pcgpart);
-          launch_scg_iter<float>(s, 0, F, X.Ps, w, h->pcg, h->pcgpart);
-          launch_scg_iter<float>(s, 1, F, X.Ps, w, h->pcg, h->pcgpart);
+          launch_scg_init<float>(s, X, w, h->pcg, 0.0, h->pcgpart);
+          launch_scg_iter<float>(s, 0, F, X, w, h->pcg, h->pcgpart);
+          launch_scg_iter<float>(s, 1, F, X, w, h->pcg, h->pcgpart);
           VEM_HIP(hipEventRecord(e0, s));
-          for (int r = 0; r < reps; ++r) launch_scg_iter<float>(s, 2 + r, F, X.Ps, w, h->pcg, h->pcgpart);
+          for (int r = 0; r < reps; ++r) launch_scg_iter<float>(s, 2 + r, F, X, w, h->pcg, h->pcgpart);
           VEM_HIP(hipEventRecord(e1, s));
-          b = 8.0 * (Fc.nnz + X.Pc.nnz) + 4.0 * nF * 13.0;
+          // face blocks: one 4-byte index per block and two block offsets per face
+          b = X.blocked ? 4.0 * (Fc.nnz + X.Pc.nnz) + 4.0 * (X.Fb.nblk + X.Pb.nblk) + 16.0 * (X.Fb.nf + 1) +
+                              4.0 * nF * 13.0
+                        : 8.0 * (Fc.nnz + X.Pc.nnz) + 4.0 * nF * 13.0;
         } else {
           PcgWork w{h->xw.p, h->pr, h->pz, h->ps, h->pp, h->pw0, h->pw1, nullptr};
           launch_schwarz_rhs<double>(s, m, L, X, nullptr, h->Vb, w.r);
-          launch_scg_init<double>(s, X.Ps, w, h->pcg, 0.0, h->pcgpart);
-          launch_scg_iter<double>(s, 0, F, X.Ps, w, h->pcg, h->pcgpart);
-          launch_scg_iter<double>(s, 1, F, X.Ps, w, h->pcg, h->pcgpart);
+          launch_scg_init<double>(s, X, w, h->pcg, 0.0, h->pcgpart);
+          launch_scg_iter<double>(s, 0, F, X, w, h->pcg, h->pcgpart);
+          launch_scg_iter<double>(s, 1, F, X, w, h->pcg, h->pcgpart);
           VEM_HIP(hipEventRecord(e0, s));
-          for (int r = 0; r < reps; ++r) launch_scg_iter<double>(s, 2 + r, F, X.Ps, w, h->pcg, h->pcgpart);
+          for (int r = 0; r < reps; ++r) launch_scg_iter<double>(s, 2 + r, F, X, w, h->pcg, h->pcgpart);
           VEM_HIP(hipEventRecord(e1, s));
           // both matrices once; [product] z gathered, p and q read and written; [update] q gathered,
           // r, z and x read and written, p read: 13 vector accesses per row
-          b = 12.0 * (Fc.nnz + X.Pc.nnz) + 8.0 * nF * 13.0;
+          b = X.blocked ? 8.0 * (Fc.nnz + X.Pc.nnz) + 4.0 * (X.Fb.nblk + X.Pb.nblk) + 16.0 * (X.Fb.nf + 1) +
+                              8.0 * nF * 13.0
+                        : 12.0 * (Fc.nnz + X.Pc.nnz) + 8.0 * nF * 13.0;
         }
       } else {
         Sell& A = schur ? h->Ss : h->As;

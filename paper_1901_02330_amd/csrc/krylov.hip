@@ -6,6 +6,8 @@
 // writes its partial sums, and a later kernel on the same stream adds them in
 // block order (a one-block finalize kernel, or every block of the consumer
 // kernel itself for the inner CG).  Every kernel here is bandwidth bound.
+#include <algorithm>
+
 #include "krylov_device.h"
 
 namespace vem {
@@ -287,6 +289,61 @@ __global__ void __launch_bounds__(kPcgThreads) k_cg_update(int k, int64_t n, T* 
   }
 }
 
+// ---- face blocks: one thread per DOF row of an order-k face system ---------------------------
+// Row (f, i) reads, per block j of face f, its NFD entries (contiguous) and the NFD entries of the
+// gathered vector at face bcol (contiguous), as pairs when NFD is even (both runs start at a
+// multiple of NFD elements of a 256-byte aligned allocation).  The sum runs over the columns in
+// ascending order, as the SELL-64 product does.
+template <typename T, int NFD>
+struct BlockViewT {
+  int64_t rows;
+  const int* __restrict__ bptr;
+  const int* __restrict__ bcol;
+  const T* __restrict__ val;
+};
+
+template <int N, typename E>
+__device__ inline void load_run(const E* __restrict__ p, E (&out)[N]) {
+  if constexpr (N % 2 == 0) {
+    typedef E pair_t __attribute__((ext_vector_type(2)));
+    const pair_t* q = reinterpret_cast<const pair_t*>(p);
+#pragma unroll
+    for (int u = 0; u < N / 2; ++u) {
+      const pair_t t = q[u];
+      out[2 * u] = t.x;
+      out[2 * u + 1] = t.y;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < N; ++u) out[u] = p[u];
+  }
+}
+
+template <typename T, int NFD, typename X>
+__device__ inline T mat_row(const BlockViewT<T, NFD>& A, int64_t row, const X* __restrict__ x) {
+  const int64_t f = row / NFD;
+  const int i = (int)(row - f * NFD);
+  const int b1 = A.bptr[f + 1];
+  T acc = T(0);
+  // two (FP64) or four (FP32) blocks' loads in flight per thread: measured fastest at 6 face DOFs
+  constexpr int kUnroll = sizeof(T) == 4 ? 4 : 2;
+#pragma unroll kUnroll
+  for (int b = A.bptr[f]; b < b1; ++b) {
+    T v[NFD];
+    X g[NFD];
+    load_run<NFD>(A.val + ((int64_t)b * NFD + i) * NFD, v);
+    load_run<NFD>(x + (int64_t)A.bcol[b] * NFD, g);
+#pragma unroll
+    for (int c = 0; c < NFD; ++c) acc += v[c] * (T)g[c];
+  }
+  return acc;
+}
+
+template <typename T, typename X>
+__device__ inline T mat_row(const SellViewT<T>& A, int64_t row, const X* __restrict__ x) {
+  return sell_dot(A, row, x);
+}
+
 // ---- CG on the face system F with the edge-patch Schwarz operator P (Block-Reg) -------------
 // Two kernels per iteration, each one sparse product with a single gathered vector.  The products
 // F p and P r are carried by recurrences, as F p_new = F z + beta F p_old and
@@ -301,15 +358,16 @@ __global__ void __launch_bounds__(kPcgThreads) k_cg_update(int k, int64_t n, T* 
 //   [update]  alpha = rho / p.q; x += alpha p; r -= alpha q; z -= alpha P q; partials r.z
 // Each kernel issues its row's product (which does not depend on this iteration's scalars) before
 // it sums the previous kernel's partials, so the product's loads are in flight during that prologue.
-// Block size: 1024 threads when every row has a thread, 256 when threads loop over rows.
-template <typename T, int kBlock>
-__global__ void __launch_bounds__(kBlock) k_scg_init(SellViewT<T> P, const T* __restrict__ r0, T* __restrict__ x,
+// Block size: 1024 threads when every row has a thread, 256 when threads loop over rows.  V: the
+// matrices' storage (SELL-64, or face blocks at order k).
+template <typename T, int kBlock, typename V>
+__global__ void __launch_bounds__(kBlock) k_scg_init(V P, const T* __restrict__ r0, T* __restrict__ x,
                                                      T* __restrict__ z, PcgState* st, double tol2,
                                                      double* __restrict__ prho0) {
   double acc[1] = {0.0};
   for (int64_t row = xcd_block() * blockDim.x + threadIdx.x; row < P.rows;
        row += (int64_t)gridDim.x * blockDim.x) {
-    const T zi = sell_dot(P, row, r0);
+    const T zi = mat_row(P, row, r0);
     z[row] = zi;
     x[row] = T(0);
     acc[0] += (double)r0[row] * (double)zi;
@@ -324,8 +382,8 @@ __global__ void __launch_bounds__(kBlock) k_scg_init(SellViewT<T> P, const T* __
   }
 }
 
-template <typename T, int kBlock>
-__global__ void __launch_bounds__(kBlock) k_scg_prod(int k, SellViewT<T> F, const T* __restrict__ z,
+template <typename T, int kBlock, typename V>
+__global__ void __launch_bounds__(kBlock) k_scg_prod(int k, V F, const T* __restrict__ z,
                                                      T* __restrict__ p, T* __restrict__ q, PcgState* st,
                                                      const double* __restrict__ prho, double* __restrict__ ppq) {
   const int G = gridDim.x;
@@ -334,7 +392,7 @@ __global__ void __launch_bounds__(kBlock) k_scg_prod(int k, SellViewT<T> F, cons
   int64_t row = xcd_block() * blockDim.x + threadIdx.x;
   T fz = T(0), zi = T(0), po = T(0), qo = T(0);
   auto load = [&](int64_t i) {
-    fz = sell_dot(F, i, z);
+    fz = mat_row(F, i, z);
     zi = z[i];
     if (k > 0) {
       po = p[i];
@@ -368,8 +426,8 @@ __global__ void __launch_bounds__(kBlock) k_scg_prod(int k, SellViewT<T> F, cons
   block_partials<1>(acc, ppq);
 }
 
-template <typename T, int kBlock>
-__global__ void __launch_bounds__(kBlock) k_scg_update(int k, SellViewT<T> P, T* __restrict__ x,
+template <typename T, int kBlock, typename V>
+__global__ void __launch_bounds__(kBlock) k_scg_update(int k, V P, T* __restrict__ x,
                                                        T* __restrict__ r, T* __restrict__ z,
                                                        const T* __restrict__ q, const T* __restrict__ p,
                                                        PcgState* st, double* __restrict__ prho,
@@ -380,7 +438,7 @@ __global__ void __launch_bounds__(kBlock) k_scg_update(int k, SellViewT<T> P, T*
   int64_t row = xcd_block() * blockDim.x + threadIdx.x;
   T pq_r = T(0), qi = T(0), ri = T(0), zi = T(0), xi = T(0), pi = T(0);
   auto load = [&](int64_t i) {
-    pq_r = sell_dot(P, i, q);
+    pq_r = mat_row(P, i, q);
     qi = q[i];
     ri = r[i];
     zi = z[i];
@@ -600,39 +658,96 @@ void launch_pcg_iter32(hipStream_t s, int i, const Sell& A, const PcgWork32& w, 
 }
 
 template <typename T>
-void launch_scg_init(hipStream_t s, const Sell& P, const PcgWorkT<T>& w, PcgState* st, double tol, double* part) {
+const T* block_values(const FaceBlocks& B);
+template <>
+const double* block_values<double>(const FaceBlocks& B) {
+  return B.val.p;
+}
+template <>
+const float* block_values<float>(const FaceBlocks& B) {
+  return B.val32.p;
+}
+template <typename T, int NFD>
+BlockViewT<T, NFD> block_view(const FaceBlocks& B) {
+  return {B.nf * NFD, B.bptr.p, B.bcol.p, block_values<T>(B)};
+}
+
+// Grid of the Schwarz-CG kernels: at most the blocks that are resident at once (the fewest over
+// the three kernels of a form, from their register use), since the threads loop over the rows and
+// blocks beyond one resident round would run as a second, partly filled round.  The init and the
+// iteration kernels take the same grid, so the partial sums match.
+template <typename T, int kBlock, typename V>
+int scg_grid(int64_t rows) {
+  static const int resident = [] {
+    int dev = 0, ncu = 0, a = 0, b = 0, c = 0;
+    VEM_HIP(hipGetDevice(&dev));
+    VEM_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    VEM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_scg_init<T, kBlock, V>, kBlock, 0));
+    VEM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_scg_prod<T, kBlock, V>, kBlock, 0));
+    VEM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, k_scg_update<T, kBlock, V>, kBlock, 0));
+    const int m = std::min(a, std::min(b, c));
+    return std::max(1, m) * std::max(1, ncu);
+  }();
+  return std::min(pcg_grid(rows, kBlock), resident);
+}
+
+template <typename T, typename V>
+void scg_init_as(hipStream_t s, const V& P, const PcgWorkT<T>& w, PcgState* st, double tol, double* part) {
   if (P.rows > kPcgMaxThreads)
-    k_scg_init<T, 256><<<pcg_grid(P.rows, 256), 256, 0, s>>>(values_view<T>(P), w.r, w.x, w.z, st, tol * tol, part);
+    k_scg_init<T, 256><<<scg_grid<T, 256, V>(P.rows), 256, 0, s>>>(P, w.r, w.x, w.z, st, tol * tol, part);
   else
-    k_scg_init<T, 1024><<<pcg_grid(P.rows, 1024), 1024, 0, s>>>(values_view<T>(P), w.r, w.x, w.z, st, tol * tol,
-                                                                  part);
+    k_scg_init<T, 1024><<<scg_grid<T, 1024, V>(P.rows), 1024, 0, s>>>(P, w.r, w.x, w.z, st, tol * tol, part);
 }
 
 // work layout: x, r, z, p as named, w0 = q (s and w1 unused); the init's grid (same rows, same
 // block size) leaves the partials the first product kernel sums
-template <typename T>
-void launch_scg_iter(hipStream_t s, int i, const Sell& F, const Sell& P, const PcgWorkT<T>& w, PcgState* st,
-                     double* part) {
+template <typename T, typename V>
+void scg_iter_as(hipStream_t s, int i, const V& F, const V& P, const PcgWorkT<T>& w, PcgState* st, double* part) {
   if (F.rows > kPcgMaxThreads) {
-    const int G = pcg_grid(F.rows, 256);
+    const int G = scg_grid<T, 256, V>(F.rows);
     double* prho = part;  // 2 x G slots
     double* ppq = part + 2 * (size_t)G;
-    k_scg_prod<T, 256><<<G, 256, 0, s>>>(i, values_view<T>(F), w.z, w.p, w.w0, st, prho, ppq);
-    k_scg_update<T, 256><<<G, 256, 0, s>>>(i, values_view<T>(P), w.x, w.r, w.z, w.w0, w.p, st, prho, ppq);
+    k_scg_prod<T, 256><<<G, 256, 0, s>>>(i, F, w.z, w.p, w.w0, st, prho, ppq);
+    k_scg_update<T, 256><<<G, 256, 0, s>>>(i, P, w.x, w.r, w.z, w.w0, w.p, st, prho, ppq);
   } else {
-    const int G = pcg_grid(F.rows, 1024);
+    const int G = scg_grid<T, 1024, V>(F.rows);
     double* prho = part;
     double* ppq = part + 2 * (size_t)G;
-    k_scg_prod<T, 1024><<<G, 1024, 0, s>>>(i, values_view<T>(F), w.z, w.p, w.w0, st, prho, ppq);
-    k_scg_update<T, 1024><<<G, 1024, 0, s>>>(i, values_view<T>(P), w.x, w.r, w.z, w.w0, w.p, st, prho, ppq);
+    k_scg_prod<T, 1024><<<G, 1024, 0, s>>>(i, F, w.z, w.p, w.w0, st, prho, ppq);
+    k_scg_update<T, 1024><<<G, 1024, 0, s>>>(i, P, w.x, w.r, w.z, w.w0, w.p, st, prho, ppq);
   }
 }
 
-template void launch_scg_init<double>(hipStream_t, const Sell&, const PcgWorkT<double>&, PcgState*, double, double*);
-template void launch_scg_init<float>(hipStream_t, const Sell&, const PcgWorkT<float>&, PcgState*, double, double*);
-template void launch_scg_iter<double>(hipStream_t, int, const Sell&, const Sell&, const PcgWorkT<double>&, PcgState*,
+template <typename T>
+void launch_scg_init(hipStream_t s, const Schwarz& X, const PcgWorkT<T>& w, PcgState* st, double tol, double* part) {
+  if (!X.blocked) return scg_init_as<T>(s, values_view<T>(X.Ps), w, st, tol, part);
+  switch (X.Pb.nfd) {
+    case 3: return scg_init_as<T>(s, block_view<T, 3>(X.Pb), w, st, tol, part);
+    case 6: return scg_init_as<T>(s, block_view<T, 6>(X.Pb), w, st, tol, part);
+    case 10: return scg_init_as<T>(s, block_view<T, 10>(X.Pb), w, st, tol, part);
+    default: throw Error{VEM_EINVAL, "face blocks of an unsupported size"};
+  }
+}
+
+template <typename T>
+void launch_scg_iter(hipStream_t s, int i, const Sell& F, const Schwarz& X, const PcgWorkT<T>& w, PcgState* st,
+                     double* part) {
+  if (!X.blocked) return scg_iter_as<T>(s, i, values_view<T>(F), values_view<T>(X.Ps), w, st, part);
+  switch (X.Pb.nfd) {
+    case 3: return scg_iter_as<T>(s, i, block_view<T, 3>(X.Fb), block_view<T, 3>(X.Pb), w, st, part);
+    case 6: return scg_iter_as<T>(s, i, block_view<T, 6>(X.Fb), block_view<T, 6>(X.Pb), w, st, part);
+    case 10: return scg_iter_as<T>(s, i, block_view<T, 10>(X.Fb), block_view<T, 10>(X.Pb), w, st, part);
+    default: throw Error{VEM_EINVAL, "face blocks of an unsupported size"};
+  }
+}
+
+template void launch_scg_init<double>(hipStream_t, const Schwarz&, const PcgWorkT<double>&, PcgState*, double,
                                       double*);
-template void launch_scg_iter<float>(hipStream_t, int, const Sell&, const Sell&, const PcgWorkT<float>&, PcgState*,
+template void launch_scg_init<float>(hipStream_t, const Schwarz&, const PcgWorkT<float>&, PcgState*, double,
                                      double*);
+template void launch_scg_iter<double>(hipStream_t, int, const Sell&, const Schwarz&, const PcgWorkT<double>&,
+                                      PcgState*, double*);
+template void launch_scg_iter<float>(hipStream_t, int, const Sell&, const Schwarz&, const PcgWorkT<float>&,
+                                     PcgState*, double*);
 
 }  // namespace vem

@@ -176,6 +176,25 @@ __global__ void k_fc_cols(int64_t nF, const int* __restrict__ Aptr, const int* _
 
 __device__ inline bool fixed_face_dof(const int* bnd, int nfd, int64_t gid) { return bnd && bnd[gid / nfd]; }
 
+// Storage position of the k-th entry (in column order) of row r: SELL-64 slots, or face blocks
+// (the columns of an order-k face row come in whole faces, nfd at a time, so entry k lies in block
+// k / nfd at column c = k mod nfd).
+struct Slots {
+  const int* slice_ptr;  // SELL-64 (bptr null)
+  const int* bptr;       // face blocks
+  int nfd;
+  __device__ int64_t at(int64_t r, int k) const {
+    if (bptr) {
+      const int64_t f = r / nfd;
+      const int i = (int)(r - f * nfd), j = k / nfd, c = k - j * nfd;
+      return (((int64_t)bptr[f] + j) * nfd + i) * nfd + c;
+    }
+    return (int64_t)slice_ptr[r >> 6] + (r & 63) + 64 * (int64_t)k;
+  }
+};
+inline Slots slots_of(const Sell& S) { return {S.slice_ptr.p, nullptr, 1}; }
+inline Slots slots_of(const FaceBlocks& B) { return {nullptr, B.bptr.p, B.nfd}; }
+
 // Local A_gamma entry (i, j) of cell P in the cell's outward orientation:
 // nu_P M1_P[i][j] + gamma^{-1} sum_q B_P[q][i] B_P[q][j].
 __device__ inline double local_a(const double* __restrict__ M, const double* __restrict__ Bp, int nd, int npd,
@@ -258,7 +277,7 @@ __global__ void k_fc_values(DofLayout L, const int* __restrict__ cptr, const int
                             const int64_t* __restrict__ lmat_ptr, const double* __restrict__ M1,
                             const int64_t* __restrict__ lb_ptr, const double* __restrict__ Bdiv1,
                             const double* __restrict__ nu, double ig, const int* __restrict__ bnd,
-                            const double* __restrict__ W, const int* __restrict__ Fslice, double* __restrict__ Fval) {
+                            const double* __restrict__ W, Slots Fs, double* __restrict__ Fval) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nF = (int64_t)L.nf * L.nfd;
   if (r >= nF) return;
@@ -296,7 +315,6 @@ __global__ void k_fc_values(DofLayout L, const int* __restrict__ cptr, const int
     na[c] = Fn[c];  // the face DOFs come first in the sorted list
     wo[c] = ((int64_t)ldof_ptr[P[c]] - (int64_t)P[c] * L.nint) * L.nint;
   }
-  const int64_t base = (int64_t)Fslice[r >> 6] + (r & 63);
   int k = 0, ia = 0, ib = 0;
   const int nb = n == 2 ? na[1] : 0;
   while (ia < na[0] || ib < nb) {
@@ -328,25 +346,24 @@ __global__ void k_fc_values(DofLayout L, const int* __restrict__ cptr, const int
     if (ga == g) ++ia;
     if (gb == g) ++ib;
     if (fixed_row || (bnd && bnd[g / L.nfd])) v = (g == r) ? 1.0 : 0.0;
-    Fval[base + 64 * (int64_t)(k++)] = v;
+    Fval[Fs.at(r, k++)] = v;
   }
 }
 
-// Entry (r, c) of a matrix given by its CSR pattern (sorted columns) and SELL values; 0 where the
-// pattern has none.
-__device__ inline double csr_sell_entry(const int* __restrict__ rowptr, const int* __restrict__ col,
-                                        const int* __restrict__ slice_ptr, const double* __restrict__ val, int64_t r,
-                                        int c) {
+// Entry (r, c) of a matrix given by its CSR pattern (sorted columns) and its stored values; 0 where
+// the pattern has none.
+__device__ inline double csr_entry(const int* __restrict__ rowptr, const int* __restrict__ col, Slots S,
+                                   const double* __restrict__ val, int64_t r, int c) {
   const int b = rowptr[r], n = rowptr[r + 1] - b;
   const int k = lower_bound_i32(col + b, n, c);
   if (k >= n || col[b + k] != c) return 0.0;
-  return val[(int64_t)slice_ptr[r >> 6] + (r & 63) + 64 * (int64_t)k];
+  return val[S.at(r, k)];
 }
 
 // One block per edge: the face system restricted to the DOFs of the edge's faces, inverted.
 __global__ void k_edge_inv(int ne, int nfd, const int* __restrict__ edge_ptr, const int* __restrict__ edge_face,
-                           const int* __restrict__ Fptr, const int* __restrict__ Fcol,
-                           const int* __restrict__ Fslice, const double* __restrict__ Fval,
+                           const int* __restrict__ Fptr, const int* __restrict__ Fcol, Slots Fs,
+                           const double* __restrict__ Fval,
                            const int64_t* __restrict__ einv_ptr, double* __restrict__ einv) {
   extern __shared__ double sh[];
   const int e = blockIdx.x;
@@ -360,7 +377,7 @@ __global__ void k_edge_inv(int ne, int nfd, const int* __restrict__ edge_ptr, co
     const int i = t / n, j = t - i * n;
     const int64_t gi = (int64_t)fe[i / nfd] * nfd + i % nfd;
     const int gj = fe[j / nfd] * nfd + j % nfd;
-    a[t] = csr_sell_entry(Fptr, Fcol, Fslice, Fval, gi, gj);
+    a[t] = csr_entry(Fptr, Fcol, Fs, Fval, gi, gj);
   }
   gj_invert(a, rk, ck, n);
   double* out = einv + einv_ptr[e];
@@ -371,14 +388,13 @@ __global__ void k_edge_inv(int ne, int nfd, const int* __restrict__ edge_ptr, co
 __global__ void k_p_values(int nf, int nfd, const int* __restrict__ fptr, const int* __restrict__ face_edge,
                            const int* __restrict__ edge_ptr, const int* __restrict__ edge_face,
                            const int64_t* __restrict__ einv_ptr, const double* __restrict__ einv,
-                           const int* __restrict__ Pptr, const int* __restrict__ Pcol,
-                           const int* __restrict__ Pslice, double* __restrict__ Pval) {
+                           const int* __restrict__ Pptr, const int* __restrict__ Pcol, Slots Ps,
+                           double* __restrict__ Pval) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= (int64_t)nf * nfd) return;
   const int f = (int)(r / nfd), beta = (int)(r - (int64_t)f * nfd);
   const int rb = Pptr[r], rn = Pptr[r + 1] - rb;
-  const int64_t base = (int64_t)Pslice[r >> 6] + (r & 63);
-  for (int k = 0; k < rn; ++k) Pval[base + 64 * (int64_t)k] = 0.0;
+  for (int k = 0; k < rn; ++k) Pval[Ps.at(r, k)] = 0.0;
   for (int i = fptr[f]; i < fptr[f + 1]; ++i) {
     const int e = face_edge[i];
     const int* fe = edge_face + edge_ptr[e];
@@ -388,9 +404,47 @@ __global__ void k_p_values(int nf, int nfd, const int* __restrict__ fptr, const 
     const double* inv = einv + einv_ptr[e] + (int64_t)(pf * nfd + beta) * n;
     for (int j = 0; j < m; ++j) {
       const int k0 = lower_bound_i32(Pcol + rb, rn, fe[j] * nfd);
-      for (int c = 0; c < nfd; ++c) Pval[base + 64 * (int64_t)(k0 + c)] += inv[j * nfd + c];
+      for (int c = 0; c < nfd; ++c) Pval[Ps.at(r, k0 + c)] += inv[j * nfd + c];
     }
   }
+}
+
+// Face-block pattern of an order-k face-DOF matrix from its CSR pattern: every row of face f must
+// list the same faces, each with all nfd columns in order (err otherwise).
+__global__ void k_blk_len(int nf, int nfd, const int* __restrict__ rowptr, int* __restrict__ len,
+                          int* __restrict__ err) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  const int64_t r0 = (int64_t)f * nfd;
+  const int n = rowptr[r0 + 1] - rowptr[r0];
+  bool ok = n % nfd == 0;
+  for (int i = 1; i < nfd; ++i) ok = ok && rowptr[r0 + i + 1] - rowptr[r0 + i] == n;
+  if (!ok) *err = 1;
+  len[f] = ok ? n / nfd : 0;
+}
+
+__global__ void k_blk_cols(int nf, int nfd, const int* __restrict__ rowptr, const int* __restrict__ col,
+                           const int* __restrict__ bptr, int* __restrict__ bcol, int* __restrict__ err) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  const int64_t r0 = (int64_t)f * nfd;
+  const int nb = bptr[f + 1] - bptr[f];
+  for (int j = 0; j < nb; ++j) {
+    const int g = col[rowptr[r0] + j * nfd] / nfd;
+    bcol[bptr[f] + j] = g;
+    for (int i = 0; i < nfd; ++i)
+      for (int c = 0; c < nfd; ++c)
+        if (col[rowptr[r0 + i] + j * nfd + c] != g * nfd + c) *err = 1;
+  }
+}
+
+// CSR values from the stored copy (export)
+__global__ void k_stored_to_csr(int64_t rows, const int* __restrict__ rowptr, Slots S, const double* __restrict__ v,
+                                double* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const int b = rowptr[r], n = rowptr[r + 1] - b;
+  for (int k = 0; k < n; ++k) out[b + k] = v[S.at(r, k)];
 }
 
 __global__ void k_round32(int64_t n, const double* __restrict__ x, float* __restrict__ y) {
@@ -449,11 +503,36 @@ __global__ void k_schwarz_back(DofLayout L, const int* __restrict__ cptr, const 
   z[nF + t] = acc;
 }
 
+// Face-block copy of the pattern of C (an order-k face-DOF matrix); synchronises.
+void build_blocks(hipStream_t s, Scratch& tmp, const Csr& C, int nf, int nfd, FaceBlocks& B) {
+  DBuf<int> len, err;
+  len.alloc((size_t)nf + 1);
+  err.alloc(1);
+  VEM_HIP(hipMemsetAsync(err.p, 0, sizeof(int), s));
+  k_blk_len<<<grid(nf), kT, 0, s>>>(nf, nfd, C.rowptr, len, err);
+  VEM_HIP(hipGetLastError());
+  B.nfd = nfd;
+  B.nf = nf;
+  B.bptr.alloc((size_t)nf + 1);
+  B.nblk = scan_i32(s, tmp, len, nf, B.bptr);
+  B.bcol.alloc(B.nblk);
+  k_blk_cols<<<grid(nf), kT, 0, s>>>(nf, nfd, C.rowptr, C.col, B.bptr, B.bcol, err);
+  VEM_HIP(hipGetLastError());
+  int h_err = 0;
+  VEM_HIP(hipMemcpyAsync(&h_err, err.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  VEM_HIP(hipStreamSynchronize(s));
+  VEM_REQUIRE(h_err == 0 && B.nblk * nfd * nfd == C.nnz, VEM_EINVAL,
+              "face system whose rows do not couple whole faces");
+  B.val.alloc(C.nnz);
+  B.val32.release();
+}
+
 }  // namespace
 
 void schwarz_build(hipStream_t s, Scratch& tmp, const SchwarzMesh& m, const DofLayout& L, const Csr& A,
                    Schwarz& X) {
   X.built = X.ready = X.ready32 = false;
+  X.blocked = false;
   // incidences of the face loops
   int64_t ninc = 0;
   {
@@ -547,9 +626,15 @@ void schwarz_build(hipStream_t s, Scratch& tmp, const SchwarzMesh& m, const DofL
     X.Fc.val.alloc(X.Fc.nnz);
     k_fc_cols<<<grid(nF), kT, 0, s>>>(nF, A.rowptr, A.col, X.Fc.rowptr, X.Fc.col);
     VEM_HIP(hipGetLastError());
-    const Csr* csr[2] = {&X.Fc, &X.Pc};
-    Sell* sell[2] = {&X.Fs, &X.Ps};
-    build_sells(s, tmp, csr, sell, 2);
+    if (face_blocks_supported(L.nfd)) {
+      build_blocks(s, tmp, X.Fc, m.nf, L.nfd, X.Fb);
+      build_blocks(s, tmp, X.Pc, m.nf, L.nfd, X.Pb);
+      X.blocked = true;
+    } else {
+      const Csr* csr[2] = {&X.Fc, &X.Pc};
+      Sell* sell[2] = {&X.Fs, &X.Ps};
+      build_sells(s, tmp, csr, sell, 2);
+    }
     X.Aiinv.alloc((size_t)m.nc * L.nint * L.nint);
     // W: (sum of face DOFs over the cells) x nint
     int h_ld = 0;
@@ -581,6 +666,11 @@ void schwarz_values(hipStream_t s, const SchwarzMesh& m, const DofLayout& L, con
   VEM_REQUIRE(X.built, VEM_EINVAL, "Schwarz pattern not built");
   const Csr& F = L.nint > 0 ? X.Fc : A;
   const Sell& Fs = schwarz_face_sell(X, As, L);
+  // where the face system's and P's values live
+  const Slots fsl = X.blocked ? slots_of(X.Fb) : slots_of(Fs);
+  double* fval = X.blocked ? X.Fb.val.p : Fs.val.p;
+  const Slots psl = X.blocked ? slots_of(X.Pb) : slots_of(X.Ps);
+  double* pval = X.blocked ? X.Pb.val.p : X.Ps.val.p;
   if (L.nint > 0) {
     const size_t lds = ((size_t)L.nint * L.nint + 2 * L.nint) * sizeof(double);
     k_cell_condense<<<m.nc, 64, lds, s>>>(L, m.cptr, m.cface, lmat_ptr, M1, lb_ptr, Bdiv1, nu, inv_gamma, bnd,
@@ -588,23 +678,32 @@ void schwarz_values(hipStream_t s, const SchwarzMesh& m, const DofLayout& L, con
     VEM_HIP(hipGetLastError());
     k_fc_values<<<grid(X.nF), kT, 0, s>>>(L, m.cptr, m.cface, m.csign, m.ldof_ptr, m.sorted_gid, m.sorted_l,
                                            m.face_cell, m.face_lidx, lmat_ptr, M1, lb_ptr, Bdiv1, nu, inv_gamma, bnd,
-                                           X.W, X.Fs.slice_ptr, X.Fs.val);
+                                           X.W, fsl, fval);
     VEM_HIP(hipGetLastError());
   }
   const int n = X.max_patch * L.nfd;
   const size_t lds = ((size_t)n * n + 2 * n) * sizeof(double);
   if (X.ne > 0)
-    k_edge_inv<<<(int)X.ne, 64, lds, s>>>((int)X.ne, L.nfd, X.edge_ptr, X.edge_face, F.rowptr, F.col, Fs.slice_ptr,
-                                           Fs.val, X.einv_ptr, X.einv);
+    k_edge_inv<<<(int)X.ne, 64, lds, s>>>((int)X.ne, L.nfd, X.edge_ptr, X.edge_face, F.rowptr, F.col, fsl, fval,
+                                           X.einv_ptr, X.einv);
   VEM_HIP(hipGetLastError());
   k_p_values<<<grid(X.nF), kT, 0, s>>>(m.nf, L.nfd, m.fptr, X.face_edge, X.edge_ptr, X.edge_face, X.einv_ptr, X.einv,
-                                        X.Pc.rowptr, X.Pc.col, X.Ps.slice_ptr, X.Ps.val);
+                                        X.Pc.rowptr, X.Pc.col, psl, pval);
   VEM_HIP(hipGetLastError());
   X.ready = true;
   X.ready32 = false;
 }
 
 void schwarz_round32(hipStream_t s, const DofLayout& L, Schwarz& X) {
+  if (X.blocked) {
+    for (FaceBlocks* B : {&X.Fb, &X.Pb}) {
+      B->val32.alloc(B->val.n);
+      k_round32<<<1024, kT, 0, s>>>((int64_t)B->val.n, B->val, B->val32);
+    }
+    VEM_HIP(hipGetLastError());
+    X.ready32 = true;
+    return;
+  }
   X.Ps.val32.alloc(X.Ps.nnz);
   k_round32<<<1024, kT, 0, s>>>(X.Ps.nnz, X.Ps.val, X.Ps.val32);
   if (L.nint > 0) {
@@ -613,6 +712,17 @@ void schwarz_round32(hipStream_t s, const DofLayout& L, Schwarz& X) {
   }
   VEM_HIP(hipGetLastError());
   X.ready32 = true;
+}
+
+void schwarz_export(hipStream_t s, const Schwarz& X, bool face, Csr& C) {
+  if (!X.blocked) {
+    sell_to_csr(s, face ? X.Fs : X.Ps, C);
+    return;
+  }
+  const FaceBlocks& B = face ? X.Fb : X.Pb;
+  if (C.rows > 0)
+    k_stored_to_csr<<<grid(C.rows), kT, 0, s>>>(C.rows, C.rowptr, slots_of(B), B.val, C.val);
+  VEM_HIP(hipGetLastError());
 }
 
 template <typename T>

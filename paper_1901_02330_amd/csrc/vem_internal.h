@@ -327,8 +327,25 @@ void launch_gershgorin(hipStream_t s, const Sell& A, const double* dinv, double*
 // leaving F = A_ff - A_fi A_ii^{-1} A_if on the face DOFs.  The preconditioner of the CG on F is
 // P = sum_e R_e^T F_e^{-1} R_e over the mesh edges e, R_e restricting to the DOFs of the faces
 // that contain e (the patches that hold the local divergence-free fields).
+// Order-k face systems couple whole faces: the entries between two faces form a dense nfd x nfd
+// block (nfd face DOFs each).  Block rows by face, one column index per block:
+//   bcol[bptr[f] + j] = face of block j of face f (ascending),
+//   val[((bptr[f] + j) nfd + i) nfd + c] = entry (f nfd + i, bcol nfd + c),
+// so a DOF row reads its nfd entries of a block contiguously, with no padding and one 4-byte index
+// per nfd^2 entries (against one per entry, and padded slices, in SELL-64).
+struct FaceBlocks {
+  int nfd = 0;
+  int64_t nf = 0, nblk = 0;
+  DBuf<int> bptr, bcol;
+  DBuf<double> val;
+  DBuf<float> val32;
+};
+// the face-DOF counts with a block kernel (the paper's k = 1, 2, 3)
+inline bool face_blocks_supported(int nfd) { return nfd == 3 || nfd == 6 || nfd == 10; }
+
 struct Schwarz {
   bool built = false;  // pattern of the current discretisation
+  bool blocked = false;  // order k: F and P held as face blocks (Fb, Pb) instead of SELL (Fs, Ps)
   bool ready = false;  // values for the current coefficient, gamma and boundary data
   bool ready32 = false;
   double gamma = 0.0;
@@ -342,6 +359,7 @@ struct Schwarz {
   Sell Fs;
   Csr Pc;                            // the Schwarz operator on the face DOFs
   Sell Ps;
+  FaceBlocks Fb, Pb;                 // F and P as face blocks (blocked)
   DBuf<int64_t> w_ptr;               // order k: per cell W = A_fi A_ii^{-1} (face DOFs x nint)
   DBuf<double> W, Aiinv;             // and A_ii^{-1} (nint x nint)
 };
@@ -359,6 +377,9 @@ void schwarz_values(hipStream_t s, const SchwarzMesh& m, const DofLayout& L, con
                     double inv_gamma, const int* bnd, const Csr& A, const Sell& As, Schwarz& X);
 // FP32 roundings of P and (order k) of the face system, for mixed-precision inner solves
 void schwarz_round32(hipStream_t s, const DofLayout& L, Schwarz& X);
+// CSR values of the face system (face) or of P into C.val (C: X.Fc or X.Pc) from whichever copy
+// the solver holds (SELL or face blocks); the lowest order's face system is A_gamma itself
+void schwarz_export(hipStream_t s, const Schwarz& X, bool face, Csr& C);
 // the face system's SELL (As at the lowest order) and CSR pattern
 inline const Sell& schwarz_face_sell(const Schwarz& X, const Sell& As, const DofLayout& L) {
   return L.nint > 0 ? X.Fs : As;
@@ -375,10 +396,11 @@ void launch_schwarz_back(hipStream_t s, const SchwarzMesh& m, const DofLayout& L
 //   [product] beta, stop test; p = z + beta p; q = F z + beta q; partials p.q
 //   [update]  alpha; x += alpha p; r -= alpha q; z -= alpha P q; partials r.z
 // Work layout: x, r, z, p, w0 = q.  T = double, or float with FP64 dot products.
+// F: the face system's SELL (schwarz_face_sell), used unless X.blocked.
 template <typename T>
-void launch_scg_init(hipStream_t s, const Sell& P, const PcgWorkT<T>& w, PcgState* st, double tol, double* part);
+void launch_scg_init(hipStream_t s, const Schwarz& X, const PcgWorkT<T>& w, PcgState* st, double tol, double* part);
 template <typename T>
-void launch_scg_iter(hipStream_t s, int i, const Sell& F, const Sell& P, const PcgWorkT<T>& w, PcgState* st,
+void launch_scg_iter(hipStream_t s, int i, const Sell& F, const Schwarz& X, const PcgWorkT<T>& w, PcgState* st,
                      double* part);
 
 // host utilities

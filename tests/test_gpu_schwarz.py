@@ -7,6 +7,9 @@
 * Solves to 1e-13 against the oracle's direct solve (relative 1e-10 in u and p), FP64 and with FP32
   inner iterations (within the tolerance times the conditioning).
 * The preconditioner's purpose: far fewer inner iterations than the Jacobi-CG on the same solve.
+* At order k the face system and P are stored as dense face-to-face blocks (k = 1, 2, 3: 3, 6, 10
+  DOFs per face); the operator and solve tests above run through that storage, and the timing hook
+  counts its bytes (one index per block).
 """
 import sys
 
@@ -125,6 +128,7 @@ def test_schwarz_operators_match_reference(name, flux):
 SOLVE_CASES = {
     "cube675_lo": (lambda: cube_mesh(6, 7, 5), "lo", 0, 2.0),
     "voronoi150_lo": (lambda: voronoi_mesh(150, seed=0), "lo", 0, 1.0),
+    "cube432_k1": (lambda: cube_mesh(4, 3, 2), "paper", 1, 1.5),
     "cube322_k2": (lambda: cube_mesh(3, 2, 2), "paper", 2, 1.0),
     "voronoi25_k2": (lambda: voronoi_mesh(25, seed=3), "paper", 2, 1.0),
     "cube322_k3": (lambda: cube_mesh(3, 2, 2), "paper", 3, 1.0),
@@ -228,3 +232,39 @@ def test_voronoi_checkerboard_order2_converges_with_fp32_inner_solves():
     _say("fp64", i64, "backward error", berr, "mixed vs fp64", diff)
     assert berr <= 1.01e-8
     assert diff <= 1e-5
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_face_block_iteration_bytes_and_solve_unchanged(k):
+    """The timing hook's Schwarz-CG iteration at order k runs on the face blocks, and its algorithmic
+    bytes are the blocks' own: 8 (FP64) or 4 (FP32) bytes per entry of F and P, one 4-byte column per
+    nfd x nfd block, two block offsets per face, and 13 vector accesses per face DOF.  A solve after
+    the timing loops gives the same bits as before them."""
+    _say("face blocks", k)
+    m = cube_mesh(4, 3, 3)
+    nc = 36
+    nu = 1.0 / lognormal_field(nc, 1.0, 2)
+    s = _solver(m, "paper", k, nu)
+    s.set_rhs_functions(SineSolution.f, SineSolution.pD)
+    kw = dict(precond="reg", tol=1e-12, maxit=500, inner_tol=1e-2)
+    u0, p0, i0 = s.solve(**kw)
+    assert i0["converged"], i0
+    u1, p1, i1 = s.solve(precision="mixed", **dict(kw, tol=1e-9))
+    assert i1["converged"], i1
+    sz = s.sizes()
+    nF, nf = sz["n_face_dofs"], sz["n_faces"]
+    nfd = nF // nf
+    assert nfd == (k + 1) * (k + 2) // 2
+    nnzF = int(s.export_csr("reg_face")[0][-1])
+    nnzP = int(s.export_csr("reg_schwarz")[0][-1])
+    assert nnzF % (nfd * nfd) == 0 and nnzP % (nfd * nfd) == 0
+    nblk = (nnzF + nnzP) // (nfd * nfd)
+    for which, vb in (("cg_reg_schwarz", 8), ("cg_reg_schwarz32", 4)):
+        ms, nbytes = s.time_kernel(which, reps=5)
+        assert ms > 0
+        assert nbytes == vb * (nnzF + nnzP) + 4 * nblk + 16 * (nf + 1) + vb * 13 * nF, (which, nbytes)
+    u2, p2, i2 = s.solve(**kw)
+    assert i2["iterations"] == i0["iterations"]
+    import torch
+
+    assert torch.equal(u0, u2) and torch.equal(p0, p2)
