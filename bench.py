@@ -78,6 +78,23 @@ def parse():
     return ap.parse_args()
 
 
+def kernel_short(full: str):
+    """A kernel's name with its template arguments (nested brackets kept), without the namespaces;
+    None when the name holds no library kernel."""
+    t = full.replace("vem::(anonymous namespace)::", "")
+    m = re.search(r"\bk_[A-Za-z0-9_]+", t)
+    if not m:
+        return None
+    i = m.end()
+    if i < len(t) and t[i] == "<":
+        depth = 0
+        for j in range(i, len(t)):
+            depth += {"<": 1, ">": -1}.get(t[j], 0)
+            if depth == 0:
+                return t[m.start():j + 1]
+    return m.group(0)
+
+
 def summarize(prefix: str):
     """Markdown summary of a rocprofv3 --kernel-trace --stats --output-format csv run."""
     import csv
@@ -97,8 +114,7 @@ def summarize(prefix: str):
                 "| kernel | grid | launches | working | avg working us | median us |", "|---|---|---|---|---|---|"]
         by = {}
         for r in csv.DictReader(open(trace)):
-            mt = re.search(r"(k_[A-Za-z0-9_]+(?:<[^>]*>)?)\(", r["Kernel_Name"])
-            name = mt.group(1) if mt else r["Kernel_Name"][:40]
+            name = kernel_short(r["Kernel_Name"]) or r["Kernel_Name"][:40]
             if not any(k in name for k in ("k_ppcg_iter", "k_spmv", "k_scg_", "k_cheb_iter")):
                 continue
             d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
@@ -147,8 +163,7 @@ def schur_window(trace: str):
     seg = rows[s:e]
     busy, calls = {}, {}
     for r in seg:
-        mt = re.search(r"(k_[A-Za-z0-9_]+(?:<[^>]*>)?)\(", r["Kernel_Name"])
-        name = mt.group(1) if mt else r["Kernel_Name"].split("(")[0][:40]
+        name = kernel_short(r["Kernel_Name"]) or r["Kernel_Name"].split("(")[0][:40]
         name = re.sub(r"^(k_(?:dots|dots_fix|update_dots|combine))<\d+>$", r"\1<j>", name)
         d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
         busy[name] = busy.get(name, 0.0) + d
@@ -239,7 +254,7 @@ def pmc_probe(mesh, n):
     dispatch each), so that per-dispatch FETCH_SIZE / WRITE_SIZE can be scaled by the copy's."""
     import torch
 
-    from paper_1901_02330_amd.inputs import SineSolution, lognormal_field
+    from paper_1901_02330_amd.inputs import SineSolution, cube_mesh, lognormal_field
     from paper_1901_02330_amd.vem import Solver
 
     src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")  # 512 MiB, twice the MALL
@@ -256,6 +271,17 @@ def pmc_probe(mesh, n):
         ms, nb = s.time_kernel(which, reps=20)
         log(f"{which}: {ms * 1e3:.1f} us, algorithmic {nb / 1e6:.1f} MB")
         rec["kernels"][which] = {"avg_us": ms * 1e3, "algorithmic_bytes": nb}
+    s.close()
+    # the order-k Schwarz-CG on face blocks: Cube 32^3, the paper's k = 2, log K = 1.5 N(0,1)
+    s = Solver()
+    s.set_mesh(cube_mesh(32))
+    s.discretize("paper", k=2)
+    s.set_coefficient(torch.as_tensor(1.0 / lognormal_field(32**3, 1.5, 0), device="cuda"))
+    for which in ("cg_reg_schwarz", "cg_reg_schwarz32"):
+        ms, nb = s.time_kernel(which, reps=20)
+        log(f"{which} (cube 32^3, k = 2): {ms * 1e3:.1f} us, algorithmic {nb / 1e6:.1f} MB")
+        rec["kernels"][which + "_k2"] = {"avg_us": ms * 1e3, "algorithmic_bytes": nb}
+    s.close()
     print(json.dumps(rec), flush=True)
 
 
@@ -274,8 +300,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str):
             for r in csv.DictReader(open(f)):
                 if r["Counter_Name"] != counter:
                     continue
-                mt = re.search(r"(k_[A-Za-z0-9_]+(?:<[^>]*>)?)\(", r["Kernel_Name"])
-                name = mt.group(1) if mt else ("copy" if "neg" in r["Kernel_Name"] else None)
+                name = kernel_short(r["Kernel_Name"]) or ("copy" if "neg" in r["Kernel_Name"] else None)
                 if name is None:
                     continue
                 by.setdefault((name, int(r["Grid_Size"])), []).append(float(r["Counter_Value"]) * 1024.0)
@@ -310,7 +335,11 @@ def summarize_pmc(fetch_dir: str, write_dir: str):
     for which, prefixes in (("spmv", ["k_spmv"]), ("cheb_schur", ["k_cheb_iter<double"]),
                             ("cg_schur", ["k_ppcg_iter<double, false, 1024"]),
                             ("cg_reg", ["k_ppcg_iter<double, false, 256"]),
-                            ("cg_reg_schwarz", ["k_scg_prod<double,", "k_scg_update<double,"])):
+                            ("cg_reg_schwarz", ["k_scg_prod<double, 256, SellViewT", "k_scg_update<double, 256, SellViewT"]),
+                            ("cg_reg_schwarz_k2", ["k_scg_prod<double, 256, BlockViewT<double, 6>",
+                                                   "k_scg_update<double, 256, BlockViewT<double, 6>"]),
+                            ("cg_reg_schwarz32_k2", ["k_scg_prod<float, 256, BlockViewT<float, 6>",
+                                                     "k_scg_update<float, 256, BlockViewT<float, 6>"])):
         keys = [most(p) for p in prefixes]
         if any(k is None for k in keys) or which not in probe["kernels"]:
             continue
