@@ -504,12 +504,13 @@ SchwarzMesh schwarz_mesh(vem_handle h) {
           h->face_cell, h->face_lidx, h->ldof_ptr,    h->sorted_gid, h->sorted_l,  h->csign};
 }
 
-// Block-Reg's Schwarz preconditioner for gamma: A_gamma's values (the lowest order's face system),
-// the edge patterns on first use, then the face system and the patch inverses when the coefficient,
+// Block-Reg's Schwarz preconditioner for gamma: A_gamma's values (the lowest order's face system;
+// order k builds its face system from the local matrices and needs only A_gamma's pattern), the
+// edge patterns on first use, then the face system and the patch inverses when the coefficient,
 // gamma or the boundary data changed; FP32 roundings when f32.
 void ensure_schwarz(vem_handle h, double gamma, bool f32) {
   const DofLayout L = h->L;
-  ensure_values(h, false, true, f32 && L.nint == 0, gamma);
+  ensure_values(h, false, L.nint == 0, f32 && L.nint == 0, gamma);
   hipStream_t s = h->stream;
   const SchwarzMesh m = schwarz_mesh(h);
   if (!h->sz.built) schwarz_build(s, h->tmp, m, L, h->A, h->sz);
@@ -1756,8 +1757,11 @@ static vem_status solve_impl(vem_handle h, const vem_solve_opts* opts, const dou
     const int m = o.restart;
     const int64_t Nu = h->L.Nu, Np = h->L.Np, N = Nu + Np;
     const double gam = o.gamma > 0 ? o.gamma : h->gamma_default;
-    ensure_values(h, o.precond == VEM_PREC_SCHUR, o.precond == VEM_PREC_REG, o.precision == VEM_MIXED, gam);
-    if (o.precond == VEM_PREC_REG && o.reg_inner == VEM_REG_SCHWARZ) ensure_schwarz(h, gam, o.precision == VEM_MIXED);
+    // the Schwarz form asks for A_gamma's values itself where it needs them (the lowest order)
+    const bool schwarz = o.precond == VEM_PREC_REG && o.reg_inner == VEM_REG_SCHWARZ;
+    ensure_values(h, o.precond == VEM_PREC_SCHUR, o.precond == VEM_PREC_REG && !schwarz, o.precision == VEM_MIXED,
+                  gam);
+    if (schwarz) ensure_schwarz(h, gam, o.precision == VEM_MIXED);
     if (!user_rhs && h->bc == VEM_BC_FLUX) rhs = flux_rhs(h);
     ensure_workspace(h, m);
     double* V = h->Vb;

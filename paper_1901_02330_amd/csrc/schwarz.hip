@@ -231,19 +231,26 @@ __device__ inline void gj_invert(double* a, double* rk, double* ck, int n) {
 }
 
 // Per cell (one block): A_ii^{-1} and W = A_fi A_ii^{-1} (rows of prescribed face DOFs zero: A_gamma
-// holds identity rows and columns there).  LDS: nint^2 + 2 nint doubles.
+// holds identity rows and columns there); with Sp, also the condensed cell matrix
+// S_P = A_ff - W A_if (Fn x Fn, row-major at sp_ptr[P]), A_if and W staged in LDS.  Each S_P entry is
+// formed as the face system's gather formed it from the local matrices (the same operands in the
+// same order), so the face system is the same either way.
+// LDS: nint^2 + 2 nint doubles, plus 2 nint fn_max with Sp.
 __global__ void k_cell_condense(DofLayout L, const int* __restrict__ cptr, const int* __restrict__ cface,
                                 const int64_t* __restrict__ lmat_ptr, const double* __restrict__ M1,
                                 const int64_t* __restrict__ lb_ptr, const double* __restrict__ Bdiv1,
                                 const double* __restrict__ nu, double ig, const int* __restrict__ bnd,
                                 const int* __restrict__ ldof_ptr, double* __restrict__ Aiinv,
-                                double* __restrict__ W) {
+                                double* __restrict__ W, int fn_max, const int64_t* __restrict__ sp_ptr,
+                                double* __restrict__ Sp) {
   extern __shared__ double sh[];
   const int P = blockIdx.x;
   const int ni = L.nint;
   double* a = sh;
   double* rk = sh + ni * ni;
   double* ck = rk + ni;
+  double* aif = ck + ni;              // A_if[c][m] = A(m, interior c), nint x Fn (with Sp)
+  double* wl = aif + ni * fn_max;     // W[l][c], Fn x nint (with Sp)
   const int F = cptr[P + 1] - cptr[P], Fn = F * L.nfd, nd = Fn + ni;
   const double* M = M1 + lmat_ptr[P];
   const double* Bp = Bdiv1 + lb_ptr[P];
@@ -252,6 +259,11 @@ __global__ void k_cell_condense(DofLayout L, const int* __restrict__ cptr, const
     const int i = t / ni, j = t - i * ni;
     a[t] = local_a(M, Bp, nd, L.npd, nuP, ig, Fn + i, Fn + j);
   }
+  if (Sp)
+    for (int t = threadIdx.x; t < ni * Fn; t += blockDim.x) {
+      const int c = t / Fn, m = t - c * Fn;
+      aif[t] = local_a(M, Bp, nd, L.npd, nuP, ig, m, Fn + c);
+    }
   gj_invert(a, rk, ck, ni);
   for (int t = threadIdx.x; t < ni * ni; t += blockDim.x) Aiinv[(int64_t)P * ni * ni + t] = a[t];
   const int64_t wo = ((int64_t)ldof_ptr[P] - (int64_t)P * ni) * ni;
@@ -264,8 +276,33 @@ __global__ void k_cell_condense(DofLayout L, const int* __restrict__ cptr, const
       double t = 0.0;
       for (int b = 0; b < ni; ++b) t += af[b] * a[b * ni + c];
       W[wo + (int64_t)l * ni + c] = t;
+      if (Sp) wl[l * ni + c] = t;
     }
   }
+  if (!Sp) return;
+  __syncthreads();
+  double* out = Sp + sp_ptr[P];
+  for (int t = threadIdx.x; t < Fn * Fn; t += blockDim.x) {
+    const int l = t / Fn, m = t - l * Fn;
+    double v = local_a(M, Bp, nd, L.npd, nuP, ig, l, m);
+    for (int c = 0; c < ni; ++c) v -= wl[l * ni + c] * aif[c * Fn + m];
+    out[t] = v;
+  }
+}
+
+__global__ void k_cell_fn2(int nc, int nfd, const int* __restrict__ cptr, int64_t* __restrict__ len,
+                           int* __restrict__ fmax) {
+  const int P = blockIdx.x * blockDim.x + threadIdx.x;
+  int f = 0;
+  if (P < nc) {
+    f = (cptr[P + 1] - cptr[P]) * nfd;
+    len[P] = (int64_t)f * f;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const int t = __shfl_xor(f, o, 64);
+    f = t > f ? t : f;
+  }
+  if ((threadIdx.x & 63) == 0 && f > 0) atomicMax(fmax, f);
 }
 
 // Face system values (order k): row r (face DOF) of F = sum over its cells of
@@ -277,7 +314,8 @@ __global__ void k_fc_values(DofLayout L, const int* __restrict__ cptr, const int
                             const int64_t* __restrict__ lmat_ptr, const double* __restrict__ M1,
                             const int64_t* __restrict__ lb_ptr, const double* __restrict__ Bdiv1,
                             const double* __restrict__ nu, double ig, const int* __restrict__ bnd,
-                            const double* __restrict__ W, Slots Fs, double* __restrict__ Fval) {
+                            const double* __restrict__ W, const int64_t* __restrict__ sp_ptr,
+                            const double* __restrict__ Sp, Slots Fs, double* __restrict__ Fval) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nF = (int64_t)L.nf * L.nfd;
   if (r >= nF) return;
@@ -332,14 +370,19 @@ __global__ void k_fc_values(DofLayout L, const int* __restrict__ cptr, const int
       }
       const int lg = ll[c][idx];
       const double sg = (double)csign[cptr[P[c]] + lg / L.nfd];
-      const double* M = M1 + lmat_ptr[P[c]];
-      const double* Bp = Bdiv1 + lb_ptr[P[c]];
-      const double nuP = nu[P[c]];
-      double t = local_a(M, Bp, nd[c], L.npd, nuP, ig, lr[c], lg);
-      const bool fixed_col = bnd && bnd[g / L.nfd];
-      if (!fixed_row && !fixed_col) {
-        const double* Wr = W + wo[c] + (int64_t)lr[c] * L.nint;
-        for (int a = 0; a < L.nint; ++a) t -= Wr[a] * local_a(M, Bp, nd[c], L.npd, nuP, ig, lg, Fn[c] + a);
+      double t;
+      if (Sp) {
+        t = Sp[sp_ptr[P[c]] + (int64_t)lr[c] * Fn[c] + lg];
+      } else {
+        const double* M = M1 + lmat_ptr[P[c]];
+        const double* Bp = Bdiv1 + lb_ptr[P[c]];
+        const double nuP = nu[P[c]];
+        t = local_a(M, Bp, nd[c], L.npd, nuP, ig, lr[c], lg);
+        const bool fixed_col = bnd && bnd[g / L.nfd];
+        if (!fixed_row && !fixed_col) {
+          const double* Wr = W + wo[c] + (int64_t)lr[c] * L.nint;
+          for (int a = 0; a < L.nint; ++a) t -= Wr[a] * local_a(M, Bp, nd[c], L.npd, nuP, ig, lg, Fn[c] + a);
+        }
       }
       v += sr[c] * sg * t;
     }
@@ -641,6 +684,28 @@ void schwarz_build(hipStream_t s, Scratch& tmp, const SchwarzMesh& m, const DofL
     VEM_HIP(hipMemcpyAsync(&h_ld, m.ldof_ptr + m.nc, sizeof(int), hipMemcpyDeviceToHost, s));
     VEM_HIP(hipStreamSynchronize(s));
     X.W.alloc(((size_t)h_ld - (size_t)m.nc * L.nint) * L.nint);
+    // condensed cell matrices, when A_if and W of the largest cell fit in 64 KiB of LDS beside A_ii
+    {
+      DBuf<int64_t> len;
+      DBuf<int> fmax;
+      len.alloc((size_t)m.nc + 1);
+      fmax.alloc(1);
+      VEM_HIP(hipMemsetAsync(fmax.p, 0, sizeof(int), s));
+      k_cell_fn2<<<grid(m.nc), kT, 0, s>>>(m.nc, L.nfd, m.cptr, len, fmax);
+      VEM_HIP(hipGetLastError());
+      int h_f = 0;
+      VEM_HIP(hipMemcpyAsync(&h_f, fmax.p, sizeof(int), hipMemcpyDeviceToHost, s));
+      VEM_HIP(hipStreamSynchronize(s));
+      X.fn_max = h_f;
+      const size_t lds = ((size_t)L.nint * L.nint + 2 * L.nint + 2 * (size_t)L.nint * h_f) * sizeof(double);
+      X.sp_ptr.release();
+      X.Sp.release();
+      if (lds <= 64 * 1024) {
+        X.sp_ptr.alloc((size_t)m.nc + 1);
+        const int64_t tot = scan_i64(s, tmp, len, m.nc, X.sp_ptr);
+        X.Sp.alloc(tot);
+      }
+    }
   } else {
     const Csr* csr[1] = {&X.Pc};
     Sell* sell[1] = {&X.Ps};
@@ -672,13 +737,15 @@ void schwarz_values(hipStream_t s, const SchwarzMesh& m, const DofLayout& L, con
   const Slots psl = X.blocked ? slots_of(X.Pb) : slots_of(X.Ps);
   double* pval = X.blocked ? X.Pb.val.p : X.Ps.val.p;
   if (L.nint > 0) {
-    const size_t lds = ((size_t)L.nint * L.nint + 2 * L.nint) * sizeof(double);
+    const bool sp = X.Sp.p != nullptr;
+    const size_t lds =
+        ((size_t)L.nint * L.nint + 2 * L.nint + (sp ? 2 * (size_t)L.nint * X.fn_max : 0)) * sizeof(double);
     k_cell_condense<<<m.nc, 64, lds, s>>>(L, m.cptr, m.cface, lmat_ptr, M1, lb_ptr, Bdiv1, nu, inv_gamma, bnd,
-                                          m.ldof_ptr, X.Aiinv, X.W);
+                                          m.ldof_ptr, X.Aiinv, X.W, X.fn_max, X.sp_ptr, X.Sp);
     VEM_HIP(hipGetLastError());
     k_fc_values<<<grid(X.nF), kT, 0, s>>>(L, m.cptr, m.cface, m.csign, m.ldof_ptr, m.sorted_gid, m.sorted_l,
                                            m.face_cell, m.face_lidx, lmat_ptr, M1, lb_ptr, Bdiv1, nu, inv_gamma, bnd,
-                                           X.W, fsl, fval);
+                                           X.W, X.sp_ptr, X.Sp, fsl, fval);
     VEM_HIP(hipGetLastError());
   }
   const int n = X.max_patch * L.nfd;
