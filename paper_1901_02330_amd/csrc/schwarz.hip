@@ -34,6 +34,9 @@ inline int grid(int64_t n) { return (int)((n + kT - 1) / kT); }
 constexpr int kMaxNb = 160;
 // DOFs of one edge patch (faces around the edge times face DOFs); more is rejected
 constexpr int kMaxPatchDof = 80;
+// LDS of the per-cell staged kernels of the inner solve's right-hand side and back-substitution;
+// cells too large for it take the unstaged kernels
+constexpr size_t kCellStageLds = 48 * 1024;
 
 __global__ void k_inc_face(int nf, const int* __restrict__ fptr, int* __restrict__ inc_face) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
@@ -497,10 +500,54 @@ __global__ void k_round32(int64_t n, const double* __restrict__ x, float* __rest
 
 // ---- inner solve: right-hand side and back-substitution --------------------------------------
 
+// u = W_P v_i,P for every face DOF of every cell (order k): one wavefront per cell, each lane a
+// face DOF, reading its row of W (contiguous) and the cell's interior part of v, so that a cell's W
+// is read by one wavefront at once.
+__global__ void k_schwarz_cell_u(DofLayout L, const int* __restrict__ cptr, const int* __restrict__ ldof_ptr,
+                                 const double* __restrict__ W, const double* __restrict__ v, double* __restrict__ u) {
+  const int P = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (P >= L.nc) return;
+  const int lane = threadIdx.x & 63;
+  const int Fn = (cptr[P + 1] - cptr[P]) * L.nfd;
+  const int64_t fo = (int64_t)ldof_ptr[P] - (int64_t)P * L.nint;  // face-DOF incidences of the cells before P
+  const double* Wp = W + fo * L.nint;
+  const double* vi = v + (int64_t)L.nf * L.nfd + (int64_t)P * L.nint;
+  for (int l = lane; l < Fn; l += 64) {
+    const double* Wr = Wp + (int64_t)l * L.nint;
+    double acc = 0.0;
+    for (int a = 0; a < L.nint; ++a) acc += Wr[a] * vi[a];
+    u[fo + l] = acc;
+  }
+}
+
+// The same with the cell's W and v_i staged in LDS first by coalesced loads (one 64-thread block
+// per cell; LDS: fn_max nint + nint doubles); the row products then run from LDS in the same order.
+__global__ void __launch_bounds__(64) k_schwarz_cell_u_lds(DofLayout L, const int* __restrict__ cptr,
+                                                           const int* __restrict__ ldof_ptr,
+                                                           const double* __restrict__ W,
+                                                           const double* __restrict__ v, double* __restrict__ u) {
+  extern __shared__ double sh[];
+  const int P = blockIdx.x;
+  const int ni = L.nint, Fn = (cptr[P + 1] - cptr[P]) * L.nfd, n = Fn * ni;
+  const int64_t fo = (int64_t)ldof_ptr[P] - (int64_t)P * ni;
+  const double* Wp = W + fo * ni;
+  const double* vi = v + (int64_t)L.nf * L.nfd + (int64_t)P * ni;
+  double* vs = sh + n;
+  for (int t = threadIdx.x; t < n; t += 64) sh[t] = Wp[t];
+  for (int t = threadIdx.x; t < ni; t += 64) vs[t] = vi[t];
+  __syncthreads();
+  for (int l = threadIdx.x; l < Fn; l += 64) {
+    double acc = 0.0;
+    for (int a = 0; a < ni; ++a) acc += sh[l * ni + a] * vs[a];
+    u[fo + l] = acc;
+  }
+}
+
+// r0 = v_f - sum over the face's cells of sigma u (order k), or v_f (lowest order)
 template <typename T>
 __global__ void k_schwarz_rhs(DofLayout L, const int* __restrict__ cptr, const int8_t* __restrict__ csign,
                               const int* __restrict__ face_cell, const int* __restrict__ face_lidx,
-                              const int* __restrict__ ldof_ptr, const double* __restrict__ W,
+                              const int* __restrict__ ldof_ptr, const double* __restrict__ u,
                               const double* __restrict__ v, T* __restrict__ r0) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nF = (int64_t)L.nf * L.nfd;
@@ -512,13 +559,8 @@ __global__ void k_schwarz_rhs(DofLayout L, const int* __restrict__ cptr, const i
       const int P = face_cell[2 * f + side];
       if (P < 0) continue;
       const int j = face_lidx[2 * f + side];
-      const int l = j * L.nfd + beta;
       const double s = (double)csign[cptr[P] + j];
-      const double* Wr = W + ((int64_t)ldof_ptr[P] - (int64_t)P * L.nint) * L.nint + (int64_t)l * L.nint;
-      const double* vi = v + nF + (int64_t)P * L.nint;
-      double u = 0.0;
-      for (int a = 0; a < L.nint; ++a) u += Wr[a] * vi[a];
-      t -= s * u;
+      t -= s * u[(int64_t)ldof_ptr[P] - (int64_t)P * L.nint + j * L.nfd + beta];
     }
   }
   r0[r] = (T)t;
@@ -544,6 +586,46 @@ __global__ void k_schwarz_back(DofLayout L, const int* __restrict__ cptr, const 
     for (int b = 0; b < L.nfd; ++b) acc -= Wc[(int64_t)(j * L.nfd + b) * L.nint] * s * z[g0 + b];
   }
   z[nF + t] = acc;
+}
+
+// The back-substitution with the cell's W, A_ii^{-1}, v_i and signed face values staged in LDS by
+// coalesced loads (one 64-thread block per cell; LDS: fn_max nint + 2 fn_max + nint^2 + nint
+// doubles), summing in the same order as k_schwarz_back.
+__global__ void __launch_bounds__(64) k_schwarz_back_lds(DofLayout L, const int* __restrict__ cptr,
+                                                         const int* __restrict__ cface,
+                                                         const int8_t* __restrict__ csign,
+                                                         const int* __restrict__ ldof_ptr,
+                                                         const double* __restrict__ Aiinv,
+                                                         const double* __restrict__ W,
+                                                         const double* __restrict__ v, double* __restrict__ z) {
+  extern __shared__ double sh[];
+  const int P = blockIdx.x;
+  const int ni = L.nint, s0 = cptr[P], Fn = (cptr[P + 1] - s0) * L.nfd, n = Fn * ni;
+  const int64_t nF = (int64_t)L.nf * L.nfd;
+  const int64_t fo = (int64_t)ldof_ptr[P] - (int64_t)P * ni;
+  double* Ws = sh;
+  double* ss = Ws + n;
+  double* zs = ss + Fn;
+  double* As = zs + Fn;
+  double* vs = As + ni * ni;
+  const double* Wp = W + fo * ni;
+  const double* Ap = Aiinv + (int64_t)P * ni * ni;
+  const double* vi = v + nF + (int64_t)P * ni;
+  for (int t = threadIdx.x; t < n; t += 64) Ws[t] = Wp[t];
+  for (int t = threadIdx.x; t < ni * ni; t += 64) As[t] = Ap[t];
+  for (int t = threadIdx.x; t < ni; t += 64) vs[t] = vi[t];
+  for (int l = threadIdx.x; l < Fn; l += 64) {
+    const int j = l / L.nfd, b = l - j * L.nfd;
+    ss[l] = (double)csign[s0 + j];
+    zs[l] = z[(int64_t)cface[s0 + j] * L.nfd + b];
+  }
+  __syncthreads();
+  for (int a = threadIdx.x; a < ni; a += 64) {
+    double acc = 0.0;
+    for (int b = 0; b < ni; ++b) acc += As[a * ni + b] * vs[b];
+    for (int l = 0; l < Fn; ++l) acc -= Ws[l * ni + a] * ss[l] * zs[l];
+    z[nF + (int64_t)P * ni + a] = acc;
+  }
 }
 
 // Face-block copy of the pattern of C (an order-k face-DOF matrix); synchronises.
@@ -684,6 +766,7 @@ void schwarz_build(hipStream_t s, Scratch& tmp, const SchwarzMesh& m, const DofL
     VEM_HIP(hipMemcpyAsync(&h_ld, m.ldof_ptr + m.nc, sizeof(int), hipMemcpyDeviceToHost, s));
     VEM_HIP(hipStreamSynchronize(s));
     X.W.alloc(((size_t)h_ld - (size_t)m.nc * L.nint) * L.nint);
+    X.ucell.alloc((size_t)h_ld - (size_t)m.nc * L.nint);
     // condensed cell matrices, when A_if and W of the largest cell fit in 64 KiB of LDS beside A_ii
     {
       DBuf<int64_t> len;
@@ -796,7 +879,16 @@ template <typename T>
 void launch_schwarz_rhs(hipStream_t s, const SchwarzMesh& m, const DofLayout& L, const Schwarz& X, const int* bnd,
                         const double* v, T* r0) {
   (void)bnd;  // W rows of prescribed DOFs are zero
-  k_schwarz_rhs<T><<<grid(X.nF), kT, 0, s>>>(L, m.cptr, m.csign, m.face_cell, m.face_lidx, m.ldof_ptr, X.W, v, r0);
+  if (L.nint > 0 && L.nc > 0) {
+    VEM_REQUIRE(X.ucell.p != nullptr, VEM_EINVAL, "Schwarz cell buffers not built");
+    const size_t lds = ((size_t)X.fn_max * L.nint + L.nint) * sizeof(double);
+    if (lds <= kCellStageLds)
+      k_schwarz_cell_u_lds<<<L.nc, 64, lds, s>>>(L, m.cptr, m.ldof_ptr, X.W, v, X.ucell);
+    else
+      k_schwarz_cell_u<<<(L.nc + 3) / 4, 256, 0, s>>>(L, m.cptr, m.ldof_ptr, X.W, v, X.ucell);
+  }
+  k_schwarz_rhs<T><<<grid(X.nF), kT, 0, s>>>(L, m.cptr, m.csign, m.face_cell, m.face_lidx, m.ldof_ptr, X.ucell, v,
+                                             r0);
 }
 template void launch_schwarz_rhs<double>(hipStream_t, const SchwarzMesh&, const DofLayout&, const Schwarz&,
                                          const int*, const double*, double*);
@@ -806,7 +898,12 @@ template void launch_schwarz_rhs<float>(hipStream_t, const SchwarzMesh&, const D
 void launch_schwarz_back(hipStream_t s, const SchwarzMesh& m, const DofLayout& L, const Schwarz& X,
                          const double* v, double* z) {
   const int64_t n = (int64_t)L.nc * L.nint;
-  if (n > 0)
+  if (n == 0) return;
+  const size_t lds = ((size_t)X.fn_max * L.nint + 2 * (size_t)X.fn_max + (size_t)L.nint * L.nint + L.nint) *
+                     sizeof(double);
+  if (lds <= kCellStageLds)
+    k_schwarz_back_lds<<<L.nc, 64, lds, s>>>(L, m.cptr, m.cface, m.csign, m.ldof_ptr, X.Aiinv, X.W, v, z);
+  else
     k_schwarz_back<<<grid(n), kT, 0, s>>>(L, m.cptr, m.cface, m.csign, m.ldof_ptr, X.Aiinv, X.W, v, z);
 }
 

@@ -362,6 +362,7 @@ struct Schwarz {
   FaceBlocks Fb, Pb;                 // F and P as face blocks (blocked)
   DBuf<int64_t> w_ptr;               // order k: per cell W = A_fi A_ii^{-1} (face DOFs x nint)
   DBuf<double> W, Aiinv;             // and A_ii^{-1} (nint x nint)
+  DBuf<double> ucell;                // order k: W v_i per cell face DOF (inner-solve right-hand side)
   int fn_max = 0;                    // order k: most face DOFs of a cell
   DBuf<int64_t> sp_ptr;              // order k: per cell the condensed matrix A_ff - W A_if
   DBuf<double> Sp;                   // (face DOFs^2, row-major), when its set-up fits in LDS
