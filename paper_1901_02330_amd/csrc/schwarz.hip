@@ -455,6 +455,72 @@ __global__ void k_p_values(int nf, int nfd, const int* __restrict__ fptr, const 
   }
 }
 
+// The same on face blocks: row (f, beta), block by block (face g of the row), sums over the edges of
+// f in loop order the inverse entries of the edges whose patch holds g (the same terms in the same
+// order as above), then writes the block row once.
+template <int NFD>
+__global__ void k_p_values_blk(int nf, const int* __restrict__ fptr, const int* __restrict__ face_edge,
+                               const int* __restrict__ edge_ptr, const int* __restrict__ edge_face,
+                               const int64_t* __restrict__ einv_ptr, const double* __restrict__ einv,
+                               const int* __restrict__ bptr, const int* __restrict__ bcol,
+                               double* __restrict__ Pval) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= (int64_t)nf * NFD) return;
+  const int f = (int)(r / NFD), beta = (int)(r - (int64_t)f * NFD);
+  const int b0 = bptr[f], b1 = bptr[f + 1];
+  for (int b = b0; b < b1; ++b) {
+    const int g = bcol[b];
+    double acc[NFD];
+#pragma unroll
+    for (int c = 0; c < NFD; ++c) acc[c] = 0.0;
+    for (int i = fptr[f]; i < fptr[f + 1]; ++i) {
+      const int e = face_edge[i];
+      const int* fe = edge_face + edge_ptr[e];
+      const int m = edge_ptr[e + 1] - edge_ptr[e];
+      int pf = 0, pg = -1;
+      for (int q = 0; q < m; ++q) {
+        if (fe[q] == f) pf = q;
+        if (fe[q] == g) pg = q;
+      }
+      if (pg < 0) continue;
+      const double* inv = einv + einv_ptr[e] + (int64_t)(pf * NFD + beta) * (m * NFD) + pg * NFD;
+#pragma unroll
+      for (int c = 0; c < NFD; ++c) acc[c] += inv[c];
+    }
+    double* out = Pval + ((int64_t)b * NFD + beta) * NFD;
+#pragma unroll
+    for (int c = 0; c < NFD; ++c) out[c] = acc[c];
+  }
+}
+
+// One block per edge on face blocks: each pair of the patch's faces copies its block of the face
+// system (one search in the block row), then the inverse as in k_edge_inv.
+__global__ void k_edge_inv_blk(int ne, int nfd, const int* __restrict__ edge_ptr, const int* __restrict__ edge_face,
+                               const int* __restrict__ bptr, const int* __restrict__ bcol,
+                               const double* __restrict__ Fval, const int64_t* __restrict__ einv_ptr,
+                               double* __restrict__ einv) {
+  extern __shared__ double sh[];
+  const int e = blockIdx.x;
+  if (e >= ne) return;
+  const int m = edge_ptr[e + 1] - edge_ptr[e], n = m * nfd;
+  const int* fe = edge_face + edge_ptr[e];
+  double* a = sh;
+  double* rk = sh + n * n;
+  double* ck = rk + n;
+  for (int t = threadIdx.x; t < m * m; t += blockDim.x) {
+    const int i = t / m, j = t - i * m;
+    const int fi = fe[i], fj = fe[j];
+    const int b0 = bptr[fi], nb = bptr[fi + 1] - b0;
+    const int k = lower_bound_i32(bcol + b0, nb, fj);
+    const double* blk = (k < nb && bcol[b0 + k] == fj) ? Fval + (int64_t)(b0 + k) * nfd * nfd : nullptr;
+    for (int bi = 0; bi < nfd; ++bi)
+      for (int c = 0; c < nfd; ++c) a[(i * nfd + bi) * n + j * nfd + c] = blk ? blk[bi * nfd + c] : 0.0;
+  }
+  gj_invert(a, rk, ck, n);
+  double* out = einv + einv_ptr[e];
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x) out[t] = a[t];
+}
+
 // Face-block pattern of an order-k face-DOF matrix from its CSR pattern: every row of face f must
 // list the same faces, each with all nfd columns in order (err otherwise).
 __global__ void k_blk_len(int nf, int nfd, const int* __restrict__ rowptr, int* __restrict__ len,
@@ -833,12 +899,36 @@ void schwarz_values(hipStream_t s, const SchwarzMesh& m, const DofLayout& L, con
   }
   const int n = X.max_patch * L.nfd;
   const size_t lds = ((size_t)n * n + 2 * n) * sizeof(double);
-  if (X.ne > 0)
+  if (X.ne > 0 && X.blocked)
+    k_edge_inv_blk<<<(int)X.ne, 64, lds, s>>>((int)X.ne, L.nfd, X.edge_ptr, X.edge_face, X.Fb.bptr, X.Fb.bcol, fval,
+                                               X.einv_ptr, X.einv);
+  else if (X.ne > 0)
     k_edge_inv<<<(int)X.ne, 64, lds, s>>>((int)X.ne, L.nfd, X.edge_ptr, X.edge_face, F.rowptr, F.col, fsl, fval,
                                            X.einv_ptr, X.einv);
   VEM_HIP(hipGetLastError());
-  k_p_values<<<grid(X.nF), kT, 0, s>>>(m.nf, L.nfd, m.fptr, X.face_edge, X.edge_ptr, X.edge_face, X.einv_ptr, X.einv,
-                                        X.Pc.rowptr, X.Pc.col, psl, pval);
+  if (X.blocked) {
+    const int* bp = X.Pb.bptr;
+    const int* bc = X.Pb.bcol;
+    switch (L.nfd) {
+      case 3:
+        k_p_values_blk<3><<<grid(X.nF), kT, 0, s>>>(m.nf, m.fptr, X.face_edge, X.edge_ptr, X.edge_face, X.einv_ptr,
+                                                     X.einv, bp, bc, pval);
+        break;
+      case 6:
+        k_p_values_blk<6><<<grid(X.nF), kT, 0, s>>>(m.nf, m.fptr, X.face_edge, X.edge_ptr, X.edge_face, X.einv_ptr,
+                                                     X.einv, bp, bc, pval);
+        break;
+      case 10:
+        k_p_values_blk<10><<<grid(X.nF), kT, 0, s>>>(m.nf, m.fptr, X.face_edge, X.edge_ptr, X.edge_face, X.einv_ptr,
+                                                      X.einv, bp, bc, pval);
+        break;
+      default:
+        throw Error{VEM_EINVAL, "face blocks of an unsupported size"};
+    }
+  } else {
+    k_p_values<<<grid(X.nF), kT, 0, s>>>(m.nf, L.nfd, m.fptr, X.face_edge, X.edge_ptr, X.edge_face, X.einv_ptr,
+                                          X.einv, X.Pc.rowptr, X.Pc.col, psl, pval);
+  }
   VEM_HIP(hipGetLastError());
   X.ready = true;
   X.ready32 = false;
