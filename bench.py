@@ -821,7 +821,7 @@ def main():
             "traffic": None,
             "avg_launch_us": val["avg_us"],
             "algorithmic_bytes_per_launch": val["bytes"],
-            "bytes_formula": "12 nnz(S) + 7 * 8 n_p",
+            "bytes_formula": "12 nnz(S) + 4 * 8 n_p",
         },
         "kernels": kern,
     }

@@ -1617,15 +1617,15 @@ vem_status vem_time_kernel(vem_handle h, int which, int reps, double* avg_ms, do
           VEM_HIP(hipEventRecord(e0, s));
           launch_cheb<float>(s, h->Ss, w, h->Vb, h->cheb.p, 1.0 / 400.0, reps, h->pcg);
           VEM_HIP(hipEventRecord(e1, s));
-          b = 8.0 * h->S.nnz + 4.0 * h->S.rows * 7.0;
+          b = 8.0 * h->S.nnz + 4.0 * h->S.rows * 4.0;
         } else {
           PcgWork w{h->xw.p, h->pr, h->pz, h->ps, h->pp, h->pw0, h->pw1, h->dSinv};
           launch_cheb<double>(s, h->Ss, w, h->Vb, h->cheb.p, 1.0 / 400.0, 2, h->pcg);
           VEM_HIP(hipEventRecord(e0, s));
           launch_cheb<double>(s, h->Ss, w, h->Vb, h->cheb.p, 1.0 / 400.0, reps, h->pcg);
           VEM_HIP(hipEventRecord(e1, s));
-          // S once; d gathered; D^{-1} read; r and x read and written; the next d written
-          b = 12.0 * h->S.nnz + 8.0 * h->S.rows * 7.0;
+          // S D^{-1} once; the iterate gathered; the previous iterate and b read; the next written
+          b = 12.0 * h->S.nnz + 8.0 * h->S.rows * 4.0;
         }
       } else if (schwarz) {
         const DofLayout L = h->L;

@@ -199,51 +199,57 @@ void pcg_iter_sel(hipStream_t s, int i, const Sell& A, SellViewT<T> Av, const Pc
 }
 
 // ---- inner Chebyshev-Jacobi: a fixed polynomial in D^{-1}A, no reductions ----------------------
-// Chebyshev iteration for D^{-1}A x = D^{-1}b on [lo, hi] = [c hi, hi], from x = 0:
-//   d_0 = D^{-1}b / theta,  x_{k+1} = x_k + d_k,  r_{k+1} = r_k - A d_k,
-//   rho_{k+1} = 1 / (2 sigma - rho_k),  d_{k+1} = rho_{k+1} rho_k d_k + (2 rho_{k+1} / delta) D^{-1} r_{k+1},
-// theta = (hi + lo) / 2, delta = (hi - lo) / 2, sigma = theta / delta, rho_0 = 1 / sigma.  The
-// rho_k depend on c only, so the host forms every coefficient in units of 1/hi, and the kernels
-// scale them by the device-resident 1/hi (the Gershgorin bound of D^{-1}A, taken when the values
-// are built): nothing is read back.  The last product's kernel also adds d_m, so m products give
-// x_{m+1}, a polynomial of degree m in D^{-1}A applied to D^{-1}b.  d alternates between two
-// buffers (neighbours gather it while its owner writes the next one).
-template <typename T>
-__global__ void __launch_bounds__(1024) k_cheb_init(int64_t n, const double* __restrict__ b,
-                                                    const T* __restrict__ dinv, T* __restrict__ d,
-                                                    const double* __restrict__ inv_hi, double c0, PcgState* st,
-                                                    int m) {
-  const T c = (T)(c0 * inv_hi[0]);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    d[i] = c * dinv[i] * (T)b[i];
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+// Chebyshev iteration for D^{-1}A x = D^{-1}b on [lo, hi] = [c hi, hi], from x = 0: with
+// theta = (hi + lo) / 2, delta = (hi - lo) / 2, sigma = theta / delta, rho_0 = 1 / sigma and
+// rho_{k+1} = 1 / (2 sigma - rho_k), the iterates satisfy x_1 = D^{-1}b / theta and
+//   x_{k+2} = x_{k+1} + rho_{k+1} rho_k (x_{k+1} - x_k) + (2 rho_{k+1} / delta) D^{-1}(b - A x_{k+1}).
+// The kernels run it in y = D x, on the column-scaled values A D^{-1} (the same spectrum):
+//   y_1 = b / theta,  y_{k+2} = y_{k+1} + c1_k (y_{k+1} - y_k) + c2_k (b - A D^{-1} y_{k+1}),
+// and the last product writes x = D^{-1} y.  A product gathers one vector (y_{k+1}) and reads y_k and
+// b at its own row; y_{k+2} overwrites y_k (each row reads and writes only its own entry of that
+// buffer), so the two iterates alternate between two buffers, and D^{-1} is read by the last product
+// only.  The residual is formed from the iterate at every step rather than carried.  The rho_k
+// depend on c only, so the host forms every coefficient in units of 1/hi, and the kernels scale them
+// by the device-resident 1/hi (the Gershgorin bound of D^{-1}A, taken when the values are built):
+// nothing is read back.  m products give x_{m+1}, a polynomial of degree m in D^{-1}A applied to
+// D^{-1}b.  The first product also sets the inner-solve counters (no separate start kernel).
+template <typename T, bool kShort, bool kFirst, bool kLast>
+__global__ void __launch_bounds__(1024) k_cheb_iter(SellViewT<T> Acs, const T* __restrict__ dinv,
+                                                    const double* __restrict__ b, T* __restrict__ bT,
+                                                    const T* __restrict__ ycur, T* yprev, T* yout,
+                                                    T* __restrict__ x,
+                                                    const double* __restrict__ inv_hi, double c0u, double c1,
+                                                    double c2u, PcgState* st, int m) {
+  const T c2 = (T)(c2u * inv_hi[0]), t1 = (T)c1;
+  if (kFirst && blockIdx.x == 0 && threadIdx.x == 0) {
     st->count = m;
     st->total += m;
     st->done = 0;
   }
-}
-
-template <typename T, bool kShort, bool kFirst, bool kLast>
-__global__ void __launch_bounds__(1024) k_cheb_iter(SellViewT<T> A, const T* __restrict__ dinv,
-                                                    const double* __restrict__ b, T* __restrict__ x,
-                                                    T* __restrict__ r, const T* __restrict__ dold,
-                                                    T* __restrict__ dnew, const double* __restrict__ inv_hi,
-                                                    double c1, double c2u) {
-  const T c2 = (T)(c2u * inv_hi[0]), t1 = (T)c1;
-  for (int64_t row = xcd_block() * blockDim.x + threadIdx.x; row < A.rows;
+  for (int64_t row = xcd_block() * blockDim.x + threadIdx.x; row < Acs.rows;
        row += (int64_t)gridDim.x * blockDim.x) {
-    const T ad = sell_row<kShort>(A, row, dold);
-    const T di = dold[row];
-    const T rn = (kFirst ? (T)b[row] : r[row]) - ad;
-    const T dn = t1 * di + c2 * dinv[row] * rn;
-    const T xo = kFirst ? T(0) : x[row];
-    if (kLast) {
-      x[row] = xo + di + dn;
+    T yn;
+    if constexpr (kFirst) {
+      // y_1 = c0 b and y_0 = 0, with A D^{-1} y_1 = c0 (A D^{-1} b)
+      const T c0 = (T)(c0u * inv_hi[0]);
+      const T ab = sell_row<kShort>(Acs, row, b);
+      const T bi = (T)b[row];
+      const T y1 = c0 * bi;
+      yn = y1 + t1 * y1 + c2 * (bi - c0 * ab);
+      if (!kLast) {
+        yprev[row] = y1;
+        if (bT) bT[row] = bi;
+      }
     } else {
-      x[row] = xo + di;
-      r[row] = rn;
-      dnew[row] = dn;
+      const T ay = sell_row<kShort>(Acs, row, ycur);
+      const T yj = ycur[row], yp = yprev[row];
+      const T bi = bT ? bT[row] : (T)b[row];
+      yn = yj + t1 * (yj - yp) + c2 * (bi - ay);
     }
+    if constexpr (kLast)
+      x[row] = dinv[row] * yn;
+    else
+      yout[row] = yn;
   }
 }
 
@@ -295,18 +301,23 @@ __global__ void __launch_bounds__(256) k_gersh_final(int nparts, const double* _
 }
 
 template <typename T, bool kShort>
-void cheb_iter_as(hipStream_t s, int k, int m, SellViewT<T> Av, const T* dinv, const double* b, T* x, T* r,
-                  const T* dold, T* dnew, const double* inv_hi, double c1, double c2u) {
-  const int G = pcg_grid(Av.rows, 1024);
+void cheb_iter_as(hipStream_t s, int k, int m, SellViewT<T> Acs, const T* dinv, const double* b, T* bT,
+                  const T* ycur, T* yprev, T* yout, T* x, const double* inv_hi, double c0u, double c1, double c2u,
+                  PcgState* st) {
+  const int G = pcg_grid(Acs.rows, 1024);
   const bool first = k == 0, last = k == m - 1;
   if (first && last)
-    k_cheb_iter<T, kShort, true, true><<<G, 1024, 0, s>>>(Av, dinv, b, x, r, dold, dnew, inv_hi, c1, c2u);
+    k_cheb_iter<T, kShort, true, true><<<G, 1024, 0, s>>>(Acs, dinv, b, bT, ycur, yprev, yout, x, inv_hi, c0u, c1,
+                                                          c2u, st, m);
   else if (first)
-    k_cheb_iter<T, kShort, true, false><<<G, 1024, 0, s>>>(Av, dinv, b, x, r, dold, dnew, inv_hi, c1, c2u);
+    k_cheb_iter<T, kShort, true, false><<<G, 1024, 0, s>>>(Acs, dinv, b, bT, ycur, yprev, yout, x, inv_hi, c0u, c1,
+                                                           c2u, st, m);
   else if (last)
-    k_cheb_iter<T, kShort, false, true><<<G, 1024, 0, s>>>(Av, dinv, b, x, r, dold, dnew, inv_hi, c1, c2u);
+    k_cheb_iter<T, kShort, false, true><<<G, 1024, 0, s>>>(Acs, dinv, b, bT, ycur, yprev, yout, x, inv_hi, c0u, c1,
+                                                           c2u, st, m);
   else
-    k_cheb_iter<T, kShort, false, false><<<G, 1024, 0, s>>>(Av, dinv, b, x, r, dold, dnew, inv_hi, c1, c2u);
+    k_cheb_iter<T, kShort, false, false><<<G, 1024, 0, s>>>(Acs, dinv, b, bT, ycur, yprev, yout, x, inv_hi, c0u,
+                                                            c1, c2u, st, m);
 }
 
 }  // namespace
@@ -315,22 +326,27 @@ template <typename T>
 void launch_cheb(hipStream_t s, const Sell& A, const PcgWorkT<T>& w, const double* b, const double* inv_hi,
                  double c, int m, PcgState* st) {
   VEM_REQUIRE(c > 0.0 && c < 1.0 && m >= 1, VEM_EINVAL, "Chebyshev interval or degree out of range");
-  SellViewT<T> Av = std::is_same<T, float>::value ? SellViewT<T>{A.rows, A.slice_ptr, A.slice_len, A.col,
-                                                                 (const T*)(const void*)A.val32.p}
-                                                  : SellViewT<T>{A.rows, A.slice_ptr, A.slice_len, A.col,
-                                                                 (const T*)(const void*)A.val.p};
+  const T* vcs = std::is_same<T, float>::value ? (const T*)(const void*)A.val32_cs.p : (const T*)(const void*)A.val_cs.p;
+  VEM_REQUIRE(vcs != nullptr, VEM_EINVAL, "Chebyshev inner solve without the column-scaled values");
+  const SellViewT<T> Acs{A.rows, A.slice_ptr, A.slice_len, A.col, vcs};
+  // b rounded to T once (FP32), or read in FP64 where T is double
+  T* bT = std::is_same<T, float>::value ? w.r : nullptr;
   const double sigma = (1.0 + c) / (1.0 - c);
+  const double c0u = 2.0 / (1.0 + c);  // 1 / theta, theta = hi (1 + c) / 2
   double rho = 1.0 / sigma;
-  // d_0 = D^{-1} b / theta, theta = hi (1 + c) / 2
-  k_cheb_init<T><<<pcg_grid(A.rows, 1024), 1024, 0, s>>>(A.rows, b, w.dinv, w.p, inv_hi, 2.0 / (1.0 + c), st, m);
-  T* dbuf[2] = {w.p, w.s};
+  T* ybuf[2] = {w.p, w.s};
+  const bool short_rows = A.max_len <= kShortRow && A.rows <= kPcgMaxThreads;
   for (int k = 0; k < m; ++k) {
     const double rho1 = 1.0 / (2.0 * sigma - rho);
     const double c1 = rho1 * rho, c2u = 4.0 * rho1 / (1.0 - c);  // 2 rho_{k+1} / delta, delta = hi (1 - c) / 2
-    if (A.max_len <= kShortRow && A.rows <= kPcgMaxThreads)
-      cheb_iter_as<T, true>(s, k, m, Av, w.dinv, b, w.x, w.r, dbuf[k & 1], dbuf[(k + 1) & 1], inv_hi, c1, c2u);
+    // after product k, y_{k+2} is in ybuf[k & 1] and y_{k+1} in ybuf[(k + 1) & 1]
+    const T* ycur = k == 0 ? nullptr : ybuf[(k + 1) & 1];
+    T* yprev = k == 0 ? ybuf[1] : ybuf[k & 1];
+    T* yout = ybuf[k & 1];
+    if (short_rows)
+      cheb_iter_as<T, true>(s, k, m, Acs, w.dinv, b, bT, ycur, yprev, yout, w.x, inv_hi, c0u, c1, c2u, st);
     else
-      cheb_iter_as<T, false>(s, k, m, Av, w.dinv, b, w.x, w.r, dbuf[k & 1], dbuf[(k + 1) & 1], inv_hi, c1, c2u);
+      cheb_iter_as<T, false>(s, k, m, Acs, w.dinv, b, bT, ycur, yprev, yout, w.x, inv_hi, c0u, c1, c2u, st);
     rho = rho1;
   }
 }

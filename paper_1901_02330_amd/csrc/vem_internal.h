@@ -313,8 +313,9 @@ void launch_pcg_init32p(hipStream_t s, const Sell& A, const PcgWork32& w, const 
                         int maxit, double* part);
 void launch_pcg_iter32p(hipStream_t s, int i, const Sell& A, const PcgWork32& w, PcgState* st, double* part);
 void launch_to_f64(hipStream_t s, int64_t n, const float* x, double* y);
-// Chebyshev-Jacobi inner solve: m products, interval [c hi, hi] with 1/hi at inv_hi (device);
-// x (FP64: w.x; FP32: w.x rounded), uses w.r, w.p, w.s; adds m to st->total
+// Chebyshev-Jacobi inner solve: m products, interval [c hi, hi] with 1/hi at inv_hi (device), on the
+// column-scaled values (val_cs, FP32: val32_cs) and w.dinv; x (FP64: w.x; FP32: w.x rounded); the
+// iterates alternate in w.p and w.s, and FP32 keeps b rounded in w.r; adds m to st->total
 template <typename T>
 void launch_cheb(hipStream_t s, const Sell& A, const PcgWorkT<T>& w, const double* b, const double* inv_hi,
                  double c, int m, PcgState* st);
