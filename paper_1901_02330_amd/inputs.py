@@ -257,8 +257,11 @@ class SineSolution:
 
     @staticmethod
     def p(x):
+        # sin(pi x_d) for the three coordinates in one pass over the (n, 3) points, then their product
         L = _lib(x)
-        return L.sin(math.pi * x[..., 0]) * L.sin(math.pi * x[..., 1]) * L.sin(math.pi * x[..., 2])
+        s = math.pi * x
+        L.sin(s, out=s)
+        return s[..., 0] * s[..., 1] * s[..., 2]
 
     @staticmethod
     def f(x):
