@@ -68,6 +68,9 @@ def parse():
     ap.add_argument("--voronoi-checkerboard", action="store_true",
                     help="also solve the mixed-precision workload: Random Voronoi 20,000 cells, the paper's k = 2, "
                          "checkerboard K in {1e-3, 1e3}, Block-Reg with FP32 and FP64 inner solves (minutes)")
+    ap.add_argument("--k2-fields-only", type=int, default=0, metavar="FIELDS",
+                    help="run only the batched order-2 workload (FIELDS fields on Cube 32^3 through "
+                         "vem_solve_batch), print its JSON and exit (for kernel traces)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=0, help="Cube size of the CPU oracle run (default: the workload's)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
@@ -705,6 +708,9 @@ def main():
     mesh = cube_mesh(n)
     if args.pmc_probe:
         pmc_probe(mesh, n)
+        return
+    if args.k2_fields_only > 0:
+        print(json.dumps({"batch_cube32_k2": k2_fields(args, torch, dev, args.k2_fields_only)}), flush=True)
         return
     # inputs resident in HBM before the timed region
     mdev = {k: torch.as_tensor(mesh[k]).to(dev) for k in
