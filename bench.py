@@ -573,6 +573,25 @@ def extras(args, torch, dev):
     return out
 
 
+def copy_ceiling(torch, nbytes, reps=200):
+    """Rate of a plain device copy that moves the same bytes (half read, half written), timed like the
+    kernels (events around `reps` back-to-back copies on torch's stream): what a kernel with this
+    working set can reach on this part, beside the 8 TB/s peak."""
+    n = max(1, int(nbytes / 16))
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"copy_bytes": 16.0 * n, "copy_us": ms * 1e3, "gbs": 16.0 * n / (ms * 1e-3) / 1e9}
+
+
 def schwarz_rates(s, reps=100):
     """One Schwarz-CG iteration (both launches), FP64 and FP32: mean time over `reps` back-to-back
     iterations (HIP events), algorithmic bytes (every stored matrix entry, index and vector element
@@ -842,6 +861,12 @@ def main():
     if args.k2_batch > 0:
         log("k=2 batch ...")
         line.setdefault("extras", {})["batch_cube32_k2"] = k2_batch(args.k2_batch, torch, dev)
+    # the same-size plain copy beside each roofline figure
+    for obj in ("roofline", "roofline_value"):
+        nb = line[obj].get("algorithmic_bytes_per_iteration") or line[obj]["algorithmic_bytes_per_launch"]
+        cc = copy_ceiling(torch, nb)
+        cc["frac_of_copy"] = line[obj]["achieved"] / cc["gbs"]
+        line[obj]["copy_ceiling"] = cc
     tr = traffic_from_profiles()
     if tr is not None:
         for key, obj in (("traffic", "roofline"), ("traffic_value", "roofline_value")):

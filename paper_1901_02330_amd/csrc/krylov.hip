@@ -392,12 +392,12 @@ __global__ void __launch_bounds__(kBlock) k_scg_prod(int k, V F, const T* __rest
   int64_t row = xcd_block() * blockDim.x + threadIdx.x;
   T fz = T(0), zi = T(0), po = T(0), qo = T(0);
   auto load = [&](int64_t i) {
-    fz = mat_row(F, i, z);
     zi = z[i];
     if (k > 0) {
       po = p[i];
       qo = q[i];
     }
+    fz = mat_row(F, i, z);
   };
   if (row < F.rows) load(row);
   const int was_done = st->done;
@@ -438,12 +438,12 @@ __global__ void __launch_bounds__(kBlock) k_scg_update(int k, V P, T* __restrict
   int64_t row = xcd_block() * blockDim.x + threadIdx.x;
   T pq_r = T(0), qi = T(0), ri = T(0), zi = T(0), xi = T(0), pi = T(0);
   auto load = [&](int64_t i) {
-    pq_r = mat_row(P, i, q);
     qi = q[i];
     ri = r[i];
     zi = z[i];
     xi = x[i];
     pi = p[i];
+    pq_r = mat_row(P, i, q);
   };
   if (row < P.rows) load(row);
   const int was_done = st->done;

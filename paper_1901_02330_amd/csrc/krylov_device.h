@@ -119,11 +119,20 @@ using SellView = SellViewT<double>;
 
 inline SellView view(const Sell& A) { return {A.rows, A.slice_ptr, A.slice_len, A.col, A.val}; }
 
-// Whole waves share a slice because every block size here is a multiple of 64.
+// Whole waves share a slice because every block size here is a multiple of 64 and every kernel
+// gives a wave 64 consecutive rows from a multiple of 64.  The slice index is therefore the same on
+// all lanes: taken from the first active lane it sits in scalar registers, and the slice's offset and
+// length arrive through scalar loads, ahead of the vector loads that depend on them.
+__device__ inline int64_t wave_uniform(int64_t v) {
+  const int lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 // The product is formed in the matrix's precision T from x of type X.
 template <typename T, typename X>
 __device__ inline T sell_dot(const SellViewT<T>& A, int64_t row, const X* __restrict__ x) {
-  const int64_t s = row >> 6;
+  const int64_t s = wave_uniform(row >> 6);
   const int64_t base = A.slice_ptr[s] + (row & 63);
   const int len = A.slice_len[s];
   T acc = T(0);
@@ -134,26 +143,26 @@ __device__ inline T sell_dot(const SellViewT<T>& A, int64_t row, const X* __rest
 
 // The same product for slices of at most kShortRow entries: all column and value loads are
 // issued first, then all gathers, so a row costs two memory round trips instead of a chain
-// per entry.  The tests on the slice length are uniform over the wave, and the sum is formed
-// in the same order (same bits).
+// per entry.  The loads take no branches (slots past the slice's length reload its first slot,
+// a cache hit, so every address is valid), which lets every load of the row be in flight at
+// once; only the sum skips those slots, in the same order as the loop above (same bits).
 constexpr int kShortRow = 8;
 template <typename T, typename X>
 __device__ inline T sell_dot_short(const SellViewT<T>& A, int64_t row, const X* __restrict__ x) {
-  const int64_t s = row >> 6;
+  const int64_t s = wave_uniform(row >> 6);
   const int64_t base = A.slice_ptr[s] + (row & 63);
   const int len = A.slice_len[s];
   int c[kShortRow];
   T v[kShortRow];
 #pragma unroll
-  for (int u = 0; u < kShortRow; ++u)
-    if (u < len) {
-      c[u] = A.col[base + 64 * u];
-      v[u] = A.val[base + 64 * u];
-    }
+  for (int u = 0; u < kShortRow; ++u) {
+    const int64_t at = base + 64 * (u < len ? u : 0);
+    c[u] = A.col[at];
+    v[u] = A.val[at];
+  }
   X g[kShortRow];
 #pragma unroll
-  for (int u = 0; u < kShortRow; ++u)
-    if (u < len) g[u] = x[c[u]];
+  for (int u = 0; u < kShortRow; ++u) g[u] = x[c[u]];
   T acc = T(0);
 #pragma unroll
   for (int u = 0; u < kShortRow; ++u)

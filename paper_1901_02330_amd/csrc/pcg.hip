@@ -232,8 +232,8 @@ __global__ void __launch_bounds__(1024) k_cheb_iter(SellViewT<T> Acs, const T* _
     if constexpr (kFirst) {
       // y_1 = c0 b and y_0 = 0, with A D^{-1} y_1 = c0 (A D^{-1} b)
       const T c0 = (T)(c0u * inv_hi[0]);
-      const T ab = sell_row<kShort>(Acs, row, b);
       const T bi = (T)b[row];
+      const T ab = sell_row<kShort>(Acs, row, b);
       const T y1 = c0 * bi;
       yn = y1 + t1 * y1 + c2 * (bi - c0 * ab);
       if (!kLast) {
@@ -241,9 +241,10 @@ __global__ void __launch_bounds__(1024) k_cheb_iter(SellViewT<T> Acs, const T* _
         if (bT) bT[row] = bi;
       }
     } else {
-      const T ay = sell_row<kShort>(Acs, row, ycur);
+      // the row's own entries first: their loads overlap the product's
       const T yj = ycur[row], yp = yprev[row];
       const T bi = bT ? bT[row] : (T)b[row];
+      const T ay = sell_row<kShort>(Acs, row, ycur);
       yn = yj + t1 * (yj - yp) + c2 * (bi - ay);
     }
     if constexpr (kLast)
