@@ -350,7 +350,9 @@ enum { VEM_KERNEL_SPMV = 0, VEM_KERNEL_CG_SCHUR = 1, VEM_KERNEL_CG_REG = 2, VEM_
        VEM_KERNEL_CHEB_SCHUR32 = 10 };
 
 /* Measurement hook for benchmarks: time `reps` back-to-back launches of one
- * hot kernel with HIP events recorded on the handle's stream.
+ * hot kernel with HIP events recorded on the handle's stream (the Chebyshev
+ * products: each launch with start and stop events of its own, so that the
+ * mean is the kernels' own time, without the dispatch gaps between launches).
  *   VEM_KERNEL_SPMV:     the saddle product y = K x;
  *   VEM_KERNEL_CG_SCHUR: one pipelined inner-CG iteration on S (Block-Schur);
  *   VEM_KERNEL_CG_REG:   one pipelined inner-CG iteration on M + B^T B / gamma;

@@ -3,6 +3,10 @@
 #include <algorithm>
 #include <type_traits>
 
+#include <hip/hip_ext.h>
+
+#include <vector>
+
 #include "krylov_device.h"
 
 namespace vem {
@@ -351,6 +355,65 @@ void launch_cheb(hipStream_t s, const Sell& A, const PcgWorkT<T>& w, const doubl
     rho = rho1;
   }
 }
+// Mean duration (ms) of `reps` Chebyshev products of the middle form (the form of every product of a
+// solve but its first and last), each launched with start and stop events of its own: the kernels'
+// own time, without the dispatch gaps between back-to-back launches.  A degree-2 solve sets up the
+// two iterates first; the timed products continue its recurrence.
+template <typename T>
+double time_cheb_products(hipStream_t s, const Sell& A, const PcgWorkT<T>& w, const double* b,
+                          const double* inv_hi, double c, int reps, PcgState* st) {
+  VEM_REQUIRE(reps >= 1, VEM_EINVAL, "at least one timed product");
+  launch_cheb<T>(s, A, w, b, inv_hi, c, 2, st);
+  const T* vcs = std::is_same<T, float>::value ? (const T*)(const void*)A.val32_cs.p : (const T*)(const void*)A.val_cs.p;
+  const SellViewT<T> Acs{A.rows, A.slice_ptr, A.slice_len, A.col, vcs};
+  T* bT = std::is_same<T, float>::value ? w.r : nullptr;
+  const double sigma = (1.0 + c) / (1.0 - c), c0u = 2.0 / (1.0 + c);
+  double rho = 1.0 / sigma;
+  rho = 1.0 / (2.0 * sigma - rho);  // the degree-2 solve's two steps
+  rho = 1.0 / (2.0 * sigma - rho);
+  const bool short_rows = A.max_len <= kShortRow && A.rows <= kPcgMaxThreads;
+  const int G = pcg_grid(Acs.rows, 1024);
+  std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
+  double total = 0.0;
+  try {
+    for (auto& e : ev) VEM_HIP(hipEventCreate(&e));
+    T* ybuf[2] = {w.p, w.s};
+    for (int r = 0; r < reps; ++r) {
+      const int k = r + 1;  // after the set-up, y_2 is in ybuf[0] and y_1 in ybuf[1]
+      const double rho1 = 1.0 / (2.0 * sigma - rho);
+      const double c1 = rho1 * rho, c2u = 4.0 * rho1 / (1.0 - c);
+      rho = rho1;
+      const T* ycur = ybuf[(k + 1) & 1];
+      T* ynext = ybuf[k & 1];
+      if (short_rows)
+        hipExtLaunchKernelGGL(k_cheb_iter<T, true, false, false>, dim3(G), dim3(1024), 0, s, ev[2 * r],
+                              ev[2 * r + 1], 0, Acs, (const T*)w.dinv, b, bT, ycur, ynext, ynext, w.x, inv_hi, c0u,
+                              c1, c2u, st, reps);
+      else
+        hipExtLaunchKernelGGL(k_cheb_iter<T, false, false, false>, dim3(G), dim3(1024), 0, s, ev[2 * r],
+                              ev[2 * r + 1], 0, Acs, (const T*)w.dinv, b, bT, ycur, ynext, ynext, w.x, inv_hi, c0u,
+                              c1, c2u, st, reps);
+      VEM_HIP(hipGetLastError());
+    }
+    VEM_HIP(hipEventSynchronize(ev.back()));
+    for (int r = 0; r < reps; ++r) {
+      float ms = 0.f;
+      VEM_HIP(hipEventElapsedTime(&ms, ev[2 * r], ev[2 * r + 1]));
+      total += ms;
+    }
+  } catch (...) {
+    for (auto e : ev)
+      if (e) (void)hipEventDestroy(e);
+    throw;
+  }
+  for (auto e : ev) (void)hipEventDestroy(e);
+  return total / reps;
+}
+template double time_cheb_products<double>(hipStream_t, const Sell&, const PcgWorkT<double>&, const double*,
+                                           const double*, double, int, PcgState*);
+template double time_cheb_products<float>(hipStream_t, const Sell&, const PcgWorkT<float>&, const double*,
+                                          const double*, double, int, PcgState*);
+
 template void launch_cheb<double>(hipStream_t, const Sell&, const PcgWorkT<double>&, const double*, const double*,
                                   double, int, PcgState*);
 template void launch_cheb<float>(hipStream_t, const Sell&, const PcgWorkT<float>&, const double*, const double*,

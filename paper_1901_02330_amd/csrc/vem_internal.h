@@ -319,6 +319,11 @@ void launch_to_f64(hipStream_t s, int64_t n, const float* x, double* y);
 template <typename T>
 void launch_cheb(hipStream_t s, const Sell& A, const PcgWorkT<T>& w, const double* b, const double* inv_hi,
                  double c, int m, PcgState* st);
+// mean kernel time (ms) of reps middle-form Chebyshev products, each timed by its own start and stop
+// events (after a degree-2 solve that sets up the iterates; synchronises)
+template <typename T>
+double time_cheb_products(hipStream_t s, const Sell& A, const PcgWorkT<T>& w, const double* b,
+                          const double* inv_hi, double c, int reps, PcgState* st);
 // inv_hi[0] = 1 / (Gershgorin bound of D^{-1}A); part holds up to 1024 doubles
 void launch_gershgorin(hipStream_t s, const Sell& A, const double* dinv, double* part, double* inv_hi);
 
