@@ -512,7 +512,8 @@ def extras(args, torch, dev):
                         "solve_s": time.perf_counter() - t0, "relres": info["relres"]}
     out[f"cube{args.n}_lo_flux"] = fl
     s.close()
-    # the paper's element on the paper's Cube meshes (Table 1: 32^3 at k = 1, 24^3 at k = 2), nu = 1,
+    # the paper's element on the paper's Cube meshes (Table 1: 32^3 at k = 1, 24^3 at k = 2, 20^3 at
+    # k = 3), nu = 1,
     # the paper's polynomial solution, with the paper's boundary data (flux, zero-mean pressure; its
     # counts carry one more unknown, the multiplier of the mean) and with pressure data.  The paper
     # does not state its GMRES tolerance or restart: iteration counts are context.
@@ -521,7 +522,10 @@ def extras(args, torch, dev):
     paper = {(32, 1): {"dofs": 435201, "T_ass_p1_s": 68, "T_ass_p32_s": 3, "schur_its": 66, "schur_T_sol_p1_s": 50,
                        "schur_T_sol_p32_s": 9, "reg_its_p1": 84, "reg_T_sol_p1_s": 53, "reg_T_sol_p32_s": 26},
              (24, 2): {"dofs": 508033, "T_ass_p1_s": 271, "T_ass_p32_s": 13, "schur_its": 72, "schur_T_sol_p1_s": 347,
-                       "schur_T_sol_p32_s": 40, "reg_its_p1": 98, "reg_T_sol_p1_s": 138, "reg_T_sol_p32_s": 58}}
+                       "schur_T_sol_p32_s": 40, "reg_its_p1": 98, "reg_T_sol_p1_s": 138, "reg_T_sol_p32_s": 58},
+             # k = 3: the paper's smallest run is on 4 processes
+             (20, 3): {"dofs": 612001, "T_ass_p4_s": 623, "T_ass_p32_s": 97, "schur_its": 147, "schur_T_sol_p4_s": 570,
+                       "schur_T_sol_p32_s": 192, "reg_its_p4": 720, "reg_T_sol_p4_s": 450, "reg_T_sol_p32_s": 197}}
     tab = {}
     for (nn, k), ref in paper.items():
       for bc in ("flux", "pressure"):
@@ -536,7 +540,11 @@ def extras(args, torch, dev):
             torch.cuda.synchronize()
             t_ass = time.perf_counter() - t0
         row = {"boundary_data": bc, "n_unknowns": s.sizes()["n"], "assembly_s": t_ass}
-        for prec, kw in (("schur", dict(inner_tol=1e-8, inner_maxit=2000)), ("reg", dict(inner_tol=1e-1))):
+        precs = (("schur", dict(inner_tol=1e-8, inner_maxit=2000)), ("reg", dict(inner_tol=1e-1)))
+        if k == 3 and bc == "pressure":
+            # Block-Schur with diag(M) does not reach 1e-8 in 3,000 iterations here (about a minute)
+            precs = precs[1:]
+        for prec, kw in precs:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             _, _, info = s.solve(prec, tol=1e-8, maxit=3000, **kw)
