@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--k2-fields-only", type=int, default=0, metavar="FIELDS",
                     help="run only the batched order-2 workload (FIELDS fields on Cube 32^3 through "
                          "vem_solve_batch), print its JSON and exit (for kernel traces)")
+    ap.add_argument("--voronoi-sweep", action="store_true",
+                    help="also run the order-2 sweep on Random Voronoi meshes of 1,000 to 16,000 cells, flux data (minutes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=0, help="Cube size of the CPU oracle run (default: the workload's)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
@@ -688,6 +690,36 @@ def voronoi_checkerboard(torch, dev):
     return out
 
 
+def voronoi_sweep(torch, dev):
+    """The optimality trend on Random Voronoi meshes (the paper's sweep is on CVT meshes, whose recipe it
+    does not give): the paper's k = 2, nu = 1, its polynomial solution with its flux data, 1,000 to
+    16,000 seeded uniform points; Block-Reg (Schwarz-CG to 0.1) and Block-Schur (inner CG to 1e-8)."""
+    from paper_1901_02330_amd.inputs import PolynomialSolution, voronoi_mesh
+    from paper_1901_02330_amd.vem import Solver
+
+    out = {}
+    for cells in (1000, 2000, 4000, 8000, 16000):
+        m = voronoi_mesh(cells, seed=0)
+        s = Solver()
+        s.set_mesh(m)
+        s.set_boundary("flux")
+        s.discretize("paper", k=2)
+        s.set_rhs_functions(PolynomialSolution.f, PolynomialSolution.u)
+        row = {"n_unknowns": s.sizes()["n"]}
+        for prec, kw in (("reg", dict(inner_tol=1e-1)), ("schur", dict(inner_tol=1e-8, inner_maxit=2000))):
+            s.solve(prec, tol=1e-8, maxit=3000, **kw)  # warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, _, info = s.solve(prec, tol=1e-8, maxit=3000, **kw)
+            torch.cuda.synchronize()
+            row[prec] = {"iterations": info["iterations"], "inner_iterations": info["inner_iterations"],
+                         "solve_s": time.perf_counter() - t0, "converged": info["converged"]}
+        log(f"voronoi {cells}: {row}")
+        out[f"voronoi{cells}_k2_flux"] = row
+        s.close()
+    return out
+
+
 def k2_batch(fields, torch, dev):
     """Fields seeds 0..fields-1 (log K = 1.5 N(0,1)) on the Cube 32^3 mesh, the paper's k = 2, Block-Reg
     with FP32 inner solves to 1e-8: one lane (sequential) and `fields` concurrent lanes."""
@@ -866,6 +898,9 @@ def main():
     if args.voronoi_checkerboard:
         log("voronoi checkerboard ...")
         line.setdefault("extras", {})["voronoi20k_k2_checkerboard"] = voronoi_checkerboard(torch, dev)
+    if args.voronoi_sweep:
+        log("voronoi sweep ...")
+        line.setdefault("extras", {})["voronoi_sweep_k2_flux"] = voronoi_sweep(torch, dev)
     if args.k2_batch > 0:
         log("k=2 batch ...")
         line.setdefault("extras", {})["batch_cube32_k2"] = k2_batch(args.k2_batch, torch, dev)
