@@ -725,18 +725,20 @@ void schwarz_inner(vem_handle h, const vem_solve_opts& o, const double* v, doubl
   const Sell& F = schwarz_face_sell(X, h->As, L);
   const SchwarzMesh m = schwarz_mesh(h);
   const int* bnd = h->bc == VEM_BC_FLUX ? h->is_bnd.p : nullptr;
+  // iterations enqueued in chunks between polls: launches past convergence return at once
+  const bool polled = o.inner_maxit > kBlindInner;
   if (o.precision == VEM_MIXED) {
     PcgWork32 w{h->px32, (float*)h->pr.p, (float*)h->pz.p, (float*)h->ps.p, (float*)h->pp.p, (float*)h->pw0.p,
                 (float*)h->pw1.p, nullptr};
     launch_schwarz_rhs<float>(s, m, L, X, bnd, v, w.r);
     launch_scg_init<float>(s, X, w, h->pcg, o.inner_tol, h->pcgpart);
-    run_inner(h, o, h->expect_A, [&](int i) { launch_scg_iter<float>(s, i, F, X, w, h->pcg, h->pcgpart); });
+    run_inner(h, o, h->expect_A, [&](int i) { launch_scg_iter<float>(s, i, F, X, w, h->pcg, h->pcgpart, polled); });
     launch_to_f64(s, X.nF, h->px32, z);
   } else {
     PcgWork w{z, h->pr, h->pz, h->ps, h->pp, h->pw0, h->pw1, nullptr};
     launch_schwarz_rhs<double>(s, m, L, X, bnd, v, w.r);
     launch_scg_init<double>(s, X, w, h->pcg, o.inner_tol, h->pcgpart);
-    run_inner(h, o, h->expect_A, [&](int i) { launch_scg_iter<double>(s, i, F, X, w, h->pcg, h->pcgpart); });
+    run_inner(h, o, h->expect_A, [&](int i) { launch_scg_iter<double>(s, i, F, X, w, h->pcg, h->pcgpart, polled); });
   }
   if (L.nint > 0) launch_schwarz_back(s, m, L, X, v, z);
   check_launch();

@@ -383,9 +383,10 @@ __global__ void __launch_bounds__(kBlock) k_scg_init(V P, const T* __restrict__ 
 }
 
 template <typename T, int kBlock, typename V>
-__global__ void __launch_bounds__(kBlock) k_scg_prod(int k, V F, const T* __restrict__ z,
+__global__ void __launch_bounds__(kBlock) k_scg_prod(int k, int early, V F, const T* __restrict__ z,
                                                      T* __restrict__ p, T* __restrict__ q, PcgState* st,
                                                      const double* __restrict__ prho, double* __restrict__ ppq) {
+  if (early && st->done) return;
   const int G = gridDim.x;
   const int cur = k & 1;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -427,11 +428,12 @@ __global__ void __launch_bounds__(kBlock) k_scg_prod(int k, V F, const T* __rest
 }
 
 template <typename T, int kBlock, typename V>
-__global__ void __launch_bounds__(kBlock) k_scg_update(int k, V P, T* __restrict__ x,
+__global__ void __launch_bounds__(kBlock) k_scg_update(int k, int early, V P, T* __restrict__ x,
                                                        T* __restrict__ r, T* __restrict__ z,
                                                        const T* __restrict__ q, const T* __restrict__ p,
                                                        PcgState* st, double* __restrict__ prho,
                                                        const double* __restrict__ ppq) {
+  if (early && st->done) return;
   const int G = gridDim.x;
   const int cur = k & 1;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -702,19 +704,20 @@ void scg_init_as(hipStream_t s, const V& P, const PcgWorkT<T>& w, PcgState* st, 
 // work layout: x, r, z, p as named, w0 = q (s and w1 unused); the init's grid (same rows, same
 // block size) leaves the partials the first product kernel sums
 template <typename T, typename V>
-void scg_iter_as(hipStream_t s, int i, const V& F, const V& P, const PcgWorkT<T>& w, PcgState* st, double* part) {
+void scg_iter_as(hipStream_t s, int i, const V& F, const V& P, const PcgWorkT<T>& w, PcgState* st, double* part,
+                 int early) {
   if (F.rows > kPcgMaxThreads) {
     const int G = scg_grid<T, 256, V>(F.rows);
     double* prho = part;  // 2 x G slots
     double* ppq = part + 2 * (size_t)G;
-    k_scg_prod<T, 256><<<G, 256, 0, s>>>(i, F, w.z, w.p, w.w0, st, prho, ppq);
-    k_scg_update<T, 256><<<G, 256, 0, s>>>(i, P, w.x, w.r, w.z, w.w0, w.p, st, prho, ppq);
+    k_scg_prod<T, 256><<<G, 256, 0, s>>>(i, early, F, w.z, w.p, w.w0, st, prho, ppq);
+    k_scg_update<T, 256><<<G, 256, 0, s>>>(i, early, P, w.x, w.r, w.z, w.w0, w.p, st, prho, ppq);
   } else {
     const int G = scg_grid<T, 1024, V>(F.rows);
     double* prho = part;
     double* ppq = part + 2 * (size_t)G;
-    k_scg_prod<T, 1024><<<G, 1024, 0, s>>>(i, F, w.z, w.p, w.w0, st, prho, ppq);
-    k_scg_update<T, 1024><<<G, 1024, 0, s>>>(i, P, w.x, w.r, w.z, w.w0, w.p, st, prho, ppq);
+    k_scg_prod<T, 1024><<<G, 1024, 0, s>>>(i, early, F, w.z, w.p, w.w0, st, prho, ppq);
+    k_scg_update<T, 1024><<<G, 1024, 0, s>>>(i, early, P, w.x, w.r, w.z, w.w0, w.p, st, prho, ppq);
   }
 }
 
@@ -731,12 +734,13 @@ void launch_scg_init(hipStream_t s, const Schwarz& X, const PcgWorkT<T>& w, PcgS
 
 template <typename T>
 void launch_scg_iter(hipStream_t s, int i, const Sell& F, const Schwarz& X, const PcgWorkT<T>& w, PcgState* st,
-                     double* part) {
-  if (!X.blocked) return scg_iter_as<T>(s, i, values_view<T>(F), values_view<T>(X.Ps), w, st, part);
+                     double* part, bool early_exit) {
+  const int e = early_exit ? 1 : 0;
+  if (!X.blocked) return scg_iter_as<T>(s, i, values_view<T>(F), values_view<T>(X.Ps), w, st, part, e);
   switch (X.Pb.nfd) {
-    case 3: return scg_iter_as<T>(s, i, block_view<T, 3>(X.Fb), block_view<T, 3>(X.Pb), w, st, part);
-    case 6: return scg_iter_as<T>(s, i, block_view<T, 6>(X.Fb), block_view<T, 6>(X.Pb), w, st, part);
-    case 10: return scg_iter_as<T>(s, i, block_view<T, 10>(X.Fb), block_view<T, 10>(X.Pb), w, st, part);
+    case 3: return scg_iter_as<T>(s, i, block_view<T, 3>(X.Fb), block_view<T, 3>(X.Pb), w, st, part, e);
+    case 6: return scg_iter_as<T>(s, i, block_view<T, 6>(X.Fb), block_view<T, 6>(X.Pb), w, st, part, e);
+    case 10: return scg_iter_as<T>(s, i, block_view<T, 10>(X.Fb), block_view<T, 10>(X.Pb), w, st, part, e);
     default: throw Error{VEM_EINVAL, "face blocks of an unsupported size"};
   }
 }
@@ -746,8 +750,8 @@ template void launch_scg_init<double>(hipStream_t, const Schwarz&, const PcgWork
 template void launch_scg_init<float>(hipStream_t, const Schwarz&, const PcgWorkT<float>&, PcgState*, double,
                                      double*);
 template void launch_scg_iter<double>(hipStream_t, int, const Sell&, const Schwarz&, const PcgWorkT<double>&,
-                                      PcgState*, double*);
+                                      PcgState*, double*, bool);
 template void launch_scg_iter<float>(hipStream_t, int, const Sell&, const Schwarz&, const PcgWorkT<float>&,
-                                     PcgState*, double*);
+                                     PcgState*, double*, bool);
 
 }  // namespace vem

@@ -406,12 +406,14 @@ void launch_schwarz_back(hipStream_t s, const SchwarzMesh& m, const DofLayout& L
 //   [product] beta, stop test; p = z + beta p; q = F z + beta q; partials p.q
 //   [update]  alpha; x += alpha p; r -= alpha q; z -= alpha P q; partials r.z
 // Work layout: x, r, z, p, w0 = q.  T = double, or float with FP64 dot products.
-// F: the face system's SELL (schwarz_face_sell), used unless X.blocked.
+// F: the face system's SELL (schwarz_face_sell), used unless X.blocked.  early_exit: each kernel reads
+// the stop flag before anything else and returns at once when it is set (for iterations enqueued in
+// chunks between polls, where launches past convergence would otherwise load their first rows).
 template <typename T>
 void launch_scg_init(hipStream_t s, const Schwarz& X, const PcgWorkT<T>& w, PcgState* st, double tol, double* part);
 template <typename T>
 void launch_scg_iter(hipStream_t s, int i, const Sell& F, const Schwarz& X, const PcgWorkT<T>& w, PcgState* st,
-                     double* part);
+                     double* part, bool early_exit = false);
 
 // host utilities
 void gauss_jacobi01(int n, int alpha, double* t, double* w);  // int_0^1 (1-t)^alpha g(t) dt
