@@ -136,9 +136,9 @@ def summarize(prefix: str):
         out += ["", "The live timing loops (the last 200 launches of each roofline kernel, FP64):", "",
                 "| kernel | grid | mean us | median us |", "|---|---|---|---|"]
         pair = 0.0
-        for pref in ("k_scg_prod<double,", "k_scg_update<double,", "k_cheb_iter<double, true, false, false>",
-                     "k_cheb_iter<double, false, false, false>"):
-            it = [k for k in by if k[0].startswith(pref)]
+        # the Chebyshev product's middle variant, whatever its row form (fixed count, masked or loop)
+        for pref in ("k_scg_prod<double,", "k_scg_update<double,", r"k_cheb_iter<double, [^,]+, false, false>"):
+            it = [k for k in by if re.match(re.escape(pref) if pref.startswith("k_scg") else pref, k[0])]
             if not it:
                 continue
             key = max(it, key=lambda k: k[1])

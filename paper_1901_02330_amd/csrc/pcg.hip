@@ -42,7 +42,7 @@ struct PcgViewT {
 
 // w = (A D^{-1}) b, x = 0, r = b; partials of gamma_0, delta_0 (slot 0).  b is FP64 and is
 // rounded to T element by element (also where it is gathered).
-template <typename T, int kBlock, bool kShort>
+template <typename T, int kBlock, int kRow>
 __global__ void __launch_bounds__(kBlock) k_ppcg_init(SellViewT<T> Ac, PcgViewT<T> v,
                                                            const double* __restrict__ b, PcgState* st, double tol2,
                                                            int maxit, double* __restrict__ part) {
@@ -50,7 +50,7 @@ __global__ void __launch_bounds__(kBlock) k_ppcg_init(SellViewT<T> Ac, PcgViewT<
   for (int64_t row = xcd_block() * blockDim.x + threadIdx.x; row < Ac.rows;
        row += (int64_t)gridDim.x * blockDim.x) {
     const T bi = (T)b[row], di = v.dinv[row];
-    const T wi = sell_row<kShort>(Ac, row, b);
+    const T wi = sell_row<kRow>(Ac, row, b);
     v.x[row] = T(0);
     v.r[row] = bi;
     v.w0[row] = wi;
@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(kBlock) k_ppcg_init(SellViewT<T> Ac, PcgViewT<
 }
 
 // One pipelined CG iteration.  Vectors and matrix values in T; scalars and dot products in FP64.
-template <typename T, bool kFirst, int kBlock, bool kShort>
+template <typename T, bool kFirst, int kBlock, int kRow>
 __global__ void __launch_bounds__(kBlock) k_ppcg_iter(int parity, SellViewT<T> Ac, PcgViewT<T> v, PcgState* st,
                                                            double* __restrict__ part) {
   const int P = gridDim.x;
@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(kBlock) k_ppcg_iter(int parity, SellViewT<T> A
   // the partials of gamma and delta left by the previous iteration.
   T n = T(0), wi = T(0), di = T(0), ri = T(0), zo = T(0), so = T(0), po = T(0), xo = T(0);
   auto load = [&](int64_t i) {
-    n = sell_row<kShort>(Ac, i, win);
+    n = sell_row<kRow>(Ac, i, win);
     wi = win[i];
     di = v.dinv[i];
     ri = v.r[i];
@@ -159,47 +159,44 @@ PcgViewT<T> pview(const PcgWorkT<T>& w) {
   return {w.x, w.r, w.z, w.s, w.p, w.w0, w.w1, w.dinv};
 }
 
-template <typename T, int kBlock, bool kShort>
+template <typename T, int kBlock, int kRow>
 void pcg_init_as(hipStream_t s, SellViewT<T> Av, const PcgWorkT<T>& w, const double* b, PcgState* st, double tol,
                  int maxit, double* part) {
-  k_ppcg_init<T, kBlock, kShort><<<pcg_grid(Av.rows, kBlock), kBlock, 0, s>>>(Av, pview(w), b, st, tol * tol, maxit,
+  k_ppcg_init<T, kBlock, kRow><<<pcg_grid(Av.rows, kBlock), kBlock, 0, s>>>(Av, pview(w), b, st, tol * tol, maxit,
                                                                               part);
 }
 
-template <typename T, int kBlock, bool kShort>
+template <typename T, int kBlock, int kRow>
 void pcg_iter_as(hipStream_t s, int i, SellViewT<T> Av, const PcgWorkT<T>& w, PcgState* st, double* part) {
   const int P = pcg_grid(Av.rows, kBlock);
   if (i == 0)
-    k_ppcg_iter<T, true, kBlock, kShort><<<P, kBlock, 0, s>>>(0, Av, pview(w), st, part);
+    k_ppcg_iter<T, true, kBlock, kRow><<<P, kBlock, 0, s>>>(0, Av, pview(w), st, part);
   else
-    k_ppcg_iter<T, false, kBlock, kShort><<<P, kBlock, 0, s>>>(i & 1, Av, pview(w), st, part);
+    k_ppcg_iter<T, false, kBlock, kRow><<<P, kBlock, 0, s>>>(i & 1, Av, pview(w), st, part);
 }
 
 // Launch shape: 1024-thread blocks when every row has a thread, 256-thread blocks when threads
 // loop over rows (their barriers hold fewer waves).  One-row-per-thread launches take the
 // short-row product when no slice is longer than kShortRow (measured on the 64^3 cube: S, 7 per
 // row, 10.95 -> 10.53 us per iteration; rows of 11-13 entries were slower with it, 31.5 ->
-// 33.9 us for A_gamma, so longer rows keep the plain loop).
+// 33.9 us for A_gamma, so longer rows keep the plain loop), and its fixed-count form where every
+// slice was padded to one length.
 template <typename T>
 void pcg_init_sel(hipStream_t s, const Sell& A, SellViewT<T> Av, const PcgWorkT<T>& w, const double* b,
                   PcgState* st, double tol, int maxit, double* part) {
   if (A.rows > kPcgMaxThreads)  // threads loop over rows
-    pcg_init_as<T, 256, false>(s, Av, w, b, st, tol, maxit, part);
-  else if (A.max_len <= kShortRow)
-    pcg_init_as<T, 1024, true>(s, Av, w, b, st, tol, maxit, part);
+    pcg_init_as<T, 256, kRowAny>(s, Av, w, b, st, tol, maxit, part);
   else
-    pcg_init_as<T, 1024, false>(s, Av, w, b, st, tol, maxit, part);
+    with_row_form(row_form(A), [&](auto R) { pcg_init_as<T, 1024, decltype(R)::value>(s, Av, w, b, st, tol, maxit, part); });
 }
 
 template <typename T>
 void pcg_iter_sel(hipStream_t s, int i, const Sell& A, SellViewT<T> Av, const PcgWorkT<T>& w, PcgState* st,
                   double* part) {
   if (A.rows > kPcgMaxThreads)
-    pcg_iter_as<T, 256, false>(s, i, Av, w, st, part);
-  else if (A.max_len <= kShortRow)
-    pcg_iter_as<T, 1024, true>(s, i, Av, w, st, part);
+    pcg_iter_as<T, 256, kRowAny>(s, i, Av, w, st, part);
   else
-    pcg_iter_as<T, 1024, false>(s, i, Av, w, st, part);
+    with_row_form(row_form(A), [&](auto R) { pcg_iter_as<T, 1024, decltype(R)::value>(s, i, Av, w, st, part); });
 }
 
 // ---- inner Chebyshev-Jacobi: a fixed polynomial in D^{-1}A, no reductions ----------------------
@@ -217,7 +214,7 @@ void pcg_iter_sel(hipStream_t s, int i, const Sell& A, SellViewT<T> Av, const Pc
 // by the device-resident 1/hi (the Gershgorin bound of D^{-1}A, taken when the values are built):
 // nothing is read back.  m products give x_{m+1}, a polynomial of degree m in D^{-1}A applied to
 // D^{-1}b.  The first product also sets the inner-solve counters (no separate start kernel).
-template <typename T, bool kShort, bool kFirst, bool kLast>
+template <typename T, int kRow, bool kFirst, bool kLast>
 __global__ void __launch_bounds__(1024) k_cheb_iter(SellViewT<T> Acs, const T* __restrict__ dinv,
                                                     const double* __restrict__ b, T* __restrict__ bT,
                                                     const T* __restrict__ ycur, T* yprev, T* yout,
@@ -237,7 +234,7 @@ __global__ void __launch_bounds__(1024) k_cheb_iter(SellViewT<T> Acs, const T* _
       // y_1 = c0 b and y_0 = 0, with A D^{-1} y_1 = c0 (A D^{-1} b)
       const T c0 = (T)(c0u * inv_hi[0]);
       const T bi = (T)b[row];
-      const T ab = sell_row<kShort>(Acs, row, b);
+      const T ab = sell_row<kRow>(Acs, row, b);
       const T y1 = c0 * bi;
       yn = y1 + t1 * y1 + c2 * (bi - c0 * ab);
       if (!kLast) {
@@ -248,7 +245,7 @@ __global__ void __launch_bounds__(1024) k_cheb_iter(SellViewT<T> Acs, const T* _
       // the row's own entries first: their loads overlap the product's
       const T yj = ycur[row], yp = yprev[row];
       const T bi = bT ? bT[row] : (T)b[row];
-      const T ay = sell_row<kShort>(Acs, row, ycur);
+      const T ay = sell_row<kRow>(Acs, row, ycur);
       yn = yj + t1 * (yj - yp) + c2 * (bi - ay);
     }
     if constexpr (kLast)
@@ -305,23 +302,23 @@ __global__ void __launch_bounds__(256) k_gersh_final(int nparts, const double* _
   }
 }
 
-template <typename T, bool kShort>
+template <typename T, int kRow>
 void cheb_iter_as(hipStream_t s, int k, int m, SellViewT<T> Acs, const T* dinv, const double* b, T* bT,
                   const T* ycur, T* yprev, T* yout, T* x, const double* inv_hi, double c0u, double c1, double c2u,
                   PcgState* st) {
   const int G = pcg_grid(Acs.rows, 1024);
   const bool first = k == 0, last = k == m - 1;
   if (first && last)
-    k_cheb_iter<T, kShort, true, true><<<G, 1024, 0, s>>>(Acs, dinv, b, bT, ycur, yprev, yout, x, inv_hi, c0u, c1,
+    k_cheb_iter<T, kRow, true, true><<<G, 1024, 0, s>>>(Acs, dinv, b, bT, ycur, yprev, yout, x, inv_hi, c0u, c1,
                                                           c2u, st, m);
   else if (first)
-    k_cheb_iter<T, kShort, true, false><<<G, 1024, 0, s>>>(Acs, dinv, b, bT, ycur, yprev, yout, x, inv_hi, c0u, c1,
+    k_cheb_iter<T, kRow, true, false><<<G, 1024, 0, s>>>(Acs, dinv, b, bT, ycur, yprev, yout, x, inv_hi, c0u, c1,
                                                            c2u, st, m);
   else if (last)
-    k_cheb_iter<T, kShort, false, true><<<G, 1024, 0, s>>>(Acs, dinv, b, bT, ycur, yprev, yout, x, inv_hi, c0u, c1,
+    k_cheb_iter<T, kRow, false, true><<<G, 1024, 0, s>>>(Acs, dinv, b, bT, ycur, yprev, yout, x, inv_hi, c0u, c1,
                                                            c2u, st, m);
   else
-    k_cheb_iter<T, kShort, false, false><<<G, 1024, 0, s>>>(Acs, dinv, b, bT, ycur, yprev, yout, x, inv_hi, c0u,
+    k_cheb_iter<T, kRow, false, false><<<G, 1024, 0, s>>>(Acs, dinv, b, bT, ycur, yprev, yout, x, inv_hi, c0u,
                                                             c1, c2u, st, m);
 }
 
@@ -340,7 +337,7 @@ void launch_cheb(hipStream_t s, const Sell& A, const PcgWorkT<T>& w, const doubl
   const double c0u = 2.0 / (1.0 + c);  // 1 / theta, theta = hi (1 + c) / 2
   double rho = 1.0 / sigma;
   T* ybuf[2] = {w.p, w.s};
-  const bool short_rows = A.max_len <= kShortRow && A.rows <= kPcgMaxThreads;
+  const int form = A.rows <= kPcgMaxThreads ? row_form(A) : kRowAny;
   for (int k = 0; k < m; ++k) {
     const double rho1 = 1.0 / (2.0 * sigma - rho);
     const double c1 = rho1 * rho, c2u = 4.0 * rho1 / (1.0 - c);  // 2 rho_{k+1} / delta, delta = hi (1 - c) / 2
@@ -348,10 +345,10 @@ void launch_cheb(hipStream_t s, const Sell& A, const PcgWorkT<T>& w, const doubl
     const T* ycur = k == 0 ? nullptr : ybuf[(k + 1) & 1];
     T* yprev = k == 0 ? ybuf[1] : ybuf[k & 1];
     T* yout = ybuf[k & 1];
-    if (short_rows)
-      cheb_iter_as<T, true>(s, k, m, Acs, w.dinv, b, bT, ycur, yprev, yout, w.x, inv_hi, c0u, c1, c2u, st);
-    else
-      cheb_iter_as<T, false>(s, k, m, Acs, w.dinv, b, bT, ycur, yprev, yout, w.x, inv_hi, c0u, c1, c2u, st);
+    with_row_form(form, [&](auto R) {
+      cheb_iter_as<T, decltype(R)::value>(s, k, m, Acs, w.dinv, b, bT, ycur, yprev, yout, w.x, inv_hi, c0u, c1, c2u,
+                                          st);
+    });
     rho = rho1;
   }
 }
@@ -371,7 +368,7 @@ double time_cheb_products(hipStream_t s, const Sell& A, const PcgWorkT<T>& w, co
   double rho = 1.0 / sigma;
   rho = 1.0 / (2.0 * sigma - rho);  // the degree-2 solve's two steps
   rho = 1.0 / (2.0 * sigma - rho);
-  const bool short_rows = A.max_len <= kShortRow && A.rows <= kPcgMaxThreads;
+  const int form = A.rows <= kPcgMaxThreads ? row_form(A) : kRowAny;
   const int G = pcg_grid(Acs.rows, 1024);
   std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
   double total = 0.0;
@@ -385,14 +382,11 @@ double time_cheb_products(hipStream_t s, const Sell& A, const PcgWorkT<T>& w, co
       rho = rho1;
       const T* ycur = ybuf[(k + 1) & 1];
       T* ynext = ybuf[k & 1];
-      if (short_rows)
-        hipExtLaunchKernelGGL(k_cheb_iter<T, true, false, false>, dim3(G), dim3(1024), 0, s, ev[2 * r],
+      with_row_form(form, [&](auto R) {
+        hipExtLaunchKernelGGL(k_cheb_iter<T, decltype(R)::value, false, false>, dim3(G), dim3(1024), 0, s, ev[2 * r],
                               ev[2 * r + 1], 0, Acs, (const T*)w.dinv, b, bT, ycur, ynext, ynext, w.x, inv_hi, c0u,
                               c1, c2u, st, reps);
-      else
-        hipExtLaunchKernelGGL(k_cheb_iter<T, false, false, false>, dim3(G), dim3(1024), 0, s, ev[2 * r],
-                              ev[2 * r + 1], 0, Acs, (const T*)w.dinv, b, bT, ycur, ynext, ynext, w.x, inv_hi, c0u,
-                              c1, c2u, st, reps);
+      });
       VEM_HIP(hipGetLastError());
     }
     VEM_HIP(hipEventSynchronize(ev.back()));

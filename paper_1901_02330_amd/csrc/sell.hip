@@ -5,7 +5,8 @@
 // contiguous 512-byte load of values and a 256-byte load of column indices.
 // A thread owns a row; its loads do not depend on a row pointer and are
 // independent of each other, which keeps many loads in flight per wave.
-// Padding entries carry value 0 and the row's own column.  The CSR pattern
+// Padding entries carry value 0 and the row's own column; a matrix of short rows may have every
+// slice padded to its longest row (a fixed entry count per row).  The CSR pattern
 // is built first; the value kernels then write straight into the SELL slots
 // (entry k of row r at slice_ptr[r/64] + r%64 + 64k: coalesced across a
 // wave), and src[] maps every slot back to its CSR entry (-1 for padding)
@@ -65,6 +66,14 @@ __global__ void k_sell_fill(int64_t rows, const int* __restrict__ rowptr, const 
   }
 }
 
+// Every slice padded to one length: slice_len[s] = len and slice_ptr[s] = 64 len s (s <= nslices).
+__global__ void k_sell_uniform(int64_t nslices, int len, int* __restrict__ slice_len, int64_t* __restrict__ ptr) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s > nslices) return;
+  if (s < nslices) slice_len[s] = len;
+  ptr[s] = s * 64 * len;
+}
+
 // CSR values from the SELL slots (for the export)
 __global__ void k_sell_to_csr(int64_t n, const int* __restrict__ src, const double* __restrict__ sval,
                               double* __restrict__ val) {
@@ -88,6 +97,9 @@ __global__ void k_narrow64(int64_t n, const int64_t* __restrict__ in, int* __res
 }
 
 inline int grid256(int64_t n) { return (int)((n + 255) / 256); }
+
+// rows of at most this many entries may be padded to one length per matrix
+constexpr int kSellFixedMax = 8;
 
 }  // namespace
 
@@ -115,10 +127,26 @@ void build_sells(hipStream_t s, Scratch& tmp, const Csr* const* A, Sell* const* 
   }
   VEM_HIP(hipMemcpyAsync(tmp.ti.p, mlen.p, count * sizeof(int), hipMemcpyDeviceToHost, s));
   VEM_HIP(hipStreamSynchronize(s));
-  for (int m = 0; m < count; ++m) S[m]->max_len = tmp.ti.p[m];
+  // Short rows: where padding every slice to the longest adds at most 1/16 of the slots, it is done,
+  // and the products take a fixed number of entries per row with no per-slice masks (the 64^3 cube's
+  // S: 7 per row, 0.9% more slots).
+  int64_t totals[3];
   for (int m = 0; m < count; ++m) {
     Sell& B = *S[m];
-    const int64_t total = tmp.tot.p[m];
+    B.max_len = tmp.ti.p[m];
+    totals[m] = tmp.tot.p[m];
+    const int64_t even = B.nslices * 64 * (int64_t)B.max_len;
+    B.fixed_len = 0;
+    if (B.max_len > 0 && B.max_len <= kSellFixedMax && even <= totals[m] + totals[m] / 16) {
+      B.fixed_len = B.max_len;
+      totals[m] = even;
+      k_sell_uniform<<<grid256(B.nslices + 1), 256, 0, s>>>(B.nslices, B.max_len, B.slice_len, tmp.i64[2 * m + 1]);
+      VEM_HIP(hipGetLastError());
+    }
+  }
+  for (int m = 0; m < count; ++m) {
+    Sell& B = *S[m];
+    const int64_t total = totals[m];
     VEM_REQUIRE(total < INT32_MAX, VEM_ENOMEM, "padded matrix exceeds 2^31-1 entries");
     DBuf<int64_t>& ptr = tmp.i64[2 * m + 1];
     B.nnz = total;

@@ -139,6 +139,7 @@ struct Csr {
 struct Sell {
   int64_t rows = 0, nslices = 0, nnz = 0;
   int max_len = 0;       // longest slice (entries per row after padding)
+  int fixed_len = 0;     // every slice padded to max_len (short rows only), else 0
   DBuf<int> slice_ptr, slice_len, col, src;
   DBuf<double> val;
   DBuf<double> val_cs;   // column-scaled copy A D^{-1} (inner CG matrices only)
