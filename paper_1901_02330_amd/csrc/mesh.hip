@@ -267,13 +267,20 @@ __global__ void k_bnd_tri_counts(int nb, const int* __restrict__ bface, const in
 }
 
 // Points x = O + xi (v0 - O) + eta (v_a - O) + zeta (v_{a+1} - O).  A block takes a run of
-// whole tetrahedra (about 2048 points, at most kQpTets tetrahedra): their corners are fetched
+// whole tetrahedra (about 4096 points, at most kQpTets tetrahedra): their corners are fetched
 // once into LDS by one thread each, then the block's threads write the run's points in
-// order, so that consecutive threads store consecutive entries of each coordinate array.
+// order, so that consecutive threads store consecutive entries of each coordinate array.  The
+// reference points are staged in LDS too, so the write loop reads no global memory.  LDS is
+// sized to the run (about 15 KB at 27 points per tetrahedron), which leaves room for eight
+// blocks per CU to overlap their corner fetches (chains of dependent index loads).
 constexpr int kQpTets = 256;
+constexpr int kQpRefMax = 216;  // reference points per tetrahedron: 6 per direction at most
 inline int qp_tets_per_block(int npts) {
-  const int t = 2048 / (npts > 0 ? npts : 1);
+  const int t = 4096 / (npts > 0 ? npts : 1);
   return t < 1 ? 1 : (t > kQpTets ? kQpTets : t);
+}
+inline size_t qp_lds_bytes(int npts) {
+  return sizeof(double) * (12 * (size_t)qp_tets_per_block(npts) + 3 * (size_t)npts);
 }
 
 __global__ void __launch_bounds__(kThreads) k_qp_cell(int64_t ntet, int npts, int tets_per_block,
@@ -283,18 +290,35 @@ __global__ void __launch_bounds__(kThreads) k_qp_cell(int64_t ntet, int npts, in
                                                       const int* __restrict__ fptr, const int* __restrict__ fvtx,
                                                       const int* __restrict__ cface, const double* __restrict__ xref,
                                                       double* qp) {
-  __shared__ double corner[kQpTets][12];  // O, v0, v_a, v_{a+1}
+  extern __shared__ double qp_lds[];
+  double* corner = qp_lds;                        // [tets_per_block][12]: O, v0, v_a, v_{a+1}
+  double* sref = qp_lds + 12 * tets_per_block;  // [3 npts]
   const int64_t t0 = (int64_t)blockIdx.x * tets_per_block;
   const int nt = (int)(ntet - t0 < tets_per_block ? ntet - t0 : tets_per_block);
+  {
+    constexpr int kPer = (3 * kQpRefMax + kThreads - 1) / kThreads;
+    const int nr = 3 * npts;
+    double rv[kPer];  // slots past the table reload its last entry (no branch around a load)
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int q = threadIdx.x + u * kThreads;
+      rv[u] = ref[q < nr ? q : nr - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int q = threadIdx.x + u * kThreads;
+      if (q < nr) sref[q] = rv[u];
+    }
+  }
   for (int i = threadIdx.x; i < nt; i += kThreads) {
     const int64_t t = t0 + i;
     const int j = tet_inc[t], a = tet_a[t];
     const int fs = fptr[cface[j]];
     const V3 v[4] = {ld3(xref, inc_cell[j]), ld3(xyz, fvtx[fs]), ld3(xyz, fvtx[fs + a]), ld3(xyz, fvtx[fs + a + 1])};
     for (int c = 0; c < 4; ++c) {
-      corner[i][3 * c] = v[c].x;
-      corner[i][3 * c + 1] = v[c].y;
-      corner[i][3 * c + 2] = v[c].z;
+      corner[12 * i + 3 * c] = v[c].x;
+      corner[12 * i + 3 * c + 1] = v[c].y;
+      corner[12 * i + 3 * c + 2] = v[c].z;
     }
   }
   __syncthreads();
@@ -302,9 +326,9 @@ __global__ void __launch_bounds__(kThreads) k_qp_cell(int64_t ntet, int npts, in
   const int np = nt * npts;
   for (int q = threadIdx.x; q < np; q += kThreads) {
     const int i = q / npts, r = q - i * npts;
-    const double* c = corner[i];
+    const double* c = corner + 12 * i;
     const V3 O{c[0], c[1], c[2]}, A{c[3], c[4], c[5]}, B{c[6], c[7], c[8]}, C{c[9], c[10], c[11]};
-    const double xi = ref[3 * r], eta = ref[3 * r + 1], zeta = ref[3 * r + 2];
+    const double xi = sref[3 * r], eta = sref[3 * r + 1], zeta = sref[3 * r + 2];
     st3_soa(qp, total, q0 + q, O + xi * (A - O) + eta * (B - O) + zeta * (C - O));
   }
 }
@@ -327,9 +351,11 @@ __global__ void k_qp_face(int nb, int npts, int64_t total, const double* __restr
 
 // Per tetrahedron: sigma det * sum_r w_r f(x_r).  A block takes a run of whole tetrahedra
 // (at most kThreads of them, at most kLoadPts points): their point values are contiguous,
-// are read into LDS with coalesced loads all in flight at once, and each thread then sums
-// its own tetrahedron's points in order.
+// are read into LDS with coalesced loads all in flight at once (a fixed count per thread, so
+// that no load waits for the previous one's store), and each thread then sums its own
+// tetrahedron's points in order.
 constexpr int kLoadPts = 4096;
+constexpr int kLoadPerThread = kLoadPts / kThreads;
 inline int load_tets_per_block(int npts) {
   const int t = kLoadPts / (npts > 0 ? npts : 1);
   return t < 1 ? 1 : (t > kThreads ? kThreads : t);
@@ -349,16 +375,26 @@ __global__ void __launch_bounds__(kThreads) k_load_tets(int64_t ntet, int npts, 
   const int nt = (int)(ntet - t0 < tets_per_block ? ntet - t0 : tets_per_block);
   const int np = nt * npts;
   const int64_t q0 = t0 * npts;
-  for (int q = threadIdx.x; q < np; q += kThreads) vals[q] = fq[q0 + q];
-  double det = 0.0;
+  // The determinant's chain of dependent index loads runs on every thread (threads past the run
+  // repeat its last tetrahedron and discard the result), without a branch, so that it proceeds while
+  // the point-value loads are in flight.
+  double v[kLoadPerThread];  // slots past the run reload its last value (no branch around a load)
+#pragma unroll
+  for (int u = 0; u < kLoadPerThread; ++u) {
+    const int q = threadIdx.x + u * kThreads;
+    v[u] = fq[q0 + (q < np ? q : np - 1)];
+  }
   const int i = threadIdx.x;
-  if (i < nt) {
-    const int64_t t = t0 + i;
-    const int j = tet_inc[t], a = tet_a[t];
-    const int fs = fptr[cface[j]];
-    const V3 O = ld3(xref, inc_cell[j]);
-    const V3 A = ld3(xyz, fvtx[fs]), B = ld3(xyz, fvtx[fs + a]), C = ld3(xyz, fvtx[fs + a + 1]);
-    det = dot(A - O, cross(B - O, C - O)) * (double)csign[j];
+  const int64_t t = t0 + (i < nt ? i : nt - 1);
+  const int j = tet_inc[t], a = tet_a[t];
+  const int fs = fptr[cface[j]];
+  const V3 O = ld3(xref, inc_cell[j]);
+  const V3 A = ld3(xyz, fvtx[fs]), B = ld3(xyz, fvtx[fs + a]), C = ld3(xyz, fvtx[fs + a + 1]);
+  const double det = dot(A - O, cross(B - O, C - O)) * (double)csign[j];
+#pragma unroll
+  for (int u = 0; u < kLoadPerThread; ++u) {
+    const int q = threadIdx.x + u * kThreads;
+    if (q < np) vals[q] = v[u];
   }
   __syncthreads();
   if (i >= nt) return;
@@ -474,10 +510,12 @@ void launch_bnd_tri_counts(hipStream_t s, int nb, const int* bface, const int* f
 void launch_qp_cell(hipStream_t s, int64_t ntet, int npts, const double* ref, const int* tet_inc, const int* tet_a,
                     const int* inc_cell, const double* xyz, const int* fptr, const int* fvtx, const int* cface,
                     const double* xref, double* qp) {
+  VEM_REQUIRE(npts <= kQpRefMax, VEM_EINVAL, "more cell quadrature points per tetrahedron than staged");
   if (ntet > 0 && npts > 0) {
     const int tpb = qp_tets_per_block(npts);
-    k_qp_cell<<<(int)((ntet + tpb - 1) / tpb), kThreads, 0, s>>>(ntet, npts, tpb, ref, tet_inc, tet_a, inc_cell,
-                                                                   xyz, fptr, fvtx, cface, xref, qp);
+    k_qp_cell<<<(int)((ntet + tpb - 1) / tpb), kThreads, qp_lds_bytes(npts), s>>>(ntet, npts, tpb, ref, tet_inc,
+                                                                                  tet_a, inc_cell, xyz, fptr, fvtx,
+                                                                                  cface, xref, qp);
   }
 }
 void launch_qp_face(hipStream_t s, int nb, int npts, int64_t total, const double* ref, const int* bface,

@@ -258,14 +258,17 @@ class SineSolution:
     @staticmethod
     def p(x):
         # sin(pi x_d) for the three coordinates in one pass over the (n, 3) points, then their product
+        # in one reduction over the last axis
         L = _lib(x)
         s = math.pi * x
         L.sin(s, out=s)
-        return s[..., 0] * s[..., 1] * s[..., 2]
+        return L.prod(s, -1)
 
     @staticmethod
     def f(x):
-        return 3.0 * math.pi**2 * SineSolution.p(x)
+        q = SineSolution.p(x)
+        q *= 3.0 * math.pi**2
+        return q
 
     @staticmethod
     def pD(x):
