@@ -206,20 +206,42 @@ __global__ void k_cell_geometry(int nc, const double* __restrict__ xyz, const in
     }
   }
   // largest vertex-vertex distance; squared distances are compared and one root taken
-  // (the root is monotone and correctly rounded, so this is the same number).  A wavefront
-  // per cell with the incidences staged in LDS was measured slower (235 us against 258 us
-  // for this whole kernel at 64^3): the chain of dependent index loads dominates, and a
-  // thread per cell overlaps 64 of them per wave.
+  // (the root is monotone and correctly rounded, so this is the same number).  Every vertex of
+  // face j is compared with every vertex of the faces j2 >= j: a face of at most kFaceV vertices
+  // is held in registers (its padding slots repeat its first vertex, which leaves the maximum
+  // unchanged), so each vertex of the later faces is loaded once per face j rather than once per
+  // vertex of face j.  A wavefront per cell with the incidences staged in LDS was measured slower:
+  // the chain of dependent index loads dominates, and a thread per cell overlaps 64 of them per
+  // wave.
+  constexpr int kFaceV = 8;
   double dmax2 = 0.0;
   for (int j = s; j < e; ++j) {
-    int f = cface[j];
-    for (int q = fptr[f]; q < fptr[f + 1]; ++q) {
-      V3 P = ld3(xyz, fvtx[q]);
+    const int f = cface[j];
+    const int fs = fptr[f], nj = fptr[f + 1] - fs;
+    if (nj <= kFaceV) {
+      V3 P[kFaceV];
+#pragma unroll
+      for (int u = 0; u < kFaceV; ++u) P[u] = ld3(xyz, fvtx[fs + (u < nj ? u : 0)]);
       for (int j2 = j; j2 < e; ++j2) {
-        int f2 = cface[j2];
+        const int f2 = cface[j2];
         for (int q2 = fptr[f2]; q2 < fptr[f2 + 1]; ++q2) {
-          const V3 d = ld3(xyz, fvtx[q2]) - P;
-          dmax2 = fmax(dmax2, dot(d, d));
+          const V3 Q = ld3(xyz, fvtx[q2]);
+#pragma unroll
+          for (int u = 0; u < kFaceV; ++u) {
+            const V3 d = Q - P[u];
+            dmax2 = fmax(dmax2, dot(d, d));
+          }
+        }
+      }
+    } else {
+      for (int q = fs; q < fs + nj; ++q) {
+        const V3 P = ld3(xyz, fvtx[q]);
+        for (int j2 = j; j2 < e; ++j2) {
+          const int f2 = cface[j2];
+          for (int q2 = fptr[f2]; q2 < fptr[f2 + 1]; ++q2) {
+            const V3 d = ld3(xyz, fvtx[q2]) - P;
+            dmax2 = fmax(dmax2, dot(d, d));
+          }
         }
       }
     }
@@ -276,7 +298,7 @@ __global__ void k_bnd_tri_counts(int nb, const int* __restrict__ bface, const in
 constexpr int kQpTets = 256;
 constexpr int kQpRefMax = 216;  // reference points per tetrahedron: 6 per direction at most
 inline int qp_tets_per_block(int npts) {
-  const int t = 4096 / (npts > 0 ? npts : 1);
+  const int t = 8192 / (npts > 0 ? npts : 1);
   return t < 1 ? 1 : (t > kQpTets ? kQpTets : t);
 }
 inline size_t qp_lds_bytes(int npts) {
