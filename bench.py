@@ -155,18 +155,22 @@ def summarize(prefix: str):
 
 def schur_window(trace: str):
     """Kernel time inside the first Block-Schur solve of a traced step: from its value build (the
-    first k_schur_values) to the last launch before the Block-Reg solve's first inner-CG init.
-    Template arguments that only count Krylov vectors are folded into one row."""
+    k_values launch that builds K, just before the first k_schur_values) to the launch before the
+    Block-Reg solve's own value build (the next k_values).  Template arguments that only count
+    Krylov vectors are folded into one row."""
     import csv
 
     rows = sorted(csv.DictReader(open(trace)), key=lambda r: int(r["Start_Timestamp"]))
     names = [r["Kernel_Name"] for r in rows]
+
+    def is_values(n):
+        return re.search(r"\bk_values\(", n) is not None
+
     try:
-        s = next(i for i, n in enumerate(names) if "k_schur_values" in n)
-        e = next(i for i in range(s, len(names))
-                 if any(k in names[i] for k in ("k_inc_face", "k_cell_condense", "k_edge_inv", "k_schwarz_rhs",
-                                                "k_ppcg_init<double, 256")))
-    except StopIteration:
+        sv = next(i for i, n in enumerate(names) if "k_schur_values" in n)
+        s = max(i for i in range(sv) if is_values(names[i]))
+        e = next(i for i in range(sv, len(names)) if is_values(names[i]))
+    except (StopIteration, ValueError):
         return []
     seg = rows[s:e]
     busy, calls = {}, {}

@@ -127,6 +127,7 @@ struct vem_ctx {
   // Arnoldi scalars of every step of a restart cycle, one slot per step (pinned), and
   // the events that mark each step's copy (steps alternate between the two)
   HBuf<double> hcol;
+  double* hcol_dev = nullptr;  // the device address of hcol (pinned host memory the kernels write)
   Scratch tmp;  // temporaries of the set-up calls
   // boundary data: VEM_BC_PRESSURE (natural, in g) or VEM_BC_FLUX (prescribed boundary fluxes xB and
   // a zero-mean pressure; n_p is the discrete constant pressure, pw the mean weights)
@@ -440,7 +441,9 @@ void ensure_scratch(vem_handle h) {
     h->scal.alloc(4 * kMaxDots + 16);
     h->pcg.alloc(1);
     h->hbuf.alloc(4 * kMaxDots + 16);
-    h->hcol.alloc((size_t)(kMaxRestart + 1) * kColSlot);
+    // coherent: the kernels' stores reach host memory without passing through the GPU's caches
+    h->hcol.alloc((size_t)(kMaxRestart + 1) * kColSlot, hipHostMallocMapped | hipHostMallocCoherent);
+    VEM_HIP(hipHostGetDevicePointer((void**)&h->hcol_dev, h->hcol.p, 0));
     h->hpcg.alloc(1);
     for (hipEvent_t& e : h->step_done) VEM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     sync(h);
@@ -1835,16 +1838,16 @@ static vem_status solve_impl(vem_handle h, const vem_solve_opts* opts, const dou
         double* w = V + (size_t)(j + 1) * N;
         apply_prec(h, o, vj, zj);
         launch_spmv(s, h->Ks, zj, w);
-        if (j == 0)
-          launch_dots(s, N, 1, V, N, w, h->partials, dh);
-        else
-          launch_dots_fix(s, N, j + 1, V, N, dh2, w, h->partials, dh);
-        launch_update_dots(s, N, j + 1, V, N, dh, w, h->partials, dh2);
-        check_launch();
         // h at scal[0], its correction at scal[kMaxDots], ||w||^2 between the passes at
-        // scal[kMaxDots + j + 1]
-        VEM_HIP(hipMemcpyAsync(h->hcol.p + (size_t)j * kColSlot, dh, kColSlot * sizeof(double),
-                               hipMemcpyDeviceToHost, s));
+        // scal[kMaxDots + j + 1]; the reductions also write them to the step's pinned host slot
+        // (same offsets), so no copy is enqueued
+        double* hc = h->hcol_dev + (size_t)j * kColSlot;
+        if (j == 0)
+          launch_dots(s, N, 1, V, N, w, h->partials, dh, hc);
+        else
+          launch_dots_fix(s, N, j + 1, V, N, dh2, w, h->partials, dh, hc);
+        launch_update_dots(s, N, j + 1, V, N, dh, w, h->partials, dh2, hc + kMaxDots);
+        check_launch();
         VEM_HIP(hipEventRecord(h->step_done[j & 1], s));
       };
       enqueue_step(0);

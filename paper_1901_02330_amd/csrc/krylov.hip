@@ -13,12 +13,16 @@
 namespace vem {
 namespace {
 
-// out[k] = sum over nparts partials; block k handles component k
+// out[k] = sum over nparts partials; block k handles component k.  hout (or null): a copy in pinned
+// host memory (its device address), which the host reads once the stream has passed this kernel.
 __global__ void __launch_bounds__(kThreads) k_finalize(int nparts, int K, const double* __restrict__ partials,
-                                                       double* __restrict__ out) {
+                                                       double* __restrict__ out, double* __restrict__ hout) {
   const int k = blockIdx.x;
   double v = block_sum_partials(partials, nparts, K, k);
-  if (threadIdx.x == 0) out[k] = v;
+  if (threadIdx.x == 0) {
+    out[k] = v;
+    if (hout) hout[k] = v;
+  }
 }
 
 inline int red_grid(int64_t n) {
@@ -513,8 +517,8 @@ inline int stream_grid(int64_t n) {
   X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
 #define VEM_K_CASES(X) X(1) VEM_K_CASES_FROM2(X)
 
-void finalize(hipStream_t s, int nparts, int K, const double* partials, double* out) {
-  k_finalize<<<K, kThreads, 0, s>>>(nparts, K, partials, out);
+void finalize(hipStream_t s, int nparts, int K, const double* partials, double* out, double* hout = nullptr) {
+  k_finalize<<<K, kThreads, 0, s>>>(nparts, K, partials, out, hout);
 }
 
 }  // namespace
@@ -533,7 +537,7 @@ void launch_residual(hipStream_t s, const Sell& A, const double* x, const double
 }
 
 void launch_dots(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* w, double* partials,
-                 double* out) {
+                 double* out, double* hout) {
   int grid = red_grid(n);
   switch (k) {
 #define X(K) \
@@ -542,11 +546,11 @@ void launch_dots(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, 
 #undef X
     default: throw Error{VEM_EINVAL, "too many basis vectors"};
   }
-  finalize(s, grid, k, partials, out);
+  finalize(s, grid, k, partials, out, hout);
 }
 
 void launch_update_dots(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* h, double* w,
-                        double* partials, double* out) {
+                        double* partials, double* out, double* hout) {
   int grid = red_grid(n);
   switch (k) {
 #define X(K) \
@@ -555,11 +559,11 @@ void launch_update_dots(hipStream_t s, int64_t n, int k, const double* V, int64_
 #undef X
     default: throw Error{VEM_EINVAL, "too many basis vectors"};
   }
-  finalize(s, grid, k + 1, partials, out);
+  finalize(s, grid, k + 1, partials, out, hout);
 }
 
 void launch_dots_fix(hipStream_t s, int64_t n, int k, double* V, int64_t ldv, const double* hp, const double* w,
-                     double* partials, double* out) {
+                     double* partials, double* out, double* hout) {
   int grid = red_grid(n);
   switch (k) {
 #define X(K) \
@@ -568,7 +572,7 @@ void launch_dots_fix(hipStream_t s, int64_t n, int k, double* V, int64_t ldv, co
 #undef X
     default: throw Error{VEM_EINVAL, "the folded first pass needs 2 to 32 basis vectors"};
   }
-  finalize(s, grid, k, partials, out);
+  finalize(s, grid, k, partials, out, hout);
 }
 
 void launch_project(hipStream_t s, int64_t n, const double* x, const double* v, const double* dot, double inv_vv,

@@ -73,11 +73,11 @@ struct HBuf {
   ~HBuf() {
     if (p) (void)hipHostFree(p);
   }
-  void alloc(size_t count) {
+  void alloc(size_t count, unsigned flags = hipHostMallocDefault) {
     if (count <= n && p) return;
     if (p) (void)hipHostFree(p);
     p = nullptr;
-    VEM_HIP(hipHostMalloc((void**)&p, count * sizeof(T), hipHostMallocDefault));
+    VEM_HIP(hipHostMalloc((void**)&p, count * sizeof(T), flags));
     n = count;
   }
   T& operator[](size_t i) { return p[i]; }
@@ -280,14 +280,16 @@ void launch_rhs_from_moments(hipStream_t s, int64_t Nu, int64_t Np, double* rhs)
 void launch_spmv(hipStream_t s, const Sell& A, const double* x, double* y);
 void launch_residual(hipStream_t s, const Sell& A, const double* x, const double* b, double* r, double* partials,
                      double* out);
+// The reductions below write their results to out (device) and, when hout is given (the device
+// address of pinned host memory), a copy there for the host.
 void launch_dots(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* w, double* partials,
-                 double* out);
+                 double* out, double* hout = nullptr);
 void launch_update_dots(hipStream_t s, int64_t n, int k, const double* V, int64_t ldv, const double* h, double* w,
-                        double* partials, double* out);
+                        double* partials, double* out, double* hout = nullptr);
 // First Gram-Schmidt pass with the previous step's second pass folded in: V[k-1] = (V[k-1] -
 // V[0..k-1) hp) / sqrt(hp[k-1] - |hp[0..k-1)|^2) in place, then out[0..k) = V^T w (k >= 2)
 void launch_dots_fix(hipStream_t s, int64_t n, int k, double* V, int64_t ldv, const double* hp, const double* w,
-                     double* partials, double* out);
+                     double* partials, double* out, double* hout = nullptr);
 void launch_scale_to(hipStream_t s, int64_t n, const double* w, const double* norm2, double* dst);
 void launch_scale_by(hipStream_t s, int64_t n, const double* x, const double* d, double c, double* y);
 void launch_combine(hipStream_t s, int64_t n, int k, const double* Z, int64_t ldz, const double* y, double* x);
