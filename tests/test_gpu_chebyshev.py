@@ -20,11 +20,16 @@ def _say(*a):
     sys.stdout.flush()
 
 
+# The three row forms of the products of S: cube675 (every slice of S padded to 7 entries per row:
+# the fixed-count form), cubeslab (one layer of cells, at most 5 entries per row: the masked
+# short-row form) and voronoi150 (longer rows: the loop).
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("name", ["cube675", "voronoi150"])
+@pytest.mark.parametrize("name", ["cube675", "cubeslab", "voronoi150"])
 def test_chebyshev_schur_solve_matches_oracle(name, precision):
     _say("chebyshev", name, precision)
-    m = cube_mesh(6, 7, 5) if name == "cube675" else voronoi_mesh(150, seed=0)
+    meshes = {"cube675": lambda: cube_mesh(6, 7, 5), "cubeslab": lambda: cube_mesh(16, 12, 1),
+              "voronoi150": lambda: voronoi_mesh(150, seed=0)}
+    m = meshes[name]()
     nc = len(m["cell_ptr"]) - 1
     nu = 1.0 / lognormal_field(nc, 2.0, 0)
     s = gpu_solver(m, nu=nu, rhs=SineSolution())
@@ -42,6 +47,23 @@ def test_chebyshev_schur_solve_matches_oracle(name, precision):
     assert berr <= 1.5 * tol
     bound = 1e-10 if precision == "fp64" else 1e-7
     assert eu <= bound and ep <= bound
+
+
+def test_pipelined_schur_on_short_rows_matches_oracle():
+    """The pipelined Jacobi-CG on S in its masked short-row form (one layer of cells, at most 5
+    entries per row of S) against the oracle's direct solve."""
+    _say("pipelined cubeslab")
+    m = cube_mesh(16, 12, 1)
+    nu = 1.0 / lognormal_field(192, 2.0, 1)
+    s = gpu_solver(m, nu=nu, rhs=SineSolution())
+    u, p, info = s.solve(precond="schur", tol=1e-13, maxit=3000, inner_tol=1e-8, inner_maxit=200)
+    assert info["converged"], info
+    d = discretize(m, nu=nu, rhs=SineSolution())
+    x = direct_solve(d["K"], d["b"])
+    xg = np.concatenate([u.cpu().numpy(), p.cpu().numpy()])
+    eu, ep = rel(xg[: d["Nu"]], x[: d["Nu"]]), rel(xg[d["Nu"]:], x[d["Nu"]:])
+    _say(info, eu, ep)
+    assert eu <= 1e-10 and ep <= 1e-10
 
 
 def test_chebyshev_rejects_bad_interval():
