@@ -77,9 +77,8 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1
 // is <= 0), then forms the partials of V_k . w with the finished vectors.  V[0..K-2] are read once
 // for both jobs.
 template <int K>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))) k_dots_fix(int64_t n, double* __restrict__ V, int64_t ldv,
-                                                       const double* __restrict__ hp, const double* __restrict__ w,
-                                                       double* partials) {
+__device__ inline void dots_fix_body(int64_t n, double* __restrict__ V, int64_t ldv, const double* __restrict__ hp,
+                                     const double* __restrict__ w, double* partials) {
   double hk[K - 1];
   double hh = 0.0;
 #pragma unroll
@@ -106,6 +105,21 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1
     acc[K - 1] += t * wi;
   }
   block_partials<K>(acc, partials);
+}
+template <int K>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))) k_dots_fix(int64_t n, double* __restrict__ V, int64_t ldv,
+                                                       const double* __restrict__ hp, const double* __restrict__ w,
+                                                       double* partials) {
+  dots_fix_body<K>(n, V, ldv, hp, w, partials);
+}
+// The same pass for K >= 29 basis vectors, with the register budget of two waves per SIMD: at four,
+// the K - 1 coefficients and K accumulators did not fit, and the basis loads were issued one at a
+// time (85 us against 53 us at K = 29, 64^3).
+template <int K>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 2))) k_dots_fix_wide(int64_t n, double* __restrict__ V, int64_t ldv,
+                                                       const double* __restrict__ hp, const double* __restrict__ w,
+                                                       double* partials) {
+  dots_fix_body<K>(n, V, ldv, hp, w, partials);
 }
 
 // w -= V h; partials of V_k . w (k < K) and of ||w||^2 (component K)
@@ -517,6 +531,15 @@ inline int stream_grid(int64_t n) {
   X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32)
 #define VEM_K_CASES(X) X(1) VEM_K_CASES_FROM2(X)
 
+template <int K>
+void dots_fix_launch(hipStream_t s, int grid, int64_t n, double* V, int64_t ldv, const double* hp, const double* w,
+                     double* partials) {
+  if constexpr (K >= 29)
+    k_dots_fix_wide<K><<<grid, kThreads, 0, s>>>(n, V, ldv, hp, w, partials);
+  else
+    k_dots_fix<K><<<grid, kThreads, 0, s>>>(n, V, ldv, hp, w, partials);
+}
+
 void finalize(hipStream_t s, int nparts, int K, const double* partials, double* out, double* hout = nullptr) {
   k_finalize<<<K, kThreads, 0, s>>>(nparts, K, partials, out, hout);
 }
@@ -567,7 +590,7 @@ void launch_dots_fix(hipStream_t s, int64_t n, int k, double* V, int64_t ldv, co
   int grid = red_grid(n);
   switch (k) {
 #define X(K) \
-  case K: k_dots_fix<K><<<grid, kThreads, 0, s>>>(n, V, ldv, hp, w, partials); break;
+  case K: dots_fix_launch<K>(s, grid, n, V, ldv, hp, w, partials); break;
     VEM_K_CASES_FROM2(X)
 #undef X
     default: throw Error{VEM_EINVAL, "the folded first pass needs 2 to 32 basis vectors"};
