@@ -608,8 +608,11 @@ hipGraphExec_t inner_graph(vem_handle h, const Sell& A, const PcgWork& w, const 
 // kGraphIters iterations (inner_maxit is then rounded up to that length);
 // the iterate is formed in a fixed workspace and copied to x.  Returns the
 // iterations performed.
+// `side` (a diagonal scaling) is performed by the Chebyshev form's first launch, or by a launch of its
+// own before the other forms.
 void inner_pcg(vem_handle h, const Sell& A, const double* dinv, const float* dinv32, const double* b, double* x,
-               const vem_solve_opts& o, int& expect, InnerGraph& g64, InnerGraph& g32) {
+               const vem_solve_opts& o, int& expect, InnerGraph& g64, InnerGraph& g32,
+               const ScaleJob& side = ScaleJob{}) {
   hipStream_t s = h->stream;
   if (o.inner_form == VEM_INNER_CHEBYSHEV) {
     // a fixed polynomial of degree inner_maxit on [cheb_lo hi, hi]; inner_tol and graphs do not apply
@@ -618,15 +621,16 @@ void inner_pcg(vem_handle h, const Sell& A, const double* dinv, const float* din
     if (o.precision == VEM_MIXED) {
       PcgWork32 w{h->px32, (float*)h->pr.p, (float*)h->pz.p, (float*)h->ps.p, (float*)h->pp.p, (float*)h->pw0.p,
                   (float*)h->pw1.p, dinv32};
-      launch_cheb<float>(s, A, w, b, inv_hi, c, o.inner_maxit, h->pcg);
+      launch_cheb<float>(s, A, w, b, inv_hi, c, o.inner_maxit, h->pcg, side);
       launch_to_f64(s, A.rows, h->px32, x);
     } else {
       PcgWork w{x, h->pr, h->pz, h->ps, h->pp, h->pw0, h->pw1, dinv};
-      launch_cheb<double>(s, A, w, b, inv_hi, c, o.inner_maxit, h->pcg);
+      launch_cheb<double>(s, A, w, b, inv_hi, c, o.inner_maxit, h->pcg, side);
     }
     check_launch();
     return;
   }
+  if (side.n > 0) launch_scale_by(s, side.n, side.x, side.d, 1.0, side.y);
   const bool mixed = o.precision == VEM_MIXED;
   const bool classical = o.inner_form == VEM_INNER_CLASSICAL;
   const InnerMode mode = !mixed ? (classical ? kClassic64 : kPipe64)
@@ -753,7 +757,8 @@ void apply_prec(vem_handle h, const vem_solve_opts& o, const double* v, double* 
   const int64_t Nu = h->L.Nu, Np = h->L.Np;
   switch (o.precond) {
     case VEM_PREC_SCHUR: {
-      launch_scale_by(s, Nu, v, h->dMinv, 1.0, z);
+      // z_u = diag(M)^{-1} v_u, performed inside the inner solve's first launch where it can be
+      const ScaleJob zu{Nu, v, h->dMinv, z};
       const double* rp = v + Nu;
       if (h->bc == VEM_BC_FLUX) {
         // S has the constant pressure in its kernel: the inner CG takes the part of r_p
@@ -763,7 +768,7 @@ void apply_prec(vem_handle h, const vem_solve_opts& o, const double* v, double* 
         launch_project(s, Np, rp, h->n_p, d, 1.0 / h->np_nn, h->ptmp);
         rp = h->ptmp;
       }
-      inner_pcg(h, h->Ss, h->dSinv, h->dSinv32, rp, z + Nu, o, h->expect_S, h->gS, h->gS32);
+      inner_pcg(h, h->Ss, h->dSinv, h->dSinv32, rp, z + Nu, o, h->expect_S, h->gS, h->gS32, zu);
       return;
     }
     case VEM_PREC_REG:

@@ -220,7 +220,7 @@ __global__ void __launch_bounds__(1024) k_cheb_iter(SellViewT<T> Acs, const T* _
                                                     const T* __restrict__ ycur, T* yprev, T* yout,
                                                     T* __restrict__ x,
                                                     const double* __restrict__ inv_hi, double c0u, double c1,
-                                                    double c2u, PcgState* st, int m) {
+                                                    double c2u, PcgState* st, int m, ScaleJob side) {
   const T c2 = (T)(c2u * inv_hi[0]), t1 = (T)c1;
   if (kFirst && blockIdx.x == 0 && threadIdx.x == 0) {
     st->count = m;
@@ -252,6 +252,10 @@ __global__ void __launch_bounds__(1024) k_cheb_iter(SellViewT<T> Acs, const T* _
       x[row] = dinv[row] * yn;
     else
       yout[row] = yn;
+  }
+  if constexpr (kFirst) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < side.n; i += (int64_t)gridDim.x * blockDim.x)
+      side.y[i] = side.d[i] * side.x[i];
   }
 }
 
@@ -305,28 +309,28 @@ __global__ void __launch_bounds__(256) k_gersh_final(int nparts, const double* _
 template <typename T, int kRow>
 void cheb_iter_as(hipStream_t s, int k, int m, SellViewT<T> Acs, const T* dinv, const double* b, T* bT,
                   const T* ycur, T* yprev, T* yout, T* x, const double* inv_hi, double c0u, double c1, double c2u,
-                  PcgState* st) {
+                  PcgState* st, const ScaleJob& side) {
   const int G = pcg_grid(Acs.rows, 1024);
   const bool first = k == 0, last = k == m - 1;
   if (first && last)
     k_cheb_iter<T, kRow, true, true><<<G, 1024, 0, s>>>(Acs, dinv, b, bT, ycur, yprev, yout, x, inv_hi, c0u, c1,
-                                                          c2u, st, m);
+                                                          c2u, st, m, side);
   else if (first)
     k_cheb_iter<T, kRow, true, false><<<G, 1024, 0, s>>>(Acs, dinv, b, bT, ycur, yprev, yout, x, inv_hi, c0u, c1,
-                                                           c2u, st, m);
+                                                           c2u, st, m, side);
   else if (last)
     k_cheb_iter<T, kRow, false, true><<<G, 1024, 0, s>>>(Acs, dinv, b, bT, ycur, yprev, yout, x, inv_hi, c0u, c1,
-                                                           c2u, st, m);
+                                                           c2u, st, m, side);
   else
     k_cheb_iter<T, kRow, false, false><<<G, 1024, 0, s>>>(Acs, dinv, b, bT, ycur, yprev, yout, x, inv_hi, c0u,
-                                                            c1, c2u, st, m);
+                                                            c1, c2u, st, m, side);
 }
 
 }  // namespace
 
 template <typename T>
 void launch_cheb(hipStream_t s, const Sell& A, const PcgWorkT<T>& w, const double* b, const double* inv_hi,
-                 double c, int m, PcgState* st) {
+                 double c, int m, PcgState* st, const ScaleJob& side) {
   VEM_REQUIRE(c > 0.0 && c < 1.0 && m >= 1, VEM_EINVAL, "Chebyshev interval or degree out of range");
   const T* vcs = std::is_same<T, float>::value ? (const T*)(const void*)A.val32_cs.p : (const T*)(const void*)A.val_cs.p;
   VEM_REQUIRE(vcs != nullptr, VEM_EINVAL, "Chebyshev inner solve without the column-scaled values");
@@ -347,7 +351,7 @@ void launch_cheb(hipStream_t s, const Sell& A, const PcgWorkT<T>& w, const doubl
     T* yout = ybuf[k & 1];
     with_row_form(form, [&](auto R) {
       cheb_iter_as<T, decltype(R)::value>(s, k, m, Acs, w.dinv, b, bT, ycur, yprev, yout, w.x, inv_hi, c0u, c1, c2u,
-                                          st);
+                                          st, k == 0 ? side : ScaleJob{});
     });
     rho = rho1;
   }
@@ -385,7 +389,7 @@ double time_cheb_products(hipStream_t s, const Sell& A, const PcgWorkT<T>& w, co
       with_row_form(form, [&](auto R) {
         hipExtLaunchKernelGGL(k_cheb_iter<T, decltype(R)::value, false, false>, dim3(G), dim3(1024), 0, s, ev[2 * r],
                               ev[2 * r + 1], 0, Acs, (const T*)w.dinv, b, bT, ycur, ynext, ynext, w.x, inv_hi, c0u,
-                              c1, c2u, st, reps);
+                              c1, c2u, st, reps, ScaleJob{});
       });
       VEM_HIP(hipGetLastError());
     }
@@ -409,9 +413,9 @@ template double time_cheb_products<float>(hipStream_t, const Sell&, const PcgWor
                                           const double*, double, int, PcgState*);
 
 template void launch_cheb<double>(hipStream_t, const Sell&, const PcgWorkT<double>&, const double*, const double*,
-                                  double, int, PcgState*);
+                                  double, int, PcgState*, const ScaleJob&);
 template void launch_cheb<float>(hipStream_t, const Sell&, const PcgWorkT<float>&, const double*, const double*,
-                                 double, int, PcgState*);
+                                 double, int, PcgState*, const ScaleJob&);
 
 void launch_gershgorin(hipStream_t s, const Sell& A, const double* dinv, double* part, double* inv_hi) {
   const int G = (int)std::min<int64_t>(1024, (A.rows + 255) / 256);

@@ -316,12 +316,20 @@ void launch_pcg_init32p(hipStream_t s, const Sell& A, const PcgWork32& w, const 
                         int maxit, double* part);
 void launch_pcg_iter32p(hipStream_t s, int i, const Sell& A, const PcgWork32& w, PcgState* st, double* part);
 void launch_to_f64(hipStream_t s, int64_t n, const float* x, double* y);
+// A diagonal scaling y = d x of n FP64 entries that a launch performs beside its own work.
+struct ScaleJob {
+  int64_t n = 0;
+  const double* x = nullptr;
+  const double* d = nullptr;
+  double* y = nullptr;
+};
 // Chebyshev-Jacobi inner solve: m products, interval [c hi, hi] with 1/hi at inv_hi (device), on the
 // column-scaled values (val_cs, FP32: val32_cs) and w.dinv; x (FP64: w.x; FP32: w.x rounded); the
-// iterates alternate in w.p and w.s, and FP32 keeps b rounded in w.r; adds m to st->total
+// iterates alternate in w.p and w.s, and FP32 keeps b rounded in w.r; adds m to st->total.  The
+// first product also performs `side` (Block-Schur's diag(M)^{-1} on the flux part), saving a launch.
 template <typename T>
 void launch_cheb(hipStream_t s, const Sell& A, const PcgWorkT<T>& w, const double* b, const double* inv_hi,
-                 double c, int m, PcgState* st);
+                 double c, int m, PcgState* st, const ScaleJob& side = ScaleJob{});
 // mean kernel time (ms) of reps middle-form Chebyshev products, each timed by its own start and stop
 // events (after a degree-2 solve that sets up the iterates; synchronises)
 template <typename T>
