@@ -18,7 +18,7 @@ namespace {
 __global__ void __launch_bounds__(kThreads) k_finalize(int nparts, int K, const double* __restrict__ partials,
                                                        double* __restrict__ out, double* __restrict__ hout) {
   const int k = blockIdx.x;
-  double v = block_sum_partials(partials, nparts, K, k);
+  double v = block_sum_partials<kThreads>(partials, nparts, K, k);
   if (threadIdx.x == 0) {
     out[k] = v;
     if (hout) hout[k] = v;
@@ -32,8 +32,8 @@ inline int red_grid(int64_t n) {
 
 // ---- SELL-64 SpMV: one thread per row -------------------------------------------------------
 __global__ void __launch_bounds__(kThreads) k_spmv(SellView A, const double* __restrict__ x, double* __restrict__ y) {
-  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < A.rows;
-       row += (int64_t)gridDim.x * blockDim.x)
+  for (int64_t row = (int64_t)blockIdx.x * kThreads + threadIdx.x; row < A.rows;
+       row += (int64_t)gridDim.x * kThreads)
     y[row] = sell_dot(A, row, x);
 }
 
@@ -42,13 +42,13 @@ __global__ void __launch_bounds__(kThreads) k_residual(SellView A, const double*
                                                        const double* __restrict__ b, double* __restrict__ r,
                                                        double* partials) {
   double acc[1] = {0.0};
-  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < A.rows;
-       row += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t row = (int64_t)blockIdx.x * kThreads + threadIdx.x; row < A.rows;
+       row += (int64_t)gridDim.x * kThreads) {
     double ri = b[row] - sell_dot(A, row, x);
     r[row] = ri;
     acc[0] += ri * ri;
   }
-  block_partials<1>(acc, partials);
+  block_partials<1, kThreads>(acc, partials);
 }
 
 // ---- Gram-Schmidt kernels ------------------------------------------------------------------
@@ -61,12 +61,12 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1
   double acc[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
     double wi = w[i];
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] += V[k * ldv + i] * wi;
   }
-  block_partials<K>(acc, partials);
+  block_partials<K, kThreads>(acc, partials);
 }
 
 // First Gram-Schmidt pass of Arnoldi step j (K = j + 1 >= 2 basis vectors) with the previous
@@ -91,7 +91,7 @@ __device__ inline void dots_fix_body(int64_t n, double* __restrict__ V, int64_t 
   double acc[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) acc[k] = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
     const double wi = w[i];
     double t = V[(K - 1) * ldv + i];
 #pragma unroll
@@ -104,7 +104,7 @@ __device__ inline void dots_fix_body(int64_t n, double* __restrict__ V, int64_t 
     V[(K - 1) * ldv + i] = t;
     acc[K - 1] += t * wi;
   }
-  block_partials<K>(acc, partials);
+  block_partials<K, kThreads>(acc, partials);
 }
 template <int K>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))) k_dots_fix(int64_t n, double* __restrict__ V, int64_t ldv,
@@ -134,7 +134,7 @@ __global__ void __launch_bounds__(kThreads) k_update_dots(int64_t n, const doubl
     acc[k] = 0.0;
   }
   acc[K] = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
     double v[K];
     double wi = w[i];
 #pragma unroll
@@ -147,14 +147,14 @@ __global__ void __launch_bounds__(kThreads) k_update_dots(int64_t n, const doubl
     for (int k = 0; k < K; ++k) acc[k] += v[k] * wi;
     acc[K] += wi * wi;
   }
-  block_partials<K + 1>(acc, partials);
+  block_partials<K + 1, kThreads>(acc, partials);
 }
 
 // out = x - v (dot * inv_vv): x without its component along v (dot = v . x on the device)
-__global__ void k_project(int64_t n, const double* x, const double* __restrict__ v, const double* __restrict__ dot,
+__global__ void __launch_bounds__(kThreads) k_project(int64_t n, const double* x, const double* __restrict__ v, const double* __restrict__ dot,
                           double inv_vv, double* out) {
   const double c = *dot * inv_vv;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
     out[i] = x[i] - v[i] * c;
 }
 
@@ -165,7 +165,7 @@ __global__ void __launch_bounds__(kThreads) k_combine(int64_t n, const double* _
   double yk[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) yk[k] = y[k];
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
     double s = x[i];
 #pragma unroll
     for (int k = 0; k < K; ++k) s += Z[k * ldz + i] * yk[k];
@@ -173,29 +173,29 @@ __global__ void __launch_bounds__(kThreads) k_combine(int64_t n, const double* _
   }
 }
 
-__global__ void k_scale_to(int64_t n, const double* __restrict__ w, const double* __restrict__ norm2,
+__global__ void __launch_bounds__(kThreads) k_scale_to(int64_t n, const double* __restrict__ w, const double* __restrict__ norm2,
                            double* __restrict__ dst) {
   double inv = 1.0 / sqrt(norm2[0]);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
     dst[i] = w[i] * inv;
 }
 
-__global__ void k_scale_by(int64_t n, const double* __restrict__ x, const double* __restrict__ d, double c,
+__global__ void __launch_bounds__(kThreads) k_scale_by(int64_t n, const double* __restrict__ x, const double* __restrict__ d, double c,
                            double* __restrict__ y) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
     y[i] = d ? c * d[i] * x[i] : c * x[i];
 }
 
-__global__ void k_fill(int64_t n, double v, double* __restrict__ y) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+__global__ void __launch_bounds__(kThreads) k_fill(int64_t n, double v, double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
     y[i] = v;
 }
 
-__global__ void k_sum(int64_t n, const double* __restrict__ x, double* partials) {
+__global__ void __launch_bounds__(kThreads) k_sum(int64_t n, const double* __restrict__ x, double* partials) {
   double acc[1] = {0.0};
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
     acc[0] += x[i];
-  block_partials<1>(acc, partials);
+  block_partials<1, kThreads>(acc, partials);
 }
 
 // ---- classical Jacobi-PCG in FP32 (mixed-precision inner solves) --------------------------
@@ -213,14 +213,14 @@ __global__ void __launch_bounds__(kPcgThreads) k_cg_init(int64_t n, const double
                                                          T* __restrict__ r, T* __restrict__ z, PcgState* st,
                                                          double tol2, double* __restrict__ prho0) {
   double acc[1] = {0.0};
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = (int64_t)blockIdx.x * kPcgThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kPcgThreads) {
     const T bi = (T)b[i], zi = dinv[i] * bi;
     x[i] = T(0);
     r[i] = bi;
     z[i] = zi;
     acc[0] += (double)bi * (double)zi;
   }
-  block_partials<1>(acc, prho0);
+  block_partials<1, kPcgThreads>(acc, prho0);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->gamma[0] = st->gamma[1] = 0.0;
     st->gamma0 = 0.0;
@@ -238,7 +238,7 @@ __global__ void __launch_bounds__(kPcgThreads) k_cg_spmv(int k, SellViewT<T> A, 
   if (st->done) return;
   const int P = gridDim.x;
   const int cur = k & 1;
-  const double rho = block_sum_partials(prho + (size_t)cur * P, P, 1, 0);
+  const double rho = block_sum_partials<kPcgThreads>(prho + (size_t)cur * P, P, 1, 0);
   const double rho0 = k == 0 ? rho : st->gamma0;
   const double beta = k == 0 ? 0.0 : rho / st->gamma[1 - cur];
   const bool done = !(rho > st->tol2 * rho0);
@@ -250,8 +250,8 @@ __global__ void __launch_bounds__(kPcgThreads) k_cg_spmv(int k, SellViewT<T> A, 
   if (done) return;
   const T bt = (T)beta;
   double acc[1] = {0.0};
-  for (int64_t row = xcd_block() * blockDim.x + threadIdx.x; row < A.rows;
-       row += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t row = xcd_block_n<kPcgThreads>() * kPcgThreads + threadIdx.x; row < A.rows;
+       row += (int64_t)gridDim.x * kPcgThreads) {
     const int64_t sl = row >> 6;
     const int64_t base = A.slice_ptr[sl] + (row & 63);
     const int len = A.slice_len[sl];
@@ -272,7 +272,7 @@ __global__ void __launch_bounds__(kPcgThreads) k_cg_spmv(int k, SellViewT<T> A, 
     q[row] = s;
     acc[0] += (double)pn * (double)s;
   }
-  block_partials<1>(acc, ppq);
+  block_partials<1, kPcgThreads>(acc, ppq);
 }
 
 template <typename T>
@@ -284,15 +284,15 @@ __global__ void __launch_bounds__(kPcgThreads) k_cg_update(int k, int64_t n, T* 
   if (st->done) return;
   const int P = gridDim.x;
   const int cur = k & 1;
-  const double rho = block_sum_partials(prho + (size_t)cur * P, P, 1, 0);
-  const double pq = block_sum_partials(ppq, P, 1, 0);
+  const double rho = block_sum_partials<kPcgThreads>(prho + (size_t)cur * P, P, 1, 0);
+  const double pq = block_sum_partials<kPcgThreads>(ppq, P, 1, 0);
   if (!(pq > 0.0)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) st->done = 2;
     return;
   }
   const T a = (T)(rho / pq);
   double acc[1] = {0.0};
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = (int64_t)blockIdx.x * kPcgThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kPcgThreads) {
     x[i] += a * p[i];
     const T ri = r[i] - a * q[i];
     r[i] = ri;
@@ -300,7 +300,7 @@ __global__ void __launch_bounds__(kPcgThreads) k_cg_update(int k, int64_t n, T* 
     z[i] = zi;
     acc[0] += (double)ri * (double)zi;
   }
-  block_partials<1>(acc, prho + (size_t)(1 - cur) * P);
+  block_partials<1, kPcgThreads>(acc, prho + (size_t)(1 - cur) * P);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->count += 1;
     st->total += 1;
@@ -383,14 +383,14 @@ __global__ void __launch_bounds__(kBlock) k_scg_init(V P, const T* __restrict__ 
                                                      T* __restrict__ z, PcgState* st, double tol2,
                                                      double* __restrict__ prho0) {
   double acc[1] = {0.0};
-  for (int64_t row = xcd_block() * blockDim.x + threadIdx.x; row < P.rows;
-       row += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t row = xcd_block_n<kBlock>() * kBlock + threadIdx.x; row < P.rows;
+       row += (int64_t)gridDim.x * kBlock) {
     const T zi = mat_row(P, row, r0);
     z[row] = zi;
     x[row] = T(0);
     acc[0] += (double)r0[row] * (double)zi;
   }
-  block_partials<1>(acc, prho0);
+  block_partials<1, kBlock>(acc, prho0);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->gamma[0] = st->gamma[1] = 0.0;
     st->gamma0 = 0.0;
@@ -407,8 +407,8 @@ __global__ void __launch_bounds__(kBlock) k_scg_prod(int k, int early, V F, cons
   if (early && st->done) return;
   const int G = gridDim.x;
   const int cur = k & 1;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t row = xcd_block() * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  int64_t row = xcd_block_n<kBlock>() * kBlock + threadIdx.x;
   T fz = T(0), zi = T(0), po = T(0), qo = T(0);
   auto load = [&](int64_t i) {
     zi = z[i];
@@ -420,7 +420,7 @@ __global__ void __launch_bounds__(kBlock) k_scg_prod(int k, int early, V F, cons
   };
   if (row < F.rows) load(row);
   const int was_done = st->done;
-  const double rho = block_sum_partials(prho + (size_t)cur * G, G, 1, 0);
+  const double rho = block_sum_partials<kBlock>(prho + (size_t)cur * G, G, 1, 0);
   if (was_done) return;
   const double rho0 = k == 0 ? rho : st->gamma0;
   const double beta = k == 0 ? 0.0 : rho / st->gamma[1 - cur];
@@ -442,7 +442,7 @@ __global__ void __launch_bounds__(kBlock) k_scg_prod(int k, int early, V F, cons
     row += stride;
     if (row < F.rows) load(row);
   }
-  block_partials<1>(acc, ppq);
+  block_partials<1, kBlock>(acc, ppq);
 }
 
 template <typename T, int kBlock, typename V>
@@ -454,8 +454,8 @@ __global__ void __launch_bounds__(kBlock) k_scg_update(int k, int early, V P, T*
   if (early && st->done) return;
   const int G = gridDim.x;
   const int cur = k & 1;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t row = xcd_block() * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  int64_t row = xcd_block_n<kBlock>() * kBlock + threadIdx.x;
   T pq_r = T(0), qi = T(0), ri = T(0), zi = T(0), xi = T(0), pi = T(0);
   auto load = [&](int64_t i) {
     qi = q[i];
@@ -467,8 +467,8 @@ __global__ void __launch_bounds__(kBlock) k_scg_update(int k, int early, V P, T*
   };
   if (row < P.rows) load(row);
   const int was_done = st->done;
-  const double rho = block_sum_partials(prho + (size_t)cur * G, G, 1, 0);
-  const double pq = block_sum_partials(ppq, G, 1, 0);
+  const double rho = block_sum_partials<kBlock>(prho + (size_t)cur * G, G, 1, 0);
+  const double pq = block_sum_partials<kBlock>(ppq, G, 1, 0);
   if (was_done) return;
   if (!(pq > 0.0)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) st->done = 2;
@@ -486,7 +486,7 @@ __global__ void __launch_bounds__(kBlock) k_scg_update(int k, int early, V P, T*
     row += stride;
     if (row < P.rows) load(row);
   }
-  block_partials<1>(acc, prho + (size_t)(1 - cur) * G);
+  block_partials<1, kBlock>(acc, prho + (size_t)(1 - cur) * G);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->count += 1;
     st->total += 1;
@@ -504,19 +504,19 @@ SellViewT<float> values_view<float>(const Sell& A) {
   return view32(A);
 }
 
-__global__ void k_to_f32(int64_t n, const double* __restrict__ x, float* __restrict__ y) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+__global__ void __launch_bounds__(kThreads) k_to_f32(int64_t n, const double* __restrict__ x, float* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
     y[i] = (float)x[i];
 }
 
-__global__ void k_to_f64(int64_t n, const float* __restrict__ x, double* __restrict__ y) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+__global__ void __launch_bounds__(kThreads) k_to_f64(int64_t n, const float* __restrict__ x, double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
     y[i] = (double)x[i];
 }
 
-__global__ void k_col_scale(int64_t n, const int* __restrict__ col, const double* __restrict__ val,
+__global__ void __launch_bounds__(kThreads) k_col_scale(int64_t n, const int* __restrict__ col, const double* __restrict__ val,
                             const double* __restrict__ dinv, double* __restrict__ out) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
     out[i] = val[i] * dinv[col[i]];
 }
 

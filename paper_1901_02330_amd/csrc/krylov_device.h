@@ -28,23 +28,31 @@ __device__ inline double wave_sum(double v) {
 // A_gamma iteration, 3.5% off the S iteration.  The saddle SpMV keeps the hardware
 // order: its flux and pressure rows differ in cost, and contiguous bands per XCD
 // left it 10% slower.)
-__device__ inline int64_t xcd_block() {
+__device__ inline int64_t xcd_block_of(int block) {
   const int b = blockIdx.x, P = gridDim.x;
-  const int C = (16384 / (int)blockDim.x) > 0 ? (16384 / (int)blockDim.x) : 1;
+  const int C = (16384 / block) > 0 ? (16384 / block) : 1;
   const int full = P / (8 * C) * (8 * C);
   if (b >= full) return b;
   const int x = b & 7, i = b >> 3, j = i / C, off = i % C;
   return (int64_t)(j * 8 + x) * C + off;
 }
+__device__ inline int64_t xcd_block() { return xcd_block_of((int)blockDim.x); }
+// The same for a kernel whose block size is the compile-time constant kBlock.  Kernels use the
+// constant rather than blockDim.x where they know it: reading blockDim.x for arithmetic such as the
+// divisions above costs a vector load of the dispatch's 16-bit block size at the start of the
+// kernel, ahead of every other load (on the 64^3 Chebyshev product about 0.6 us of 5.7 us).
+template <int kBlock>
+__device__ inline int64_t xcd_block_n() { return xcd_block_of(kBlock); }
 
 // Block-reduce K accumulators and store this block's partial sums at
 // partials[blockIdx.x * K + k].  No atomics and no fences: the consumer is a
 // later kernel on the same stream, and the kernel boundary makes the partials
-// visible to every XCD.
-template <int K>
+// visible to every XCD.  kBlock: the launch's block size (these helpers take it as a constant).
+template <int K, int kBlock>
 __device__ inline void block_partials(const double (&acc)[K], double* partials) {
+  static_assert(kBlock % 64 == 0 && kBlock / 64 <= kMaxWaves, "block size");
   __shared__ double sh[kMaxWaves][K];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = kBlock >> 6;
 #pragma unroll
   for (int i = 0; i < K; ++i) {
     double v = wave_sum(acc[i]);
@@ -60,13 +68,14 @@ __device__ inline void block_partials(const double (&acc)[K], double* partials) 
 
 // Sum of nparts partials (stride K, component k) by the whole block, in a fixed
 // order: every block that calls it obtains the same bits.
+template <int kBlock>
 __device__ inline double block_sum_partials(const double* __restrict__ partials, int nparts, int K, int k) {
   __shared__ double sh[kMaxWaves];
   __shared__ double total;
   double s = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += blockDim.x) s += partials[(size_t)b * K + k];
+  for (int b = threadIdx.x; b < nparts; b += kBlock) s += partials[(size_t)b * K + k];
   s = wave_sum(s);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = kBlock >> 6;
   if (lane == 0) sh[wid] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -82,17 +91,18 @@ __device__ inline double block_sum_partials(const double* __restrict__ partials,
 
 // Both components of nparts (gamma, delta) partial pairs, summed by the whole block
 // in one pass, in a fixed order (every block obtains the same bits).
+template <int kBlock>
 __device__ inline void block_sum_partials2(const double* __restrict__ partials, int nparts, double (&out)[2]) {
   __shared__ double sh[kMaxWaves][2];
   __shared__ double total[2];
   double g = 0.0, d = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
+  for (int b = threadIdx.x; b < nparts; b += kBlock) {
     g += partials[2 * (size_t)b];
     d += partials[2 * (size_t)b + 1];
   }
   g = wave_sum(g);
   d = wave_sum(d);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = kBlock >> 6;
   if (lane == 0) {
     sh[wid][0] = g;
     sh[wid][1] = d;

@@ -47,8 +47,8 @@ __global__ void __launch_bounds__(kBlock) k_ppcg_init(SellViewT<T> Ac, PcgViewT<
                                                            const double* __restrict__ b, PcgState* st, double tol2,
                                                            int maxit, double* __restrict__ part) {
   double acc[2] = {0.0, 0.0};
-  for (int64_t row = xcd_block() * blockDim.x + threadIdx.x; row < Ac.rows;
-       row += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t row = xcd_block_n<kBlock>() * kBlock + threadIdx.x; row < Ac.rows;
+       row += (int64_t)gridDim.x * kBlock) {
     const T bi = (T)b[row], di = v.dinv[row];
     const T wi = sell_row<kRow>(Ac, row, b);
     v.x[row] = T(0);
@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(kBlock) k_ppcg_init(SellViewT<T> Ac, PcgViewT<
     acc[0] += (double)bi * (double)bi * (double)di;
     acc[1] += (double)wi * (double)bi * (double)di;
   }
-  block_partials<2>(acc, part);
+  block_partials<2, kBlock>(acc, part);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->gamma[0] = st->gamma[1] = 0.0;
     st->alpha[0] = st->alpha[1] = 0.0;
@@ -77,8 +77,8 @@ __global__ void __launch_bounds__(kBlock) k_ppcg_iter(int parity, SellViewT<T> A
   const int cur = parity;
   const T* __restrict__ win = cur ? v.w1 : v.w0;
   T* __restrict__ wout = cur ? v.w0 : v.w1;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int64_t row = xcd_block() * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * kBlock;
+  int64_t row = xcd_block_n<kBlock>() * kBlock + threadIdx.x;
   // The product and the old vector entries do not depend on this iteration's
   // scalars: their loads are issued first and are in flight while the block sums
   // the partials of gamma and delta left by the previous iteration.
@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(kBlock) k_ppcg_iter(int parity, SellViewT<T> A
   if (row < Ac.rows) load(row);
   const int was_done = st->done;
   double gd[2];
-  block_sum_partials2(part + (size_t)cur * 2 * P, P, gd);
+  block_sum_partials2<kBlock>(part + (size_t)cur * 2 * P, P, gd);
   if (was_done) return;
   const double gamma = gd[0], delta = gd[1];
   double gamma0, beta, alpha;
@@ -147,7 +147,7 @@ __global__ void __launch_bounds__(kBlock) k_ppcg_iter(int parity, SellViewT<T> A
     row += stride;
     if (row < Ac.rows) load(row);
   }
-  block_partials<2>(acc, part + (size_t)(1 - cur) * 2 * P);
+  block_partials<2, kBlock>(acc, part + (size_t)(1 - cur) * 2 * P);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     st->count += 1;
     st->total += 1;
@@ -214,8 +214,9 @@ void pcg_iter_sel(hipStream_t s, int i, const Sell& A, SellViewT<T> Av, const Pc
 // by the device-resident 1/hi (the Gershgorin bound of D^{-1}A, taken when the values are built):
 // nothing is read back.  m products give x_{m+1}, a polynomial of degree m in D^{-1}A applied to
 // D^{-1}b.  The first product also sets the inner-solve counters (no separate start kernel).
+constexpr int kChebBlock = 1024;  // the Chebyshev products' block size (every launch)
 template <typename T, int kRow, bool kFirst, bool kLast>
-__global__ void __launch_bounds__(1024) k_cheb_iter(SellViewT<T> Acs, const T* __restrict__ dinv,
+__global__ void __launch_bounds__(kChebBlock) k_cheb_iter(SellViewT<T> Acs, const T* __restrict__ dinv,
                                                     const double* __restrict__ b, T* __restrict__ bT,
                                                     const T* __restrict__ ycur, T* yprev, T* yout,
                                                     T* __restrict__ x,
@@ -227,8 +228,24 @@ __global__ void __launch_bounds__(1024) k_cheb_iter(SellViewT<T> Acs, const T* _
     st->total += m;
     st->done = 0;
   }
-  for (int64_t row = xcd_block() * blockDim.x + threadIdx.x; row < Acs.rows;
-       row += (int64_t)gridDim.x * blockDim.x) {
+  // The side job's first kSide entries per thread are loaded before the product's rows, so that their
+  // loads are in flight while the rows' dependent loads proceed; they are stored after the rows.  The
+  // block size is the launch's constant kChebBlock (not read from the dispatch: a vector load of it
+  // would be ordered behind those loads).
+  constexpr int kSide = 4;
+  const int64_t tid = (int64_t)blockIdx.x * kChebBlock + threadIdx.x, nthr = (int64_t)gridDim.x * kChebBlock;
+  double sx[kSide], sd[kSide];
+  if constexpr (kFirst) {
+    if (side.n > 0) {  // the same on every thread; the loads take no branch (slots past n reload entry n - 1)
+#pragma unroll
+      for (int u = 0; u < kSide; ++u) {
+        const int64_t i = tid + u * nthr, j = i < side.n ? i : side.n - 1;
+        sx[u] = side.x[j];
+        sd[u] = side.d[j];
+      }
+    }
+  }
+  for (int64_t row = xcd_block_of(kChebBlock) * kChebBlock + threadIdx.x; row < Acs.rows; row += nthr) {
     T yn;
     if constexpr (kFirst) {
       // y_1 = c0 b and y_0 = 0, with A D^{-1} y_1 = c0 (A D^{-1} b)
@@ -254,8 +271,12 @@ __global__ void __launch_bounds__(1024) k_cheb_iter(SellViewT<T> Acs, const T* _
       yout[row] = yn;
   }
   if constexpr (kFirst) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < side.n; i += (int64_t)gridDim.x * blockDim.x)
-      side.y[i] = side.d[i] * side.x[i];
+#pragma unroll
+    for (int u = 0; u < kSide; ++u) {
+      const int64_t i = tid + u * nthr;
+      if (i < side.n) side.y[i] = sd[u] * sx[u];
+    }
+    for (int64_t i = tid + kSide * nthr; i < side.n; i += nthr) side.y[i] = side.d[i] * side.x[i];
   }
 }
 
@@ -310,19 +331,19 @@ template <typename T, int kRow>
 void cheb_iter_as(hipStream_t s, int k, int m, SellViewT<T> Acs, const T* dinv, const double* b, T* bT,
                   const T* ycur, T* yprev, T* yout, T* x, const double* inv_hi, double c0u, double c1, double c2u,
                   PcgState* st, const ScaleJob& side) {
-  const int G = pcg_grid(Acs.rows, 1024);
+  const int G = pcg_grid(Acs.rows, kChebBlock);
   const bool first = k == 0, last = k == m - 1;
   if (first && last)
-    k_cheb_iter<T, kRow, true, true><<<G, 1024, 0, s>>>(Acs, dinv, b, bT, ycur, yprev, yout, x, inv_hi, c0u, c1,
+    k_cheb_iter<T, kRow, true, true><<<G, kChebBlock, 0, s>>>(Acs, dinv, b, bT, ycur, yprev, yout, x, inv_hi, c0u, c1,
                                                           c2u, st, m, side);
   else if (first)
-    k_cheb_iter<T, kRow, true, false><<<G, 1024, 0, s>>>(Acs, dinv, b, bT, ycur, yprev, yout, x, inv_hi, c0u, c1,
+    k_cheb_iter<T, kRow, true, false><<<G, kChebBlock, 0, s>>>(Acs, dinv, b, bT, ycur, yprev, yout, x, inv_hi, c0u, c1,
                                                            c2u, st, m, side);
   else if (last)
-    k_cheb_iter<T, kRow, false, true><<<G, 1024, 0, s>>>(Acs, dinv, b, bT, ycur, yprev, yout, x, inv_hi, c0u, c1,
+    k_cheb_iter<T, kRow, false, true><<<G, kChebBlock, 0, s>>>(Acs, dinv, b, bT, ycur, yprev, yout, x, inv_hi, c0u, c1,
                                                            c2u, st, m, side);
   else
-    k_cheb_iter<T, kRow, false, false><<<G, 1024, 0, s>>>(Acs, dinv, b, bT, ycur, yprev, yout, x, inv_hi, c0u,
+    k_cheb_iter<T, kRow, false, false><<<G, kChebBlock, 0, s>>>(Acs, dinv, b, bT, ycur, yprev, yout, x, inv_hi, c0u,
                                                             c1, c2u, st, m, side);
 }
 
@@ -373,7 +394,7 @@ double time_cheb_products(hipStream_t s, const Sell& A, const PcgWorkT<T>& w, co
   rho = 1.0 / (2.0 * sigma - rho);  // the degree-2 solve's two steps
   rho = 1.0 / (2.0 * sigma - rho);
   const int form = A.rows <= kPcgMaxThreads ? row_form(A) : kRowAny;
-  const int G = pcg_grid(Acs.rows, 1024);
+  const int G = pcg_grid(Acs.rows, kChebBlock);
   std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
   double total = 0.0;
   try {
@@ -387,7 +408,7 @@ double time_cheb_products(hipStream_t s, const Sell& A, const PcgWorkT<T>& w, co
       const T* ycur = ybuf[(k + 1) & 1];
       T* ynext = ybuf[k & 1];
       with_row_form(form, [&](auto R) {
-        hipExtLaunchKernelGGL(k_cheb_iter<T, decltype(R)::value, false, false>, dim3(G), dim3(1024), 0, s, ev[2 * r],
+        hipExtLaunchKernelGGL(k_cheb_iter<T, decltype(R)::value, false, false>, dim3(G), dim3(kChebBlock), 0, s, ev[2 * r],
                               ev[2 * r + 1], 0, Acs, (const T*)w.dinv, b, bT, ycur, ynext, ynext, w.x, inv_hi, c0u,
                               c1, c2u, st, reps, ScaleJob{});
       });
