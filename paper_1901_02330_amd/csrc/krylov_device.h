@@ -32,9 +32,9 @@ __device__ inline int64_t xcd_block_of(int block) {
   const int b = blockIdx.x, P = gridDim.x;
   const int C = (16384 / block) > 0 ? (16384 / block) : 1;
   const int full = P / (8 * C) * (8 * C);
-  if (b >= full) return b;
   const int x = b & 7, i = b >> 3, j = i / C, off = i % C;
-  return (int64_t)(j * 8 + x) * C + off;
+  const int64_t mapped = (int64_t)(j * 8 + x) * C + off;
+  return b >= full ? (int64_t)b : mapped;  // a select, not a branch: the kernel's loads stay in one block
 }
 __device__ inline int64_t xcd_block() { return xcd_block_of((int)blockDim.x); }
 // The same for a kernel whose block size is the compile-time constant kBlock.  Kernels use the
@@ -185,10 +185,11 @@ __device__ inline T sell_dot_short(const SellViewT<T>& A, int64_t row, const X* 
 // The same product where every slice holds exactly N entries per row (a matrix of short rows whose
 // slices were all padded to one length): N loads of each kind at fixed offsets and no masks, the
 // same sum (padding entries add +0).  On the 64^3 cube's S (N = 7) a Chebyshev product took 4.8 us
-// against 5.2-5.4 us with the masked form.
+// against 5.2-5.4 us with the masked form (stand-alone, per-launch events).
 template <int N, typename T, typename X>
 __device__ inline T sell_dot_fixed(const SellViewT<T>& A, int64_t row, const X* __restrict__ x) {
-  const int64_t base = A.slice_ptr[wave_uniform(row >> 6)] + (row & 63);
+  // every slice holds 64 N slots, so slice s starts at 64 N s: no slice offset to load
+  const int64_t base = (row >> 6) * (64 * N) + (row & 63);
   int c[N];
   T v[N];
 #pragma unroll

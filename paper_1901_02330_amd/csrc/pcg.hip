@@ -222,7 +222,7 @@ __global__ void __launch_bounds__(kChebBlock) k_cheb_iter(SellViewT<T> Acs, cons
                                                     T* __restrict__ x,
                                                     const double* __restrict__ inv_hi, double c0u, double c1,
                                                     double c2u, PcgState* st, int m, ScaleJob side) {
-  const T c2 = (T)(c2u * inv_hi[0]), t1 = (T)c1;
+  const T t1 = (T)c1;
   if (kFirst && blockIdx.x == 0 && threadIdx.x == 0) {
     st->count = m;
     st->total += m;
@@ -245,13 +245,14 @@ __global__ void __launch_bounds__(kChebBlock) k_cheb_iter(SellViewT<T> Acs, cons
       }
     }
   }
-  for (int64_t row = xcd_block_of(kChebBlock) * kChebBlock + threadIdx.x; row < Acs.rows; row += nthr) {
+  auto one_row = [&](int64_t row) {
     T yn;
     if constexpr (kFirst) {
       // y_1 = c0 b and y_0 = 0, with A D^{-1} y_1 = c0 (A D^{-1} b)
-      const T c0 = (T)(c0u * inv_hi[0]);
       const T bi = (T)b[row];
       const T ab = sell_row<kRow>(Acs, row, b);
+      const double ih = inv_hi[0];
+      const T c0 = (T)(c0u * ih), c2 = (T)(c2u * ih);
       const T y1 = c0 * bi;
       yn = y1 + t1 * y1 + c2 * (bi - c0 * ab);
       if (!kLast) {
@@ -263,12 +264,21 @@ __global__ void __launch_bounds__(kChebBlock) k_cheb_iter(SellViewT<T> Acs, cons
       const T yj = ycur[row], yp = yprev[row];
       const T bi = bT ? bT[row] : (T)b[row];
       const T ay = sell_row<kRow>(Acs, row, ycur);
+      const T c2 = (T)(c2u * inv_hi[0]);
       yn = yj + t1 * (yj - yp) + c2 * (bi - ay);
     }
     if constexpr (kLast)
       x[row] = dinv[row] * yn;
     else
       yout[row] = yn;
+  };
+  const int64_t row0 = xcd_block_of(kChebBlock) * kChebBlock + threadIdx.x;
+  if constexpr (kRow == kRowAny) {
+    for (int64_t row = row0; row < Acs.rows; row += nthr) one_row(row);
+  } else if (row0 < Acs.rows) {
+    // the short-row forms are launched with a thread for every row: no loop, so that nothing is
+    // hoisted ahead of the row's first loads
+    one_row(row0);
   }
   if constexpr (kFirst) {
 #pragma unroll
