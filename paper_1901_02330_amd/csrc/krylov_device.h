@@ -68,12 +68,26 @@ __device__ inline void block_partials(const double (&acc)[K], double* partials) 
 
 // Sum of nparts partials (stride K, component k) by the whole block, in a fixed
 // order: every block that calls it obtains the same bits.
+// Each thread's share of the partials is loaded kSumLoads at a time, all in flight at once (a loop
+// that adds as it loads waits for every load in turn), and added in the same order as such a loop:
+// the same bits.  Slots past nparts load partial 0 and add nothing.
+constexpr int kSumLoads = 8;
 template <int kBlock>
 __device__ inline double block_sum_partials(const double* __restrict__ partials, int nparts, int K, int k) {
   __shared__ double sh[kMaxWaves];
   __shared__ double total;
   double s = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += kBlock) s += partials[(size_t)b * K + k];
+  for (int b0 = threadIdx.x; b0 < nparts; b0 += kSumLoads * kBlock) {
+    double v[kSumLoads];
+#pragma unroll
+    for (int u = 0; u < kSumLoads; ++u) {
+      const int b = b0 + u * kBlock;
+      v[u] = partials[(size_t)(b < nparts ? b : 0) * K + k];
+    }
+#pragma unroll
+    for (int u = 0; u < kSumLoads; ++u)
+      if (b0 + u * kBlock < nparts) s += v[u];
+  }
   s = wave_sum(s);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = kBlock >> 6;
   if (lane == 0) sh[wid] = s;
@@ -96,9 +110,20 @@ __device__ inline void block_sum_partials2(const double* __restrict__ partials, 
   __shared__ double sh[kMaxWaves][2];
   __shared__ double total[2];
   double g = 0.0, d = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += kBlock) {
-    g += partials[2 * (size_t)b];
-    d += partials[2 * (size_t)b + 1];
+  for (int b0 = threadIdx.x; b0 < nparts; b0 += kSumLoads * kBlock) {
+    double vg[kSumLoads], vd[kSumLoads];
+#pragma unroll
+    for (int u = 0; u < kSumLoads; ++u) {
+      const int b = b0 + u * kBlock, c = b < nparts ? b : 0;
+      vg[u] = partials[2 * (size_t)c];
+      vd[u] = partials[2 * (size_t)c + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kSumLoads; ++u)
+      if (b0 + u * kBlock < nparts) {
+        g += vg[u];
+        d += vd[u];
+      }
   }
   g = wave_sum(g);
   d = wave_sum(d);
